@@ -1,0 +1,21 @@
+"""FP64 CPU oracle of the SPPC eigensolver -- TEST INFRASTRUCTURE ONLY.
+
+A plain, slow, obviously correct implementation of what the GPU path computes,
+written from the paper (Alg. 2; Sec. IV eqs. EP_small, first_PC, exp_seq2,
+bl_diag, sm_first, sm_lin_proj, blkGS, QR, Qp; eq. rrn) in float64 with NumPy /
+SciPy (LAPACK).  Only the tests, the smoke check and the benchmark's CPU
+baseline leg may import it.  It shares no code with the GPU library and the
+GPU library never imports it.
+"""
+from .core import (  # noqa: F401
+    Options,
+    Result,
+    symmetric_from_upper,
+    small_space_matrix,
+    zeroth_order,
+    rs_corrections,
+    sppc,
+    final_check,
+    jacobi_correction,
+    rayleigh_ritz,
+)

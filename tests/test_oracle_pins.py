@@ -1,0 +1,249 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by linear algebra.
+
+Each test checks the oracle against something other than itself: closed forms
+that follow from the splitting (eq. first_PC), the perturbation series of
+H(c) = H0 + cV (eq. Hc, eq. exp), the Krylov space the method must reproduce
+when the small space is as small as the block, dense brute force on tiny
+inputs, and eigenvalue bounds for Rayleigh-Ritz pairs.
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import levelgen
+import oracle
+from oracle import core as osp
+
+
+def _H(sizes, d, seed):
+    A = levelgen.generate(sizes, d, seed)
+    return oracle.symmetric_from_upper(A.row_ptr, A.col, A.val, A.n), A
+
+
+@pytest.fixture(scope="module")
+def cfg0():
+    w = levelgen.WORKLOADS[0]
+    A = w.generate()
+    H = oracle.symmetric_from_upper(A.row_ptr, A.col, A.val, A.n)
+    lam, X = np.linalg.eigh(H.toarray())
+    return H, w.n0, w.k, lam, X
+
+
+@pytest.fixture(scope="module")
+def cfg0_run(cfg0):
+    H, n0, k, lam, _ = cfg0
+    return oracle.sppc(H, n0, k, oracle.Options())
+
+
+# --- P2: at p = 0 the projected matrix is diag(E^(0)) because V11 = 0 (eq. split2)
+def test_p0_projected_matrix_is_diag_E0(cfg0_run):
+    T0 = cfg0_run.history[0]["T0"]
+    assert np.allclose(T0, np.diag(cfg0_run.E0), rtol=0, atol=1e-14 * np.abs(cfg0_run.E0).max())
+
+
+# --- P3: E^(1) = 0 and Psi^(1) = (H Psi^(0) - E^(0) Psi^(0)) / E^(0) (eq. first_PC)
+def test_first_order_closed_form():
+    H, A = _H((30, 120, 400), 24, 5)
+    n0, k = 30, 3
+    E, Psi = oracle.rs_corrections(H, n0, k, 2)
+    assert np.max(np.abs(E[1])) < 1e-14
+    Psi0 = Psi[0]
+    E0 = E[0]
+    expect = (H @ Psi0 - Psi0 * E0[None, :]) / E0[None, :]
+    assert np.max(np.abs(Psi[1] - expect)) < 1e-14 * np.max(np.abs(expect))
+
+
+# --- P4: E^(2) = ||V21 psi||^2 / E^(0) (eq. exp_seq with eq. first_PC)
+def test_second_order_energy_closed_form():
+    H, A = _H((30, 120, 400), 24, 6)
+    n0, k = 30, 3
+    E, Psi = oracle.rs_corrections(H, n0, k, 2)
+    Hd = H.toarray()
+    V21 = Hd[n0:, :n0]
+    w, U = np.linalg.eigh(Hd[:n0, :n0])
+    e2 = np.sum((V21 @ U[:, :k]) ** 2, axis=0) / w[:k]
+    assert np.allclose(E[2], e2, rtol=1e-13, atol=0)
+
+
+# --- P5: the energy series of H(c) = H0 + cV is reproduced order by order (eq. Hc, eq. exp)
+def _series_slopes(H, n0, k, P, c):
+    E, _ = oracle.rs_corrections(H, n0, k, P)
+    Hd = H.toarray()
+    H0 = np.zeros_like(Hd)
+    H0[:n0, :n0] = Hd[:n0, :n0]
+    V = Hd - H0
+    out = []
+    for cc in (c, c / 2):
+        exact = np.linalg.eigvalsh(H0 + cc * V)[:k]
+        partial = sum(cc ** p * E[p] for p in range(P + 1))
+        out.append(np.abs(exact - partial))
+    return out[0] / out[1]
+
+
+@pytest.mark.parametrize("P", [1, 2, 3, 4, 5])
+def test_perturbation_series_order(P):
+    H, _ = _H((12, 60, 150), 10, 3)
+    ratio = _series_slopes(H, 12, 2, P, 0.04)
+    # the truncation error must scale like c^(P+1)
+    assert np.all(ratio > 2 ** (P + 1) * 0.75) and np.all(ratio < 2 ** (P + 1) * 1.33), ratio
+
+
+def test_series_pin_catches_a_dropped_sum_term(monkeypatch):
+    """Plant a mistake in the oracle (drop the sum over lower orders): the series pin must fail.
+
+    The sum first changes Psi^(3) (its l = 0 term is projected out), hence E^(4): P = 5 sees it.
+    """
+    def broken(VPsi_prev, E_hist, Psi_hist, p):
+        return -VPsi_prev.copy()
+    monkeypatch.setattr(osp, "correction_rhs", broken)
+    H, _ = _H((12, 60, 150), 10, 3)
+    ratio = _series_slopes(H, 12, 2, 5, 0.04)
+    assert not (np.all(ratio > 2 ** 6 * 0.75) and np.all(ratio < 2 ** 6 * 1.33))
+
+
+# --- P13: the block shortcut (eqs. bl_diag, sm_first, sm_lin_proj) equals the dense
+#          full-space minimum-norm solve of eq. exp_seq with psi_k projected out
+def test_block_split_equals_dense_pseudoinverse():
+    H, _ = _H((20, 80, 200), 16, 9)
+    n0, k, P = 20, 3, 4
+    E, Psi = oracle.rs_corrections(H, n0, k, P)
+    Hd = H.toarray()
+    n = Hd.shape[0]
+    H0 = np.zeros_like(Hd)
+    H0[:n0, :n0] = Hd[:n0, :n0]
+    V = Hd - H0
+    for kk in range(k):
+        w, U = np.linalg.eigh(Hd[:n0, :n0])
+        psi0 = np.zeros(n)
+        psi0[:n0] = U[:, kk] * np.sign(U[np.argmax(np.abs(U[:, kk])), kk])
+        Ek = w[kk]
+        A = np.linalg.pinv(H0 - Ek * np.eye(n), rcond=1e-12)
+        Pj = np.eye(n) - np.outer(psi0, psi0)
+        ps = [psi0]
+        es = [Ek, psi0 @ V @ psi0]
+        for p in range(1, P + 1):
+            if p >= 2:
+                es.append(ps[p - 1] @ V @ psi0)
+            rhs = (es[1] * np.eye(n) - V) @ ps[p - 1]
+            for l in range(0, p - 1):
+                rhs = rhs + es[p - l] * ps[l]
+            ps.append(A @ (Pj @ rhs))
+            assert np.allclose(ps[p], Psi[p][:, kk], rtol=0, atol=1e-11 * np.abs(ps[p]).max())
+
+
+# --- P6: with n0 = k the SPPC subspace is the block Krylov space K_{p+1}(H, Psi^(0))
+@pytest.mark.parametrize("k", [1, 3])
+def test_tiny_small_space_gives_block_krylov(k):
+    H, _ = _H((k, 50, 160), 14, 21 + k)
+    res = oracle.sppc(H, k, k, oracle.Options(continuation=False, maxiter=5, tol=1e-300,
+                                               final_check=False))
+    Hd = H.toarray()
+    X = np.zeros((Hd.shape[0], k))
+    X[:k, :k] = np.linalg.eigh(Hd[:k, :k])[1]
+    blocks = [X]
+    for p in range(1, 6):
+        Y = Hd @ blocks[-1]
+        B = np.hstack(blocks)
+        for _ in range(2):
+            Y = Y - B @ (B.T @ Y)
+        Y, _ = np.linalg.qr(Y)
+        blocks.append(Y)
+        Qk = np.hstack(blocks)
+        ritz = np.linalg.eigvalsh(Qk.T @ Hd @ Qk)[:k]
+        th = res.history[p]["theta"]
+        assert np.allclose(th, ritz, rtol=1e-12, atol=0), (p, th, ritz)
+
+
+# --- P7: 2 x 2 with n0 = 1 is exact after one correction
+def test_two_by_two_closed_form():
+    a, b, d = -1.3, 0.7, 2.9
+    H = sp.csr_matrix(np.array([[a, b], [b, d]]))
+    res = oracle.sppc(H, 1, 1, oracle.Options(tol=1e-300, maxiter=1, continuation=False,
+                                              final_check=False))
+    exact = (a + d) / 2 - np.sqrt(((a - d) / 2) ** 2 + b ** 2)
+    assert abs(res.history[1]["theta"][0] - exact) < 1e-15 * 4
+
+
+# --- P1: Rayleigh-Ritz bounds: theta_i >= lambda_i, monotone in p (nested subspaces)
+def test_interlacing_and_monotone(cfg0, cfg0_run):
+    lam = cfg0[3][:cfg0[2]]
+    prev = None
+    for h in cfg0_run.history:
+        th = h["theta"]
+        assert np.all(th >= lam - 1e-13 * np.abs(lam))
+        if prev is not None:
+            assert np.all(th <= prev + 1e-13 * np.abs(prev))
+        prev = th
+
+
+def test_full_space_is_exact():
+    H, _ = _H((6, 12, 20), 8, 4)
+    n = H.shape[0]
+    res = oracle.sppc(H, 6, 2, oracle.Options(tol=1e-300, maxiter=60, continuation=False,
+                                              final_check=False))
+    assert res.history[-1]["m"] == n
+    lam = np.linalg.eigvalsh(H.toarray())[:2]
+    assert np.allclose(res.history[-1]["theta"], lam, rtol=1e-13, atol=0)
+
+
+# --- P9: orthonormal basis
+def test_basis_orthonormal(cfg0_run):
+    Q = cfg0_run.Q
+    assert np.max(np.abs(Q.T @ Q - np.eye(Q.shape[1]))) < 1e-12
+
+
+# --- P10: decoupled blocks (V12 = 0) or n0 = n converge at p = 0
+def test_decoupled_converges_at_p0():
+    H, _ = _H((20, 60, 100), 12, 8)
+    Hd = H.toarray()
+    Hd[:20, 20:] = 0.0
+    Hd[20:, :20] = 0.0
+    Hd[20:, 20:] += 20.0 * np.eye(Hd.shape[0] - 20)   # keep the wanted pairs in the small block
+    res = oracle.sppc(sp.csr_matrix(Hd), 20, 3, oracle.Options())
+    assert res.history[-1]["p"] == 0 and np.all(res.rrn < 1e-13)
+    H2, _ = _H((40,), 10, 8)
+    res2 = oracle.sppc(H2, 40, 3, oracle.Options())
+    assert res2.history[-1]["p"] == 0 and np.all(res2.rrn < 1e-12)
+
+
+# --- P11: converged pairs obey the residual and Kato-Temple bounds and equal eigh's
+def test_converged_pairs_bounds(cfg0, cfg0_run):
+    H, n0, k, lam, X = cfg0
+    res = cfg0_run
+    assert res.converged
+    for i in range(k):
+        r = np.linalg.norm(H @ res.Z[:, i] - res.theta[i] * res.Z[:, i])
+        assert abs(res.theta[i] - lam[i]) <= r
+        a = lam[i - 1] if i > 0 else -np.inf
+        b = lam[i + 1]
+        assert res.theta[i] - r * r / (b - res.theta[i]) <= lam[i] + 1e-14
+        if np.isfinite(a):
+            assert lam[i] <= res.theta[i] + r * r / (res.theta[i] - a) + 1e-14
+        assert abs(res.theta[i] - lam[i]) / abs(lam[i]) < 1e-10
+        assert res.rrn[i] < 1e-6
+
+
+# --- P12: k products with H per SPPC step (Sec. IV.B-C)
+def test_spmv_accounting(cfg0_run):
+    k = len(cfg0_run.theta)
+    for h in cfg0_run.history:
+        if h["phase"] == "sppc":
+            assert h["n_spmv"] == k * (h["p"] + 1)
+
+
+# --- P14: stagnation of pure SPPC (Sec. VI): angles decay, residual stalls above 1e-6
+def test_stagnation_pattern(cfg0):
+    H, n0, k, lam, _ = cfg0
+    res = oracle.sppc(H, n0, k, oracle.Options(continuation=False, maxiter=30, final_check=False))
+    ang = [np.min(h["angles"]) for h in res.history[1:]]
+    assert ang[14] < 1e-5 and ang[14] < ang[4] * 1e-3
+    assert not res.converged and res.history[-1]["rrn"].max() > 1e-6
+    assert res.history[15]["rrn"].max() < res.history[0]["rrn"].max() * 1e-2
+
+
+# --- zero E^(0) is refused (eq. sm_first divides by it)
+def test_zero_E0_refused():
+    Hd = np.diag([0.0, 1.0, 5.0, 6.0])
+    Hd[0, 2] = Hd[2, 0] = 0.3
+    with pytest.raises(ZeroDivisionError):
+        oracle.sppc(sp.csr_matrix(Hd), 2, 1, oracle.Options())
