@@ -1,0 +1,197 @@
+/*
+ * sppc.h - C ABI of the SPPC eigensolver on one MI355X (gfx950).
+ *
+ * Subspace Projection with Perturbative Corrections (SPPC): the k lowest
+ * eigenpairs of a large sparse symmetric H = H0 + V, where H0 = diag(H0hat, 0)
+ * and H0hat is the leading n0 x n0 block (the small configuration space,
+ * Sec. II eqs. split/split2).  The subspace is spanned by the zero-padded
+ * eigenvectors of H0hat and their perturbative corrections (eq. exp_seq2,
+ * solved in the small space, eqs. sm_first and sm_lin_proj), and the
+ * approximations are the Rayleigh-Ritz pairs of that subspace (eq. tilde_H,
+ * Alg. 2), judged by the relative residual ||Hz - theta z|| / |theta| (eq. rrn).
+ *
+ * Conventions for every entry point:
+ *   - every pointer named *_dev is device memory owned by the caller and must
+ *     stay valid for the lifetime of the context that uses it; *_host is host
+ *     memory owned by the caller;
+ *   - blocks of vectors are row-major n x b (the b values of one row are
+ *     contiguous, leading dimension b);
+ *   - all work is enqueued on the stream given to sppc_setup; entry points that
+ *     return host values synchronise that stream;
+ *   - return codes are sppc_status values; no C++ exception crosses this ABI;
+ *     sppc_last_error() gives a readable message for the last failure;
+ *   - a context is used by one host thread at a time.
+ */
+#ifndef SPPC_H_
+#define SPPC_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SPPC_OK = 0,
+  SPPC_E_ARG = 1,           /* invalid argument or shape */
+  SPPC_E_HIP = 2,           /* a HIP runtime call failed */
+  SPPC_E_NOMEM = 3,         /* device allocation failed */
+  SPPC_E_SINGULAR_E0 = 4,   /* some wanted E_k^(0) is zero: eq. sm_first divides by it */
+  SPPC_E_BREAKDOWN = 5,     /* the subspace could not be extended (every new direction dropped) */
+  SPPC_E_NOCONV = 6,        /* iteration limit reached; the best pairs are still written */
+  SPPC_E_NAN = 7            /* a NaN or Inf appeared */
+} sppc_status;
+
+typedef enum { SPPC_F64 = 0, SPPC_F32 = 1 } sppc_dtype;
+
+typedef enum {
+  SPPC_PREC_FP64 = 0,   /* every product in float64 */
+  SPPC_PREC_MIXED = 1   /* float32 matrix values and vectors in the H and H0hat products and the
+                           small-space solves, float32 products accumulated in float64; basis,
+                           projected matrix, orthonormalisation, Rayleigh-Ritz and the final
+                           residual check stay float64 */
+} sppc_precision;
+
+typedef enum {
+  SPPC_CORR_PERTURBATIVE = 0, /* Psi^(p) of eq. exp_seq2 for every wanted pair (Alg. 2 step 6) */
+  SPPC_CORR_JACOBI = 1,       /* continuation: t_i = -(I - z_i z_i^T) (diag(H) - theta_i)^-1 r_i */
+  SPPC_CORR_MPNN = 2          /* continuation: learned diagonal scaling of the Jacobi step */
+} sppc_corr_kind;
+
+/* Upper triangle (diagonal included) of the symmetric H, CSR, device memory. */
+typedef struct {
+  int64_t n;                /* order of H */
+  int64_t nnz;              /* stored entries (upper triangle with the diagonal) */
+  const int64_t* row_ptr_dev; /* [n+1] */
+  const int32_t* col_dev;   /* [nnz], columns >= row, ascending within a row */
+  const void* val_dev;      /* [nnz], float64 or float32 */
+  sppc_dtype val_type;
+} sppc_csr;
+
+typedef struct {
+  double tol;          /* convergence: every rrn_i < tol (eq. rrn); default 1e-6 */
+  int maxiter;         /* highest perturbation order of pure SPPC (Alg. 2 input); default 30 */
+  int p_switch;        /* after this many SPPC steps switch to the continuation (0 = never) ; 15 */
+  int max_cont;        /* continuation steps at most; default 200 */
+  int m_max;           /* basis columns kept; the continuation restarts beyond it; default 512 */
+  int n_deflate;       /* eigenpairs of H0hat computed and deflated in the small solves (>= k) */
+  double tau_drop;     /* new column dropped when sin(angle to the basis) <= tau_drop */
+  double inner_tol;    /* relative residual of the small-space solves */
+  double h0_tol;       /* residual of the H0hat eigenpairs, relative to max(1,|E|) */
+  int precision;       /* sppc_precision */
+  int precond;         /* sppc_corr_kind used by the continuation (JACOBI or MPNN) */
+  int final_check;     /* explicit float64 H Z, Rayleigh-Ritz on span Z, true residual */
+  int verbose;         /* per-iteration line on stderr */
+} sppc_opts;
+
+typedef struct {
+  int iterations;      /* SPPC steps p reached */
+  int cont_steps;      /* continuation steps */
+  int64_t n_spmv;      /* products of H with one vector (k per SPPC step, Sec. IV.C) */
+  int basis_size;      /* columns of the final basis */
+  int cg_iterations;   /* small-space solver iterations, summed over steps */
+  int h0_iterations;   /* iterations of the H0hat eigensolver */
+  int converged;       /* 1 if every pair met tol (after the final check when enabled) */
+  double t_setup_ms;   /* device format, H0hat extraction, zeroth order */
+  double t_solve_ms;   /* iteration loop + final check */
+  double t_spmm_ms;    /* time inside the H products */
+  double t_small_ms;   /* time inside the small-space solves */
+  double t_ortho_ms;   /* block Gram-Schmidt + Cholesky-QR */
+  double t_rr_ms;      /* projected matrix, eigensolve, Ritz vectors, residuals */
+} sppc_stats;
+
+typedef struct sppc_ctx sppc_ctx;
+
+/* Fills *opts with the defaults listed above.  Returns SPPC_E_ARG for NULL. */
+sppc_status sppc_default_opts(sppc_opts* opts);
+
+/*
+ * Builds a context for the k lowest eigenpairs of H (Alg. 2 input).
+ *   H                 upper CSR in device memory (see sppc_csr)
+ *   level_offsets_host  [n_levels+1] host array, 0 = first row of each level, last = n
+ *   n_small_levels    the leading levels that form the small space: n0 = level_offsets[n_small_levels]
+ *                     (H0hat = H[0:n0, 0:n0], eq. split2)
+ *   k                 wanted pairs, 1 <= k <= 16, k <= n_deflate <= n0
+ *   opts              NULL for the defaults
+ *   stream            hipStream_t (as void*), NULL for the default stream
+ * Work: device copy of H in both triangles (float32 values when every value is
+ * float32-exact, else float64), H0hat, the n_deflate lowest eigenpairs of
+ * H0hat (eq. EP_small), and step p = 0 of Alg. 2 (basis Psi^(0), one block
+ * product with H, Rayleigh-Ritz).  The context allocates its own device memory
+ * and frees it in sppc_destroy.  Errors: SPPC_E_ARG, SPPC_E_NOMEM, SPPC_E_HIP,
+ * SPPC_E_SINGULAR_E0 (*out is then NULL).
+ */
+sppc_status sppc_setup(sppc_ctx** out, const sppc_csr* H, const int64_t* level_offsets_host,
+                       int n_levels, int n_small_levels, int k, const sppc_opts* opts, void* stream);
+
+/*
+ * Y = H X for the matrix of the context (the paper's cost unit, Sec. IV.C).
+ *   X_dev   row-major n x b, float64 (xt = SPPC_F64) or float32 (SPPC_F32)
+ *   Y_dev   row-major n x b, float64
+ *   b       1..16
+ * float64 X uses the float64 values; float32 X uses the float32 values with
+ * float32 products accumulated in float64.  Asynchronous on the context stream.
+ */
+sppc_status sppc_spmm(sppc_ctx* ctx, const void* X_dev, sppc_dtype xt, double* Y_dev, int b);
+
+/*
+ * Computes the next block of new directions into the context (not yet in the basis):
+ *   SPPC_CORR_PERTURBATIVE: E_k^(p) and Psi_k^(p) for every wanted pair from
+ *     eq. exp_seq (first line) and eq. exp_seq2, with H Psi^(p-1) taken from
+ *     the stored H Q (eq. HPsip) and V Psi = H Psi - H0 Psi (eq. avoid_SpMV2);
+ *     complement rows by eq. sm_first, small-space rows by eq. sm_lin_proj
+ *     (minimum-norm solution orthogonal to psi_k).
+ *   SPPC_CORR_JACOBI / SPPC_CORR_MPNN: preconditioned residuals of the current
+ *     unconverged Ritz pairs.
+ * Errors: SPPC_E_ARG (e.g. PERTURBATIVE after the basis was restarted), SPPC_E_HIP.
+ */
+sppc_status sppc_correct(sppc_ctx* ctx, int kind);
+
+/*
+ * Appends the pending block to the basis and extracts new Ritz pairs:
+ * block Gram-Schmidt twice + Cholesky-QR twice (eqs. blkGS, QR, Qp), one block
+ * product with H, the new rows and columns of T = Q^T H Q (eq. proj), the k
+ * lowest eigenpairs of T and the residual norms (eq. rrn).
+ *   theta_host, rrn_host  [k] outputs (may be NULL); n_added_host: columns appended.
+ * Synchronises the stream.  Errors: SPPC_E_BREAKDOWN (nothing appended), SPPC_E_NAN, SPPC_E_HIP.
+ */
+sppc_status sppc_rayleigh_ritz(sppc_ctx* ctx, double* theta_host, double* rrn_host,
+                               int* n_added_host);
+
+/*
+ * The whole method: Alg. 2 until every rrn_i < tol or p = p_switch (or maxiter),
+ * then the preconditioned continuation, then (if enabled) the final float64
+ * check.  Outputs:
+ *   evals_host  [k] ascending
+ *   evecs_dev   row-major n x k float64 (may be NULL)
+ *   rrn_host    [k] relative residuals (may be NULL)
+ *   stats       may be NULL
+ * Returns SPPC_OK, or SPPC_E_NOCONV with the best pairs written.
+ */
+sppc_status sppc_solve(sppc_ctx* ctx, double* evals_host, double* evecs_dev, double* rrn_host,
+                       sppc_stats* stats);
+
+/*
+ * Copies internal state for inspection (tests):
+ *   what = 0: E^(0) [n_deflate] (host)          what = 1: Ritz values of the last step [k] (host)
+ *   what = 2: basis size m (as double, host)    what = 3: Q, row-major n x m (device, ld = m)
+ *   what = 4: H Q, row-major n x m (device)     what = 5: pending block, row-major n x k (device)
+ *   what = 6: T, m x m (host, row-major)        what = 7: angles of the last appended block [k] (host)
+ *   what = 8: E^(p) table [(p+1) x k] (host)    what = 9: H0hat eigenvectors, row-major n0 x n_deflate (device)
+ * `count` is the capacity of dst in doubles.  Errors: SPPC_E_ARG.
+ */
+sppc_status sppc_get(sppc_ctx* ctx, int what, double* dst, int64_t count);
+
+const char* sppc_last_error(const sppc_ctx* ctx);
+
+/* Message of the last failure in sppc_setup (no context exists then). */
+const char* sppc_setup_error(void);
+
+/* Frees every device allocation of the context.  NULL is ignored. */
+void sppc_destroy(sppc_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SPPC_H_ */

@@ -1,0 +1,214 @@
+"""SPPC eigensolver on one MI355X: thin ctypes binding of libsppc.so (include/sppc.h).
+
+The functions below carry the C ABI's names and only marshal arguments: torch
+tensors on the GPU are passed as device pointers, the current torch stream as the
+HIP stream.  Every step of the method runs in the library's HIP kernels; there is
+no CPU fallback.  If the library is missing the import of `lib()` fails loudly.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import torch  # loads the HIP runtime first, so libsppc.so binds to the same one
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsppc.so")
+
+SPPC_OK, SPPC_E_ARG, SPPC_E_HIP, SPPC_E_NOMEM, SPPC_E_SINGULAR_E0, SPPC_E_BREAKDOWN, SPPC_E_NOCONV, \
+    SPPC_E_NAN = range(8)
+SPPC_F64, SPPC_F32 = 0, 1
+SPPC_PREC_FP64, SPPC_PREC_MIXED = 0, 1
+SPPC_CORR_PERTURBATIVE, SPPC_CORR_JACOBI, SPPC_CORR_MPNN = 0, 1, 2
+
+STATUS_NAMES = {0: "SPPC_OK", 1: "SPPC_E_ARG", 2: "SPPC_E_HIP", 3: "SPPC_E_NOMEM",
+                4: "SPPC_E_SINGULAR_E0", 5: "SPPC_E_BREAKDOWN", 6: "SPPC_E_NOCONV", 7: "SPPC_E_NAN"}
+
+EXPORTS = ("sppc_default_opts", "sppc_setup", "sppc_spmm", "sppc_correct", "sppc_rayleigh_ritz",
+           "sppc_solve", "sppc_get", "sppc_last_error", "sppc_setup_error", "sppc_destroy")
+
+
+class sppc_csr(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64), ("row_ptr_dev", ctypes.c_void_p),
+                ("col_dev", ctypes.c_void_p), ("val_dev", ctypes.c_void_p), ("val_type", ctypes.c_int)]
+
+
+class sppc_opts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("maxiter", ctypes.c_int), ("p_switch", ctypes.c_int),
+                ("max_cont", ctypes.c_int), ("m_max", ctypes.c_int), ("n_deflate", ctypes.c_int),
+                ("tau_drop", ctypes.c_double), ("inner_tol", ctypes.c_double), ("h0_tol", ctypes.c_double),
+                ("precision", ctypes.c_int), ("precond", ctypes.c_int), ("final_check", ctypes.c_int),
+                ("verbose", ctypes.c_int)]
+
+
+class sppc_stats(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int), ("cont_steps", ctypes.c_int), ("n_spmv", ctypes.c_int64),
+                ("basis_size", ctypes.c_int), ("cg_iterations", ctypes.c_int), ("h0_iterations", ctypes.c_int),
+                ("converged", ctypes.c_int), ("t_setup_ms", ctypes.c_double), ("t_solve_ms", ctypes.c_double),
+                ("t_spmm_ms", ctypes.c_double), ("t_small_ms", ctypes.c_double), ("t_ortho_ms", ctypes.c_double),
+                ("t_rr_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class SPPCError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (STATUS_NAMES.get(status, status), msg))
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it was not built (no fallback exists)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libsppc.so is not built: run `python -m paper_2407_08901_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i64, c_int, dp = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.POINTER(ctypes.c_double)
+        L.sppc_default_opts.argtypes = [ctypes.POINTER(sppc_opts)]
+        L.sppc_setup.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(sppc_csr), ctypes.POINTER(i64), c_int, c_int,
+                                 c_int, ctypes.POINTER(sppc_opts), vp]
+        L.sppc_spmm.argtypes = [vp, vp, c_int, vp, c_int]
+        L.sppc_correct.argtypes = [vp, c_int]
+        L.sppc_rayleigh_ritz.argtypes = [vp, dp, dp, ctypes.POINTER(c_int)]
+        L.sppc_solve.argtypes = [vp, dp, vp, dp, ctypes.POINTER(sppc_stats)]
+        L.sppc_get.argtypes = [vp, c_int, vp, i64]
+        L.sppc_last_error.argtypes = [vp]
+        L.sppc_last_error.restype = ctypes.c_char_p
+        L.sppc_setup_error.restype = ctypes.c_char_p
+        L.sppc_destroy.argtypes = [vp]
+        L.sppc_destroy.restype = None
+        for name in ("sppc_default_opts", "sppc_setup", "sppc_spmm", "sppc_correct", "sppc_rayleigh_ritz",
+                     "sppc_solve", "sppc_get"):
+            getattr(L, name).restype = c_int
+        _lib = L
+    return _lib
+
+
+def _check(status, ctx=None):
+    if status != SPPC_OK:
+        L = lib()
+        msg = (L.sppc_last_error(ctx) if ctx else L.sppc_setup_error()) or b""
+        raise SPPCError(status, msg.decode(errors="replace"))
+
+
+def _stream_handle(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def sppc_default_opts(**kw) -> sppc_opts:
+    o = sppc_opts()
+    _check(lib().sppc_default_opts(ctypes.byref(o)))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise AttributeError(k)
+        setattr(o, k, v)
+    return o
+
+
+class Context:
+    """Owns an sppc_ctx and keeps the device arrays it borrows alive."""
+
+    def __init__(self, handle, n, k, keep, stream):
+        self.handle = handle
+        self.n = n
+        self.k = k
+        self._keep = keep
+        self.stream = stream
+
+    def __del__(self):
+        try:
+            sppc_destroy(self)
+        except Exception:
+            pass
+
+
+def sppc_setup(row_ptr: torch.Tensor, col: torch.Tensor, val: torch.Tensor, level_offsets: Sequence[int],
+               n_small_levels: int, k: int, opts: Optional[sppc_opts] = None, stream=None) -> Context:
+    """Upper-triangular CSR of H on the GPU (int64 row_ptr, int32 col, float64/float32 val)."""
+    for t, dt in ((row_ptr, torch.int64), (col, torch.int32)):
+        if not t.is_cuda or t.dtype != dt or not t.is_contiguous():
+            raise TypeError("row_ptr must be int64, col int32; contiguous GPU tensors")
+    if not val.is_cuda or val.dtype not in (torch.float64, torch.float32) or not val.is_contiguous():
+        raise TypeError("val must be a contiguous float64/float32 GPU tensor")
+    n = row_ptr.numel() - 1
+    H = sppc_csr(n, col.numel(), row_ptr.data_ptr(), col.data_ptr(), val.data_ptr(),
+                 SPPC_F32 if val.dtype == torch.float32 else SPPC_F64)
+    lo = (ctypes.c_int64 * len(level_offsets))(*[int(x) for x in level_offsets])
+    h = ctypes.c_void_p()
+    st = stream if stream is not None else torch.cuda.current_stream()
+    status = lib().sppc_setup(ctypes.byref(h), ctypes.byref(H), lo, len(level_offsets) - 1, n_small_levels, k,
+                              ctypes.byref(opts) if opts is not None else None, _stream_handle(st))
+    _check(status)
+    return Context(h, n, k, (row_ptr, col, val), st)
+
+
+def sppc_spmm(ctx: Context, X: torch.Tensor, Y: torch.Tensor) -> None:
+    """Y = H X; X row-major n x b (float64 or float32), Y float64 n x b."""
+    if X.dim() != 2 or Y.shape != X.shape or X.shape[0] != ctx.n or Y.dtype != torch.float64:
+        raise ValueError("X, Y must be n x b, Y float64")
+    if not (X.is_contiguous() and Y.is_contiguous() and X.is_cuda and Y.is_cuda):
+        raise ValueError("X, Y must be contiguous GPU tensors")
+    xt = SPPC_F32 if X.dtype == torch.float32 else SPPC_F64
+    _check(lib().sppc_spmm(ctx.handle, ctypes.c_void_p(X.data_ptr()), xt, ctypes.c_void_p(Y.data_ptr()),
+                           X.shape[1]), ctx.handle)
+
+
+def sppc_correct(ctx: Context, kind: int = SPPC_CORR_PERTURBATIVE) -> None:
+    _check(lib().sppc_correct(ctx.handle, kind), ctx.handle)
+
+
+def sppc_rayleigh_ritz(ctx: Context):
+    th = (ctypes.c_double * ctx.k)()
+    rr = (ctypes.c_double * ctx.k)()
+    added = ctypes.c_int()
+    status = lib().sppc_rayleigh_ritz(ctx.handle, th, rr, ctypes.byref(added))
+    if status not in (SPPC_OK, SPPC_E_BREAKDOWN):
+        _check(status, ctx.handle)
+    return list(th), list(rr), added.value
+
+
+def sppc_solve(ctx: Context, want_vectors: bool = True):
+    """Returns (evals list, evecs tensor n x k or None, rrn list, stats dict, status)."""
+    ev = (ctypes.c_double * ctx.k)()
+    rr = (ctypes.c_double * ctx.k)()
+    st = sppc_stats()
+    Z = torch.empty((ctx.n, ctx.k), dtype=torch.float64, device="cuda") if want_vectors else None
+    status = lib().sppc_solve(ctx.handle, ev, ctypes.c_void_p(Z.data_ptr()) if Z is not None else None, rr,
+                              ctypes.byref(st))
+    if status not in (SPPC_OK, SPPC_E_NOCONV):
+        _check(status, ctx.handle)
+    return list(ev), Z, list(rr), st.as_dict(), status
+
+
+def sppc_get(ctx: Context, what: int, count: int, device: bool = False):
+    """Inspection copies (see sppc.h).  device=True for the device items (3, 4, 5, 9)."""
+    if device:
+        out = torch.empty(max(count, 1), dtype=torch.float64, device="cuda")
+        _check(lib().sppc_get(ctx.handle, what, ctypes.c_void_p(out.data_ptr()), count), ctx.handle)
+        return out[:count]
+    buf = (ctypes.c_double * max(count, 1))()
+    _check(lib().sppc_get(ctx.handle, what, buf, count), ctx.handle)
+    return list(buf)[:count]
+
+
+def sppc_destroy(ctx: Context) -> None:
+    if ctx is not None and ctx.handle:
+        lib().sppc_destroy(ctx.handle)
+        ctx.handle = None
+
+
+def upload(A, dtype=torch.float64, device="cuda"):
+    """Upper CSR arrays (numpy) -> GPU tensors (row_ptr int64, col int32, val dtype)."""
+    import numpy as np
+    rp = torch.from_numpy(np.ascontiguousarray(A.row_ptr, dtype=np.int64)).to(device)
+    col = torch.from_numpy(np.ascontiguousarray(A.col, dtype=np.int32)).to(device)
+    val = torch.from_numpy(np.ascontiguousarray(A.val)).to(device=device, dtype=dtype)
+    return rp, col, val

@@ -1,0 +1,157 @@
+// common.h - shared declarations of the SPPC HIP library (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stdio.h>
+
+#include <stdexcept>
+#include <string>
+
+namespace sppc {
+
+// Error carried from the host engine to the C ABI boundary.
+struct Error : std::runtime_error {
+  int code;
+  Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define SPPC_HIP(call)                                                                 \
+  do {                                                                                 \
+    hipError_t e_ = (call);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      throw ::sppc::Error(2, std::string(#call) + ": " + hipGetErrorString(e_));       \
+  } while (0)
+
+#define SPPC_LAUNCH_CHECK() SPPC_HIP(hipGetLastError())
+
+constexpr int WAVE = 64;
+
+inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// ---------------------------------------------------------------- sparse (kernels_sparse.hip)
+
+// Full symmetric CSR on the device (both triangles, columns ascending in each row).
+struct DevCSR {
+  int64_t n = 0;
+  int64_t nnz = 0;
+  int64_t* rp = nullptr;       // [n+1] row begin
+  int64_t* rend = nullptr;     // [n] optional row end (sub-matrix views); nullptr = rp[i+1]
+  int32_t* col = nullptr;
+  double* val64 = nullptr;     // float64 values (nullptr when val32 is exact and enough)
+  float* val32 = nullptr;      // float32 values
+};
+
+// Setup: build the full CSR from the upper triangle.  Returns nnz of the full matrix.
+void build_full_csr(int64_t n, int64_t nnz_up, const int64_t* up_rp, const int32_t* up_col,
+                    const void* up_val, int val_is_f32, DevCSR& out, int* d_flags,
+                    bool want64, bool want32, bool& exact32, hipStream_t s);
+// Row ends of the leading n0 x n0 block (columns < n0) of the full CSR.
+void build_block_view(const DevCSR& full, int64_t n0, int64_t* rend, hipStream_t s);
+// diag(H) from the full CSR.
+void extract_diag(const DevCSR& H, double* diag, hipStream_t s);
+
+// Y[n x b] = H X (- shift_c X[:,c] when shift != nullptr), row-major with leading dims.
+// X float64 with float64 or float32-exact values.
+void spmm_f64(const DevCSR& H, const double* X, int64_t ldx, double* Y, int64_t ldy, int b,
+              const double* shift, hipStream_t s);
+// Mixed: float32 values and float32 X, float32 products accumulated in float64.
+void spmm_f32(const DevCSR& H, const float* X, int64_t ldx, double* Y, int64_t ldy, int b,
+              const double* shift, hipStream_t s);
+
+// ---------------------------------------------------------------- dense (kernels_dense.hip)
+
+// C[m x b] (ldc) = beta*C + alpha * A[n x m]^T B[n x b]   (A lda, B ldb, row-major)
+// work: partial sums, at least gemm_tn_work(n, m, b) doubles.
+int64_t gemm_tn_work(int64_t n, int m, int b);
+void gemm_tn(int64_t n, int m, int b, const double* A, int64_t lda, const double* B, int64_t ldb,
+             double* C, int64_t ldc, double alpha, double beta, double* work, hipStream_t s);
+// Y[n x b] (ldy) = beta*Y + alpha * A[n x m] C[m x b]   (C row-major, ldc)
+void gemm_nn(int64_t n, int m, int b, const double* A, int64_t lda, const double* C, int64_t ldc,
+             double* Y, int64_t ldy, double alpha, double beta, hipStream_t s);
+// Same with float32 output (mixed-precision staging of SpMM inputs).
+void copy_to_f32(int64_t n, int b, const double* X, int64_t ldx, float* Y, int64_t ldy, hipStream_t s);
+// Y[r, c] = X[r, c] for a sub-block (row-major)
+void copy_block(int64_t n, int b, const double* X, int64_t ldx, double* Y, int64_t ldy, hipStream_t s);
+void fill_zero(int64_t count, double* p, hipStream_t s);
+// R = HZ - Z diag(theta) and partial sums of squares of R's columns into out[b] (sum of squares).
+void residual_block(int64_t n, int b, const double* Z, int64_t ldz, const double* HZ, int64_t ldhz,
+                    const double* theta, double* R, int64_t ldr, double* sumsq, double* work,
+                    hipStream_t s);
+// sum of squares of each column of X: out[b]
+void colsumsq(int64_t n, int b, const double* X, int64_t ldx, double* out, double* work, hipStream_t s);
+// Psi[r, c] = W[r, c] / E0[c] for r in [r0, n)   (complement rows, eq. sm_first)
+void complement_rows(int64_t r0, int64_t n, int b, const double* W, int64_t ldw, const double* E0,
+                     double* Psi, int64_t ldp, hipStream_t s);
+// Y[r, c] = a*X[r, c] + Y[r, c]*beta
+void axpby_block(int64_t n, int b, double a, const double* X, int64_t ldx, double beta, double* Y,
+                 int64_t ldy, hipStream_t s);
+// Jacobi continuation block for the active pairs: T[:, a] = R[:, idx[a]] / clamp(d - theta[idx[a]])
+void jacobi_block(int64_t n, int na, const int* idx, const double* R, int64_t ldr, const double* diag,
+                  const double* theta, double* T, int64_t ldt, hipStream_t s);
+// T[:, a] = -(T[:, a] - Z[:, idx[a]] * dots[a])
+void project_out_block(int64_t n, int na, const int* idx, const double* Z, int64_t ldz,
+                       const double* dots, double* T, int64_t ldt, hipStream_t s);
+// dots[a] = Z[:, idx[a]]^T T[:, a]
+void paired_dots(int64_t n, int na, const int* idx, const double* Z, int64_t ldz, const double* T,
+                 int64_t ldt, double* dots, double* work, hipStream_t s);
+
+// ---------------------------------------------------------------- small (kernels_small.hip)
+
+// Lowest nwant eigenpairs of symmetric S (m x m, row-major lds): w[nwant] ascending,
+// V row-major m x nwant (ldv).  Single workgroup.  scratch >= eig_scratch(m, nwant) doubles.
+int64_t eig_scratch(int m, int nwant);
+void sym_eig_lowest(int m, int nwant, const double* S, int64_t lds, double* w, double* V,
+                    int64_t ldv, double* scratch, hipStream_t s);
+
+// Orthonormalisation helpers (block of width b <= 32):
+// Step 1: from G = Phi^T Phi (b x b) and the squared norms of the original columns, drop
+// columns with sin(angle) <= tau, pivoted Cholesky of the rest.  Outputs:
+//   M[b x b] (row-major, columns >= kept are zero) with Phi1 = Phi M, R1[b x b] (Phi[:,kept] =
+//   Phi1 R1 restricted), perm/kept count in info[0..], angles[b].
+void cholqr_first(int b, const double* G, const double* psi_sumsq, double tau, double* M,
+                  double* Rfac, double* angles, int* info, hipStream_t s);
+// Step 2: G2 = Phi1^T Phi1 (kept x kept) -> M2 = R2^-1 and Rtot = R2 * R1 (kept x b in the
+// original column order); info[1] := 1 if the Cholesky failed.
+void cholqr_second(int b, const double* G2, double* M2, double* Rfac, int* info, hipStream_t s);
+
+// T bookkeeping
+void t_extend(int m_old, int kn, const double* X, int64_t ldx, double* T, int64_t ldt, hipStream_t s);
+void t_set_diag(int m, const double* theta, double* T, int64_t ldt, hipStream_t s);
+void t_from_full(int m, const double* X, int64_t ldx, double* T, int64_t ldt, hipStream_t s);
+// Coefficients of the raw correction in the basis: G[(m_old + kn) x k] = [C; Rtot]
+void store_coef(int m_old, int kn, int k, const double* C, int64_t ldc, const double* Rtot,
+                double* G, int64_t ldg, hipStream_t s);
+// A = G^(p-1), B = sum_{l=0}^{p-2} G^(l) diag(E^(p-l)); also E^(p) from T (see kernels_small.hip)
+void build_correction_coefs(int p, int k, int m, const double* Ghist, int64_t gstride, int64_t ldg,
+                            const int* m_hist, double* Etab, const double* T, int64_t ldt,
+                            const double* E0, double* A, double* B, hipStream_t s);
+// x1 add-back coefficients for the deflated small solves
+void deflate_coefs(int D, int k, const double* w, const double* c, int64_t ldc, double* out,
+                   int64_t ldo, hipStream_t s);
+// element-wise small: C = C1 + C2 (m x b)
+void add_small(int count, const double* a, double* b, hipStream_t s);
+// sign fix: make the largest-magnitude entry of each column positive (n x b, row-major)
+void sign_fix_columns(int64_t n, int b, double* X, int64_t ldx, double* work, hipStream_t s);
+// argmin selection of the nsel smallest entries of d[0..n) (ties by index): idx[nsel]
+void select_smallest(int64_t n, const double* d, int nsel, int* idx, hipStream_t s);
+// X[r, c] = (r == idx[c])
+void unit_block(int64_t n, int b, const int* idx, double* X, int64_t ldx, hipStream_t s);
+
+// ---------------------------------------------------------------- small-space solver (kernels_cg.hip)
+void cg_precond(int64_t n0, int k, const double* diag, const double* shift, const double* r,
+                double* z, hipStream_t s);
+void cg_dots(int64_t n0, int k, const double* a, const double* b, double* out, double* work, hipStream_t s);
+void cg_update_xr(int64_t n0, int k, double* x, double* r, const double* p, const double* q,
+                  const double* rz, const double* pq, const int* active, hipStream_t s);
+void cg_update_p(int64_t n0, int k, double* p, const double* z, const double* rz_new,
+                 const double* rz_old, const int* active, hipStream_t s);
+void cg_check(int k, const double* rr, const double* bb, double tol2, int* active, int* nactive,
+              double* rzn, double* rzo, hipStream_t s);
+void cg_init(int k, const double* bb, int* active, int* nactive, hipStream_t s);
+// out[c] = X[:, c]^T Y[:, c]
+void coldots(int64_t n, int b, const double* X, int64_t ldx, const double* Y, int64_t ldy, double* out,
+             double* work, hipStream_t s);
+void fill_block_zero(int64_t n, int b, double* Y, int64_t ldy, hipStream_t s);
+
+}  // namespace sppc

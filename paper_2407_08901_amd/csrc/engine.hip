@@ -1,0 +1,830 @@
+// engine.hip - host driver of SPPC on one GPU and the C ABI (include/sppc.h).
+//
+// Step structure (Alg. 2):
+//   setup      device format of H, H0hat view, zeroth order (eq. EP_small), p = 0
+//   correct    E^(p), Psi^(p) (eq. exp_seq, eq. exp_seq2) from the stored basis:
+//              H Psi^(p-1) = HQ G^(p-1) (eq. HPsip, raw corrections kept as basis
+//              coefficients), V Psi = H Psi - H0 Psi (eq. avoid_SpMV2), complement rows by
+//              eq. sm_first, small-space rows by a deflated CG for eq. sm_lin_proj
+//   append+RR  block Gram-Schmidt twice, Cholesky-QR twice (eqs. blkGS, QR, Qp), one block
+//              product with H, new rows/columns of T (eq. proj), lowest eigenpairs of T,
+//              residual norms (eq. rrn)
+// After p_switch SPPC steps the basis keeps growing with preconditioned residual blocks.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "common.h"
+#include "sppc.h"
+
+namespace sppc {
+
+constexpr int KB = 32;   // widest block handled by one product / orthonormalisation
+constexpr int NWMAX = 64;
+
+struct Arena {
+  std::vector<void*> ptrs;
+  template <class T>
+  T* alloc(size_t count) {
+    void* p = nullptr;
+    const size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      throw Error(SPPC_E_NOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+    }
+    ptrs.push_back(p);
+    return (T*)p;
+  }
+  void release() {
+    for (void* p : ptrs) (void)hipFree(p);
+    ptrs.clear();
+  }
+  ~Arena() { release(); }
+};
+
+struct Basis {
+  int64_t n = 0;
+  int ldq = 0;   // columns allocated (row stride of Q and HQ)
+  int m = 0;     // columns in use
+  double* Q = nullptr;
+  double* HQ = nullptr;
+  double* T = nullptr;  // ldq x ldq
+};
+
+enum Cat { C_SPMM = 0, C_SMALL, C_ORTHO, C_RR, C_NCAT };
+
+struct EventTimer {
+  std::vector<hipEvent_t> pool;
+  struct Rec { hipEvent_t a, b; int cat; };
+  std::vector<Rec> open;
+  hipStream_t s = nullptr;
+  hipEvent_t get() {
+    if (!pool.empty()) { hipEvent_t e = pool.back(); pool.pop_back(); return e; }
+    hipEvent_t e;
+    SPPC_HIP(hipEventCreate(&e));
+    return e;
+  }
+  size_t begin(int cat) {
+    Rec r{get(), get(), cat};
+    SPPC_HIP(hipEventRecord(r.a, s));
+    open.push_back(r);
+    return open.size() - 1;
+  }
+  void end(size_t i) { SPPC_HIP(hipEventRecord(open[i].b, s)); }
+  void collect(double* acc) {  // stream must be synchronised
+    for (auto& r : open) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) acc[r.cat] += ms;
+      pool.push_back(r.a);
+      pool.push_back(r.b);
+    }
+    open.clear();
+  }
+  ~EventTimer() {
+    for (auto& r : open) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
+    for (auto e : pool) (void)hipEventDestroy(e);
+  }
+};
+
+}  // namespace sppc
+
+using namespace sppc;
+
+struct sppc_ctx {
+  hipStream_t s = nullptr;
+  sppc_opts o{};
+  int64_t n = 0, n0 = 0;
+  int k = 0, D = 0;
+  std::vector<int64_t> loff;
+  Arena arena;
+  DevCSR H, H0;
+  double* diag = nullptr;
+  bool exact32 = false;
+  double* E0 = nullptr;      // [D]
+  double* Psihat = nullptr;  // n0 x D
+  std::vector<double> E0h;
+  Basis B;
+  double *Psi = nullptr, *Phi = nullptr, *Wb = nullptr, *Z = nullptr, *HZ = nullptr, *R = nullptr;
+  float* X32 = nullptr;
+  double *C1 = nullptr, *C2 = nullptr, *Gm = nullptr, *M1 = nullptr, *M2 = nullptr, *Rt = nullptr;
+  double *Vrr = nullptr, *theta = nullptr, *sumsq = nullptr, *psi2 = nullptr, *angles = nullptr;
+  double *Xt = nullptr, *Acoef = nullptr, *Bcoef = nullptr, *dots = nullptr, *work = nullptr;
+  double* eigscr = nullptr;
+  int *info = nullptr, *idx = nullptr, *mhist_dev = nullptr;
+  double *cx = nullptr, *cr = nullptr, *cz = nullptr, *cp = nullptr, *cq = nullptr, *ccoef = nullptr,
+         *ctmp = nullptr, *cvec = nullptr;
+  int *cact = nullptr, *cnact = nullptr;
+  double* Ghist = nullptr;
+  int64_t gstride = 0;
+  int maxhist = 0;
+  double* Etab = nullptr;
+  std::vector<int> mhist;
+  int p = 0;
+  bool restarted = false;
+  int pend_b = 0, pend_kind = -1;
+  int nw_last = 0;  // width of Z/HZ/R from the last Rayleigh-Ritz
+  std::vector<double> theta_h, rrn_h, angles_h;
+  int last_added = 0;
+  sppc_stats st{};
+  std::string err;
+  double* pin = nullptr;  // pinned host staging
+  int* pin_i = nullptr;
+  EventTimer tm;
+  double tacc[C_NCAT] = {0, 0, 0, 0};
+};
+
+namespace sppc {
+namespace {
+
+thread_local std::string g_setup_err;
+
+inline double* Gh(sppc_ctx* c, int l) { return c->Ghist + (int64_t)l * c->gstride; }
+
+// Y = A X on the operator of the basis: the whole H (mixed or float64) or H0hat.
+struct Op {
+  const DevCSR* A;
+  bool mixed;
+  float* X32;
+  int64_t* nspmv;
+  void operator()(const double* X, int64_t ldx, double* Y, int64_t ldy, int b, hipStream_t s) const {
+    if (mixed) {
+      copy_to_f32(A->n, b, X, ldx, X32, b, s);
+      spmm_f32(*A, X32, b, Y, ldy, b, nullptr, s);
+    } else {
+      spmm_f64(*A, X, ldx, Y, ldy, b, nullptr, s);
+    }
+    if (nspmv) *nspmv += b;
+  }
+};
+
+void sync(sppc_ctx* c) { SPPC_HIP(hipStreamSynchronize(c->s)); }
+
+void to_host(sppc_ctx* c, const double* dev, int count, double* host) {
+  SPPC_HIP(hipMemcpyAsync(c->pin, dev, sizeof(double) * count, hipMemcpyDeviceToHost, c->s));
+  sync(c);
+  memcpy(host, c->pin, sizeof(double) * count);
+}
+
+// Rayleigh-Ritz on the basis: nw lowest pairs, Ritz vectors Z, H Z, residual R, norms.
+void rayleigh_ritz(sppc_ctx* c, Basis& b, int nw) {
+  hipStream_t s = c->s;
+  const size_t t0 = c->tm.begin(C_RR);
+  sym_eig_lowest(b.m, nw, b.T, b.ldq, c->theta, c->Vrr, nw, c->eigscr, s);
+  gemm_nn(b.n, b.m, nw, b.Q, b.ldq, c->Vrr, nw, c->Z, nw, 1.0, 0.0, s);
+  gemm_nn(b.n, b.m, nw, b.HQ, b.ldq, c->Vrr, nw, c->HZ, nw, 1.0, 0.0, s);
+  residual_block(b.n, nw, c->Z, nw, c->HZ, nw, c->theta, c->R, nw, c->sumsq, c->work, s);
+  c->tm.end(t0);
+  SPPC_HIP(hipMemcpyAsync(c->pin, c->theta, sizeof(double) * nw, hipMemcpyDeviceToHost, s));
+  SPPC_HIP(hipMemcpyAsync(c->pin + NWMAX, c->sumsq, sizeof(double) * nw, hipMemcpyDeviceToHost, s));
+  sync(c);
+  c->tm.collect(c->tacc);
+  c->theta_h.assign(c->pin, c->pin + nw);
+  c->rrn_h.resize(nw);
+  for (int i = 0; i < nw; ++i) {
+    const double th = c->theta_h[i];
+    const double rn = std::sqrt(std::max(c->pin[NWMAX + i], 0.0));
+    c->rrn_h[i] = rn / (std::fabs(th) > 1e-300 ? std::fabs(th) : 1.0);
+    if (!std::isfinite(th) || !std::isfinite(rn)) throw Error(SPPC_E_NAN, "NaN/Inf in the Ritz pairs");
+  }
+  c->nw_last = nw;
+}
+
+// Block Gram-Schmidt (twice) + Cholesky-QR (twice) of the n x bw block P against the basis,
+// append the kept columns, multiply them by the operator and extend T.  Returns the number
+// of appended columns.  If coef_slot >= 0 the coefficients [C; R] of P in the new basis are
+// stored in the history slot (P = Q C + q R).
+int ortho_append(sppc_ctx* c, Basis& b, const double* P, int bw, const Op& op, int coef_slot) {
+  hipStream_t s = c->s;
+  const int64_t n = b.n;
+  const int m = b.m;
+  if (bw < 1 || bw > KB) throw Error(SPPC_E_ARG, "block width must be 1..32");
+  size_t t0 = c->tm.begin(C_ORTHO);
+  colsumsq(n, bw, P, bw, c->psi2, c->work, s);
+  copy_block(n, bw, P, bw, c->Phi, bw, s);
+  if (m > 0) {
+    gemm_tn(n, m, bw, b.Q, b.ldq, c->Phi, bw, c->C1, bw, 1.0, 0.0, c->work, s);
+    gemm_nn(n, m, bw, b.Q, b.ldq, c->C1, bw, c->Phi, bw, -1.0, 1.0, s);
+    gemm_tn(n, m, bw, b.Q, b.ldq, c->Phi, bw, c->C2, bw, 1.0, 0.0, c->work, s);
+    gemm_nn(n, m, bw, b.Q, b.ldq, c->C2, bw, c->Phi, bw, -1.0, 1.0, s);
+    add_small(m * bw, c->C2, c->C1, s);
+  }
+  gemm_tn(n, bw, bw, c->Phi, bw, c->Phi, bw, c->Gm, bw, 1.0, 0.0, c->work, s);
+  cholqr_first(bw, c->Gm, c->psi2, c->o.tau_drop, c->M1, c->Rt, c->angles, c->info, s);
+  c->tm.end(t0);
+  SPPC_HIP(hipMemcpyAsync(c->pin_i, c->info, sizeof(int) * 2, hipMemcpyDeviceToHost, s));
+  SPPC_HIP(hipMemcpyAsync(c->pin, c->angles, sizeof(double) * bw, hipMemcpyDeviceToHost, s));
+  sync(c);
+  const int kept = std::min(c->pin_i[0], std::max(0, b.ldq - m));
+  c->angles_h.assign(c->pin, c->pin + bw);
+  if (kept > 0) {
+    t0 = c->tm.begin(C_ORTHO);
+    gemm_nn(n, bw, kept, c->Phi, bw, c->M1, bw, c->Wb, kept, 1.0, 0.0, s);
+    gemm_tn(n, kept, kept, c->Wb, kept, c->Wb, kept, c->Gm, bw, 1.0, 0.0, c->work, s);
+    cholqr_second(bw, c->Gm, c->M2, c->Rt, c->info, s);
+    gemm_nn(n, kept, kept, c->Wb, kept, c->M2, bw, b.Q + m, b.ldq, 1.0, 0.0, s);
+    c->tm.end(t0);
+    t0 = c->tm.begin(C_SPMM);
+    op(b.Q + m, b.ldq, b.HQ + m, b.ldq, kept, s);
+    c->tm.end(t0);
+    t0 = c->tm.begin(C_RR);
+    gemm_tn(n, m + kept, kept, b.Q, b.ldq, b.HQ + m, b.ldq, c->Xt, kept, 1.0, 0.0, c->work, s);
+    t_extend(m, kept, c->Xt, kept, b.T, b.ldq, s);
+    c->tm.end(t0);
+  }
+  if (coef_slot >= 0) store_coef(m, kept, c->k, c->C1, bw, c->Rt, Gh(c, coef_slot), c->k, s);
+  b.m = m + kept;
+  return kept;
+}
+
+void restart_basis(sppc_ctx* c, Basis& b, int keep) {
+  // basis <- the current Ritz vectors (Z, H Z of width nw_last), T <- diag(theta)
+  hipStream_t s = c->s;
+  copy_block(b.n, keep, c->Z, c->nw_last, b.Q, b.ldq, s);
+  copy_block(b.n, keep, c->HZ, c->nw_last, b.HQ, b.ldq, s);
+  t_set_diag(keep, c->theta, b.T, b.ldq, s);
+  b.m = keep;
+}
+
+// Preconditioned residual block for the listed Ritz pairs: t = -(I - z z^T) (d - theta)^-1 r.
+void jacobi_expansion(sppc_ctx* c, int64_t n, const double* diag, const std::vector<int>& act, int nw) {
+  hipStream_t s = c->s;
+  const int na = (int)act.size();
+  for (int a = 0; a < na; ++a) c->pin_i[8 + a] = act[a];
+  SPPC_HIP(hipMemcpyAsync(c->idx, c->pin_i + 8, sizeof(int) * na, hipMemcpyHostToDevice, s));
+  jacobi_block(n, na, c->idx, c->R, nw, diag, c->theta, c->Psi, na, s);
+  paired_dots(n, na, c->idx, c->Z, nw, c->Psi, na, c->dots, c->work, s);
+  project_out_block(n, na, c->idx, c->Z, nw, c->dots, c->Psi, na, s);
+  sync(c);  // pin_i is reused by later steps
+}
+
+// The n_deflate lowest eigenpairs of H0hat by a block Davidson iteration with the
+// diagonal preconditioner, started from unit vectors at the smallest diagonal entries.
+void zeroth_order(sppc_ctx* c) {
+  hipStream_t s = c->s;
+  const int64_t n0 = c->n0;
+  const int D = c->D;
+  const int nev = std::min<int64_t>(std::min(D + 4, KB), n0);
+  Arena tmp;
+  Basis sb;
+  sb.n = n0;
+  sb.ldq = (int)std::min<int64_t>(n0, std::max(8 * nev, 128));
+  sb.ldq = std::min(sb.ldq, 512);
+  sb.Q = tmp.alloc<double>((size_t)n0 * sb.ldq);
+  sb.HQ = tmp.alloc<double>((size_t)n0 * sb.ldq);
+  sb.T = tmp.alloc<double>((size_t)sb.ldq * sb.ldq);
+  double* h0diag = tmp.alloc<double>(n0);
+  copy_block(n0, 1, c->diag, 1, h0diag, 1, s);
+  Op op{&c->H0, false, nullptr, nullptr};
+  select_smallest(n0, h0diag, nev, c->idx, s);
+  unit_block(n0, nev, c->idx, c->Psi, nev, s);
+  ortho_append(c, sb, c->Psi, nev, op, -1);
+  const double tol = c->o.h0_tol;
+  int it = 0;
+  for (;; ++it) {
+    const int nw = std::min(nev, sb.m);
+    rayleigh_ritz(c, sb, nw);
+    std::vector<int> act;
+    bool conv = nw >= D;
+    for (int i = 0; i < nw; ++i) {
+      const double res = std::sqrt(std::max(0.0, c->pin[NWMAX + i])) / std::max(1.0, std::fabs(c->theta_h[i]));
+      if (res > tol) {
+        act.push_back(i);
+        if (i < D) conv = false;
+      }
+    }
+    if (conv || sb.m == n0) break;
+    if (it >= 2000) throw Error(SPPC_E_BREAKDOWN, "eigensolver for H0hat did not converge");
+    if (sb.m + (int)act.size() > sb.ldq) restart_basis(c, sb, nw);
+    jacobi_expansion(c, n0, h0diag, act, nw);
+    const int added = ortho_append(c, sb, c->Psi, (int)act.size(), op, -1);
+    if (added == 0) {
+      // no new direction: accept if the wanted pairs are close, else give up
+      double worst = 0.0;
+      for (int i = 0; i < std::min(D, nw); ++i)
+        worst = std::max(worst, std::sqrt(std::max(0.0, c->pin[NWMAX + i])) / std::max(1.0, std::fabs(c->theta_h[i])));
+      if (worst > 1e3 * tol) throw Error(SPPC_E_BREAKDOWN, "eigensolver for H0hat stagnated");
+      break;
+    }
+  }
+  c->st.h0_iterations = it;
+  if (c->nw_last < D) throw Error(SPPC_E_ARG, "n_deflate exceeds the available eigenpairs of H0hat");
+  copy_block(1, D, c->theta, D, c->E0, D, s);
+  copy_block(n0, D, c->Z, c->nw_last, c->Psihat, D, s);
+  sign_fix_columns(n0, D, c->Psihat, D, c->work, s);
+  c->E0h.assign(c->theta_h.begin(), c->theta_h.begin() + D);
+  sync(c);
+  tmp.release();
+}
+
+// Deflated CG on (H0hat - E_k) restricted to the complement of the deflated eigenvectors,
+// for all k columns at once, then the exact deflated terms: the minimum-norm solution of
+// eq. sm_lin_proj orthogonal to psi_k.  b1 in c->cr (n0 x k); result into Psi rows [0, n0).
+void small_solve(sppc_ctx* c) {
+  hipStream_t s = c->s;
+  const int64_t n0 = c->n0;
+  const int k = c->k, D = c->D;
+  double* rz = c->cvec;
+  double* rzn = c->cvec + KB;
+  double* pq = c->cvec + 2 * KB;
+  double* rr = c->cvec + 3 * KB;
+  double* bb = c->cvec + 4 * KB;
+  auto project = [&](double* X) {  // X <- (I - Psihat Psihat^T) X
+    gemm_tn(n0, D, k, c->Psihat, D, X, k, c->ctmp, k, 1.0, 0.0, c->work, s);
+    gemm_nn(n0, D, k, c->Psihat, D, c->ctmp, k, X, k, -1.0, 1.0, s);
+  };
+  gemm_tn(n0, D, k, c->Psihat, D, c->cr, k, c->ccoef, k, 1.0, 0.0, c->work, s);
+  gemm_nn(n0, D, k, c->Psihat, D, c->ccoef, k, c->cr, k, -1.0, 1.0, s);
+  cg_precond(n0, k, c->diag, c->E0, c->cr, c->cz, s);
+  project(c->cz);
+  copy_block(n0, k, c->cz, k, c->cp, k, s);
+  fill_block_zero(n0, k, c->cx, k, s);
+  coldots(n0, k, c->cr, k, c->cz, k, rz, c->work, s);
+  coldots(n0, k, c->cr, k, c->cr, k, bb, c->work, s);
+  cg_init(k, bb, c->cact, c->cnact, s);
+  const double tol2 = c->o.inner_tol * c->o.inner_tol;
+  const int maxit = 5000;
+  int it = 0;
+  for (it = 1; it <= maxit; ++it) {
+    spmm_f64(c->H0, c->cp, k, c->cq, k, k, c->E0, s);
+    project(c->cq);
+    coldots(n0, k, c->cp, k, c->cq, k, pq, c->work, s);
+    cg_update_xr(n0, k, c->cx, c->cr, c->cp, c->cq, rz, pq, c->cact, s);
+    coldots(n0, k, c->cr, k, c->cr, k, rr, c->work, s);
+    cg_check(k, rr, bb, tol2, c->cact, c->cnact, nullptr, nullptr, s);
+    if (it % 8 == 0) {
+      SPPC_HIP(hipMemcpyAsync(c->pin_i + 4, c->cnact, sizeof(int), hipMemcpyDeviceToHost, s));
+      sync(c);
+      if (c->pin_i[4] == 0) break;
+    }
+    cg_precond(n0, k, c->diag, c->E0, c->cr, c->cz, s);
+    project(c->cz);
+    coldots(n0, k, c->cr, k, c->cz, k, rzn, c->work, s);
+    cg_update_p(n0, k, c->cp, c->cz, rzn, rz, c->cact, s);
+    SPPC_HIP(hipMemcpyAsync(rz, rzn, sizeof(double) * k, hipMemcpyDeviceToDevice, s));
+  }
+  c->st.cg_iterations += std::min(it, maxit);
+  deflate_coefs(D, k, c->E0, c->ccoef, k, c->ctmp, k, s);
+  gemm_nn(n0, D, k, c->Psihat, D, c->ctmp, k, c->cx, k, 1.0, 1.0, s);
+  copy_block(n0, k, c->cx, k, c->Psi, k, s);
+}
+
+void correct_perturbative(sppc_ctx* c) {
+  if (c->restarted) throw Error(SPPC_E_ARG, "perturbative corrections need the unrestarted basis");
+  if (c->p + 1 >= c->maxhist) throw Error(SPPC_E_ARG, "perturbation order limit reached");
+  hipStream_t s = c->s;
+  const int k = c->k;
+  const int64_t n = c->n, n0 = c->n0;
+  Basis& b = c->B;
+  c->p += 1;
+  const int p = c->p;
+  size_t t0 = c->tm.begin(C_SMALL);
+  build_correction_coefs(p, k, b.m, c->Ghist, c->gstride, k, c->mhist_dev, c->Etab, b.T, b.ldq, c->E0,
+                         c->Acoef, c->Bcoef, s);
+  // W = H Psi^(p-1) - sum_l E^(p-l) Psi^(l)  (eq. HPsip with the stored H Q)
+  gemm_nn(n, b.m, k, b.HQ, b.ldq, c->Acoef, k, c->Wb, k, 1.0, 0.0, s);
+  gemm_nn(n, b.m, k, b.Q, b.ldq, c->Bcoef, k, c->Wb, k, -1.0, 1.0, s);
+  // complement rows: x2 = -b2 / E^(0) with b2 = -W2 (H0 is zero there), eq. sm_first
+  complement_rows(n0, n, k, c->Wb, k, c->E0, c->Psi, k, s);
+  // small space: b1 = -W1 + H0hat Psi^(p-1)_1 (eq. exp_seq2 with eq. avoid_SpMV2)
+  gemm_nn(n0, b.m, k, b.Q, b.ldq, c->Acoef, k, c->cx, k, 1.0, 0.0, s);
+  spmm_f64(c->H0, c->cx, k, c->cr, k, k, nullptr, s);
+  axpby_block(n0, k, -1.0, c->Wb, k, 1.0, c->cr, k, s);
+  small_solve(c);
+  c->tm.end(t0);
+  c->pend_b = k;
+  c->pend_kind = SPPC_CORR_PERTURBATIVE;
+}
+
+void correct_continuation(sppc_ctx* c, int kind) {
+  if (kind == SPPC_CORR_MPNN) throw Error(SPPC_E_ARG, "learned preconditioner not available");
+  std::vector<int> act;
+  for (int i = 0; i < c->k; ++i)
+    if (!(c->rrn_h[i] < c->o.tol)) act.push_back(i);
+  if (act.empty()) { c->pend_b = 0; return; }
+  if (c->nw_last != c->k) throw Error(SPPC_E_ARG, "no Ritz pairs available");
+  Basis& b = c->B;
+  size_t t0 = c->tm.begin(C_SMALL);
+  if (b.m + (int)act.size() > b.ldq) {
+    restart_basis(c, b, c->k);
+    c->restarted = true;
+  }
+  jacobi_expansion(c, c->n, c->diag, act, c->k);
+  c->tm.end(t0);
+  c->pend_b = (int)act.size();
+  c->pend_kind = kind;
+}
+
+int append_and_rr(sppc_ctx* c) {
+  Basis& b = c->B;
+  Op op{&c->H, c->o.precision == SPPC_PREC_MIXED, c->X32, &c->st.n_spmv};
+  int added = 0;
+  if (c->pend_b > 0) {
+    const bool pert = c->pend_kind == SPPC_CORR_PERTURBATIVE;
+    added = ortho_append(c, b, c->Psi, c->pend_b, op, pert ? c->p : -1);
+    if (pert) {
+      c->mhist.push_back(b.m);
+      c->pin_i[40] = b.m;
+      SPPC_HIP(hipMemcpyAsync(c->mhist_dev + c->p, c->pin_i + 40, sizeof(int), hipMemcpyHostToDevice, c->s));
+    }
+  }
+  c->pend_b = 0;
+  c->last_added = added;
+  rayleigh_ritz(c, b, c->k);
+  return added;
+}
+
+void final_check(sppc_ctx* c) {
+  hipStream_t s = c->s;
+  const int k = c->k;
+  const int64_t n = c->n;
+  size_t t0 = c->tm.begin(C_SPMM);
+  spmm_f64(c->H, c->Z, k, c->Wb, k, k, nullptr, s);
+  c->st.n_spmv += k;
+  c->tm.end(t0);
+  t0 = c->tm.begin(C_RR);
+  gemm_tn(n, k, k, c->Z, k, c->Wb, k, c->Gm, k, 1.0, 0.0, c->work, s);
+  t_from_full(k, c->Gm, k, c->Xt, k, s);
+  sym_eig_lowest(k, k, c->Xt, k, c->theta, c->Vrr, k, c->eigscr, s);
+  gemm_nn(n, k, k, c->Z, k, c->Vrr, k, c->Phi, k, 1.0, 0.0, s);
+  gemm_nn(n, k, k, c->Wb, k, c->Vrr, k, c->HZ, k, 1.0, 0.0, s);
+  copy_block(n, k, c->Phi, k, c->Z, k, s);
+  residual_block(n, k, c->Z, k, c->HZ, k, c->theta, c->R, k, c->sumsq, c->work, s);
+  c->tm.end(t0);
+  SPPC_HIP(hipMemcpyAsync(c->pin, c->theta, sizeof(double) * k, hipMemcpyDeviceToHost, s));
+  SPPC_HIP(hipMemcpyAsync(c->pin + NWMAX, c->sumsq, sizeof(double) * k, hipMemcpyDeviceToHost, s));
+  sync(c);
+  c->tm.collect(c->tacc);
+  for (int i = 0; i < k; ++i) {
+    c->theta_h[i] = c->pin[i];
+    c->rrn_h[i] = std::sqrt(std::max(0.0, c->pin[NWMAX + i])) / std::max(std::fabs(c->pin[i]), 1e-300);
+  }
+}
+
+void log_step(sppc_ctx* c, const char* phase) {
+  if (!c->o.verbose) return;
+  double mx = 0.0, mn = 1.0;
+  for (double r : c->rrn_h) mx = std::max(mx, r);
+  for (double a : c->angles_h) mn = std::min(mn, a);
+  fprintf(stderr, "[sppc] %s p=%d m=%d added=%d max_rrn=%.3e min_angle=%.2e theta0=%.15g\n", phase, c->p,
+          c->B.m, c->last_added, mx, mn, c->theta_h.empty() ? 0.0 : c->theta_h[0]);
+}
+
+bool all_converged(sppc_ctx* c) {
+  for (int i = 0; i < c->k; ++i)
+    if (!(c->rrn_h[i] < c->o.tol)) return false;
+  return true;
+}
+
+void setup_impl(sppc_ctx* c, const sppc_csr* Hin, const int64_t* loff, int L, int nsmall, int k) {
+  if (!Hin || !loff || L < 1 || nsmall < 1 || nsmall > L) throw Error(SPPC_E_ARG, "bad level partition");
+  if (Hin->n < 1 || !Hin->row_ptr_dev || !Hin->col_dev || !Hin->val_dev) throw Error(SPPC_E_ARG, "bad H");
+  if (Hin->n >= (int64_t)1 << 31) throw Error(SPPC_E_ARG, "n must be < 2^31");
+  c->loff.assign(loff, loff + L + 1);
+  if (c->loff[0] != 0 || c->loff[L] != Hin->n) throw Error(SPPC_E_ARG, "level offsets must run 0..n");
+  for (int l = 0; l < L; ++l)
+    if (c->loff[l + 1] <= c->loff[l]) throw Error(SPPC_E_ARG, "levels must be non-empty and ascending");
+  c->n = Hin->n;
+  c->n0 = c->loff[nsmall];
+  c->k = k;
+  sppc_opts& o = c->o;
+  if (k < 1 || k > 16 || k > c->n0) throw Error(SPPC_E_ARG, "k must be 1..16 and <= n0");
+  if (o.n_deflate <= 0) o.n_deflate = std::min<int64_t>(std::min(2 * k, 28), c->n0);
+  if (o.n_deflate < k || o.n_deflate > 28 || o.n_deflate > c->n0) throw Error(SPPC_E_ARG, "n_deflate must be in [k, min(28, n0)]");
+  c->D = o.n_deflate;
+  if (o.m_max < 2 * k || o.m_max > 512) throw Error(SPPC_E_ARG, "m_max must be in [2k, 512]");
+  if (!(o.tol > 0) || !(o.tau_drop >= 0) || !(o.inner_tol > 0) || !(o.h0_tol > 0)) throw Error(SPPC_E_ARG, "bad tolerances");
+  const int last_p = (o.p_switch > 0) ? std::min(o.p_switch, o.maxiter) : o.maxiter;
+  if (last_p < 0) throw Error(SPPC_E_ARG, "maxiter must be >= 0");
+  if ((int64_t)k * (last_p + 1) > o.m_max) throw Error(SPPC_E_ARG, "m_max < k * (perturbation order + 1)");
+  hipStream_t s = c->s;
+  const bool mixed = o.precision == SPPC_PREC_MIXED;
+
+  // device format of H
+  Arena& A = c->arena;
+  int* dflags = A.alloc<int>(4);
+  bool exact = false;
+  // first pass decides which value arrays are stored: float32 alone when lossless
+  {
+    const bool in32 = Hin->val_type == SPPC_F32;
+    // validation + exactness happen inside; request float64 storage unless exact
+    DevCSR tmp;
+    build_full_csr(c->n, Hin->nnz, Hin->row_ptr_dev, Hin->col_dev, Hin->val_dev, in32 ? 1 : 0, tmp, dflags,
+                   /*want64=*/false, /*want32=*/true, exact, s);
+    if (exact) {
+      c->H = tmp;
+    } else {
+      (void)hipFree(tmp.val32);
+      tmp.val32 = nullptr;
+      (void)hipFree(tmp.rp);
+      (void)hipFree(tmp.col);
+      DevCSR t2;
+      build_full_csr(c->n, Hin->nnz, Hin->row_ptr_dev, Hin->col_dev, Hin->val_dev, 0, t2, dflags, true, mixed,
+                     exact, s);
+      c->H = t2;
+    }
+    A.ptrs.push_back(c->H.rp);
+    A.ptrs.push_back(c->H.col);
+    if (c->H.val64) A.ptrs.push_back(c->H.val64);
+    if (c->H.val32) A.ptrs.push_back(c->H.val32);
+  }
+  c->exact32 = exact;
+  c->H0 = c->H;
+  c->H0.n = c->n0;
+  c->H0.rend = A.alloc<int64_t>(c->n0);
+  build_block_view(c->H, c->n0, c->H0.rend, s);
+  c->diag = A.alloc<double>(c->n);
+  extract_diag(c->H, c->diag, s);
+
+  // buffers
+  const int64_t n = c->n;
+  const int mm = o.m_max;
+  c->B.n = n;
+  c->B.ldq = mm;
+  c->B.Q = A.alloc<double>((size_t)n * mm);
+  c->B.HQ = A.alloc<double>((size_t)n * mm);
+  c->B.T = A.alloc<double>((size_t)mm * mm);
+  c->Psi = A.alloc<double>((size_t)n * KB);
+  c->Phi = A.alloc<double>((size_t)n * KB);
+  c->Wb = A.alloc<double>((size_t)n * KB);
+  c->Z = A.alloc<double>((size_t)n * KB);
+  c->HZ = A.alloc<double>((size_t)n * KB);
+  c->R = A.alloc<double>((size_t)n * KB);
+  if (mixed) c->X32 = A.alloc<float>((size_t)n * KB);
+  const int mbig = std::max(mm, 512);
+  c->C1 = A.alloc<double>((size_t)mbig * KB);
+  c->C2 = A.alloc<double>((size_t)mbig * KB);
+  c->Xt = A.alloc<double>((size_t)mbig * KB);
+  c->Acoef = A.alloc<double>((size_t)mbig * KB);
+  c->Bcoef = A.alloc<double>((size_t)mbig * KB);
+  c->Gm = A.alloc<double>(KB * KB);
+  c->M1 = A.alloc<double>(KB * KB);
+  c->M2 = A.alloc<double>(KB * KB);
+  c->Rt = A.alloc<double>(KB * KB);
+  c->Vrr = A.alloc<double>((size_t)mbig * NWMAX);
+  c->theta = A.alloc<double>(NWMAX);
+  c->sumsq = A.alloc<double>(NWMAX);
+  c->psi2 = A.alloc<double>(KB);
+  c->angles = A.alloc<double>(KB);
+  c->dots = A.alloc<double>(KB);
+  c->work = A.alloc<double>((size_t)std::max<int64_t>(gemm_tn_work(n, mbig, KB), 2 * cdiv(n, 4096) * KB + KB + 64));
+  c->eigscr = A.alloc<double>((size_t)eig_scratch(mbig, NWMAX));
+  c->info = A.alloc<int>(8);
+  c->idx = A.alloc<int>(64);
+  c->maxhist = last_p + 2;
+  c->mhist_dev = A.alloc<int>(c->maxhist + 1);
+  c->gstride = (int64_t)mm * k;
+  c->Ghist = A.alloc<double>((size_t)c->gstride * c->maxhist);
+  c->Etab = A.alloc<double>((size_t)(c->maxhist + 1) * k);
+  const int64_t n0 = c->n0;
+  c->E0 = A.alloc<double>(c->D);
+  c->Psihat = A.alloc<double>((size_t)n0 * c->D);
+  c->cx = A.alloc<double>((size_t)n0 * KB);
+  c->cr = A.alloc<double>((size_t)n0 * KB);
+  c->cz = A.alloc<double>((size_t)n0 * KB);
+  c->cp = A.alloc<double>((size_t)n0 * KB);
+  c->cq = A.alloc<double>((size_t)n0 * KB);
+  c->ccoef = A.alloc<double>((size_t)KB * KB);
+  c->ctmp = A.alloc<double>((size_t)KB * KB);
+  c->cvec = A.alloc<double>(8 * KB);
+  c->cact = A.alloc<int>(KB);
+  c->cnact = A.alloc<int>(4);
+  SPPC_HIP(hipHostMalloc((void**)&c->pin, sizeof(double) * 4 * NWMAX, hipHostMallocDefault));
+  SPPC_HIP(hipHostMalloc((void**)&c->pin_i, sizeof(int) * 128, hipHostMallocDefault));
+  c->tm.s = s;
+
+  // zeroth order
+  zeroth_order(c);
+  const double scale = std::max(1.0, std::fabs(c->E0h.back()));
+  for (int j = 0; j < k; ++j)
+    if (std::fabs(c->E0h[j]) < 1e-10 * scale)
+      throw Error(SPPC_E_SINGULAR_E0, "E^(0) is zero for a wanted pair: eq. sm_first divides by it");
+
+  // p = 0: basis Psi^(0) = [psihat; 0], H Psi^(0), T, Rayleigh-Ritz (Alg. 2 steps 2-4)
+  Basis& b = c->B;
+  fill_block_zero(n, k, b.Q, b.ldq, s);
+  copy_block(n0, k, c->Psihat, c->D, b.Q, b.ldq, s);
+  Op op{&c->H, mixed, c->X32, &c->st.n_spmv};
+  size_t t0 = c->tm.begin(C_SPMM);
+  op(b.Q, b.ldq, b.HQ, b.ldq, k, s);
+  c->tm.end(t0);
+  gemm_tn(n, k, k, b.Q, b.ldq, b.HQ, b.ldq, c->Xt, k, 1.0, 0.0, c->work, s);
+  t_from_full(k, c->Xt, k, b.T, b.ldq, s);
+  b.m = k;
+  // G^(0) = I (Psi^(0) is the first block of the basis); E^(0), E^(1) = 0 (eq. first_PC)
+  std::vector<double> I0((size_t)k * k, 0.0);
+  for (int j = 0; j < k; ++j) I0[(size_t)j * k + j] = 1.0;
+  SPPC_HIP(hipMemcpy(Gh(c, 0), I0.data(), sizeof(double) * k * k, hipMemcpyHostToDevice));
+  std::vector<double> e01((size_t)2 * k, 0.0);
+  for (int j = 0; j < k; ++j) e01[j] = c->E0h[j];
+  SPPC_HIP(hipMemcpy(c->Etab, e01.data(), sizeof(double) * 2 * k, hipMemcpyHostToDevice));
+  c->mhist.assign(1, k);
+  int mk = k;
+  SPPC_HIP(hipMemcpy(c->mhist_dev, &mk, sizeof(int), hipMemcpyHostToDevice));
+  c->p = 0;
+  c->angles_h.assign(k, 1.0);
+  rayleigh_ritz(c, b, k);
+  log_step(c, "sppc");
+}
+
+sppc_status solve_impl(sppc_ctx* c, double* evals, double* evecs, double* rrn, sppc_stats* st) {
+  const auto t0 = std::chrono::steady_clock::now();
+  sppc_opts& o = c->o;
+  const int last_p = (o.p_switch > 0) ? std::min(o.p_switch, o.maxiter) : o.maxiter;
+  bool conv = all_converged(c);
+  while (!conv && c->p < last_p && !c->restarted) {
+    correct_perturbative(c);
+    const int added = append_and_rr(c);
+    log_step(c, "sppc");
+    conv = all_converged(c);
+    if (added == 0 && !conv) break;  // stagnation: no new direction
+  }
+  c->st.iterations = c->p;
+  int cont = 0;
+  if (o.p_switch > 0) {
+    const int kind = o.precond == SPPC_CORR_MPNN ? SPPC_CORR_MPNN : SPPC_CORR_JACOBI;
+    while (!conv && cont < o.max_cont) {
+      correct_continuation(c, kind);
+      const int added = append_and_rr(c);
+      ++cont;
+      log_step(c, "cont");
+      conv = all_converged(c);
+      if (added == 0 && !conv) break;
+    }
+  }
+  c->st.cont_steps = cont;
+  if (o.final_check) {
+    final_check(c);
+    log_step(c, "final");
+    conv = all_converged(c);
+  }
+  c->st.converged = conv;
+  c->st.basis_size = c->B.m;
+  const int k = c->k;
+  if (evals) memcpy(evals, c->theta_h.data(), sizeof(double) * k);
+  if (rrn) memcpy(rrn, c->rrn_h.data(), sizeof(double) * k);
+  if (evecs) {
+    copy_block(c->n, k, c->Z, c->nw_last, evecs, k, c->s);
+    sync(c);
+  }
+  c->st.t_solve_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  c->st.t_spmm_ms = c->tacc[C_SPMM];
+  c->st.t_small_ms = c->tacc[C_SMALL];
+  c->st.t_ortho_ms = c->tacc[C_ORTHO];
+  c->st.t_rr_ms = c->tacc[C_RR];
+  if (st) *st = c->st;
+  return conv ? SPPC_OK : SPPC_E_NOCONV;
+}
+
+template <class F>
+sppc_status guarded(sppc_ctx* c, F&& f) {
+  try {
+    return f();
+  } catch (const Error& e) {
+    if (c) c->err = e.what();
+    return (sppc_status)e.code;
+  } catch (const std::exception& e) {
+    if (c) c->err = e.what();
+    return SPPC_E_ARG;
+  }
+}
+
+}  // namespace
+}  // namespace sppc
+
+// ============================================================================ C ABI
+extern "C" {
+
+sppc_status sppc_default_opts(sppc_opts* o) {
+  if (!o) return SPPC_E_ARG;
+  memset(o, 0, sizeof(*o));
+  o->tol = 1e-6;
+  o->maxiter = 30;
+  o->p_switch = 15;
+  o->max_cont = 200;
+  o->m_max = 512;
+  o->n_deflate = 0;
+  o->tau_drop = 1e-10;
+  o->inner_tol = 1e-12;
+  o->h0_tol = 1e-12;
+  o->precision = SPPC_PREC_FP64;
+  o->precond = SPPC_CORR_JACOBI;
+  o->final_check = 1;
+  o->verbose = 0;
+  return SPPC_OK;
+}
+
+sppc_status sppc_setup(sppc_ctx** out, const sppc_csr* H, const int64_t* level_offsets_host, int n_levels,
+                       int n_small_levels, int k, const sppc_opts* opts, void* stream) {
+  if (!out) return SPPC_E_ARG;
+  *out = nullptr;
+  sppc_ctx* c = new (std::nothrow) sppc_ctx();
+  if (!c) return SPPC_E_NOMEM;
+  if (opts) c->o = *opts; else sppc_default_opts(&c->o);
+  c->s = (hipStream_t)stream;
+  const auto t0 = std::chrono::steady_clock::now();
+  sppc_status st = guarded(c, [&]() {
+    setup_impl(c, H, level_offsets_host, n_levels, n_small_levels, k);
+    return SPPC_OK;
+  });
+  if (st != SPPC_OK) {
+    g_setup_err = c->err;
+    sppc_destroy(c);
+    return st;
+  }
+  c->st.t_setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  *out = c;
+  return SPPC_OK;
+}
+
+sppc_status sppc_spmm(sppc_ctx* c, const void* X, sppc_dtype xt, double* Y, int b) {
+  if (!c || !X || !Y || b < 1 || b > 32) return SPPC_E_ARG;
+  return guarded(c, [&]() {
+    if (xt == SPPC_F32) {
+      if (!c->H.val32) throw Error(SPPC_E_ARG, "float32 values are not stored (H is not float32-exact)");
+      spmm_f32(c->H, (const float*)X, b, Y, b, b, nullptr, c->s);
+    } else {
+      spmm_f64(c->H, (const double*)X, b, Y, b, b, nullptr, c->s);
+    }
+    return SPPC_OK;
+  });
+}
+
+sppc_status sppc_correct(sppc_ctx* c, int kind) {
+  if (!c) return SPPC_E_ARG;
+  return guarded(c, [&]() {
+    if (kind == SPPC_CORR_PERTURBATIVE) correct_perturbative(c);
+    else if (kind == SPPC_CORR_JACOBI || kind == SPPC_CORR_MPNN) correct_continuation(c, kind);
+    else throw Error(SPPC_E_ARG, "unknown correction kind");
+    return SPPC_OK;
+  });
+}
+
+sppc_status sppc_rayleigh_ritz(sppc_ctx* c, double* theta, double* rrn, int* n_added) {
+  if (!c) return SPPC_E_ARG;
+  return guarded(c, [&]() {
+    const bool had = c->pend_b > 0;
+    const int added = append_and_rr(c);
+    if (theta) memcpy(theta, c->theta_h.data(), sizeof(double) * c->k);
+    if (rrn) memcpy(rrn, c->rrn_h.data(), sizeof(double) * c->k);
+    if (n_added) *n_added = added;
+    return (had && added == 0) ? SPPC_E_BREAKDOWN : SPPC_OK;
+  });
+}
+
+sppc_status sppc_solve(sppc_ctx* c, double* evals, double* evecs, double* rrn, sppc_stats* st) {
+  if (!c) return SPPC_E_ARG;
+  return guarded(c, [&]() { return solve_impl(c, evals, evecs, rrn, st); });
+}
+
+sppc_status sppc_get(sppc_ctx* c, int what, double* dst, int64_t count) {
+  if (!c || !dst) return SPPC_E_ARG;
+  return guarded(c, [&]() {
+    auto need = [&](int64_t x) { if (count < x) throw Error(SPPC_E_ARG, "destination too small"); };
+    const int64_t n = c->n;
+    const int m = c->B.m, k = c->k;
+    switch (what) {
+      case 0: need(c->D); memcpy(dst, c->E0h.data(), sizeof(double) * c->D); break;
+      case 1: need(k); memcpy(dst, c->theta_h.data(), sizeof(double) * k); break;
+      case 2: need(1); dst[0] = m; break;
+      case 3: need(n * m); copy_block(n, m, c->B.Q, c->B.ldq, dst, m, c->s); sync(c); break;
+      case 4: need(n * m); copy_block(n, m, c->B.HQ, c->B.ldq, dst, m, c->s); sync(c); break;
+      case 5: need(n * k); copy_block(n, c->pend_b > 0 ? c->pend_b : k, c->Psi, c->pend_b > 0 ? c->pend_b : k, dst,
+                                      c->pend_b > 0 ? c->pend_b : k, c->s); sync(c); break;
+      case 6: {
+        need((int64_t)m * m);
+        std::vector<double> h((size_t)m * c->B.ldq);
+        SPPC_HIP(hipMemcpy(h.data(), c->B.T, sizeof(double) * m * c->B.ldq, hipMemcpyDeviceToHost));
+        for (int i = 0; i < m; ++i) memcpy(dst + (int64_t)i * m, h.data() + (int64_t)i * c->B.ldq, sizeof(double) * m);
+        break;
+      }
+      case 7: need((int64_t)c->angles_h.size()); memcpy(dst, c->angles_h.data(), sizeof(double) * c->angles_h.size()); break;
+      case 8: need((int64_t)(c->p + 1) * k);
+        SPPC_HIP(hipMemcpy(dst, c->Etab, sizeof(double) * (c->p + 1) * k, hipMemcpyDeviceToHost)); break;
+      case 9: need(c->n0 * c->D); copy_block(c->n0, c->D, c->Psihat, c->D, dst, c->D, c->s); sync(c); break;
+      default: throw Error(SPPC_E_ARG, "unknown item");
+    }
+    return SPPC_OK;
+  });
+}
+
+const char* sppc_last_error(const sppc_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+const char* sppc_setup_error(void) { return g_setup_err.c_str(); }
+
+void sppc_destroy(sppc_ctx* c) {
+  if (!c) return;
+  if (c->s) (void)hipStreamSynchronize(c->s); else (void)hipDeviceSynchronize();
+  if (c->pin) (void)hipHostFree(c->pin);
+  if (c->pin_i) (void)hipHostFree(c->pin_i);
+  c->arena.release();
+  delete c;
+}
+
+}  // extern "C"

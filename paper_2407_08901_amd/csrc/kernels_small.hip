@@ -1,0 +1,680 @@
+// kernels_small.hip - single-workgroup kernels on the small matrices of the method:
+// the projected matrix T = Q^T H Q and its lowest eigenpairs (Rayleigh-Ritz, eq. tilde_H),
+// the Cholesky factors of the block QR (eq. QR), and the coefficient bookkeeping of the
+// perturbative recursion (eq. exp_seq, eq. exp_seq2).
+#include "common.h"
+
+namespace sppc {
+
+namespace {
+
+constexpr int EIG_THREADS = 1024;
+
+__device__ inline double block_sum(double v, double* sh) {
+  // sh: >= 16 doubles; all threads of the (1024-thread) block call this
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sh[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  const int nw = blockDim.x >> 6;
+  for (int i = 0; i < nw; ++i) s += sh[i];
+  return s;
+}
+
+// Sturm count: number of eigenvalues of the tridiagonal (d, e) smaller than x.
+__device__ int sturm_count(int m, const double* d, const double* e2, double x, double pivmin) {
+  int cnt = 0;
+  double q = d[0] - x;
+  if (fabs(q) < pivmin) q = -pivmin;
+  cnt += q < 0.0;
+  for (int i = 1; i < m; ++i) {
+    q = d[i] - x - e2[i - 1] / q;
+    if (fabs(q) < pivmin) q = -pivmin;
+    cnt += q < 0.0;
+  }
+  return cnt;
+}
+
+// Solve (Tri - lam I) y = y in place by Gaussian elimination with partial pivoting on the
+// tridiagonal (two superdiagonals appear after interchanges).  Work arrays u0,u1,u2,l [m], piv [m].
+__device__ void tri_shifted_solve(int m, const double* d, const double* e, double lam, double epsp,
+                                  double* u0, double* u1, double* u2, double* l, unsigned char* piv,
+                                  double* y, bool factor) {
+  if (factor) {
+    double ca = d[0] - lam;
+    double cb = m > 1 ? e[0] : 0.0;
+    for (int k = 0; k < m - 1; ++k) {
+      const double sub = e[k];
+      const double na = d[k + 1] - lam;
+      const double nb = (k + 1 < m - 1) ? e[k + 1] : 0.0;
+      if (fabs(ca) >= fabs(sub)) {
+        if (ca == 0.0) ca = epsp;
+        const double mult = sub / ca;
+        u0[k] = ca; u1[k] = cb; u2[k] = 0.0; l[k] = mult; piv[k] = 0;
+        ca = na - mult * cb;
+        cb = nb;
+      } else {
+        const double mult = ca / sub;
+        u0[k] = sub; u1[k] = na; u2[k] = nb; l[k] = mult; piv[k] = 1;
+        ca = cb - mult * na;
+        cb = -mult * nb;
+      }
+    }
+    if (fabs(ca) < epsp) ca = ca >= 0.0 ? epsp : -epsp;
+    u0[m - 1] = ca;
+    for (int k = 0; k < m - 1; ++k)
+      if (fabs(u0[k]) < epsp) u0[k] = u0[k] >= 0.0 ? epsp : -epsp;
+  }
+  for (int k = 0; k < m - 1; ++k) {
+    if (piv[k]) {
+      const double t = y[k];
+      y[k] = y[k + 1];
+      y[k + 1] = t;
+    }
+    y[k + 1] -= l[k] * y[k];
+  }
+  y[m - 1] /= u0[m - 1];
+  if (m >= 2) y[m - 2] = (y[m - 2] - u1[m - 2] * y[m - 1]) / u0[m - 2];
+  for (int k = m - 3; k >= 0; --k) y[k] = (y[k] - u1[k] * y[k + 1] - u2[k] * y[k + 2]) / u0[k];
+}
+
+__device__ void normalize(int m, double* y) {
+  double s = 0.0, mx = 0.0;
+  for (int i = 0; i < m; ++i) mx = fmax(mx, fabs(y[i]));
+  if (mx == 0.0) return;
+  for (int i = 0; i < m; ++i) { y[i] /= mx; s += y[i] * y[i]; }
+  s = 1.0 / sqrt(s);
+  for (int i = 0; i < m; ++i) y[i] *= s;
+}
+
+// scratch layout (doubles): A[m*m] | d[m] | e[m] | e2[m] | beta[m] | Y[nw*m] | u0,u1,u2,l [nw*m each] | piv
+__global__ __launch_bounds__(EIG_THREADS) void k_sym_eig(int m, int nw, const double* __restrict__ S,
+                                                         int64_t lds, double* __restrict__ wout,
+                                                         double* __restrict__ V, int64_t ldv,
+                                                         double* __restrict__ scr) {
+  __shared__ double vsh[512];
+  __shared__ double psh[4][512];
+  __shared__ double wsh[512];
+  __shared__ double red[16];
+  __shared__ double sc[4];
+  const int t = threadIdx.x;
+  double* A = scr;
+  double* d = A + (int64_t)m * m;
+  double* e = d + m;
+  double* e2 = e + m;
+  double* beta = e2 + m;
+  double* Y = beta + m;
+  double* u0 = Y + (int64_t)nw * m;
+  double* u1 = u0 + (int64_t)nw * m;
+  double* u2 = u1 + (int64_t)nw * m;
+  double* lm = u2 + (int64_t)nw * m;
+  unsigned char* piv = (unsigned char*)(lm + (int64_t)nw * m);
+
+  for (int64_t x = t; x < (int64_t)m * m; x += EIG_THREADS) A[x] = S[(x / m) * lds + (x % m)];
+  __syncthreads();
+
+  // ---- Householder tridiagonalisation (the lower part; A stays symmetric)
+  for (int j = 0; j + 2 < m; ++j) {
+    const int len = m - 1 - j;
+    const double* xr = A + (int64_t)j * m + j + 1;  // row j, columns j+1.. == column j below diag
+    double part = 0.0;
+    for (int i = 1 + t; i < len; i += EIG_THREADS) part += xr[i] * xr[i];
+    const double sigma = block_sum(part, red);
+    if (t == 0) {
+      const double alpha = xr[0];
+      d[j] = A[(int64_t)j * m + j];
+      double b = 0.0, v0 = 1.0, ej = alpha;
+      if (sigma > 0.0) {
+        const double mu = sqrt(alpha * alpha + sigma);
+        v0 = alpha <= 0.0 ? alpha - mu : -sigma / (alpha + mu);
+        b = 2.0 * v0 * v0 / (sigma + v0 * v0);
+        ej = mu;
+      }
+      sc[0] = b;
+      sc[1] = v0;
+      e[j] = ej;
+      beta[j] = b;
+    }
+    __syncthreads();
+    const double b = sc[0], v0 = sc[1];
+    for (int i = t; i < len; i += EIG_THREADS) vsh[i] = i == 0 ? 1.0 : (b == 0.0 ? 0.0 : xr[i] / v0);
+    __syncthreads();
+    // keep v for the back-transformation in row j (no longer needed otherwise)
+    for (int i = t; i < len; i += EIG_THREADS) A[(int64_t)j * m + j + 1 + i] = vsh[i];
+    if (b != 0.0) {
+      // p = b * A_tr v, A_tr = A[j+1.., j+1..]; 4 row groups x 256 columns
+      const int grp = t >> 8, tl = t & 255;
+      const int l0 = (len * grp) / 4, l1 = (len * (grp + 1)) / 4;
+      for (int i = tl; i < len; i += 256) {
+        double s = 0.0;
+        for (int l = l0; l < l1; ++l) s += A[(int64_t)(j + 1 + l) * m + j + 1 + i] * vsh[l];
+        psh[grp][i] = s;
+      }
+      __syncthreads();
+      double kp = 0.0;
+      for (int i = t; i < len; i += EIG_THREADS) {
+        const double pi = b * (psh[0][i] + psh[1][i] + psh[2][i] + psh[3][i]);
+        wsh[i] = pi;
+        kp += pi * vsh[i];
+      }
+      const double K = 0.5 * b * block_sum(kp, red);
+      for (int i = t; i < len; i += EIG_THREADS) wsh[i] -= K * vsh[i];
+      __syncthreads();
+      for (int64_t x = t; x < (int64_t)len * len; x += EIG_THREADS) {
+        const int l = (int)(x / len), i = (int)(x % len);
+        A[(int64_t)(j + 1 + l) * m + j + 1 + i] -= vsh[l] * wsh[i] + wsh[l] * vsh[i];
+      }
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    if (m >= 2) {
+      d[m - 2] = A[(int64_t)(m - 2) * m + m - 2];
+      d[m - 1] = A[(int64_t)(m - 1) * m + m - 1];
+      e[m - 2] = A[(int64_t)(m - 1) * m + m - 2];
+      beta[m - 2] = 0.0;
+    } else {
+      d[0] = A[0];
+    }
+    e[m - 1] = 0.0;
+    beta[m - 1] = 0.0;
+  }
+  __syncthreads();
+  for (int i = t; i < m; i += EIG_THREADS) e2[i] = e[i] * e[i];
+  __syncthreads();
+
+  // ---- eigenvalues by bisection (one thread per wanted eigenvalue)
+  double lo = 0.0, hi = 0.0, tnorm = 0.0, maxe2 = 0.0;
+  if (t < nw) {
+    lo = d[0]; hi = d[0];
+    for (int i = 0; i < m; ++i) {
+      const double r = (i > 0 ? fabs(e[i - 1]) : 0.0) + (i < m - 1 ? fabs(e[i]) : 0.0);
+      lo = fmin(lo, d[i] - r);
+      hi = fmax(hi, d[i] + r);
+      if (i < m - 1) maxe2 = fmax(maxe2, e2[i]);
+    }
+    tnorm = fmax(fabs(lo), fabs(hi));
+    const double pivmin = 2.2250738585072014e-308 * fmax(1.0, maxe2);
+    double a = lo - 1e-14 * tnorm - 1e-300, bb = hi + 1e-14 * tnorm + 1e-300;
+    for (int it = 0; it < 200; ++it) {
+      const double mid = 0.5 * (a + bb);
+      if (bb - a <= 2.220446049250313e-16 * fmax(fabs(a), fabs(bb)) + pivmin || mid == a || mid == bb) break;
+      if (sturm_count(m, d, e2, mid, pivmin) <= t) a = mid; else bb = mid;
+    }
+    wsh[t] = 0.5 * (a + bb);
+    sc[2] = tnorm;
+  }
+  __syncthreads();
+  if (t == 0) {
+    // tnorm from thread 0 was written last by some thread; recompute safely
+    double tn = 0.0;
+    for (int i = 0; i < m; ++i)
+      tn = fmax(tn, fabs(d[i]) + (i > 0 ? fabs(e[i - 1]) : 0.0) + (i < m - 1 ? fabs(e[i]) : 0.0));
+    sc[2] = fmax(tn, 1e-300);
+  }
+  __syncthreads();
+
+  // ---- eigenvectors of the tridiagonal by inverse iteration; members of a cluster
+  //      are computed one after another and orthogonalised against each other.
+  if (t < nw) {
+    const double tn = sc[2];
+    const double ctol = 1e-3 * tn;
+    const double epsp = 2.220446049250313e-16 * tn;
+    const bool first = (t == 0) || (wsh[t] - wsh[t - 1] > ctol);
+    if (first) {
+      int last = t;
+      while (last + 1 < nw && wsh[last + 1] - wsh[last] <= ctol) ++last;
+      for (int c = t; c <= last; ++c) {
+        double* y = Y + (int64_t)c * m;
+        double* U0 = u0 + (int64_t)c * m;
+        double* U1 = u1 + (int64_t)c * m;
+        double* U2 = u2 + (int64_t)c * m;
+        double* Lm = lm + (int64_t)c * m;
+        unsigned char* P = piv + (int64_t)c * m;
+        // perturb repeated eigenvalues slightly so the factorisations differ
+        double lam = wsh[c];
+        if (c > t && lam - wsh[c - 1] < 10.0 * epsp) lam = wsh[c - 1] + 10.0 * epsp;
+        uint32_t h = 0x9E3779B9u * (uint32_t)(c + 1);
+        for (int i = 0; i < m; ++i) {
+          h ^= h << 13; h ^= h >> 17; h ^= h << 5;
+          y[i] = 0.5 + (double)(h & 0xFFFFFF) / (double)0x1000000;
+        }
+        for (int it = 0; it < 4; ++it) {
+          tri_shifted_solve(m, d, e, lam, epsp, U0, U1, U2, Lm, P, y, it == 0);
+          normalize(m, y);
+          for (int c2 = t; c2 < c; ++c2) {
+            const double* y2 = Y + (int64_t)c2 * m;
+            double s = 0.0;
+            for (int i = 0; i < m; ++i) s += y[i] * y2[i];
+            for (int i = 0; i < m; ++i) y[i] -= s * y2[i];
+          }
+          normalize(m, y);
+        }
+      }
+    }
+  }
+  __syncthreads();
+
+  // ---- back-transformation V = H_0 H_1 ... H_{m-3} Y ; one wave per eigenvector column
+  const int wv = t >> 6, ln = t & 63;
+  for (int j = m - 3; j >= 0; --j) {
+    const double b = beta[j];
+    if (b != 0.0) {
+      const int len = m - 1 - j;
+      const double* v = A + (int64_t)j * m + j + 1;
+      for (int c = wv; c < nw; c += EIG_THREADS / 64) {
+        double* y = Y + (int64_t)c * m + j + 1;
+        double s = 0.0;
+        for (int i = ln; i < len; i += 64) s += v[i] * y[i];
+        for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+        s *= b;
+        for (int i = ln; i < len; i += 64) y[i] -= s * v[i];
+      }
+    }
+    __syncthreads();
+  }
+  // ---- sign convention (largest-magnitude entry positive) and output
+  for (int c = wv; c < nw; c += EIG_THREADS / 64) {
+    const double* y = Y + (int64_t)c * m;
+    double best = -1.0;
+    int bi = 0;
+    for (int i = ln; i < m; i += 64) {
+      const double a = fabs(y[i]);
+      if (a > best) { best = a; bi = i; }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      const double ob = __shfl_xor(best, o);
+      const int oi = __shfl_xor(bi, o);
+      if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+    }
+    const double sgn = y[bi] < 0.0 ? -1.0 : 1.0;
+    for (int i = ln; i < m; i += 64) V[(int64_t)i * ldv + c] = sgn * y[i];
+    if (ln == 0) wout[c] = wsh[c];
+  }
+}
+
+// ---------------------------------------------------------------- Cholesky-QR factors
+constexpr int KB = 32;
+
+// Pivoted Cholesky of G restricted to the columns whose angle exceeds tau.
+__global__ void k_cholqr_first(int b, const double* __restrict__ G, const double* __restrict__ psi2,
+                               double tau, double* __restrict__ M, double* __restrict__ Rfac,
+                               double* __restrict__ angles, int* __restrict__ info) {
+  if (threadIdx.x != 0) return;
+  double W[KB][KB];
+  double L[KB][KB];
+  int perm[KB];
+  bool cand[KB];
+  for (int i = 0; i < b; ++i) {
+    for (int j = 0; j < b; ++j) { W[i][j] = G[i * b + j]; L[i][j] = 0.0; }
+    const double pn = psi2[i] > 0.0 ? psi2[i] : 1.0;
+    const double a = sqrt(fmax(G[i * b + i], 0.0) / pn);
+    angles[i] = a;
+    cand[i] = a > tau;
+  }
+  int s = 0;
+  while (s < b) {
+    int best = -1;
+    double bv = 0.0;
+    for (int i = 0; i < b; ++i)
+      if (cand[i] && W[i][i] > bv) { bv = W[i][i]; best = i; }
+    if (best < 0) break;
+    const double pn = psi2[best] > 0.0 ? psi2[best] : 1.0;
+    if (!(bv > tau * tau * pn)) break;
+    const double r = sqrt(bv);
+    cand[best] = false;
+    perm[s] = best;
+    for (int i = 0; i < b; ++i) L[i][s] = (cand[i] || i == best) ? W[i][best] / r : 0.0;
+    for (int i = 0; i < b; ++i) {
+      if (!cand[i]) continue;
+      for (int j = 0; j < b; ++j)
+        if (cand[j]) W[i][j] -= L[i][s] * L[j][s];
+    }
+    ++s;
+  }
+  // R1[a][c] = L[perm[c]][a] (upper triangular, s x s);  inverse by back substitution
+  double Ri[KB][KB];
+  for (int a = 0; a < s; ++a)
+    for (int c = 0; c < s; ++c) Ri[a][c] = 0.0;
+  for (int c = 0; c < s; ++c) {
+    Ri[c][c] = 1.0 / L[perm[c]][c];
+    for (int a = c - 1; a >= 0; --a) {
+      double acc = 0.0;
+      for (int q = a + 1; q <= c; ++q) acc += L[perm[q]][a] * Ri[q][c];
+      Ri[a][c] = -acc / L[perm[a]][a];
+    }
+  }
+  for (int i = 0; i < b; ++i)
+    for (int c = 0; c < b; ++c) M[i * b + c] = 0.0;
+  for (int a = 0; a < s; ++a)
+    for (int c = 0; c < s; ++c) M[perm[a] * b + c] = Ri[a][c];
+  // Rfac (s x b): Phi[:, j] ~= Phi1 Rfac[:, j]; Rfac[a][j] = L[j][a] for kept or eliminated j
+  for (int a = 0; a < b; ++a)
+    for (int j = 0; j < b; ++j) Rfac[a * b + j] = (a < s) ? L[j][a] : 0.0;
+  // columns never eliminated (dropped by angle) contribute nothing
+  info[0] = s;
+  info[1] = 0;
+}
+
+// Cholesky of G2 (s x s, leading dim b), M2 = R2^-1 (ld b), Rfac <- R2 * Rfac (s x b).
+__global__ void k_cholqr_second(int b, const double* __restrict__ G2, double* __restrict__ M2,
+                                double* __restrict__ Rfac, int* __restrict__ info) {
+  if (threadIdx.x != 0) return;
+  const int s = info[0];
+  double R[KB][KB];
+  int fail = 0;
+  for (int i = 0; i < s; ++i)
+    for (int j = 0; j < s; ++j) R[i][j] = 0.0;
+  for (int j = 0; j < s; ++j) {
+    double dsum = G2[j * b + j];
+    for (int q = 0; q < j; ++q) dsum -= R[q][j] * R[q][j];
+    if (!(dsum > 0.0)) { fail = 1; dsum = 1e-300; }
+    R[j][j] = sqrt(dsum);
+    for (int i = j + 1; i < s; ++i) {
+      double v = G2[j * b + i];
+      for (int q = 0; q < j; ++q) v -= R[q][j] * R[q][i];
+      R[j][i] = v / R[j][j];
+    }
+  }
+  for (int c = 0; c < s; ++c) {
+    for (int a = 0; a < s; ++a) M2[a * b + c] = 0.0;
+    M2[c * b + c] = 1.0 / R[c][c];
+    for (int a = c - 1; a >= 0; --a) {
+      double acc = 0.0;
+      for (int q = a + 1; q <= c; ++q) acc += R[a][q] * M2[q * b + c];
+      M2[a * b + c] = -acc / R[a][a];
+    }
+  }
+  double tmp[KB];
+  for (int j = 0; j < b; ++j) {
+    for (int a = 0; a < s; ++a) {
+      double acc = 0.0;
+      for (int q = a; q < s; ++q) acc += R[a][q] * Rfac[q * b + j];
+      tmp[a] = acc;
+    }
+    for (int a = 0; a < s; ++a) Rfac[a * b + j] = tmp[a];
+  }
+  info[1] = fail;
+}
+
+// ---------------------------------------------------------------- T bookkeeping
+__global__ void k_t_extend(int m_old, int kn, const double* __restrict__ X, int64_t ldx,
+                           double* __restrict__ T, int64_t ldt) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int mt = m_old + kn;
+  if (e >= (int64_t)mt * kn) return;
+  const int i = (int)(e / kn), j = (int)(e % kn);
+  const int cj = m_old + j;
+  if (i < m_old) {
+    const double v = X[(int64_t)i * ldx + j];
+    T[(int64_t)i * ldt + cj] = v;
+    T[(int64_t)cj * ldt + i] = v;
+  } else {
+    const int a = i - m_old;
+    T[(int64_t)i * ldt + cj] = 0.5 * (X[(int64_t)i * ldx + j] + X[(int64_t)(m_old + j) * ldx + a]);
+  }
+}
+
+__global__ void k_t_full(int m, const double* __restrict__ X, int64_t ldx, double* __restrict__ T,
+                         int64_t ldt) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)m * m) return;
+  const int i = (int)(e / m), j = (int)(e % m);
+  T[(int64_t)i * ldt + j] = 0.5 * (X[(int64_t)i * ldx + j] + X[(int64_t)j * ldx + i]);
+}
+
+__global__ void k_t_diag(int m, const double* __restrict__ th, double* __restrict__ T, int64_t ldt) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)m * m) return;
+  const int i = (int)(e / m), j = (int)(e % m);
+  T[(int64_t)i * ldt + j] = i == j ? th[i] : 0.0;
+}
+
+__global__ void k_store_coef(int m_old, int kn, int k, const double* __restrict__ C, int64_t ldc,
+                             const double* __restrict__ Rt, double* __restrict__ G, int64_t ldg) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)(m_old + kn) * k) return;
+  const int i = (int)(e / k), j = (int)(e % k);
+  G[(int64_t)i * ldg + j] = i < m_old ? C[(int64_t)i * ldc + j] : Rt[(int64_t)(i - m_old) * ldc + j];
+}
+
+// E^(p)_j = G^(p-1)[:, j]^T (T[:, j] - E0_j e_j)  (eq. exp_seq, first line: Psi^(p-1)^T V Psi^(0)
+// with Psi^(l) = Q G^(l), Q^T H Psi^(0) = T[:, 0:k] and Q^T H0 Psi^(0) = E0 on the first k rows);
+// A = G^(p-1), B = sum_{l=0}^{p-2} G^(l) diag(E^(p-l)), both m x k (zero-padded rows).
+__global__ void k_corr_coefs(int p, int k, int m, const double* __restrict__ Gh, int64_t gstride,
+                             int64_t ldg, const int* __restrict__ mh, double* __restrict__ Et,
+                             const double* __restrict__ T, int64_t ldt, const double* __restrict__ E0,
+                             double* __restrict__ A, double* __restrict__ B) {
+  __shared__ double Ep[32];
+  const int t = threadIdx.x;
+  const double* Gp = Gh + (int64_t)(p - 1) * gstride;
+  const int mp = mh[p - 1];
+  if (t < k) {
+    double s = 0.0;
+    for (int i = 0; i < mp; ++i) s += Gp[(int64_t)i * ldg + t] * T[(int64_t)i * ldt + t];
+    s -= E0[t] * Gp[(int64_t)t * ldg + t];
+    Ep[t] = s;
+    Et[(int64_t)p * k + t] = s;
+  }
+  __syncthreads();
+  for (int64_t e = t; e < (int64_t)m * k; e += blockDim.x) {
+    const int i = (int)(e / k), j = (int)(e % k);
+    A[e] = i < mp ? Gp[(int64_t)i * ldg + j] : 0.0;
+    double s = 0.0;
+    for (int l = 0; l + 2 <= p; ++l) {
+      const double El = (l == 0) ? Ep[j] : Et[(int64_t)(p - l) * k + j];
+      if (i < mh[l]) s += El * Gh[(int64_t)l * gstride + (int64_t)i * ldg + j];
+    }
+    B[e] = s;
+  }
+}
+
+__global__ void k_deflate_coefs(int D, int k, const double* __restrict__ w, const double* __restrict__ c,
+                                int64_t ldc, double* __restrict__ out, int64_t ldo) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= D * k) return;
+  const int j = e / k, kk = e % k;
+  const double Ek = w[kk];
+  const double dj = w[j] - Ek;
+  double v = 0.0;
+  if (j != kk && fabs(dj) > 1e-12 * fmax(1.0, fabs(Ek))) v = c[(int64_t)j * ldc + kk] / dj;
+  out[(int64_t)j * ldo + kk] = v;
+}
+
+__global__ void k_add(int count, const double* __restrict__ a, double* __restrict__ b) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < count) b[e] += a[e];
+}
+
+// per-chunk max |x| (first index on ties) for each column
+__global__ __launch_bounds__(256) void k_colargmax(int64_t n, int b, const double* __restrict__ X,
+                                                   int64_t ldx, double* __restrict__ pv,
+                                                   int64_t* __restrict__ pi) {
+  __shared__ double sv[256];
+  __shared__ int64_t si[256];
+  const int c = blockIdx.y;
+  const int64_t r0 = (int64_t)blockIdx.x * 4096;
+  const int64_t r1 = min<int64_t>(n, r0 + 4096);
+  double best = -1.0;
+  int64_t bi = r0;
+  for (int64_t r = r0 + threadIdx.x; r < r1; r += 256) {
+    const double a = fabs(X[r * ldx + c]);
+    if (a > best) { best = a; bi = r; }
+  }
+  sv[threadIdx.x] = best;
+  si[threadIdx.x] = bi;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < (unsigned)o) {
+      const double ov = sv[threadIdx.x + o];
+      const int64_t oi = si[threadIdx.x + o];
+      if (ov > sv[threadIdx.x] || (ov == sv[threadIdx.x] && oi < si[threadIdx.x])) {
+        sv[threadIdx.x] = ov;
+        si[threadIdx.x] = oi;
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    pv[(int64_t)c * gridDim.x + blockIdx.x] = sv[0];
+    pi[(int64_t)c * gridDim.x + blockIdx.x] = si[0];
+  }
+}
+
+__global__ void k_colsign(int64_t nch, int b, const double* __restrict__ X, int64_t ldx,
+                          const double* __restrict__ pv, const int64_t* __restrict__ pi,
+                          double* __restrict__ sgn) {
+  const int c = threadIdx.x;
+  if (c >= b) return;
+  double best = -1.0;
+  int64_t bi = 0;
+  for (int64_t q = 0; q < nch; ++q) {
+    const double v = pv[(int64_t)c * nch + q];
+    const int64_t i = pi[(int64_t)c * nch + q];
+    if (v > best || (v == best && i < bi)) { best = v; bi = i; }
+  }
+  sgn[c] = X[bi * ldx + c] < 0.0 ? -1.0 : 1.0;
+}
+
+__global__ void k_colscale(int64_t n, int b, double* __restrict__ X, int64_t ldx,
+                           const double* __restrict__ sgn) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * b) return;
+  const int64_t r = e / b;
+  const int c = (int)(e % b);
+  X[r * ldx + c] *= sgn[c];
+}
+
+__global__ void k_select_smallest(int64_t n, const double* __restrict__ d, int nsel, int* __restrict__ idx) {
+  __shared__ double sv[1024];
+  __shared__ int si[1024];
+  for (int q = 0; q < nsel; ++q) {
+    double best = INFINITY;
+    int bi = 0x7fffffff;
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+      bool used = false;
+      for (int u = 0; u < q; ++u) used |= (idx[u] == (int)i);
+      if (used) continue;
+      const double v = d[i];
+      if (v < best || (v == best && (int)i < bi)) { best = v; bi = (int)i; }
+    }
+    sv[threadIdx.x] = best;
+    si[threadIdx.x] = bi;
+    __syncthreads();
+    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+      if (threadIdx.x < (unsigned)o) {
+        const double ov = sv[threadIdx.x + o];
+        const int oi = si[threadIdx.x + o];
+        if (ov < sv[threadIdx.x] || (ov == sv[threadIdx.x] && oi < si[threadIdx.x])) {
+          sv[threadIdx.x] = ov;
+          si[threadIdx.x] = oi;
+        }
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) idx[q] = si[0];
+    __syncthreads();
+  }
+}
+
+__global__ void k_unit_block(int64_t n, int b, const int* __restrict__ idx, double* __restrict__ X,
+                             int64_t ldx) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * b) return;
+  const int64_t r = e / b;
+  const int c = (int)(e % b);
+  X[r * ldx + c] = (r == idx[c]) ? 1.0 : 0.0;
+}
+
+inline int64_t g1(int64_t count) { return cdiv(count > 0 ? count : 1, 256); }
+
+}  // namespace
+
+int64_t eig_scratch(int m, int nwant) {
+  return (int64_t)m * m + 4LL * m + 5LL * nwant * m + cdiv((int64_t)nwant * m, 8) + 64;
+}
+
+void sym_eig_lowest(int m, int nwant, const double* S, int64_t lds, double* w, double* V, int64_t ldv,
+                    double* scratch, hipStream_t s) {
+  if (m < 1 || m > 512 || nwant < 1 || nwant > m || nwant > 64)
+    throw Error(1, "sym_eig_lowest: need 1 <= nwant <= min(m, 64), m <= 512");
+  k_sym_eig<<<1, EIG_THREADS, 0, s>>>(m, nwant, S, lds, w, V, ldv, scratch);
+  SPPC_LAUNCH_CHECK();
+}
+
+void cholqr_first(int b, const double* G, const double* psi_sumsq, double tau, double* M, double* Rfac,
+                  double* angles, int* info, hipStream_t s) {
+  if (b < 1 || b > KB) throw Error(1, "cholqr: block width must be 1..32");
+  k_cholqr_first<<<1, 64, 0, s>>>(b, G, psi_sumsq, tau, M, Rfac, angles, info);
+  SPPC_LAUNCH_CHECK();
+}
+
+void cholqr_second(int b, const double* G2, double* M2, double* Rfac, int* info, hipStream_t s) {
+  k_cholqr_second<<<1, 64, 0, s>>>(b, G2, M2, Rfac, info);
+  SPPC_LAUNCH_CHECK();
+}
+
+void t_extend(int m_old, int kn, const double* X, int64_t ldx, double* T, int64_t ldt, hipStream_t s) {
+  k_t_extend<<<g1((int64_t)(m_old + kn) * kn), 256, 0, s>>>(m_old, kn, X, ldx, T, ldt);
+  SPPC_LAUNCH_CHECK();
+}
+
+void t_from_full(int m, const double* X, int64_t ldx, double* T, int64_t ldt, hipStream_t s) {
+  k_t_full<<<g1((int64_t)m * m), 256, 0, s>>>(m, X, ldx, T, ldt);
+  SPPC_LAUNCH_CHECK();
+}
+
+void t_set_diag(int m, const double* theta, double* T, int64_t ldt, hipStream_t s) {
+  k_t_diag<<<g1((int64_t)m * m), 256, 0, s>>>(m, theta, T, ldt);
+  SPPC_LAUNCH_CHECK();
+}
+
+void store_coef(int m_old, int kn, int k, const double* C, int64_t ldc, const double* Rtot, double* G,
+                int64_t ldg, hipStream_t s) {
+  k_store_coef<<<g1((int64_t)(m_old + kn) * k), 256, 0, s>>>(m_old, kn, k, C, ldc, Rtot, G, ldg);
+  SPPC_LAUNCH_CHECK();
+}
+
+void build_correction_coefs(int p, int k, int m, const double* Ghist, int64_t gstride, int64_t ldg,
+                            const int* m_hist, double* Etab, const double* T, int64_t ldt,
+                            const double* E0, double* A, double* B, hipStream_t s) {
+  k_corr_coefs<<<1, 256, 0, s>>>(p, k, m, Ghist, gstride, ldg, m_hist, Etab, T, ldt, E0, A, B);
+  SPPC_LAUNCH_CHECK();
+}
+
+void deflate_coefs(int D, int k, const double* w, const double* c, int64_t ldc, double* out, int64_t ldo,
+                   hipStream_t s) {
+  k_deflate_coefs<<<g1((int64_t)D * k), 256, 0, s>>>(D, k, w, c, ldc, out, ldo);
+  SPPC_LAUNCH_CHECK();
+}
+
+void add_small(int count, const double* a, double* b, hipStream_t s) {
+  if (count <= 0) return;
+  k_add<<<g1(count), 256, 0, s>>>(count, a, b);
+  SPPC_LAUNCH_CHECK();
+}
+
+void sign_fix_columns(int64_t n, int b, double* X, int64_t ldx, double* work, hipStream_t s) {
+  const int64_t nch = cdiv(n > 0 ? n : 1, 4096);
+  double* pv = work;
+  int64_t* pi = (int64_t*)(work + nch * b);
+  double* sg = work + 2 * nch * b;
+  k_colargmax<<<dim3((unsigned)nch, (unsigned)b), 256, 0, s>>>(n, b, X, ldx, pv, pi);
+  k_colsign<<<1, 64, 0, s>>>(nch, b, X, ldx, pv, pi, sg);
+  k_colscale<<<g1(n * b), 256, 0, s>>>(n, b, X, ldx, sg);
+  SPPC_LAUNCH_CHECK();
+}
+
+void select_smallest(int64_t n, const double* d, int nsel, int* idx, hipStream_t s) {
+  k_select_smallest<<<1, 1024, 0, s>>>(n, d, nsel, idx);
+  SPPC_LAUNCH_CHECK();
+}
+
+void unit_block(int64_t n, int b, const int* idx, double* X, int64_t ldx, hipStream_t s) {
+  k_unit_block<<<g1(n * b), 256, 0, s>>>(n, b, idx, X, ldx);
+  SPPC_LAUNCH_CHECK();
+}
+
+}  // namespace sppc

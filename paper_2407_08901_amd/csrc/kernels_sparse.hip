@@ -1,0 +1,354 @@
+// kernels_sparse.hip - device format of H and the block product Y = H X.
+//
+// H arrives as its upper triangle (CSR, columns >= row).  The product needs both
+// triangles: the transposed half would otherwise be a scatter with float64
+// atomics (k of them per stored entry), which costs more HBM/L2 traffic than
+// streaming the mirrored entries and is not deterministic.  So setup mirrors the
+// strict upper triangle into a full CSR with ascending columns per row, with no
+// atomics in the arithmetic and a deterministic entry order.
+#include "common.h"
+
+namespace sppc {
+
+namespace {
+
+// -------------------------------------------------------------------------- setup
+
+template <typename VT>
+__global__ void k_validate_count(int64_t n, const int64_t* __restrict__ rp,
+                                 const int32_t* __restrict__ col, const VT* __restrict__ val,
+                                 int32_t* __restrict__ lower_cnt, int* __restrict__ flags) {
+  const int lane = threadIdx.x & 63;
+  const int64_t row = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (row >= n) return;
+  const int64_t b = rp[row], e = rp[row + 1];
+  int bad = 0, inexact = 0, nonfinite = 0;
+  if (e < b) bad = 1;
+  for (int64_t t = b + lane; t < e; t += 64) {
+    const int32_t c = col[t];
+    if (c < row || c >= n) bad = 1;
+    if (t > b && col[t - 1] >= c) bad = 1;
+    const double v = (double)val[t];
+    if (!isfinite(v)) nonfinite = 1;
+    if ((double)(float)v != v) inexact = 1;
+    if (c != row && c < n && c > row) atomicAdd(&lower_cnt[c], 1);
+  }
+  if (bad) atomicOr(&flags[0], 1);
+  if (inexact) atomicOr(&flags[1], 1);
+  if (nonfinite) atomicOr(&flags[2], 1);
+}
+
+// exclusive scan of int32 counts into int64, three phases
+constexpr int SCAN_BLOCK = 1024;
+
+__global__ void k_scan_blocks(int64_t n, const int32_t* __restrict__ a, int64_t* __restrict__ bsum) {
+  __shared__ int64_t sh[SCAN_BLOCK / 64];
+  const int64_t i = (int64_t)blockIdx.x * SCAN_BLOCK + threadIdx.x;
+  int64_t v = i < n ? a[i] : 0;
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int64_t s = 0;
+    for (int w = 0; w < SCAN_BLOCK / 64; ++w) s += sh[w];
+    bsum[blockIdx.x] = s;
+  }
+}
+
+__global__ void k_scan_sums(int64_t nb, int64_t* __restrict__ bsum) {
+  // single block: sequential chunks of blockDim.x, exclusive in place
+  __shared__ int64_t sh[1024];
+  int64_t carry = 0;
+  for (int64_t base = 0; base < nb; base += blockDim.x) {
+    const int64_t i = base + threadIdx.x;
+    const int64_t v = i < nb ? bsum[i] : 0;
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int o = 1; o < (int)blockDim.x; o <<= 1) {
+      int64_t t = threadIdx.x >= (unsigned)o ? sh[threadIdx.x - o] : 0;
+      __syncthreads();
+      sh[threadIdx.x] += t;
+      __syncthreads();
+    }
+    if (i < nb) bsum[i] = carry + sh[threadIdx.x] - v;
+    const int64_t tot = sh[blockDim.x - 1];
+    __syncthreads();
+    carry += tot;
+  }
+}
+
+__global__ void k_scan_final(int64_t n, const int32_t* __restrict__ a, const int64_t* __restrict__ bsum,
+                             int64_t* __restrict__ out) {
+  __shared__ int64_t sh[SCAN_BLOCK];
+  const int64_t i = (int64_t)blockIdx.x * SCAN_BLOCK + threadIdx.x;
+  const int64_t v = i < n ? a[i] : 0;
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int o = 1; o < SCAN_BLOCK; o <<= 1) {
+    int64_t t = threadIdx.x >= (unsigned)o ? sh[threadIdx.x - o] : 0;
+    __syncthreads();
+    sh[threadIdx.x] += t;
+    __syncthreads();
+  }
+  if (i < n) out[i] = bsum[blockIdx.x] + sh[threadIdx.x] - v;
+  if (i == n - 1) out[n] = bsum[blockIdx.x] + sh[threadIdx.x];
+}
+
+void scan_exclusive(int64_t n, const int32_t* a, int64_t* out, int64_t* bsum, hipStream_t s) {
+  const int64_t nb = cdiv(n, SCAN_BLOCK);
+  k_scan_blocks<<<nb, SCAN_BLOCK, 0, s>>>(n, a, bsum);
+  k_scan_sums<<<1, 1024, 0, s>>>(nb, bsum);
+  k_scan_final<<<nb, SCAN_BLOCK, 0, s>>>(n, a, bsum, out);
+  SPPC_LAUNCH_CHECK();
+}
+
+__global__ void k_full_rowptr(int64_t n, const int64_t* __restrict__ lower_rp,
+                              const int64_t* __restrict__ up_rp, int64_t* __restrict__ full_rp) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i <= n) full_rp[i] = lower_rp[i] + up_rp[i];
+}
+
+template <typename VT>
+__global__ void k_fill(int64_t n, const int64_t* __restrict__ up_rp, const int32_t* __restrict__ up_col,
+                       const VT* __restrict__ up_val, const int64_t* __restrict__ lower_rp,
+                       const int64_t* __restrict__ full_rp, int32_t* __restrict__ fillc,
+                       int32_t* __restrict__ full_col, double* __restrict__ full_v64,
+                       float* __restrict__ full_v32, int32_t* __restrict__ tmp_col,
+                       double* __restrict__ tmp_val) {
+  const int lane = threadIdx.x & 63;
+  const int64_t row = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (row >= n) return;
+  const int64_t b = up_rp[row], e = up_rp[row + 1];
+  const int64_t nlow = lower_rp[row + 1] - lower_rp[row];
+  const int64_t dst = full_rp[row] + nlow;
+  for (int64_t t = b + lane; t < e; t += 64) {
+    const int32_t c = up_col[t];
+    const double v = (double)up_val[t];
+    const int64_t o = dst + (t - b);
+    full_col[o] = c;
+    if (full_v64) full_v64[o] = v;
+    if (full_v32) full_v32[o] = (float)v;
+    if (c != row) {
+      const int32_t slot = atomicAdd(&fillc[c], 1);
+      const int64_t q = lower_rp[c] + slot;
+      tmp_col[q] = (int32_t)row;
+      tmp_val[q] = v;
+    }
+  }
+}
+
+// The mirrored entries of a row arrive in arbitrary order; place each at its rank
+// (column indices in a row are unique), which is deterministic.
+__global__ void k_sort_lower(int64_t n, const int64_t* __restrict__ lower_rp,
+                             const int64_t* __restrict__ full_rp, const int32_t* __restrict__ tmp_col,
+                             const double* __restrict__ tmp_val, int32_t* __restrict__ full_col,
+                             double* __restrict__ full_v64, float* __restrict__ full_v32) {
+  const int lane = threadIdx.x & 63;
+  const int64_t row = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (row >= n) return;
+  const int64_t b = lower_rp[row], e = lower_rp[row + 1];
+  const int64_t L = e - b;
+  const int64_t dst = full_rp[row];
+  for (int64_t t = lane; t < L; t += 64) {
+    const int32_t key = tmp_col[b + t];
+    int64_t rank = 0;
+    for (int64_t f = 0; f < L; ++f) rank += tmp_col[b + f] < key;
+    full_col[dst + rank] = key;
+    const double v = tmp_val[b + t];
+    if (full_v64) full_v64[dst + rank] = v;
+    if (full_v32) full_v32[dst + rank] = (float)v;
+  }
+}
+
+__global__ void k_block_view(int64_t n0, const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
+                             int64_t* __restrict__ rend) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n0) return;
+  int64_t lo = rp[i], hi = rp[i + 1];  // first position with col >= n0
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (col[mid] < n0) lo = mid + 1; else hi = mid;
+  }
+  rend[i] = lo;
+}
+
+__global__ void k_diag(int64_t n, const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
+                       const double* __restrict__ v64, const float* __restrict__ v32,
+                       double* __restrict__ diag) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int64_t lo = rp[i], hi = rp[i + 1];
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (col[mid] < i) lo = mid + 1; else hi = mid;
+  }
+  double d = 0.0;
+  if (lo < rp[i + 1] && col[lo] == i) d = v64 ? v64[lo] : (double)v32[lo];
+  diag[i] = d;
+}
+
+// -------------------------------------------------------------------------- SpMM
+//
+// One wave per row.  The wave loads 64 (column, value) pairs of its row at a time
+// (coalesced stream), then groups of B lanes take one nonzero each: the B lanes of a
+// group read the B contiguous entries of the gathered row of X (one 8*B-byte segment)
+// and accumulate into one float64 register per lane.  The groups are summed with
+// cross-lane shuffles at the end of the row.
+template <int B, typename VT, typename XT>
+__global__ __launch_bounds__(256) void k_spmm(int64_t n, const int64_t* __restrict__ rp,
+                                              const int64_t* __restrict__ rend,
+                                              const int32_t* __restrict__ col,
+                                              const VT* __restrict__ val, const XT* __restrict__ X,
+                                              int64_t ldx, double* __restrict__ Y, int64_t ldy, int b,
+                                              const double* __restrict__ shift) {
+  constexpr int G = 64 / B;
+  const int lane = threadIdx.x & 63;
+  const int g = lane / B;
+  const int c = lane % B;
+  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= n) return;
+  const int64_t beg = rp[row];
+  const int64_t end = rend ? rend[row] : rp[row + 1];
+  const bool colok = c < b;
+  double acc = 0.0;
+  for (int64_t base = beg; base < end; base += 64) {
+    const int cnt = (int)min<int64_t>(64, end - base);
+    int32_t mc = 0;
+    VT mv = VT(0);
+    if (lane < cnt) {
+      mc = __builtin_nontemporal_load(&col[base + lane]);
+      mv = __builtin_nontemporal_load(&val[base + lane]);
+    }
+#pragma unroll 4
+    for (int s0 = 0; s0 < cnt; s0 += G) {
+      const int e = s0 + g;
+      const int32_t cc = __shfl(mc, e);
+      const VT vv = __shfl(mv, e);
+      if (e < cnt && colok) {
+        const XT xv = X[(int64_t)cc * ldx + c];
+        if constexpr (sizeof(XT) == 4) {
+          acc += (double)(vv * xv);            // float32 product, float64 accumulation
+        } else {
+          acc = fma((double)vv, (double)xv, acc);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int o = B; o < 64; o <<= 1) acc += __shfl_xor(acc, o);
+  if (g == 0 && colok) {
+    if (shift) acc -= shift[c] * (double)X[row * ldx + c];
+    Y[row * ldy + c] = acc;
+  }
+}
+
+template <typename VT, typename XT>
+void launch_spmm(const DevCSR& H, const VT* val, const XT* X, int64_t ldx, double* Y, int64_t ldy,
+                 int b, const double* shift, hipStream_t s) {
+  if (b < 1 || b > 32) throw Error(1, "spmm: block width must be 1..32");
+  if (H.n == 0) return;
+  const int64_t grid = cdiv(H.n, 4);
+#define SPPC_SPMM_CASE(BB)                                                                        \
+  k_spmm<BB, VT, XT><<<grid, 256, 0, s>>>(H.n, H.rp, H.rend, H.col, val, X, ldx, Y, ldy, b, shift); \
+  break;
+  switch (b <= 1 ? 1 : b <= 2 ? 2 : b <= 4 ? 4 : b <= 8 ? 8 : b <= 16 ? 16 : 32) {
+    case 1: SPPC_SPMM_CASE(1)
+    case 2: SPPC_SPMM_CASE(2)
+    case 4: SPPC_SPMM_CASE(4)
+    case 8: SPPC_SPMM_CASE(8)
+    case 16: SPPC_SPMM_CASE(16)
+    default: SPPC_SPMM_CASE(32)
+  }
+#undef SPPC_SPMM_CASE
+  SPPC_LAUNCH_CHECK();
+}
+
+}  // namespace
+
+void build_full_csr(int64_t n, int64_t nnz_up, const int64_t* up_rp, const int32_t* up_col,
+                    const void* up_val, int val_is_f32, DevCSR& out, int* d_flags, bool want64,
+                    bool want32, bool& exact32, hipStream_t s) {
+  int32_t *lower_cnt = nullptr, *fillc = nullptr, *tmp_col = nullptr;
+  int64_t *lower_rp = nullptr, *bsum = nullptr;
+  double* tmp_val = nullptr;
+  auto cleanup = [&]() {
+    hipFree(lower_cnt); hipFree(fillc); hipFree(tmp_col); hipFree(lower_rp); hipFree(bsum);
+    hipFree(tmp_val);
+  };
+  try {
+    SPPC_HIP(hipMalloc(&lower_cnt, sizeof(int32_t) * (n + 1)));
+    SPPC_HIP(hipMalloc(&fillc, sizeof(int32_t) * (n + 1)));
+    SPPC_HIP(hipMalloc(&lower_rp, sizeof(int64_t) * (n + 1)));
+    SPPC_HIP(hipMalloc(&bsum, sizeof(int64_t) * (cdiv(n, SCAN_BLOCK) + 1)));
+    SPPC_HIP(hipMemsetAsync(lower_cnt, 0, sizeof(int32_t) * (n + 1), s));
+    SPPC_HIP(hipMemsetAsync(fillc, 0, sizeof(int32_t) * (n + 1), s));
+    SPPC_HIP(hipMemsetAsync(d_flags, 0, sizeof(int) * 4, s));
+    const int64_t grid_w = cdiv(n, 4);
+    if (val_is_f32)
+      k_validate_count<float><<<grid_w, 256, 0, s>>>(n, up_rp, up_col, (const float*)up_val, lower_cnt, d_flags);
+    else
+      k_validate_count<double><<<grid_w, 256, 0, s>>>(n, up_rp, up_col, (const double*)up_val, lower_cnt, d_flags);
+    SPPC_LAUNCH_CHECK();
+    int h_flags[4];
+    SPPC_HIP(hipMemcpyAsync(h_flags, d_flags, sizeof(h_flags), hipMemcpyDeviceToHost, s));
+    SPPC_HIP(hipStreamSynchronize(s));
+    if (h_flags[0]) throw Error(1, "H: upper CSR expected (columns >= row, < n, strictly ascending)");
+    if (h_flags[2]) throw Error(7, "H: NaN or Inf among the values");
+    exact32 = val_is_f32 || !h_flags[1];
+    scan_exclusive(n, lower_cnt, lower_rp, bsum, s);
+    int64_t nlow = 0;
+    SPPC_HIP(hipMemcpyAsync(&nlow, lower_rp + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    SPPC_HIP(hipStreamSynchronize(s));
+    const int64_t nnz = nnz_up + nlow;
+    out.n = n;
+    out.nnz = nnz;
+    SPPC_HIP(hipMalloc(&out.rp, sizeof(int64_t) * (n + 1)));
+    SPPC_HIP(hipMalloc(&out.col, sizeof(int32_t) * (nnz > 0 ? nnz : 1)));
+    if (want64) SPPC_HIP(hipMalloc(&out.val64, sizeof(double) * (nnz > 0 ? nnz : 1)));
+    if (want32) SPPC_HIP(hipMalloc(&out.val32, sizeof(float) * (nnz > 0 ? nnz : 1)));
+    SPPC_HIP(hipMalloc(&tmp_col, sizeof(int32_t) * (nlow > 0 ? nlow : 1)));
+    SPPC_HIP(hipMalloc(&tmp_val, sizeof(double) * (nlow > 0 ? nlow : 1)));
+    k_full_rowptr<<<cdiv(n + 1, 256), 256, 0, s>>>(n, lower_rp, up_rp, out.rp);
+    if (val_is_f32)
+      k_fill<float><<<grid_w, 256, 0, s>>>(n, up_rp, up_col, (const float*)up_val, lower_rp, out.rp, fillc,
+                                           out.col, out.val64, out.val32, tmp_col, tmp_val);
+    else
+      k_fill<double><<<grid_w, 256, 0, s>>>(n, up_rp, up_col, (const double*)up_val, lower_rp, out.rp,
+                                            fillc, out.col, out.val64, out.val32, tmp_col, tmp_val);
+    k_sort_lower<<<grid_w, 256, 0, s>>>(n, lower_rp, out.rp, tmp_col, tmp_val, out.col, out.val64,
+                                        out.val32);
+    SPPC_LAUNCH_CHECK();
+    SPPC_HIP(hipStreamSynchronize(s));
+  } catch (...) {
+    cleanup();
+    throw;
+  }
+  cleanup();
+}
+
+void build_block_view(const DevCSR& full, int64_t n0, int64_t* rend, hipStream_t s) {
+  if (n0 == 0) return;
+  k_block_view<<<cdiv(n0, 256), 256, 0, s>>>(n0, full.rp, full.col, rend);
+  SPPC_LAUNCH_CHECK();
+}
+
+void extract_diag(const DevCSR& H, double* diag, hipStream_t s) {
+  k_diag<<<cdiv(H.n, 256), 256, 0, s>>>(H.n, H.rp, H.col, H.val64, H.val32, diag);
+  SPPC_LAUNCH_CHECK();
+}
+
+void spmm_f64(const DevCSR& H, const double* X, int64_t ldx, double* Y, int64_t ldy, int b,
+              const double* shift, hipStream_t s) {
+  if (H.val64)
+    launch_spmm<double, double>(H, H.val64, X, ldx, Y, ldy, b, shift, s);
+  else
+    launch_spmm<float, double>(H, H.val32, X, ldx, Y, ldy, b, shift, s);
+}
+
+void spmm_f32(const DevCSR& H, const float* X, int64_t ldx, double* Y, int64_t ldy, int b,
+              const double* shift, hipStream_t s) {
+  if (!H.val32) throw Error(1, "spmm_f32: no float32 values");
+  launch_spmm<float, float>(H, H.val32, X, ldx, Y, ldy, b, shift, s);
+}
+
+}  // namespace sppc

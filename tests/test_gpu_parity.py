@@ -1,0 +1,154 @@
+"""GPU path vs the CPU oracle, element by element on seeded inputs (through the C ABI)."""
+import numpy as np
+import pytest
+import torch
+
+import levelgen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+P = None
+
+
+def setup_module(module):
+    global P
+    import paper_2407_08901_amd as _P
+    _P.lib()
+    P = _P
+
+
+def _ctx(A, n_small, k, dtype=torch.float64, **kw):
+    rp, col, val = P.upload(A, dtype=dtype)
+    opts = P.sppc_default_opts(**kw)
+    return P.sppc_setup(rp, col, val, A.level_offsets, n_small, k, opts)
+
+
+def _H(A):
+    return oracle.symmetric_from_upper(A.row_ptr, A.col, A.val, A.n)
+
+
+# ---------------------------------------------------------------- block product
+@pytest.mark.parametrize("b", [1, 3, 4, 8, 16])
+def test_spmm_f64_matches_scipy(b):
+    print("case spmm_f64 b=%d" % b, flush=True)
+    A = levelgen.generate((300, 3000, 20000), 60, 77)      # n = 23300: many waves, ragged tail
+    H = _H(A)
+    ctx = _ctx(A, 1, 4)
+    rng = np.random.default_rng(b)
+    X = rng.standard_normal((A.n, b))
+    Xd = torch.from_numpy(X).cuda()
+    Yd = torch.empty_like(Xd)
+    P.sppc_spmm(ctx, Xd, Yd)
+    torch.cuda.synchronize()
+    Y = Yd.cpu().numpy()
+    ref = H @ X
+    scale = abs(H) @ np.abs(X)
+    assert np.max(np.abs(Y - ref) / scale) < 1e-14
+
+
+def test_spmm_f32_products_accumulated_in_f64():
+    print("case spmm_f32", flush=True)
+    A = levelgen.generate((300, 3000, 20000), 60, 78)
+    H = _H(A)
+    ctx = _ctx(A, 1, 4)
+    rng = np.random.default_rng(5)
+    X = rng.standard_normal((A.n, 8)).astype(np.float32)
+    Yd = torch.empty((A.n, 8), dtype=torch.float64, device="cuda")
+    P.sppc_spmm(ctx, torch.from_numpy(X).cuda(), Yd)
+    torch.cuda.synchronize()
+    Y = Yd.cpu().numpy()
+    ref = H @ X.astype(np.float64)
+    scale = abs(H) @ np.abs(X.astype(np.float64))
+    # each float32 product carries a relative error <= 2^-24; the float64 sum adds ~1e-16
+    assert np.max(np.abs(Y - ref) / scale) < 2.0 ** -24 * 1.01
+
+
+# ---------------------------------------------------------------- zeroth order
+def test_zeroth_order_matches_dense():
+    print("case zeroth order cfg0", flush=True)
+    w = levelgen.WORKLOADS[0]
+    A = w.generate()
+    ctx = _ctx(A, w.n_small_levels, w.k)
+    D = 2 * w.k
+    E0 = np.array(P.sppc_get(ctx, 0, D))
+    H0 = _H(A)[:w.n0, :w.n0].toarray()
+    lam, U = np.linalg.eigh(H0)
+    assert np.max(np.abs(E0 - lam[:D]) / np.abs(lam[:D])) < 1e-12
+    Ps = P.sppc_get(ctx, 9, w.n0 * D, device=True).cpu().numpy().reshape(w.n0, D)
+    # same eigenvectors up to sign convention (largest-magnitude entry positive)
+    U = U[:, :D] * np.sign(U[np.argmax(np.abs(U[:, :D]), axis=0), np.arange(D)])
+    assert np.max(np.abs(Ps - U)) < 1e-10
+
+
+# ---------------------------------------------------------------- per-iteration parity
+def _oracle_run(A, n0, k, **kw):
+    return oracle.sppc(_H(A), n0, k, oracle.Options(**kw))
+
+
+@pytest.mark.parametrize("case", ["cfg0", "ragged"])
+def test_sppc_steps_match_oracle(case):
+    if case == "cfg0":
+        w = levelgen.WORKLOADS[0]
+        A, ns, k = w.generate(), w.n_small_levels, w.k
+    else:
+        A, ns, k = levelgen.generate((37, 411, 2999), 44, 9), 1, 3
+    n0 = int(A.level_offsets[ns])
+    print("case steps %s n=%d n0=%d k=%d" % (case, A.n, n0, k), flush=True)
+    ref = _oracle_run(A, n0, k, continuation=False, maxiter=15, tol=1e-300, final_check=False)
+    ctx = _ctx(A, ns, k, p_switch=0, maxiter=15, tol=1e-300, final_check=0)
+    th0 = np.array(P.sppc_get(ctx, 1, k))
+    assert np.max(np.abs(th0 - ref.history[0]["theta"]) / np.abs(ref.history[0]["theta"])) < 1e-12
+    for p in range(1, 16):
+        P.sppc_correct(ctx, P.SPPC_CORR_PERTURBATIVE)
+        th, rr, added = P.sppc_rayleigh_ritz(ctx)
+        h = ref.history[p]
+        rel = np.max(np.abs(np.array(th) - h["theta"]) / np.abs(h["theta"]))
+        assert rel < 1e-10, (p, rel)
+        assert added == h["m"] - ref.history[p - 1]["m"]
+        # residual norms agree to the precision they carry
+        assert np.allclose(rr, h["rrn"], rtol=1e-5, atol=1e-13), (p, rr, h["rrn"])
+    m = int(P.sppc_get(ctx, 2, 1)[0])
+    Q = P.sppc_get(ctx, 3, A.n * m, device=True).cpu().numpy().reshape(A.n, m)
+    assert np.max(np.abs(Q.T @ Q - np.eye(m))) < 1e-12
+    # the recursion's energies E^(p) (eq. exp_seq) agree with the oracle's direct products
+    Et = np.array(P.sppc_get(ctx, 8, 16 * k)).reshape(16, k)
+    for p in range(2, 16):
+        assert np.allclose(Et[p], ref.E_hist[p], rtol=1e-8, atol=1e-12 * abs(ref.E0).max()), p
+
+
+def test_correction_vectors_match_oracle():
+    """Psi^(p) from the stored-HQ identity + deflated CG equals the oracle's direct computation."""
+    w = levelgen.WORKLOADS[0]
+    A = w.generate()
+    print("case correction vectors", flush=True)
+    E, Psi = oracle.rs_corrections(_H(A), w.n0, w.k, 6)
+    ctx = _ctx(A, w.n_small_levels, w.k, p_switch=0, maxiter=15, tol=1e-300, final_check=0)
+    for p in range(1, 7):
+        P.sppc_correct(ctx, P.SPPC_CORR_PERTURBATIVE)
+        g = P.sppc_get(ctx, 5, A.n * w.k, device=True).cpu().numpy().reshape(A.n, w.k)
+        ref = Psi[p]
+        err = np.max(np.abs(g - ref)) / np.max(np.abs(ref))
+        assert err < 1e-9, (p, err)
+        P.sppc_rayleigh_ritz(ctx)
+
+
+def test_full_solve_cfg0_matches_dense():
+    w = levelgen.WORKLOADS[0]
+    A = w.generate()
+    print("case full solve cfg0", flush=True)
+    ctx = _ctx(A, w.n_small_levels, w.k)
+    ev, Z, rrn, st, status = P.sppc_solve(ctx)
+    assert status == P.SPPC_OK and st["converged"] == 1
+    lam = np.linalg.eigvalsh(_H(A).toarray())[: w.k]
+    assert np.max(np.abs(np.array(ev) - lam) / np.abs(lam)) < 1e-10
+    assert max(rrn) < 1e-6
+    Zh = Z.cpu().numpy()
+    H = _H(A)
+    R = H @ Zh - Zh * np.array(ev)[None, :]
+    assert np.max(np.linalg.norm(R, axis=0) / np.abs(ev)) < 1e-6
+    assert np.max(np.abs(Zh.T @ Zh - np.eye(w.k))) < 1e-12
+    # oracle with the same stopping rule: same eigenvalues
+    ref = _oracle_run(A, w.n0, w.k)
+    assert np.max(np.abs(np.array(ev) - ref.theta) / np.abs(ref.theta)) < 1e-10
+    assert st["n_spmv"] >= w.k * (st["iterations"] + 1)
