@@ -89,6 +89,8 @@ typedef struct {
   int iterations;      /* SPPC steps p reached */
   int cont_steps;      /* continuation steps */
   int64_t n_spmv;      /* products of H with one vector (k per SPPC step, Sec. IV.C) */
+  int64_t spmm_calls;  /* block products with H (kernel launches) */
+  int64_t spmm_cols;   /* sum of their block widths */
   int basis_size;      /* columns of the final basis */
   int cg_iterations;   /* small-space solver iterations, summed over steps */
   int h0_iterations;   /* iterations of the H0hat eigensolver */

@@ -44,6 +44,7 @@ class sppc_opts(ctypes.Structure):
 
 class sppc_stats(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int), ("cont_steps", ctypes.c_int), ("n_spmv", ctypes.c_int64),
+                ("spmm_calls", ctypes.c_int64), ("spmm_cols", ctypes.c_int64),
                 ("basis_size", ctypes.c_int), ("cg_iterations", ctypes.c_int), ("h0_iterations", ctypes.c_int),
                 ("converged", ctypes.c_int), ("t_setup_ms", ctypes.c_double), ("t_solve_ms", ctypes.c_double),
                 ("t_spmm_ms", ctypes.c_double), ("t_small_ms", ctypes.c_double), ("t_ortho_ms", ctypes.c_double),

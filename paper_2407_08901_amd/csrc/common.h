@@ -5,6 +5,7 @@
 #include <stdint.h>
 #include <stdio.h>
 
+#include <algorithm>
 #include <stdexcept>
 #include <string>
 
@@ -27,7 +28,7 @@ struct Error : std::runtime_error {
 
 constexpr int WAVE = 64;
 
-inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+__host__ __device__ inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 // ---------------------------------------------------------------- sparse (kernels_sparse.hip)
 
@@ -55,6 +56,11 @@ void extract_diag(const DevCSR& H, double* diag, hipStream_t s);
 // X float64 with float64 or float32-exact values.
 void spmm_f64(const DevCSR& H, const double* X, int64_t ldx, double* Y, int64_t ldy, int b,
               const double* shift, hipStream_t s);
+// Chebyshev filter step: Y = ea * (H X - ec X) + eb * Zo   (Zo must be non-null)
+void spmm_cheb(const DevCSR& H, const double* X, int64_t ldx, double* Y, int64_t ldy, int b, double ea,
+               double ec, double eb, const double* Zo, int64_t ldz, hipStream_t s);
+// max_i (h_ii + sum_{j != i} |h_ij|) into *out (device); tmp holds n doubles
+void gershgorin_upper(const DevCSR& H, double* tmp, double* out, hipStream_t s);
 // Mixed: float32 values and float32 X, float32 products accumulated in float64.
 void spmm_f32(const DevCSR& H, const float* X, int64_t ldx, double* Y, int64_t ldy, int b,
               const double* shift, hipStream_t s);
@@ -139,6 +145,11 @@ void select_smallest(int64_t n, const double* d, int nsel, int* idx, hipStream_t
 void unit_block(int64_t n, int b, const int* idx, double* X, int64_t ldx, hipStream_t s);
 
 // ---------------------------------------------------------------- small-space solver (kernels_cg.hip)
+int64_t cg_work_doubles(int64_t n0);
+// Deflated preconditioned CG for the k shifted small-space systems; b in r; returns iterations.
+int cg_solve(const DevCSR& H0, int64_t n0, int k, int D, const double* diag, const double* shift,
+             const double* Ps, double* x, double* r, double* z, double* p, double* q, double* work,
+             double* ccoef, int maxit, double tol, int* host_flag, hipStream_t s);
 void cg_precond(int64_t n0, int k, const double* diag, const double* shift, const double* r,
                 double* z, hipStream_t s);
 void cg_dots(int64_t n0, int k, const double* a, const double* b, double* out, double* work, hipStream_t s);

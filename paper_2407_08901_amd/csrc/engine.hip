@@ -118,8 +118,9 @@ struct sppc_ctx {
   double *Xt = nullptr, *Acoef = nullptr, *Bcoef = nullptr, *dots = nullptr, *work = nullptr;
   double* eigscr = nullptr;
   int *info = nullptr, *idx = nullptr, *mhist_dev = nullptr;
-  double *cx = nullptr, *cr = nullptr, *cz = nullptr, *cp = nullptr, *cq = nullptr, *ccoef = nullptr,
-         *ctmp = nullptr, *cvec = nullptr;
+  double *cx = nullptr, *cr = nullptr, *cz = nullptr, *cp = nullptr, *cp1 = nullptr, *cq = nullptr,
+         *ccoef = nullptr, *ctmp = nullptr, *cvec = nullptr, *cgpart = nullptr;
+  int cg_blocks = 1;
   int *cact = nullptr, *cnact = nullptr;
   double* Ghist = nullptr;
   int64_t gstride = 0;
@@ -152,7 +153,7 @@ struct Op {
   const DevCSR* A;
   bool mixed;
   float* X32;
-  int64_t* nspmv;
+  sppc_stats* st;
   void operator()(const double* X, int64_t ldx, double* Y, int64_t ldy, int b, hipStream_t s) const {
     if (mixed) {
       copy_to_f32(A->n, b, X, ldx, X32, b, s);
@@ -160,7 +161,11 @@ struct Op {
     } else {
       spmm_f64(*A, X, ldx, Y, ldy, b, nullptr, s);
     }
-    if (nspmv) *nspmv += b;
+    if (st) {
+      st->n_spmv += b;
+      st->spmm_calls += 1;
+      st->spmm_cols += b;
+    }
   }
 };
 
@@ -264,54 +269,67 @@ void jacobi_expansion(sppc_ctx* c, int64_t n, const double* diag, const std::vec
   sync(c);  // pin_i is reused by later steps
 }
 
-// The n_deflate lowest eigenpairs of H0hat by a block Davidson iteration with the
-// diagonal preconditioner, started from unit vectors at the smallest diagonal entries.
+// The n_deflate lowest eigenpairs of H0hat by Chebyshev-filtered subspace iteration: a block
+// of nb >= n_deflate vectors (started at unit vectors on the smallest diagonal entries) is
+// repeatedly multiplied by a Chebyshev polynomial of H0hat that damps [theta_nb, upper
+// Gershgorin bound] and grows what lies below, then Rayleigh-Ritz on the block.
 void zeroth_order(sppc_ctx* c) {
   hipStream_t s = c->s;
   const int64_t n0 = c->n0;
   const int D = c->D;
-  const int nev = std::min<int64_t>(std::min(D + 4, KB), n0);
+  const int nb = (int)std::min<int64_t>(n0, KB);
   Arena tmp;
   Basis sb;
   sb.n = n0;
-  sb.ldq = (int)std::min<int64_t>(n0, std::max(8 * nev, 128));
-  sb.ldq = std::min(sb.ldq, 512);
-  sb.Q = tmp.alloc<double>((size_t)n0 * sb.ldq);
-  sb.HQ = tmp.alloc<double>((size_t)n0 * sb.ldq);
-  sb.T = tmp.alloc<double>((size_t)sb.ldq * sb.ldq);
+  sb.ldq = nb;
+  sb.Q = tmp.alloc<double>((size_t)n0 * nb);
+  sb.HQ = tmp.alloc<double>((size_t)n0 * nb);
+  sb.T = tmp.alloc<double>((size_t)nb * nb);
   double* h0diag = tmp.alloc<double>(n0);
+  double* gtmp = tmp.alloc<double>(n0 + 1);
   copy_block(n0, 1, c->diag, 1, h0diag, 1, s);
+  gershgorin_upper(c->H0, gtmp, gtmp + n0, s);
+  double bup = 0.0;
+  SPPC_HIP(hipMemcpyAsync(c->pin, gtmp + n0, sizeof(double), hipMemcpyDeviceToHost, s));
+  sync(c);
+  bup = c->pin[0];
   Op op{&c->H0, false, nullptr, nullptr};
-  select_smallest(n0, h0diag, nev, c->idx, s);
-  unit_block(n0, nev, c->idx, c->Psi, nev, s);
-  ortho_append(c, sb, c->Psi, nev, op, -1);
+  select_smallest(n0, h0diag, nb, c->idx, s);
+  unit_block(n0, nb, c->idx, c->Psi, nb, s);
+  ortho_append(c, sb, c->Psi, nb, op, -1);
   const double tol = c->o.h0_tol;
+  const int deg = 24;
   int it = 0;
   for (;; ++it) {
-    const int nw = std::min(nev, sb.m);
+    const int nw = sb.m;
     rayleigh_ritz(c, sb, nw);
-    std::vector<int> act;
-    bool conv = nw >= D;
-    for (int i = 0; i < nw; ++i) {
-      const double res = std::sqrt(std::max(0.0, c->pin[NWMAX + i])) / std::max(1.0, std::fabs(c->theta_h[i]));
-      if (res > tol) {
-        act.push_back(i);
-        if (i < D) conv = false;
-      }
+    double worst = 0.0;
+    for (int i = 0; i < std::min(D, nw); ++i)
+      worst = std::max(worst, std::sqrt(std::max(0.0, c->pin[NWMAX + i])) / std::max(1.0, std::fabs(c->theta_h[i])));
+    if ((worst <= tol && nw >= D) || nw == n0) break;
+    if (it >= 400) throw Error(SPPC_E_BREAKDOWN, "eigensolver for H0hat did not converge");
+    // filter interval [a, bup], scaled so that the lowest Ritz value maps to ~1
+    const double a = c->theta_h[nw - 1], a0 = c->theta_h[0];
+    const double bb = std::max(bup, a + 1e-3 * std::max(1.0, std::fabs(a)));
+    const double e = 0.5 * (bb - a), cc = 0.5 * (bb + a);
+    double sigma = e / (a0 - cc);
+    const double tau = 2.0 / sigma;
+    double* buf[4] = {c->Z, c->Psi, c->R, c->HZ};
+    int i0 = 0, i1 = 1;  // Y_{j-1}, Y_j
+    // Y_1 = sigma/e (H - cc) Y_0  (Z holds the Ritz vectors, ld nw)
+    spmm_cheb(c->H0, buf[0], nw, buf[1], nw, nw, sigma / e, cc, 0.0, buf[0], nw, s);
+    for (int j = 2; j <= deg; ++j) {
+      const double sn = 1.0 / (tau - sigma);
+      int nxt = 0;
+      while (nxt == i0 || nxt == i1) ++nxt;
+      spmm_cheb(c->H0, buf[i1], nw, buf[nxt], nw, nw, 2.0 * sn / e, cc, -sigma * sn, buf[i0], nw, s);
+      i0 = i1;
+      i1 = nxt;
+      sigma = sn;
     }
-    if (conv || sb.m == n0) break;
-    if (it >= 2000) throw Error(SPPC_E_BREAKDOWN, "eigensolver for H0hat did not converge");
-    if (sb.m + (int)act.size() > sb.ldq) restart_basis(c, sb, nw);
-    jacobi_expansion(c, n0, h0diag, act, nw);
-    const int added = ortho_append(c, sb, c->Psi, (int)act.size(), op, -1);
-    if (added == 0) {
-      // no new direction: accept if the wanted pairs are close, else give up
-      double worst = 0.0;
-      for (int i = 0; i < std::min(D, nw); ++i)
-        worst = std::max(worst, std::sqrt(std::max(0.0, c->pin[NWMAX + i])) / std::max(1.0, std::fabs(c->theta_h[i])));
-      if (worst > 1e3 * tol) throw Error(SPPC_E_BREAKDOWN, "eigensolver for H0hat stagnated");
-      break;
-    }
+    sb.m = 0;
+    const int kept = ortho_append(c, sb, buf[i1], nw, op, -1);
+    if (kept < D) throw Error(SPPC_E_BREAKDOWN, "H0hat eigensolver lost directions in the filter");
   }
   c->st.h0_iterations = it;
   if (c->nw_last < D) throw Error(SPPC_E_ARG, "n_deflate exceeds the available eigenpairs of H0hat");
@@ -324,52 +342,15 @@ void zeroth_order(sppc_ctx* c) {
 }
 
 // Deflated CG on (H0hat - E_k) restricted to the complement of the deflated eigenvectors,
-// for all k columns at once, then the exact deflated terms: the minimum-norm solution of
-// eq. sm_lin_proj orthogonal to psi_k.  b1 in c->cr (n0 x k); result into Psi rows [0, n0).
+// for all k columns at once (one cooperative kernel), then the exact deflated terms: the
+// minimum-norm solution of eq. sm_lin_proj orthogonal to psi_k.  b1 in c->cr (n0 x k);
+// result into Psi rows [0, n0).
 void small_solve(sppc_ctx* c) {
   hipStream_t s = c->s;
   const int64_t n0 = c->n0;
   const int k = c->k, D = c->D;
-  double* rz = c->cvec;
-  double* rzn = c->cvec + KB;
-  double* pq = c->cvec + 2 * KB;
-  double* rr = c->cvec + 3 * KB;
-  double* bb = c->cvec + 4 * KB;
-  auto project = [&](double* X) {  // X <- (I - Psihat Psihat^T) X
-    gemm_tn(n0, D, k, c->Psihat, D, X, k, c->ctmp, k, 1.0, 0.0, c->work, s);
-    gemm_nn(n0, D, k, c->Psihat, D, c->ctmp, k, X, k, -1.0, 1.0, s);
-  };
-  gemm_tn(n0, D, k, c->Psihat, D, c->cr, k, c->ccoef, k, 1.0, 0.0, c->work, s);
-  gemm_nn(n0, D, k, c->Psihat, D, c->ccoef, k, c->cr, k, -1.0, 1.0, s);
-  cg_precond(n0, k, c->diag, c->E0, c->cr, c->cz, s);
-  project(c->cz);
-  copy_block(n0, k, c->cz, k, c->cp, k, s);
-  fill_block_zero(n0, k, c->cx, k, s);
-  coldots(n0, k, c->cr, k, c->cz, k, rz, c->work, s);
-  coldots(n0, k, c->cr, k, c->cr, k, bb, c->work, s);
-  cg_init(k, bb, c->cact, c->cnact, s);
-  const double tol2 = c->o.inner_tol * c->o.inner_tol;
-  const int maxit = 5000;
-  int it = 0;
-  for (it = 1; it <= maxit; ++it) {
-    spmm_f64(c->H0, c->cp, k, c->cq, k, k, c->E0, s);
-    project(c->cq);
-    coldots(n0, k, c->cp, k, c->cq, k, pq, c->work, s);
-    cg_update_xr(n0, k, c->cx, c->cr, c->cp, c->cq, rz, pq, c->cact, s);
-    coldots(n0, k, c->cr, k, c->cr, k, rr, c->work, s);
-    cg_check(k, rr, bb, tol2, c->cact, c->cnact, nullptr, nullptr, s);
-    if (it % 8 == 0) {
-      SPPC_HIP(hipMemcpyAsync(c->pin_i + 4, c->cnact, sizeof(int), hipMemcpyDeviceToHost, s));
-      sync(c);
-      if (c->pin_i[4] == 0) break;
-    }
-    cg_precond(n0, k, c->diag, c->E0, c->cr, c->cz, s);
-    project(c->cz);
-    coldots(n0, k, c->cr, k, c->cz, k, rzn, c->work, s);
-    cg_update_p(n0, k, c->cp, c->cz, rzn, rz, c->cact, s);
-    SPPC_HIP(hipMemcpyAsync(rz, rzn, sizeof(double) * k, hipMemcpyDeviceToDevice, s));
-  }
-  c->st.cg_iterations += std::min(it, maxit);
+  c->st.cg_iterations += cg_solve(c->H0, n0, k, D, c->diag, c->E0, c->Psihat, c->cx, c->cr, c->cz, c->cp,
+                                  c->cq, c->cgpart, c->ccoef, 5000, c->o.inner_tol, c->pin_i + 4, s);
   deflate_coefs(D, k, c->E0, c->ccoef, k, c->ctmp, k, s);
   gemm_nn(n0, D, k, c->Psihat, D, c->ctmp, k, c->cx, k, 1.0, 1.0, s);
   copy_block(n0, k, c->cx, k, c->Psi, k, s);
@@ -423,7 +404,7 @@ void correct_continuation(sppc_ctx* c, int kind) {
 
 int append_and_rr(sppc_ctx* c) {
   Basis& b = c->B;
-  Op op{&c->H, c->o.precision == SPPC_PREC_MIXED, c->X32, &c->st.n_spmv};
+  Op op{&c->H, c->o.precision == SPPC_PREC_MIXED, c->X32, &c->st};
   int added = 0;
   if (c->pend_b > 0) {
     const bool pert = c->pend_kind == SPPC_CORR_PERTURBATIVE;
@@ -447,6 +428,8 @@ void final_check(sppc_ctx* c) {
   size_t t0 = c->tm.begin(C_SPMM);
   spmm_f64(c->H, c->Z, k, c->Wb, k, k, nullptr, s);
   c->st.n_spmv += k;
+  c->st.spmm_calls += 1;
+  c->st.spmm_cols += k;
   c->tm.end(t0);
   t0 = c->tm.begin(C_RR);
   gemm_tn(n, k, k, c->Z, k, c->Wb, k, c->Gm, k, 1.0, 0.0, c->work, s);
@@ -573,7 +556,8 @@ void setup_impl(sppc_ctx* c, const sppc_csr* Hin, const int64_t* loff, int L, in
   c->psi2 = A.alloc<double>(KB);
   c->angles = A.alloc<double>(KB);
   c->dots = A.alloc<double>(KB);
-  c->work = A.alloc<double>((size_t)std::max<int64_t>(gemm_tn_work(n, mbig, KB), 2 * cdiv(n, 4096) * KB + KB + 64));
+  c->work = A.alloc<double>((size_t)std::max({gemm_tn_work(n, mbig, KB), gemm_tn_work(c->n0, mbig, KB),
+                                               2 * cdiv(n, 256) * KB + KB + 64}));
   c->eigscr = A.alloc<double>((size_t)eig_scratch(mbig, NWMAX));
   c->info = A.alloc<int>(8);
   c->idx = A.alloc<int>(64);
@@ -590,6 +574,8 @@ void setup_impl(sppc_ctx* c, const sppc_csr* Hin, const int64_t* loff, int L, in
   c->cz = A.alloc<double>((size_t)n0 * KB);
   c->cp = A.alloc<double>((size_t)n0 * KB);
   c->cq = A.alloc<double>((size_t)n0 * KB);
+  c->cp1 = A.alloc<double>((size_t)n0 * KB);
+  c->cgpart = A.alloc<double>((size_t)cg_work_doubles(n0));
   c->ccoef = A.alloc<double>((size_t)KB * KB);
   c->ctmp = A.alloc<double>((size_t)KB * KB);
   c->cvec = A.alloc<double>(8 * KB);
@@ -610,7 +596,7 @@ void setup_impl(sppc_ctx* c, const sppc_csr* Hin, const int64_t* loff, int L, in
   Basis& b = c->B;
   fill_block_zero(n, k, b.Q, b.ldq, s);
   copy_block(n0, k, c->Psihat, c->D, b.Q, b.ldq, s);
-  Op op{&c->H, mixed, c->X32, &c->st.n_spmv};
+  Op op{&c->H, mixed, c->X32, &c->st};
   size_t t0 = c->tm.begin(C_SPMM);
   op(b.Q, b.ldq, b.HQ, b.ldq, k, s);
   c->tm.end(t0);

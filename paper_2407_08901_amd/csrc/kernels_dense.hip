@@ -10,22 +10,26 @@ namespace sppc {
 
 namespace {
 
-constexpr int TN_CHUNK = 2048;  // rows per partial sum in gemm_tn
+// rows per partial sum in gemm_tn: enough chunks to fill the chip, at most 2048 rows each
+inline int64_t tn_chunk(int64_t n) {
+  int64_t c = (n / 512 + 31) / 32 * 32;
+  return c < 32 ? 32 : (c > 2048 ? 2048 : c);
+}
 constexpr int TN_MT = 64;       // columns of A per block
 constexpr int TN_RT = 32;       // rows per LDS tile
 
 // partial[chunk][i][j] = sum_{r in chunk} A[r][i0+i] B[r][j]
 __global__ __launch_bounds__(256) void k_gemm_tn(int64_t n, int m, int b, const double* __restrict__ A,
                                                  int64_t lda, const double* __restrict__ B, int64_t ldb,
-                                                 double* __restrict__ part) {
+                                                 double* __restrict__ part, int64_t chunk) {
   __shared__ double As[TN_RT][TN_MT];
   __shared__ double Bs[TN_RT][33];
   const int t = threadIdx.x;
   const int i = t & 63;
   const int jg = t >> 6;
   const int i0 = blockIdx.y * TN_MT;
-  const int64_t r0 = (int64_t)blockIdx.x * TN_CHUNK;
-  const int64_t r1 = min<int64_t>(n, r0 + TN_CHUNK);
+  const int64_t r0 = (int64_t)blockIdx.x * chunk;
+  const int64_t r1 = min<int64_t>(n, r0 + chunk);
   double acc[8];
 #pragma unroll
   for (int q = 0; q < 8; ++q) acc[q] = 0.0;
@@ -64,15 +68,21 @@ __global__ __launch_bounds__(256) void k_gemm_tn(int64_t n, int m, int b, const 
   }
 }
 
+// one wave per output element: lanes stride over the chunks, fixed-order tree sum
 __global__ void k_reduce_partials(int64_t nchunks, int m, int b, const double* __restrict__ part,
                                   double* __restrict__ C, int64_t ldc, double alpha, double beta) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t e = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
   if (e >= (int64_t)m * b) return;
-  const int i = (int)(e / b), j = (int)(e % b);
+  const int64_t mb = (int64_t)m * b;
   double s = 0.0;
-  for (int64_t c = 0; c < nchunks; ++c) s += part[c * m * b + e];
-  double* dst = C + (int64_t)i * ldc + j;
-  *dst = beta == 0.0 ? alpha * s : beta * (*dst) + alpha * s;
+  for (int64_t c = lane; c < nchunks; c += 64) s += part[c * mb + e];
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+  if (lane == 0) {
+    const int i = (int)(e / b), j = (int)(e % b);
+    double* dst = C + (int64_t)i * ldc + j;
+    *dst = beta == 0.0 ? alpha * s : beta * (*dst) + alpha * s;
+  }
 }
 
 constexpr int NN_RB = 64;  // rows per block
@@ -128,7 +138,11 @@ __global__ __launch_bounds__(256) void k_gemm_nn(int64_t n, int m, int b, const 
 }
 
 // ---------------------------------------------------------------- column reductions
-constexpr int CR_CHUNK = 4096;
+// rows per partial sum of the column reductions
+inline int64_t cr_chunk(int64_t n) {
+  int64_t c = (n / 256 + 255) / 256 * 256;
+  return c < 256 ? 256 : (c > 4096 ? 4096 : c);
+}
 
 // mode 0: sum X^2 ; mode 1: R = HZ - Z theta and sum R^2 ; mode 2: sum Z[:,idx[a]] * T[:,a]
 template <int MODE>
@@ -136,13 +150,13 @@ __global__ __launch_bounds__(256) void k_colreduce(int64_t n, int b, const doubl
                                                    int64_t ldx, const double* __restrict__ Y,
                                                    int64_t ldy, const double* __restrict__ theta,
                                                    const int* __restrict__ idx, double* __restrict__ R,
-                                                   int64_t ldr, double* __restrict__ part) {
+                                                   int64_t ldr, double* __restrict__ part, int64_t chunk) {
   __shared__ double sh[256];
   const int t = threadIdx.x;
   const int B2 = b <= 1 ? 1 : b <= 2 ? 2 : b <= 4 ? 4 : b <= 8 ? 8 : b <= 16 ? 16 : 32;
   const int tc = t % B2, tr = t / B2, nrt = 256 / B2;
-  const int64_t r0 = (int64_t)blockIdx.x * CR_CHUNK;
-  const int64_t r1 = min<int64_t>(n, r0 + CR_CHUNK);
+  const int64_t r0 = (int64_t)blockIdx.x * chunk;
+  const int64_t r1 = min<int64_t>(n, r0 + chunk);
   double s = 0.0;
   if (tc < b) {
     for (int64_t r = r0 + tr; r < r1; r += nrt) {
@@ -168,13 +182,16 @@ __global__ __launch_bounds__(256) void k_colreduce(int64_t n, int b, const doubl
   if (t < b) part[(int64_t)blockIdx.x * b + t] = sh[t];
 }
 
+// one wave per column, lanes stride over the chunks, fixed-order tree sum
 __global__ void k_colreduce_final(int64_t nchunks, int b, const double* __restrict__ part,
                                   double* __restrict__ out) {
-  const int j = threadIdx.x;
+  const int j = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
   if (j >= b) return;
   double s = 0.0;
-  for (int64_t c = 0; c < nchunks; ++c) s += part[c * b + j];
-  out[j] = s;
+  for (int64_t c = lane; c < nchunks; c += 64) s += part[c * b + j];
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+  if (lane == 0) out[j] = s;
 }
 
 __global__ void k_copy_block(int64_t n, int b, const double* __restrict__ X, int64_t ldx,
@@ -249,20 +266,21 @@ inline int64_t grid1(int64_t count) { return cdiv(count > 0 ? count : 1, 256); }
 
 }  // namespace
 
-int64_t gemm_tn_work(int64_t n, int m, int b) { return cdiv(n > 0 ? n : 1, TN_CHUNK) * (int64_t)m * b; }
+int64_t gemm_tn_work(int64_t n, int m, int b) { return cdiv(n > 0 ? n : 1, tn_chunk(n)) * (int64_t)m * b; }
 
 void gemm_tn(int64_t n, int m, int b, const double* A, int64_t lda, const double* B, int64_t ldb,
              double* C, int64_t ldc, double alpha, double beta, double* work, hipStream_t s) {
   if (m <= 0 || b <= 0) return;
   if (b > 32) throw Error(1, "gemm_tn: b must be <= 32");
-  const int64_t nch = cdiv(n > 0 ? n : 1, TN_CHUNK);
+  const int64_t chunk = tn_chunk(n);
+  const int64_t nch = cdiv(n > 0 ? n : 1, chunk);
   if (n > 0) {
     dim3 grid((unsigned)nch, (unsigned)cdiv(m, TN_MT));
-    k_gemm_tn<<<grid, 256, 0, s>>>(n, m, b, A, lda, B, ldb, work);
+    k_gemm_tn<<<grid, 256, 0, s>>>(n, m, b, A, lda, B, ldb, work, chunk);
   } else {
     k_fill_zero<<<grid1((int64_t)m * b), 256, 0, s>>>((int64_t)m * b, work);
   }
-  k_reduce_partials<<<grid1((int64_t)m * b), 256, 0, s>>>(nch, m, b, work, C, ldc, alpha, beta);
+  k_reduce_partials<<<cdiv((int64_t)m * b, 4), 256, 0, s>>>(nch, m, b, work, C, ldc, alpha, beta);
   SPPC_LAUNCH_CHECK();
 }
 
@@ -294,24 +312,24 @@ void fill_zero(int64_t count, double* p, hipStream_t s) {
 void residual_block(int64_t n, int b, const double* Z, int64_t ldz, const double* HZ, int64_t ldhz,
                     const double* theta, double* R, int64_t ldr, double* sumsq, double* work,
                     hipStream_t s) {
-  const int64_t nch = cdiv(n > 0 ? n : 1, CR_CHUNK);
-  k_colreduce<1><<<nch, 256, 0, s>>>(n, b, Z, ldz, HZ, ldhz, theta, nullptr, R, ldr, work);
-  k_colreduce_final<<<1, 64, 0, s>>>(nch, b, work, sumsq);
+  const int64_t ch = cr_chunk(n), nch = cdiv(n > 0 ? n : 1, ch);
+  k_colreduce<1><<<nch, 256, 0, s>>>(n, b, Z, ldz, HZ, ldhz, theta, nullptr, R, ldr, work, ch);
+  k_colreduce_final<<<cdiv(b, 4), 256, 0, s>>>(nch, b, work, sumsq);
   SPPC_LAUNCH_CHECK();
 }
 
 void colsumsq(int64_t n, int b, const double* X, int64_t ldx, double* out, double* work, hipStream_t s) {
-  const int64_t nch = cdiv(n > 0 ? n : 1, CR_CHUNK);
-  k_colreduce<0><<<nch, 256, 0, s>>>(n, b, X, ldx, nullptr, 0, nullptr, nullptr, nullptr, 0, work);
-  k_colreduce_final<<<1, 64, 0, s>>>(nch, b, work, out);
+  const int64_t ch = cr_chunk(n), nch = cdiv(n > 0 ? n : 1, ch);
+  k_colreduce<0><<<nch, 256, 0, s>>>(n, b, X, ldx, nullptr, 0, nullptr, nullptr, nullptr, 0, work, ch);
+  k_colreduce_final<<<cdiv(b, 4), 256, 0, s>>>(nch, b, work, out);
   SPPC_LAUNCH_CHECK();
 }
 
 void paired_dots(int64_t n, int na, const int* idx, const double* Z, int64_t ldz, const double* T,
                  int64_t ldt, double* dots, double* work, hipStream_t s) {
-  const int64_t nch = cdiv(n > 0 ? n : 1, CR_CHUNK);
-  k_colreduce<2><<<nch, 256, 0, s>>>(n, na, Z, ldz, T, ldt, nullptr, idx, nullptr, 0, work);
-  k_colreduce_final<<<1, 64, 0, s>>>(nch, na, work, dots);
+  const int64_t ch = cr_chunk(n), nch = cdiv(n > 0 ? n : 1, ch);
+  k_colreduce<2><<<nch, 256, 0, s>>>(n, na, Z, ldz, T, ldt, nullptr, idx, nullptr, 0, work, ch);
+  k_colreduce_final<<<cdiv(na, 4), 256, 0, s>>>(nch, na, work, dots);
   SPPC_LAUNCH_CHECK();
 }
 
@@ -346,13 +364,13 @@ namespace {
 
 __global__ __launch_bounds__(256) void k_coldots(int64_t n, int b, const double* __restrict__ X,
                                                  int64_t ldx, const double* __restrict__ Y, int64_t ldy,
-                                                 double* __restrict__ part) {
+                                                 double* __restrict__ part, int64_t chunk) {
   __shared__ double sh[256];
   const int t = threadIdx.x;
   const int B2 = b <= 1 ? 1 : b <= 2 ? 2 : b <= 4 ? 4 : b <= 8 ? 8 : b <= 16 ? 16 : 32;
   const int tc = t % B2, tr = t / B2, nrt = 256 / B2;
-  const int64_t r0 = (int64_t)blockIdx.x * CR_CHUNK;
-  const int64_t r1 = min<int64_t>(n, r0 + CR_CHUNK);
+  const int64_t r0 = (int64_t)blockIdx.x * chunk;
+  const int64_t r1 = min<int64_t>(n, r0 + chunk);
   double s = 0.0;
   if (tc < b)
     for (int64_t r = r0 + tr; r < r1; r += nrt) s = fma(X[r * ldx + tc], Y[r * ldy + tc], s);
@@ -430,9 +448,9 @@ __global__ void k_cg_init(int k, const double* __restrict__ bb, int* __restrict_
 
 void coldots(int64_t n, int b, const double* X, int64_t ldx, const double* Y, int64_t ldy, double* out,
              double* work, hipStream_t s) {
-  const int64_t nch = cdiv(n > 0 ? n : 1, CR_CHUNK);
-  k_coldots<<<nch, 256, 0, s>>>(n, b, X, ldx, Y, ldy, work);
-  k_colreduce_final<<<1, 64, 0, s>>>(nch, b, work, out);
+  const int64_t ch = cr_chunk(n), nch = cdiv(n > 0 ? n : 1, ch);
+  k_coldots<<<nch, 256, 0, s>>>(n, b, X, ldx, Y, ldy, work, ch);
+  k_colreduce_final<<<cdiv(b, 4), 256, 0, s>>>(nch, b, work, out);
   SPPC_LAUNCH_CHECK();
 }
 

@@ -9,6 +9,7 @@ namespace sppc {
 namespace {
 
 constexpr int EIG_THREADS = 1024;
+constexpr int EIG_LDS_M = 128;
 
 __device__ inline double block_sum(double v, double* sh) {
   // sh: >= 16 doubles; all threads of the (1024-thread) block call this
@@ -99,9 +100,10 @@ __global__ __launch_bounds__(EIG_THREADS) void k_sym_eig(int m, int nw, const do
   __shared__ double wsh[512];
   __shared__ double red[16];
   __shared__ double sc[4];
+  __shared__ double Alds[EIG_LDS_M * EIG_LDS_M];  // the working matrix when it fits
   const int t = threadIdx.x;
-  double* A = scr;
-  double* d = A + (int64_t)m * m;
+  double* A = m <= EIG_LDS_M ? Alds : scr;
+  double* d = scr + (int64_t)m * m;
   double* e = d + m;
   double* e2 = e + m;
   double* beta = e2 + m;
@@ -148,9 +150,17 @@ __global__ __launch_bounds__(EIG_THREADS) void k_sym_eig(int m, int nw, const do
       const int grp = t >> 8, tl = t & 255;
       const int l0 = (len * grp) / 4, l1 = (len * (grp + 1)) / 4;
       for (int i = tl; i < len; i += 256) {
-        double s = 0.0;
-        for (int l = l0; l < l1; ++l) s += A[(int64_t)(j + 1 + l) * m + j + 1 + i] * vsh[l];
-        psh[grp][i] = s;
+        const double* col = A + (int64_t)(j + 1) * m + j + 1 + i;
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        int l = l0;
+        for (; l + 3 < l1; l += 4) {
+          s0 += col[(int64_t)l * m] * vsh[l];
+          s1 += col[(int64_t)(l + 1) * m] * vsh[l + 1];
+          s2 += col[(int64_t)(l + 2) * m] * vsh[l + 2];
+          s3 += col[(int64_t)(l + 3) * m] * vsh[l + 3];
+        }
+        for (; l < l1; ++l) s0 += col[(int64_t)l * m] * vsh[l];
+        psh[grp][i] = (s0 + s1) + (s2 + s3);
       }
       __syncthreads();
       double kp = 0.0;
@@ -185,73 +195,98 @@ __global__ __launch_bounds__(EIG_THREADS) void k_sym_eig(int m, int nw, const do
   for (int i = t; i < m; i += EIG_THREADS) e2[i] = e[i] * e[i];
   __syncthreads();
 
-  // ---- eigenvalues by bisection (one thread per wanted eigenvalue)
-  double lo = 0.0, hi = 0.0, tnorm = 0.0, maxe2 = 0.0;
-  if (t < nw) {
-    lo = d[0]; hi = d[0];
-    for (int i = 0; i < m; ++i) {
-      const double r = (i > 0 ? fabs(e[i - 1]) : 0.0) + (i < m - 1 ? fabs(e[i]) : 0.0);
-      lo = fmin(lo, d[i] - r);
-      hi = fmax(hi, d[i] + r);
-      if (i < m - 1) maxe2 = fmax(maxe2, e2[i]);
-    }
-    tnorm = fmax(fabs(lo), fabs(hi));
-    const double pivmin = 2.2250738585072014e-308 * fmax(1.0, maxe2);
-    double a = lo - 1e-14 * tnorm - 1e-300, bb = hi + 1e-14 * tnorm + 1e-300;
-    for (int it = 0; it < 200; ++it) {
-      const double mid = 0.5 * (a + bb);
-      if (bb - a <= 2.220446049250313e-16 * fmax(fabs(a), fabs(bb)) + pivmin || mid == a || mid == bb) break;
-      if (sturm_count(m, d, e2, mid, pivmin) <= t) a = mid; else bb = mid;
-    }
-    wsh[t] = 0.5 * (a + bb);
-    sc[2] = tnorm;
+  // ---- eigenvalues by bisection (one thread per wanted eigenvalue); d, e, e2 copied to LDS
+  double* dl = psh[0];
+  double* el = psh[1];
+  double* e2l = psh[2];
+  for (int i = t; i < m; i += EIG_THREADS) {
+    dl[i] = d[i];
+    el[i] = e[i];
+    e2l[i] = e2[i];
   }
-  __syncthreads();
   if (t == 0) {
-    // tnorm from thread 0 was written last by some thread; recompute safely
     double tn = 0.0;
     for (int i = 0; i < m; ++i)
       tn = fmax(tn, fabs(d[i]) + (i > 0 ? fabs(e[i - 1]) : 0.0) + (i < m - 1 ? fabs(e[i]) : 0.0));
     sc[2] = fmax(tn, 1e-300);
   }
   __syncthreads();
-
-  // ---- eigenvectors of the tridiagonal by inverse iteration; members of a cluster
-  //      are computed one after another and orthogonalised against each other.
+  const double tn = sc[2];
   if (t < nw) {
-    const double tn = sc[2];
+    double lo = dl[0], hi = dl[0], maxe2 = 0.0;
+    for (int i = 0; i < m; ++i) {
+      const double r = (i > 0 ? fabs(el[i - 1]) : 0.0) + (i < m - 1 ? fabs(el[i]) : 0.0);
+      lo = fmin(lo, dl[i] - r);
+      hi = fmax(hi, dl[i] + r);
+      if (i < m - 1) maxe2 = fmax(maxe2, e2l[i]);
+    }
+    const double pivmin = 2.2250738585072014e-308 * fmax(1.0, maxe2);
+    double a = lo - 1e-14 * tn - 1e-300, bb = hi + 1e-14 * tn + 1e-300;
+    for (int it = 0; it < 200; ++it) {
+      const double mid = 0.5 * (a + bb);
+      if (bb - a <= 2.220446049250313e-16 * fmax(fabs(a), fabs(bb)) + pivmin || mid == a || mid == bb) break;
+      if (sturm_count(m, dl, e2l, mid, pivmin) <= t) a = mid; else bb = mid;
+    }
+    wsh[t] = 0.5 * (a + bb);
+  }
+  __syncthreads();
+
+  // ---- eigenvectors of the tridiagonal by inverse iteration, one thread per vector
+  const double epsp = 2.220446049250313e-16 * tn;
+  if (t < nw) {
+    double* y = Y + (int64_t)t * m;
+    double lam = wsh[t];
+    // repeated eigenvalues: separate the shifts slightly so the vectors differ
+    int rep = 0;
+    for (int c2 = t - 1; c2 >= 0 && wsh[t] - wsh[c2] < 10.0 * epsp; --c2) ++rep;
+    lam += 10.0 * epsp * rep;
+    uint32_t h = 0x9E3779B9u * (uint32_t)(t + 1);
+    for (int i = 0; i < m; ++i) {
+      h ^= h << 13; h ^= h >> 17; h ^= h << 5;
+      y[i] = 0.5 + (double)(h & 0xFFFFFF) / (double)0x1000000;
+    }
+    double* U0 = u0 + (int64_t)t * m;
+    double* U1 = u1 + (int64_t)t * m;
+    double* U2 = u2 + (int64_t)t * m;
+    double* Lm = lm + (int64_t)t * m;
+    unsigned char* Pv = piv + (int64_t)t * m;
+    for (int it = 0; it < 3; ++it) {
+      tri_shifted_solve(m, dl, el, lam, epsp, U0, U1, U2, Lm, Pv, y, it == 0);
+      normalize(m, y);
+    }
+  }
+  __syncthreads();
+  // vectors of close eigenvalues: classical Gram-Schmidt twice against the earlier members
+  // of their cluster (the whole block works on one vector at a time)
+  {
     const double ctol = 1e-3 * tn;
-    const double epsp = 2.220446049250313e-16 * tn;
-    const bool first = (t == 0) || (wsh[t] - wsh[t - 1] > ctol);
-    if (first) {
-      int last = t;
-      while (last + 1 < nw && wsh[last + 1] - wsh[last] <= ctol) ++last;
-      for (int c = t; c <= last; ++c) {
-        double* y = Y + (int64_t)c * m;
-        double* U0 = u0 + (int64_t)c * m;
-        double* U1 = u1 + (int64_t)c * m;
-        double* U2 = u2 + (int64_t)c * m;
-        double* Lm = lm + (int64_t)c * m;
-        unsigned char* P = piv + (int64_t)c * m;
-        // perturb repeated eigenvalues slightly so the factorisations differ
-        double lam = wsh[c];
-        if (c > t && lam - wsh[c - 1] < 10.0 * epsp) lam = wsh[c - 1] + 10.0 * epsp;
-        uint32_t h = 0x9E3779B9u * (uint32_t)(c + 1);
-        for (int i = 0; i < m; ++i) {
-          h ^= h << 13; h ^= h >> 17; h ^= h << 5;
-          y[i] = 0.5 + (double)(h & 0xFFFFFF) / (double)0x1000000;
+    const int wv = t >> 6, ln = t & 63;
+    for (int c = 1; c < nw; ++c) {
+      int c0 = c;
+      while (c0 > 0 && wsh[c0] - wsh[c0 - 1] <= ctol) --c0;
+      if (c0 == c) continue;  // uniform across the block
+      double* y = Y + (int64_t)c * m;
+      for (int pass = 0; pass < 2; ++pass) {
+        // dots with the previous members: one wave per member
+        for (int c2 = c0 + wv; c2 < c; c2 += EIG_THREADS / 64) {
+          const double* y2 = Y + (int64_t)c2 * m;
+          double sdot = 0.0;
+          for (int i = ln; i < m; i += 64) sdot += y[i] * y2[i];
+          for (int o = 32; o > 0; o >>= 1) sdot += __shfl_xor(sdot, o);
+          if (ln == 0) vsh[c2] = sdot;
         }
-        for (int it = 0; it < 4; ++it) {
-          tri_shifted_solve(m, d, e, lam, epsp, U0, U1, U2, Lm, P, y, it == 0);
-          normalize(m, y);
-          for (int c2 = t; c2 < c; ++c2) {
-            const double* y2 = Y + (int64_t)c2 * m;
-            double s = 0.0;
-            for (int i = 0; i < m; ++i) s += y[i] * y2[i];
-            for (int i = 0; i < m; ++i) y[i] -= s * y2[i];
-          }
-          normalize(m, y);
+        __syncthreads();
+        for (int i = t; i < m; i += EIG_THREADS) {
+          double v = y[i];
+          for (int c2 = c0; c2 < c; ++c2) v -= vsh[c2] * Y[(int64_t)c2 * m + i];
+          y[i] = v;
         }
+        __syncthreads();
+        double part = 0.0;
+        for (int i = t; i < m; i += EIG_THREADS) part += y[i] * y[i];
+        const double nrm = sqrt(block_sum(part, red));
+        for (int i = t; i < m; i += EIG_THREADS) y[i] = nrm > 0.0 ? y[i] / nrm : 0.0;
+        __syncthreads();
       }
     }
   }
@@ -298,47 +333,68 @@ __global__ __launch_bounds__(EIG_THREADS) void k_sym_eig(int m, int nw, const do
 // ---------------------------------------------------------------- Cholesky-QR factors
 constexpr int KB = 32;
 
-// Pivoted Cholesky of G restricted to the columns whose angle exceeds tau.
-__global__ void k_cholqr_first(int b, const double* __restrict__ G, const double* __restrict__ psi2,
-                               double tau, double* __restrict__ M, double* __restrict__ Rfac,
-                               double* __restrict__ angles, int* __restrict__ info) {
-  if (threadIdx.x != 0) return;
-  double W[KB][KB];
-  double L[KB][KB];
-  int perm[KB];
-  bool cand[KB];
-  for (int i = 0; i < b; ++i) {
-    for (int j = 0; j < b; ++j) { W[i][j] = G[i * b + j]; L[i][j] = 0.0; }
-    const double pn = psi2[i] > 0.0 ? psi2[i] : 1.0;
-    const double a = sqrt(fmax(G[i * b + i], 0.0) / pn);
-    angles[i] = a;
-    cand[i] = a > tau;
+// Pivoted Cholesky of G restricted to the columns whose angle exceeds tau (one wave, LDS).
+__global__ __launch_bounds__(64) void k_cholqr_first(int b, const double* __restrict__ G,
+                                                     const double* __restrict__ psi2, double tau,
+                                                     double* __restrict__ M, double* __restrict__ Rfac,
+                                                     double* __restrict__ angles, int* __restrict__ info) {
+  __shared__ double W[KB][KB + 1];
+  __shared__ double L[KB][KB + 1];
+  __shared__ double Ri[KB][KB + 1];
+  __shared__ int perm[KB];
+  __shared__ int cand[KB];
+  __shared__ int best_sh, stop_sh;
+  __shared__ double r_sh;
+  const int t = threadIdx.x;
+  for (int e = t; e < b * b; e += 64) {
+    W[e / b][e % b] = G[e];
+    L[e / b][e % b] = 0.0;
   }
+  if (t < b) {
+    const double pn = psi2[t] > 0.0 ? psi2[t] : 1.0;
+    const double a = sqrt(fmax(G[t * b + t], 0.0) / pn);
+    angles[t] = a;
+    cand[t] = a > tau;
+  }
+  __syncthreads();
   int s = 0;
   while (s < b) {
-    int best = -1;
-    double bv = 0.0;
-    for (int i = 0; i < b; ++i)
-      if (cand[i] && W[i][i] > bv) { bv = W[i][i]; best = i; }
-    if (best < 0) break;
-    const double pn = psi2[best] > 0.0 ? psi2[best] : 1.0;
-    if (!(bv > tau * tau * pn)) break;
-    const double r = sqrt(bv);
-    cand[best] = false;
-    perm[s] = best;
-    for (int i = 0; i < b; ++i) L[i][s] = (cand[i] || i == best) ? W[i][best] / r : 0.0;
-    for (int i = 0; i < b; ++i) {
-      if (!cand[i]) continue;
-      for (int j = 0; j < b; ++j)
-        if (cand[j]) W[i][j] -= L[i][s] * L[j][s];
+    if (t == 0) {
+      int best = -1;
+      double bv = 0.0;
+      for (int i = 0; i < b; ++i)
+        if (cand[i] && W[i][i] > bv) { bv = W[i][i]; best = i; }
+      int stop = best < 0;
+      if (!stop) {
+        const double pn = psi2[best] > 0.0 ? psi2[best] : 1.0;
+        stop = !(bv > tau * tau * pn);
+      }
+      best_sh = best;
+      stop_sh = stop;
+      r_sh = stop ? 1.0 : sqrt(bv);
     }
+    __syncthreads();
+    if (stop_sh) break;
+    const int best = best_sh;
+    const double r = r_sh;
+    if (t < b) L[t][s] = (cand[t] || t == best) ? W[t][best] / r : 0.0;
+    __syncthreads();
+    if (t == 0) {
+      cand[best] = 0;
+      perm[s] = best;
+    }
+    __syncthreads();
+    for (int e = t; e < b * b; e += 64) {
+      const int i = e / b, j = e % b;
+      if (cand[i] && cand[j]) W[i][j] -= L[i][s] * L[j][s];
+    }
+    __syncthreads();
     ++s;
   }
-  // R1[a][c] = L[perm[c]][a] (upper triangular, s x s);  inverse by back substitution
-  double Ri[KB][KB];
-  for (int a = 0; a < s; ++a)
-    for (int c = 0; c < s; ++c) Ri[a][c] = 0.0;
-  for (int c = 0; c < s; ++c) {
+  // R1[a][c] = L[perm[c]][a]; column c of R1^-1 by back substitution (one lane per column)
+  if (t < s) {
+    const int c = t;
+    for (int a = 0; a < s; ++a) Ri[a][c] = 0.0;
     Ri[c][c] = 1.0 / L[perm[c]][c];
     for (int a = c - 1; a >= 0; --a) {
       double acc = 0.0;
@@ -346,57 +402,72 @@ __global__ void k_cholqr_first(int b, const double* __restrict__ G, const double
       Ri[a][c] = -acc / L[perm[a]][a];
     }
   }
-  for (int i = 0; i < b; ++i)
-    for (int c = 0; c < b; ++c) M[i * b + c] = 0.0;
-  for (int a = 0; a < s; ++a)
-    for (int c = 0; c < s; ++c) M[perm[a] * b + c] = Ri[a][c];
-  // Rfac (s x b): Phi[:, j] ~= Phi1 Rfac[:, j]; Rfac[a][j] = L[j][a] for kept or eliminated j
-  for (int a = 0; a < b; ++a)
-    for (int j = 0; j < b; ++j) Rfac[a * b + j] = (a < s) ? L[j][a] : 0.0;
-  // columns never eliminated (dropped by angle) contribute nothing
-  info[0] = s;
-  info[1] = 0;
+  __syncthreads();
+  for (int e = t; e < b * b; e += 64) M[e] = 0.0;
+  __syncthreads();
+  for (int e = t; e < s * s; e += 64) {
+    const int a = e / s, c = e % s;
+    M[perm[a] * b + c] = Ri[a][c];
+  }
+  // Rfac (b x b, rows >= s zero): Phi[:, j] ~= Phi1 Rfac[:, j]
+  for (int e = t; e < b * b; e += 64) {
+    const int a = e / b, j = e % b;
+    Rfac[e] = (a < s) ? L[j][a] : 0.0;
+  }
+  if (t == 0) {
+    info[0] = s;
+    info[1] = 0;
+  }
 }
 
 // Cholesky of G2 (s x s, leading dim b), M2 = R2^-1 (ld b), Rfac <- R2 * Rfac (s x b).
-__global__ void k_cholqr_second(int b, const double* __restrict__ G2, double* __restrict__ M2,
-                                double* __restrict__ Rfac, int* __restrict__ info) {
-  if (threadIdx.x != 0) return;
+__global__ __launch_bounds__(64) void k_cholqr_second(int b, const double* __restrict__ G2,
+                                                      double* __restrict__ M2, double* __restrict__ Rfac,
+                                                      int* __restrict__ info) {
+  __shared__ double R[KB][KB + 1];
+  __shared__ double Mi[KB][KB + 1];
+  __shared__ double F[KB][KB + 1];
+  __shared__ int fail_sh;
+  const int t = threadIdx.x;
   const int s = info[0];
-  double R[KB][KB];
-  int fail = 0;
-  for (int i = 0; i < s; ++i)
-    for (int j = 0; j < s; ++j) R[i][j] = 0.0;
+  for (int e = t; e < KB * KB; e += 64) R[e / KB][e % KB] = 0.0;
+  if (t == 0) fail_sh = 0;
+  __syncthreads();
   for (int j = 0; j < s; ++j) {
-    double dsum = G2[j * b + j];
-    for (int q = 0; q < j; ++q) dsum -= R[q][j] * R[q][j];
-    if (!(dsum > 0.0)) { fail = 1; dsum = 1e-300; }
-    R[j][j] = sqrt(dsum);
-    for (int i = j + 1; i < s; ++i) {
-      double v = G2[j * b + i];
-      for (int q = 0; q < j; ++q) v -= R[q][j] * R[q][i];
-      R[j][i] = v / R[j][j];
+    if (t == 0) {
+      double dsum = G2[j * b + j];
+      for (int q = 0; q < j; ++q) dsum -= R[q][j] * R[q][j];
+      if (!(dsum > 0.0)) { fail_sh = 1; dsum = 1e-300; }
+      R[j][j] = sqrt(dsum);
     }
+    __syncthreads();
+    if (t > j && t < s) {
+      double v = G2[j * b + t];
+      for (int q = 0; q < j; ++q) v -= R[q][j] * R[q][t];
+      R[j][t] = v / R[j][j];
+    }
+    __syncthreads();
   }
-  for (int c = 0; c < s; ++c) {
-    for (int a = 0; a < s; ++a) M2[a * b + c] = 0.0;
-    M2[c * b + c] = 1.0 / R[c][c];
+  if (t < s) {
+    const int c = t;
+    for (int a = 0; a < s; ++a) Mi[a][c] = 0.0;
+    Mi[c][c] = 1.0 / R[c][c];
     for (int a = c - 1; a >= 0; --a) {
       double acc = 0.0;
-      for (int q = a + 1; q <= c; ++q) acc += R[a][q] * M2[q * b + c];
-      M2[a * b + c] = -acc / R[a][a];
+      for (int q = a + 1; q <= c; ++q) acc += R[a][q] * Mi[q][c];
+      Mi[a][c] = -acc / R[a][a];
     }
   }
-  double tmp[KB];
-  for (int j = 0; j < b; ++j) {
-    for (int a = 0; a < s; ++a) {
-      double acc = 0.0;
-      for (int q = a; q < s; ++q) acc += R[a][q] * Rfac[q * b + j];
-      tmp[a] = acc;
-    }
-    for (int a = 0; a < s; ++a) Rfac[a * b + j] = tmp[a];
+  for (int e = t; e < s * b; e += 64) F[e / b][e % b] = Rfac[e];
+  __syncthreads();
+  for (int e = t; e < s * s; e += 64) M2[(e / s) * b + (e % s)] = Mi[e / s][e % s];
+  for (int e = t; e < s * b; e += 64) {
+    const int a = e / b, j = e % b;
+    double acc = 0.0;
+    for (int q = a; q < s; ++q) acc += R[a][q] * F[q][j];
+    Rfac[e] = acc;
   }
-  info[1] = fail;
+  if (t == 0) info[1] = fail_sh;
 }
 
 // ---------------------------------------------------------------- T bookkeeping

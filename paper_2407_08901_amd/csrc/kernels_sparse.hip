@@ -200,7 +200,8 @@ __global__ __launch_bounds__(256) void k_spmm(int64_t n, const int64_t* __restri
                                               const int32_t* __restrict__ col,
                                               const VT* __restrict__ val, const XT* __restrict__ X,
                                               int64_t ldx, double* __restrict__ Y, int64_t ldy, int b,
-                                              const double* __restrict__ shift) {
+                                              const double* __restrict__ shift, double ea, double ec,
+                                              double eb, const double* __restrict__ Zo, int64_t ldz) {
   constexpr int G = 64 / B;
   const int lane = threadIdx.x & 63;
   const int g = lane / B;
@@ -238,18 +239,21 @@ __global__ __launch_bounds__(256) void k_spmm(int64_t n, const int64_t* __restri
   for (int o = B; o < 64; o <<= 1) acc += __shfl_xor(acc, o);
   if (g == 0 && colok) {
     if (shift) acc -= shift[c] * (double)X[row * ldx + c];
+    if (Zo) acc = ea * (acc - ec * (double)X[row * ldx + c]) + eb * Zo[row * ldz + c];
     Y[row * ldy + c] = acc;
   }
 }
 
 template <typename VT, typename XT>
 void launch_spmm(const DevCSR& H, const VT* val, const XT* X, int64_t ldx, double* Y, int64_t ldy,
-                 int b, const double* shift, hipStream_t s) {
+                 int b, const double* shift, hipStream_t s, double ea = 0.0, double ec = 0.0,
+                 double eb = 0.0, const double* Zo = nullptr, int64_t ldz = 0) {
   if (b < 1 || b > 32) throw Error(1, "spmm: block width must be 1..32");
   if (H.n == 0) return;
   const int64_t grid = cdiv(H.n, 4);
 #define SPPC_SPMM_CASE(BB)                                                                        \
-  k_spmm<BB, VT, XT><<<grid, 256, 0, s>>>(H.n, H.rp, H.rend, H.col, val, X, ldx, Y, ldy, b, shift); \
+  k_spmm<BB, VT, XT><<<grid, 256, 0, s>>>(H.n, H.rp, H.rend, H.col, val, X, ldx, Y, ldy, b, shift, ea, ec, \
+                                          eb, Zo, ldz);                                                     \
   break;
   switch (b <= 1 ? 1 : b <= 2 ? 2 : b <= 4 ? 4 : b <= 8 ? 8 : b <= 16 ? 16 : 32) {
     case 1: SPPC_SPMM_CASE(1)
@@ -263,7 +267,51 @@ void launch_spmm(const DevCSR& H, const VT* val, const XT* X, int64_t ldx, doubl
   SPPC_LAUNCH_CHECK();
 }
 
+// upper Gershgorin bound of each row: d_i + sum_{j != i} |a_ij|
+__global__ void k_gersh(int64_t n, const int64_t* __restrict__ rp, const int64_t* __restrict__ rend,
+                        const int32_t* __restrict__ col, const double* __restrict__ v64,
+                        const float* __restrict__ v32, double* __restrict__ out) {
+  const int lane = threadIdx.x & 63;
+  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= n) return;
+  const int64_t b = rp[row], e = rend ? rend[row] : rp[row + 1];
+  double s = 0.0;
+  for (int64_t t = b + lane; t < e; t += 64) {
+    const double v = v64 ? v64[t] : (double)v32[t];
+    s += col[t] == row ? v : fabs(v);
+  }
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+  if (lane == 0) out[row] = s;
+}
+
+__global__ void k_max_reduce(int64_t n, const double* __restrict__ x, double* __restrict__ out) {
+  __shared__ double sh[1024];
+  double m = -INFINITY;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) m = fmax(m, x[i]);
+  sh[threadIdx.x] = m;
+  __syncthreads();
+  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < (unsigned)o) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + o]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = sh[0];
+}
+
 }  // namespace
+
+void gershgorin_upper(const DevCSR& H, double* tmp, double* out, hipStream_t s) {
+  k_gersh<<<cdiv(H.n, 4), 256, 0, s>>>(H.n, H.rp, H.rend, H.col, H.val64, H.val32, tmp);
+  k_max_reduce<<<1, 1024, 0, s>>>(H.n, tmp, out);
+  SPPC_LAUNCH_CHECK();
+}
+
+void spmm_cheb(const DevCSR& H, const double* X, int64_t ldx, double* Y, int64_t ldy, int b, double ea,
+               double ec, double eb, const double* Zo, int64_t ldz, hipStream_t s) {
+  if (H.val64)
+    launch_spmm<double, double>(H, H.val64, X, ldx, Y, ldy, b, nullptr, s, ea, ec, eb, Zo, ldz);
+  else
+    launch_spmm<float, double>(H, H.val32, X, ldx, Y, ldy, b, nullptr, s, ea, ec, eb, Zo, ldz);
+}
 
 void build_full_csr(int64_t n, int64_t nnz_up, const int64_t* up_rp, const int32_t* up_col,
                     const void* up_val, int val_is_f32, DevCSR& out, int* d_flags, bool want64,
