@@ -77,9 +77,9 @@ typedef struct {
   int m_max;           /* basis columns kept; the continuation restarts beyond it; default 512 */
   int n_deflate;       /* eigenpairs of H0hat computed and deflated in the small solves (>= k) */
   double tau_drop;     /* new column dropped when sin(angle to the basis) <= tau_drop */
-  double inner_tol;    /* relative residual of the small-space solves */
+  double inner_tol;    /* relative residual of the small-space solves; 0 = 1e-12 (FP64) / 1e-6 (MIXED) */
   double h0_tol;       /* residual of the H0hat eigenpairs, relative to max(1,|E|) */
-  int precision;       /* sppc_precision */
+  int precision;       /* sppc_precision; MIXED adds a float64 refinement when the final check fails */
   int precond;         /* sppc_corr_kind used by the continuation (JACOBI or MPNN) */
   int final_check;     /* explicit float64 H Z, Rayleigh-Ritz on span Z, true residual */
   int verbose;         /* per-iteration line on stderr */
@@ -87,7 +87,9 @@ typedef struct {
 
 typedef struct {
   int iterations;      /* SPPC steps p reached */
-  int cont_steps;      /* continuation steps */
+  int cont_steps;      /* continuation steps (refinement steps included) */
+  int refine_steps;    /* float64 refinement steps after a mixed-precision solve */
+  int mpnn_steps;      /* continuation steps that used the learned preconditioner */
   int64_t n_spmv;      /* products of H with one vector (k per SPPC step, Sec. IV.C) */
   int64_t spmm_calls;  /* block products with H (kernel launches) */
   int64_t spmm_cols;   /* sum of their block widths */
@@ -181,9 +183,59 @@ sppc_status sppc_solve(sppc_ctx* ctx, double* evals_host, double* evecs_dev, dou
  *   what = 4: H Q, row-major n x m (device)     what = 5: pending block, row-major n x k (device)
  *   what = 6: T, m x m (host, row-major)        what = 7: angles of the last appended block [k] (host)
  *   what = 8: E^(p) table [(p+1) x k] (host)    what = 9: H0hat eigenvectors, row-major n0 x n_deflate (device)
+ *   what = 10: Ritz vectors Z, n x k (device)   what = 11: residuals R = H Z - Z diag(theta), n x k (device)
  * `count` is the capacity of dst in doubles.  Errors: SPPC_E_ARG.
  */
 sppc_status sppc_get(sppc_ctx* ctx, int what, double* dst, int64_t count);
+
+/* ------------------------------------------------------------------ learned preconditioner
+ *
+ * A 2-layer message-passing network over the graph of H (hidden width 32) scales the diagonal
+ * step of the continuation row by row.  For a Ritz pair (theta, x) with residual r:
+ *   f = [r / rms(r), (d - theta)/(1 + |theta|), level/(L-1)],  g = A f,  A = H - diag(d)
+ *   h = tanh(Ws f + Wn g + b1),  o = ws.h + A (wn.h) + b2,
+ *   t = tJ (1 + o) with the diagonal step tJ = r / (d - theta) (|d - theta| >= 1e-2 max(1,|theta|)),
+ *   t~ = t - x (x^T t);  the continuation direction is -t~.  A zero network is the diagonal step.
+ * Parameters (float32, 289): Ws[32x3] | Wn[32x3] | b1[32] | ws[32] | wn[32] | b2, row-major.
+ * The solver uses them rounded to bfloat16, with float32 arithmetic; the products with H are float64.
+ */
+#define SPPC_MPNN_NPARAM 289
+
+/* Weights for SPPC_CORR_MPNN (host, 289 floats, copied).  Non-finite weights make every pair use
+ * the diagonal step.  During the continuation a pair whose true residual did not fall below 0.9x
+ * its value at its previous learned step uses the diagonal step from then on. */
+sppc_status sppc_mpnn_set_weights(sppc_ctx* ctx, const float* w_host);
+
+/*
+ * Evaluates the network for S (1..64) samples on the matrix of the context.
+ *   w_host        289 parameters (host)
+ *   R_dev, X_dev  n x S row-major: residuals and unit Ritz vectors (device)
+ *   theta_host    [S] Ritz values
+ *   E_dev         n x S targets, or NULL (then no loss / gradient)
+ *   T_dev         n x S output t~ (device), or NULL
+ *   loss_host     [S] per-sample loss 1 - cos^2(t~, e), or NULL
+ *   grad_host     [289] gradient of the mean loss, or NULL
+ *   f64           1: float64 arithmetic and exact weights (gradient checks); 0: float32 arithmetic
+ *                 with bfloat16-rounded weights (the solver's form)
+ */
+sppc_status sppc_mpnn_eval(sppc_ctx* ctx, const float* w_host, int S, const double* R_dev, const double* X_dev,
+                           const double* theta_host, const double* E_dev, double* T_dev, double* loss_host,
+                           double* grad_host, int f64);
+
+/*
+ * One training step on the GPU: forward, backward (one more product with H), and an Adam update
+ * (beta 0.9 / 0.999) of the float32 master weights.
+ *   state_dev  device float[4 x 289]: weights | first moments | second moments | bfloat16 copy
+ *   step       Adam step count (>= 1); loss_host: mean loss of the batch before the update (or NULL)
+ */
+sppc_status sppc_mpnn_train_step(sppc_ctx* ctx, float* state_dev, int S, const double* R_dev, const double* X_dev,
+                                 const double* theta_host, const double* E_dev, float lr, int step,
+                                 double* loss_host);
+
+/* Training targets: E[:, s] = psi_s / (psi_s^T x_s) - x_s for unit Ritz vectors x_s and the exact
+ * eigenvectors psi_s (all n x S, device): the exact Jacobi-Davidson correction in the limit where
+ * theta reaches the eigenvalue. */
+sppc_status sppc_mpnn_target(sppc_ctx* ctx, int S, const double* X_dev, const double* Psi_dev, double* E_dev);
 
 const char* sppc_last_error(const sppc_ctx* ctx);
 

@@ -26,7 +26,9 @@ STATUS_NAMES = {0: "SPPC_OK", 1: "SPPC_E_ARG", 2: "SPPC_E_HIP", 3: "SPPC_E_NOMEM
                 4: "SPPC_E_SINGULAR_E0", 5: "SPPC_E_BREAKDOWN", 6: "SPPC_E_NOCONV", 7: "SPPC_E_NAN"}
 
 EXPORTS = ("sppc_default_opts", "sppc_setup", "sppc_spmm", "sppc_correct", "sppc_rayleigh_ritz",
-           "sppc_solve", "sppc_get", "sppc_last_error", "sppc_setup_error", "sppc_destroy")
+           "sppc_solve", "sppc_get", "sppc_last_error", "sppc_setup_error", "sppc_destroy",
+           "sppc_mpnn_set_weights", "sppc_mpnn_eval", "sppc_mpnn_train_step", "sppc_mpnn_target")
+SPPC_MPNN_NPARAM = 289
 
 
 class sppc_csr(ctypes.Structure):
@@ -43,7 +45,8 @@ class sppc_opts(ctypes.Structure):
 
 
 class sppc_stats(ctypes.Structure):
-    _fields_ = [("iterations", ctypes.c_int), ("cont_steps", ctypes.c_int), ("n_spmv", ctypes.c_int64),
+    _fields_ = [("iterations", ctypes.c_int), ("cont_steps", ctypes.c_int), ("refine_steps", ctypes.c_int),
+                ("mpnn_steps", ctypes.c_int), ("n_spmv", ctypes.c_int64),
                 ("spmm_calls", ctypes.c_int64), ("spmm_cols", ctypes.c_int64),
                 ("basis_size", ctypes.c_int), ("cg_iterations", ctypes.c_int), ("h0_iterations", ctypes.c_int),
                 ("converged", ctypes.c_int), ("t_setup_ms", ctypes.c_double), ("t_solve_ms", ctypes.c_double),
@@ -84,8 +87,14 @@ def lib():
         L.sppc_setup_error.restype = ctypes.c_char_p
         L.sppc_destroy.argtypes = [vp]
         L.sppc_destroy.restype = None
+        fp = ctypes.POINTER(ctypes.c_float)
+        L.sppc_mpnn_set_weights.argtypes = [vp, fp]
+        L.sppc_mpnn_eval.argtypes = [vp, fp, c_int, vp, vp, dp, vp, vp, dp, dp, c_int]
+        L.sppc_mpnn_train_step.argtypes = [vp, vp, c_int, vp, vp, dp, vp, ctypes.c_float, c_int, dp]
+        L.sppc_mpnn_target.argtypes = [vp, c_int, vp, vp, vp]
         for name in ("sppc_default_opts", "sppc_setup", "sppc_spmm", "sppc_correct", "sppc_rayleigh_ritz",
-                     "sppc_solve", "sppc_get"):
+                     "sppc_solve", "sppc_get", "sppc_mpnn_set_weights", "sppc_mpnn_eval", "sppc_mpnn_train_step",
+                     "sppc_mpnn_target"):
             getattr(L, name).restype = c_int
         _lib = L
     return _lib
@@ -198,6 +207,56 @@ def sppc_get(ctx: Context, what: int, count: int, device: bool = False):
     buf = (ctypes.c_double * max(count, 1))()
     _check(lib().sppc_get(ctx.handle, what, buf, count), ctx.handle)
     return list(buf)[:count]
+
+
+def _fptr(w):
+    import numpy as np
+    a = np.ascontiguousarray(w, dtype=np.float32)
+    if a.size != SPPC_MPNN_NPARAM:
+        raise ValueError("the network has %d parameters" % SPPC_MPNN_NPARAM)
+    return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+
+
+def _dptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def sppc_mpnn_set_weights(ctx: Context, w) -> None:
+    a, p = _fptr(w)
+    _check(lib().sppc_mpnn_set_weights(ctx.handle, p), ctx.handle)
+
+
+def sppc_mpnn_eval(ctx: Context, w, R: torch.Tensor, X: torch.Tensor, theta, E: Optional[torch.Tensor] = None,
+                   want_output: bool = True, f64: bool = False):
+    """Returns (T or None, loss list or None, grad list or None).  R, X, E: n x S float64 GPU."""
+    a, p = _fptr(w)
+    S = R.shape[1]
+    for t in (R, X, E):
+        if t is not None and (t.shape != (ctx.n, S) or t.dtype != torch.float64 or not t.is_contiguous()):
+            raise ValueError("R, X, E must be contiguous float64 n x S")
+    T = torch.empty_like(R) if want_output else None
+    th = (ctypes.c_double * S)(*[float(x) for x in theta])
+    loss = (ctypes.c_double * S)() if E is not None else None
+    grad = (ctypes.c_double * SPPC_MPNN_NPARAM)() if E is not None else None
+    _check(lib().sppc_mpnn_eval(ctx.handle, p, S, _dptr(R), _dptr(X), th, _dptr(E), _dptr(T), loss, grad,
+                                1 if f64 else 0), ctx.handle)
+    return T, (list(loss) if loss is not None else None), (list(grad) if grad is not None else None)
+
+
+def sppc_mpnn_train_step(ctx: Context, state: torch.Tensor, R, X, theta, E, lr: float, step: int) -> float:
+    """state: float32 GPU tensor [4 * 289] (weights, Adam moments, bfloat16 copy)."""
+    S = R.shape[1]
+    th = (ctypes.c_double * S)(*[float(x) for x in theta])
+    loss = ctypes.c_double()
+    _check(lib().sppc_mpnn_train_step(ctx.handle, ctypes.c_void_p(state.data_ptr()), S, _dptr(R), _dptr(X), th,
+                                      _dptr(E), ctypes.c_float(lr), step, ctypes.byref(loss)), ctx.handle)
+    return loss.value
+
+
+def sppc_mpnn_target(ctx: Context, X: torch.Tensor, Psi: torch.Tensor) -> torch.Tensor:
+    E = torch.empty_like(X)
+    _check(lib().sppc_mpnn_target(ctx.handle, X.shape[1], _dptr(X), _dptr(Psi), _dptr(E)), ctx.handle)
+    return E
 
 
 def sppc_destroy(ctx: Context) -> None:

@@ -149,7 +149,7 @@ int64_t cg_work_doubles(int64_t n0);
 // Deflated preconditioned CG for the k shifted small-space systems; b in r; returns iterations.
 int cg_solve(const DevCSR& H0, int64_t n0, int k, int D, const double* diag, const double* shift,
              const double* Ps, double* x, double* r, double* z, double* p, double* q, double* work,
-             double* ccoef, int maxit, double tol, int* host_flag, hipStream_t s);
+             double* ccoef, int maxit, double tol, bool f32prod, int* host_flag, hipStream_t s);
 void cg_precond(int64_t n0, int k, const double* diag, const double* shift, const double* r,
                 double* z, hipStream_t s);
 void cg_dots(int64_t n0, int k, const double* a, const double* b, double* out, double* work, hipStream_t s);
@@ -164,5 +164,25 @@ void cg_init(int k, const double* bb, int* active, int* nactive, hipStream_t s);
 void coldots(int64_t n, int b, const double* X, int64_t ldx, const double* Y, int64_t ldy, double* out,
              double* work, hipStream_t s);
 void fill_block_zero(int64_t n, int b, double* Y, int64_t ldy, hipStream_t s);
+// Y[:, a] = X[:, idx[a]]   /   Y[:, idx[a]] = alpha X[:, a] (idx[a] < 0 skipped)
+void gather_cols(int64_t n, int S, const int* idx, const double* X, int64_t ldx, double* Y, int64_t ldy,
+                 hipStream_t s);
+void scatter_cols(int64_t n, int S, const int* idx, const double* X, int64_t ldx, double* Y, int64_t ldy,
+                  double alpha, hipStream_t s);
+
+// ---------------------------------------------------------------- learned preconditioner (kernels_mpnn.hip)
+int mpnn_nparam();
+void mpnn_prepare(const DevCSR& H, const double* diag, const int64_t* level_off_dev, int L, double* lev,
+                  double* Ad, double* A1, double* Al, double* tmp, hipStream_t s);
+int64_t mpnn_work_doubles(int64_t n, int S);
+template <typename T>
+void mpnn_run(const DevCSR& H, const double* diag, const double* lev, const double* Ad, const double* A1,
+              const double* Al, const T* w, int S, const double* R, int64_t ldr, const double* X, int64_t ldx,
+              const double* theta_dev, const double* E, double* T_out, double* grad_out, double* loss_dev,
+              double* work, hipStream_t s);
+void mpnn_adam(float* w, float* m, float* v, const double* g, float lr, int step, float* wq, hipStream_t s);
+void mpnn_round_bf16(int cnt, const float* w, float* wq, double* wd, hipStream_t s);
+void mpnn_target(int64_t n, int S, const double* X, const double* Psi, double* E, double* dots, double* work,
+                 hipStream_t s);
 
 }  // namespace sppc

@@ -129,10 +129,20 @@ struct sppc_ctx {
   std::vector<int> mhist;
   int p = 0;
   bool restarted = false;
+  bool refining = false;  // float64 residual refinement after a mixed-precision solve
   int pend_b = 0, pend_kind = -1;
   int nw_last = 0;  // width of Z/HZ/R from the last Rayleigh-Ritz
   std::vector<double> theta_h, rrn_h, angles_h;
   int last_added = 0;
+  // learned preconditioner
+  bool mp_ready = false, mp_have_w = false, mp_invalid = false;
+  int64_t* loff_dev = nullptr;
+  double *mp_lev = nullptr, *mp_Ad = nullptr, *mp_A1 = nullptr, *mp_Al = nullptr, *mp_work = nullptr;
+  double *mp_sel = nullptr, *mp_th = nullptr, *mp_grad = nullptr, *mp_loss = nullptr, *mp_wd = nullptr;
+  float *mp_w = nullptr, *mp_wq = nullptr;
+  int mp_S = 0;
+  std::vector<int> mp_fallback;     // per pair: 1 = use the diagonal step
+  std::vector<double> mp_prev_rrn;  // residual when the learned step was last used (0 = not used)
   sppc_stats st{};
   std::string err;
   double* pin = nullptr;  // pinned host staging
@@ -349,8 +359,11 @@ void small_solve(sppc_ctx* c) {
   hipStream_t s = c->s;
   const int64_t n0 = c->n0;
   const int k = c->k, D = c->D;
+  const bool mixed = c->o.precision == SPPC_PREC_MIXED;
+  double tol = c->o.inner_tol;
+  if (tol <= 0.0) tol = mixed ? 1e-6 : 1e-12;
   c->st.cg_iterations += cg_solve(c->H0, n0, k, D, c->diag, c->E0, c->Psihat, c->cx, c->cr, c->cz, c->cp,
-                                  c->cq, c->cgpart, c->ccoef, 5000, c->o.inner_tol, c->pin_i + 4, s);
+                                  c->cq, c->cgpart, c->ccoef, 5000, tol, mixed, c->pin_i + 4, s);
   deflate_coefs(D, k, c->E0, c->ccoef, k, c->ctmp, k, s);
   gemm_nn(n0, D, k, c->Psihat, D, c->ctmp, k, c->cx, k, 1.0, 1.0, s);
   copy_block(n0, k, c->cx, k, c->Psi, k, s);
@@ -383,8 +396,45 @@ void correct_perturbative(sppc_ctx* c) {
   c->pend_kind = SPPC_CORR_PERTURBATIVE;
 }
 
+// Static inputs of the learned preconditioner and workspace for S samples (lazy).
+void mpnn_ensure(sppc_ctx* c, int S) {
+  hipStream_t s = c->s;
+  Arena& A = c->arena;
+  const int64_t n = c->n;
+  if (!c->mp_ready) {
+    const int L = (int)c->loff.size() - 1;
+    c->loff_dev = A.alloc<int64_t>(L + 1);
+    SPPC_HIP(hipMemcpy(c->loff_dev, c->loff.data(), sizeof(int64_t) * (L + 1), hipMemcpyHostToDevice));
+    c->mp_lev = A.alloc<double>(n);
+    c->mp_Ad = A.alloc<double>(n);
+    c->mp_A1 = A.alloc<double>(n);
+    c->mp_Al = A.alloc<double>(n);
+    c->mp_grad = A.alloc<double>(512);
+    c->mp_loss = A.alloc<double>(64);
+    c->mp_th = A.alloc<double>(64);
+    c->mp_wd = A.alloc<double>(512);
+    c->mp_w = A.alloc<float>(512);
+    c->mp_wq = A.alloc<float>(512);
+    double* tmp = A.alloc<double>((size_t)6 * n);
+    mpnn_prepare(c->H, c->diag, c->loff_dev, L, c->mp_lev, c->mp_Ad, c->mp_A1, c->mp_Al, tmp, s);
+    sync(c);
+    c->mp_ready = true;
+  }
+  if (S > c->mp_S) {
+    c->mp_work = A.alloc<double>((size_t)mpnn_work_doubles(n, S));
+    c->mp_sel = A.alloc<double>((size_t)n * S * 3);
+    c->mp_S = S;
+  }
+}
+
+void upload_theta(sppc_ctx* c, const double* th, int S) {
+  for (int i = 0; i < S; ++i) c->pin[3 * NWMAX + i] = th[i];
+  SPPC_HIP(hipMemcpyAsync(c->mp_th, c->pin + 3 * NWMAX, sizeof(double) * S, hipMemcpyHostToDevice, c->s));
+  sync(c);
+}
+
 void correct_continuation(sppc_ctx* c, int kind) {
-  if (kind == SPPC_CORR_MPNN) throw Error(SPPC_E_ARG, "learned preconditioner not available");
+  if (kind == SPPC_CORR_MPNN && !c->mp_have_w) throw Error(SPPC_E_ARG, "no weights for the learned preconditioner");
   std::vector<int> act;
   for (int i = 0; i < c->k; ++i)
     if (!(c->rrn_h[i] < c->o.tol)) act.push_back(i);
@@ -397,6 +447,55 @@ void correct_continuation(sppc_ctx* c, int kind) {
     c->restarted = true;
   }
   jacobi_expansion(c, c->n, c->diag, act, c->k);
+  if (kind == SPPC_CORR_MPNN && !c->mp_invalid) {
+    // the true residual judges the learned step: a pair whose residual did not fall below 0.9x
+    // its value at the previous learned step uses the diagonal step from then on
+    if ((int)c->mp_fallback.size() != c->k) {
+      c->mp_fallback.assign(c->k, 0);
+      c->mp_prev_rrn.assign(c->k, 0.0);
+    }
+    for (int i = 0; i < c->k; ++i)
+      if (c->mp_prev_rrn[i] > 0.0 && !(c->rrn_h[i] < 0.9 * c->mp_prev_rrn[i])) c->mp_fallback[i] = 1;
+    std::vector<int> sel, pos;
+    for (int a = 0; a < (int)act.size(); ++a)
+      if (!c->mp_fallback[act[a]]) { sel.push_back(act[a]); pos.push_back(a); }
+    if (!sel.empty()) {
+      const int S = (int)sel.size(), na = (int)act.size();
+      const int64_t n = c->n;
+      mpnn_ensure(c, S);
+      hipStream_t s = c->s;
+      for (int a = 0; a < S; ++a) c->pin_i[8 + a] = sel[a];
+      SPPC_HIP(hipMemcpyAsync(c->idx, c->pin_i + 8, sizeof(int) * S, hipMemcpyHostToDevice, s));
+      double* Rs = c->mp_sel;
+      double* Zs = Rs + n * S;
+      double* Ts = Zs + n * S;
+      gather_cols(n, S, c->idx, c->R, c->k, Rs, S, s);
+      gather_cols(n, S, c->idx, c->Z, c->k, Zs, S, s);
+      std::vector<double> th(S);
+      for (int a = 0; a < S; ++a) th[a] = c->theta_h[sel[a]];
+      upload_theta(c, th.data(), S);
+      mpnn_run<float>(c->H, c->diag, c->mp_lev, c->mp_Ad, c->mp_A1, c->mp_Al, c->mp_wq, S, Rs, S, Zs, S,
+                      c->mp_th, nullptr, Ts, nullptr, nullptr, c->mp_work, s);
+      // a non-finite or vanishing learned direction falls back to the diagonal step
+      colsumsq(n, S, Ts, S, c->sumsq, c->work, s);
+      SPPC_HIP(hipMemcpyAsync(c->pin + 2 * NWMAX, c->sumsq, sizeof(double) * S, hipMemcpyDeviceToHost, s));
+      sync(c);
+      for (int a = 0; a < S; ++a) {
+        const double nn = c->pin[2 * NWMAX + a];
+        if (std::isfinite(nn) && nn > 0.0) {
+          c->pin_i[8 + a] = pos[a];
+          c->mp_prev_rrn[sel[a]] = c->rrn_h[sel[a]];
+        } else {
+          c->pin_i[8 + a] = -1;
+          c->mp_fallback[sel[a]] = 1;
+        }
+      }
+      SPPC_HIP(hipMemcpyAsync(c->idx, c->pin_i + 8, sizeof(int) * S, hipMemcpyHostToDevice, s));
+      scatter_cols(n, S, c->idx, Ts, S, c->Psi, na, -1.0, s);
+      sync(c);
+      c->st.mpnn_steps += 1;
+    }
+  }
   c->tm.end(t0);
   c->pend_b = (int)act.size();
   c->pend_kind = kind;
@@ -404,7 +503,7 @@ void correct_continuation(sppc_ctx* c, int kind) {
 
 int append_and_rr(sppc_ctx* c) {
   Basis& b = c->B;
-  Op op{&c->H, c->o.precision == SPPC_PREC_MIXED, c->X32, &c->st};
+  Op op{&c->H, c->o.precision == SPPC_PREC_MIXED && !c->refining, c->X32, &c->st};
   int added = 0;
   if (c->pend_b > 0) {
     const bool pert = c->pend_kind == SPPC_CORR_PERTURBATIVE;
@@ -482,7 +581,8 @@ void setup_impl(sppc_ctx* c, const sppc_csr* Hin, const int64_t* loff, int L, in
   if (o.n_deflate < k || o.n_deflate > 28 || o.n_deflate > c->n0) throw Error(SPPC_E_ARG, "n_deflate must be in [k, min(28, n0)]");
   c->D = o.n_deflate;
   if (o.m_max < 2 * k || o.m_max > 512) throw Error(SPPC_E_ARG, "m_max must be in [2k, 512]");
-  if (!(o.tol > 0) || !(o.tau_drop >= 0) || !(o.inner_tol > 0) || !(o.h0_tol > 0)) throw Error(SPPC_E_ARG, "bad tolerances");
+  if (!(o.tol > 0) || !(o.tau_drop >= 0) || !(o.inner_tol >= 0) || !(o.h0_tol > 0)) throw Error(SPPC_E_ARG, "bad tolerances");
+  if (o.precision != SPPC_PREC_FP64 && o.precision != SPPC_PREC_MIXED) throw Error(SPPC_E_ARG, "bad precision");
   const int last_p = (o.p_switch > 0) ? std::min(o.p_switch, o.maxiter) : o.maxiter;
   if (last_p < 0) throw Error(SPPC_E_ARG, "maxiter must be >= 0");
   if ((int64_t)k * (last_p + 1) > o.m_max) throw Error(SPPC_E_ARG, "m_max < k * (perturbation order + 1)");
@@ -642,14 +742,43 @@ sppc_status solve_impl(sppc_ctx* c, double* evals, double* evecs, double* rrn, s
       log_step(c, "cont");
       conv = all_converged(c);
       if (added == 0 && !conv) break;
+      // mixed precision: within 10x of the tolerance the float32 noise (~3e-7 relative)
+      // dominates the loop's residuals; hand over to the float64 refinement
+      if (!conv && o.precision == SPPC_PREC_MIXED && o.final_check) {
+        double mx = 0.0;
+        for (int i = 0; i < c->k; ++i) mx = std::max(mx, c->rrn_h[i]);
+        if (mx < 10.0 * o.tol) break;
+      }
     }
   }
-  c->st.cont_steps = cont;
   if (o.final_check) {
     final_check(c);
     log_step(c, "final");
     conv = all_converged(c);
+    // mixed precision: the float32 products limit what the loop's residuals can see; restart on
+    // the checked Ritz vectors (float64 H Z) and continue with float64 products until the true
+    // residual meets the tolerance
+    if (!conv && o.precision == SPPC_PREC_MIXED && o.p_switch > 0) {
+      c->refining = true;
+      restart_basis(c, c->B, c->k);
+      c->restarted = true;
+      int ref = 0;
+      while (!conv && ref < o.max_cont) {
+        correct_continuation(c, SPPC_CORR_JACOBI);
+        const int added = append_and_rr(c);
+        ++ref;
+        ++cont;
+        log_step(c, "refine");
+        conv = all_converged(c);
+        if (added == 0 && !conv) break;
+      }
+      final_check(c);
+      log_step(c, "final");
+      conv = all_converged(c);
+      c->st.refine_steps = ref;
+    }
   }
+  c->st.cont_steps = cont;
   c->st.converged = conv;
   c->st.basis_size = c->B.m;
   const int k = c->k;
@@ -697,7 +826,7 @@ sppc_status sppc_default_opts(sppc_opts* o) {
   o->m_max = 512;
   o->n_deflate = 0;
   o->tau_drop = 1e-10;
-  o->inner_tol = 1e-12;
+  o->inner_tol = 0.0;  // automatic: 1e-12 (float64), 1e-6 (mixed)
   o->h0_tol = 1e-12;
   o->precision = SPPC_PREC_FP64;
   o->precond = SPPC_CORR_JACOBI;
@@ -794,8 +923,93 @@ sppc_status sppc_get(sppc_ctx* c, int what, double* dst, int64_t count) {
       case 8: need((int64_t)(c->p + 1) * k);
         SPPC_HIP(hipMemcpy(dst, c->Etab, sizeof(double) * (c->p + 1) * k, hipMemcpyDeviceToHost)); break;
       case 9: need(c->n0 * c->D); copy_block(c->n0, c->D, c->Psihat, c->D, dst, c->D, c->s); sync(c); break;
+      case 10: need(n * k); copy_block(n, k, c->Z, c->nw_last, dst, k, c->s); sync(c); break;
+      case 11: need(n * k); copy_block(n, k, c->R, c->nw_last, dst, k, c->s); sync(c); break;
       default: throw Error(SPPC_E_ARG, "unknown item");
     }
+    return SPPC_OK;
+  });
+}
+
+sppc_status sppc_mpnn_set_weights(sppc_ctx* c, const float* w_host) {
+  if (!c || !w_host) return SPPC_E_ARG;
+  return guarded(c, [&]() {
+    mpnn_ensure(c, 1);
+    bool finite = true;
+    for (int i = 0; i < SPPC_MPNN_NPARAM; ++i) finite = finite && std::isfinite(w_host[i]);
+    c->mp_invalid = !finite;  // every pair then takes the diagonal step
+    SPPC_HIP(hipMemcpy(c->mp_w, w_host, sizeof(float) * SPPC_MPNN_NPARAM, hipMemcpyHostToDevice));
+    mpnn_round_bf16(SPPC_MPNN_NPARAM, c->mp_w, c->mp_wq, nullptr, c->s);
+    sync(c);
+    c->mp_have_w = true;
+    c->mp_fallback.assign(c->k, 0);
+    c->mp_prev_rrn.assign(c->k, 0.0);
+    return SPPC_OK;
+  });
+}
+
+sppc_status sppc_mpnn_eval(sppc_ctx* c, const float* w_host, int S, const double* R_dev, const double* X_dev,
+                           const double* theta_host, const double* E_dev, double* T_dev, double* loss_host,
+                           double* grad_host, int f64) {
+  if (!c || !w_host || S < 1 || S > 64 || !R_dev || !X_dev || !theta_host) return SPPC_E_ARG;
+  if ((loss_host || grad_host) && !E_dev) return SPPC_E_ARG;
+  return guarded(c, [&]() {
+    mpnn_ensure(c, S);
+    hipStream_t s = c->s;
+    SPPC_HIP(hipMemcpy(c->mp_w, w_host, sizeof(float) * SPPC_MPNN_NPARAM, hipMemcpyHostToDevice));
+    upload_theta(c, theta_host, S);
+    if (f64) {
+      std::vector<double> wd(w_host, w_host + SPPC_MPNN_NPARAM);
+      SPPC_HIP(hipMemcpy(c->mp_wd, wd.data(), sizeof(double) * SPPC_MPNN_NPARAM, hipMemcpyHostToDevice));
+      mpnn_run<double>(c->H, c->diag, c->mp_lev, c->mp_Ad, c->mp_A1, c->mp_Al, c->mp_wd, S, R_dev, S, X_dev, S,
+                       c->mp_th, E_dev, T_dev, c->mp_grad, c->mp_loss, c->mp_work, s);
+    } else {
+      mpnn_round_bf16(SPPC_MPNN_NPARAM, c->mp_w, c->mp_wq, nullptr, s);
+      mpnn_run<float>(c->H, c->diag, c->mp_lev, c->mp_Ad, c->mp_A1, c->mp_Al, c->mp_wq, S, R_dev, S, X_dev, S,
+                      c->mp_th, E_dev, T_dev, c->mp_grad, c->mp_loss, c->mp_work, s);
+    }
+    sync(c);
+    if (loss_host) SPPC_HIP(hipMemcpy(loss_host, c->mp_loss, sizeof(double) * S, hipMemcpyDeviceToHost));
+    if (grad_host) SPPC_HIP(hipMemcpy(grad_host, c->mp_grad, sizeof(double) * SPPC_MPNN_NPARAM, hipMemcpyDeviceToHost));
+    return SPPC_OK;
+  });
+}
+
+sppc_status sppc_mpnn_train_step(sppc_ctx* c, float* state_dev, int S, const double* R_dev, const double* X_dev,
+                                 const double* theta_host, const double* E_dev, float lr, int step,
+                                 double* loss_host) {
+  if (!c || !state_dev || S < 1 || S > 64 || !R_dev || !X_dev || !theta_host || !E_dev || step < 1)
+    return SPPC_E_ARG;
+  return guarded(c, [&]() {
+    mpnn_ensure(c, S);
+    hipStream_t s = c->s;
+    float* w = state_dev;
+    float* m = w + SPPC_MPNN_NPARAM;
+    float* v = m + SPPC_MPNN_NPARAM;
+    float* wq = v + SPPC_MPNN_NPARAM;
+    upload_theta(c, theta_host, S);
+    mpnn_round_bf16(SPPC_MPNN_NPARAM, w, wq, nullptr, s);
+    mpnn_run<float>(c->H, c->diag, c->mp_lev, c->mp_Ad, c->mp_A1, c->mp_Al, wq, S, R_dev, S, X_dev, S, c->mp_th,
+                    E_dev, nullptr, c->mp_grad, c->mp_loss, c->mp_work, s);
+    mpnn_adam(w, m, v, c->mp_grad, lr, step, wq, s);
+    if (loss_host) {
+      std::vector<double> lv(S);
+      SPPC_HIP(hipMemcpyAsync(lv.data(), c->mp_loss, sizeof(double) * S, hipMemcpyDeviceToHost, s));
+      sync(c);
+      double tot = 0.0;
+      for (double x : lv) tot += x;
+      *loss_host = tot / S;
+    }
+    return SPPC_OK;
+  });
+}
+
+sppc_status sppc_mpnn_target(sppc_ctx* c, int S, const double* X_dev, const double* Psi_dev, double* E_dev) {
+  if (!c || S < 1 || S > 64 || !X_dev || !Psi_dev || !E_dev) return SPPC_E_ARG;
+  return guarded(c, [&]() {
+    mpnn_ensure(c, S);
+    mpnn_target(c->n, S, X_dev, Psi_dev, E_dev, c->mp_loss, c->work, c->s);
+    sync(c);
     return SPPC_OK;
   });
 }

@@ -190,7 +190,7 @@ __global__ __launch_bounds__(1024) void k_cg_project(CGArgs a, double* Y, double
 
 // ---- iteration, K1: beta, convergence; p = r + beta p_old (on the fly); q = (H0hat - E) p ;
 //      partial p.q.  One wave per row.
-template <int B, typename VT>
+template <int B, typename VT, bool F32P>
 __global__ __launch_bounds__(256) void k_cg_spmm(CGArgs a, int par, int first, const double* __restrict__ pold,
                                                  double* __restrict__ pnew) {
   const int t = threadIdx.x;
@@ -245,7 +245,12 @@ __global__ __launch_bounds__(256) void k_cg_spmm(CGArgs a, int par, int first, c
         const VT vv = __shfl(mv, e);
         if (e < cnt && ca) {
           const int64_t o = (int64_t)cl * k + cc;
-          acc = fma((double)vv, fma(bc, pold[o], a.r[o]), acc);
+          const double pn = fma(bc, pold[o], a.r[o]);
+          if constexpr (F32P) {
+            acc += (double)((float)vv * (float)pn);  // float32 product, float64 accumulation
+          } else {
+            acc = fma((double)vv, pn, acc);
+          }
         }
       }
     }
@@ -306,11 +311,12 @@ int64_t cg_work_doubles(int64_t n0) {
 // ccoef = Ps^T b.  Returns the number of iterations (synchronises the stream).
 int cg_solve(const DevCSR& H0, int64_t n0, int k, int D, const double* diag, const double* shift,
              const double* Ps, double* x, double* r, double* z, double* p, double* q, double* work,
-             double* ccoef, int maxit, double tol, int* host_flag, hipStream_t s) {
+             double* ccoef, int maxit, double tol, bool f32prod, int* host_flag, hipStream_t s) {
   (void)diag;
   (void)z;
   (void)p;
   if (k < 1 || k > CG_MAXK || D < 1 || D > CG_MAXD) throw Error(1, "cg: k <= 16 and D <= 28 required");
+  if (f32prod && !H0.val32) throw Error(1, "cg: float32 products need float32 values");
   const int nb1 = (int)cdiv(n0, R1);
   const int nb2 = (int)std::min<int64_t>(256, cdiv(n0, 64));
   double* part1 = work;
@@ -332,16 +338,18 @@ int cg_solve(const DevCSR& H0, int64_t n0, int k, int D, const double* diag, con
     const double* pold = (it & 1) ? pb : pa;
     double* pnew = (it & 1) ? pa : pb;
     const int first = it == 1;
+#define SPPC_CG_LAUNCH(BB)                                                                     \
+  if (f32prod) k_cg_spmm<BB, float, true><<<nb1, 256, 0, s>>>(a, par, first, pold, pnew);       \
+  else if (f64) k_cg_spmm<BB, double, false><<<nb1, 256, 0, s>>>(a, par, first, pold, pnew);    \
+  else k_cg_spmm<BB, float, false><<<nb1, 256, 0, s>>>(a, par, first, pold, pnew);
     if (k <= 4) {
-      if (f64) k_cg_spmm<4, double><<<nb1, 256, 0, s>>>(a, par, first, pold, pnew);
-      else k_cg_spmm<4, float><<<nb1, 256, 0, s>>>(a, par, first, pold, pnew);
+      SPPC_CG_LAUNCH(4)
     } else if (k <= 8) {
-      if (f64) k_cg_spmm<8, double><<<nb1, 256, 0, s>>>(a, par, first, pold, pnew);
-      else k_cg_spmm<8, float><<<nb1, 256, 0, s>>>(a, par, first, pold, pnew);
+      SPPC_CG_LAUNCH(8)
     } else {
-      if (f64) k_cg_spmm<16, double><<<nb1, 256, 0, s>>>(a, par, first, pold, pnew);
-      else k_cg_spmm<16, float><<<nb1, 256, 0, s>>>(a, par, first, pold, pnew);
+      SPPC_CG_LAUNCH(16)
     }
+#undef SPPC_CG_LAUNCH
     k_cg_update<<<nb2, 1024, 0, s>>>(a, par, pnew);
     if (it % 16 == 0 || it == maxit) {
       SPPC_LAUNCH_CHECK();

@@ -484,12 +484,43 @@ void cg_init(int k, const double* bb, int* active, int* nactive, hipStream_t s) 
 }
 
 namespace {
+__global__ void k_gather_cols(int64_t n, int S, const int* __restrict__ idx, const double* __restrict__ X,
+                              int64_t ldx, double* __restrict__ Y, int64_t ldy) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * S) return;
+  const int64_t r = e / S;
+  const int a = (int)(e % S);
+  Y[r * ldy + a] = X[r * ldx + idx[a]];
+}
+
+__global__ void k_scatter_cols(int64_t n, int S, const int* __restrict__ idx, const double* __restrict__ X,
+                               int64_t ldx, double* __restrict__ Y, int64_t ldy, double alpha) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * S) return;
+  const int64_t r = e / S;
+  const int a = (int)(e % S);
+  const int j = idx[a];
+  if (j >= 0) Y[r * ldy + j] = alpha * X[r * ldx + a];
+}
+
 __global__ void k_zero_block(int64_t n, int b, double* __restrict__ Y, int64_t ldy) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= n * b) return;
   Y[(e / b) * ldy + (e % b)] = 0.0;
 }
 }  // namespace
+
+void gather_cols(int64_t n, int S, const int* idx, const double* X, int64_t ldx, double* Y, int64_t ldy,
+                 hipStream_t s) {
+  k_gather_cols<<<grid1(n * S), 256, 0, s>>>(n, S, idx, X, ldx, Y, ldy);
+  SPPC_LAUNCH_CHECK();
+}
+
+void scatter_cols(int64_t n, int S, const int* idx, const double* X, int64_t ldx, double* Y, int64_t ldy,
+                  double alpha, hipStream_t s) {
+  k_scatter_cols<<<grid1(n * S), 256, 0, s>>>(n, S, idx, X, ldx, Y, ldy, alpha);
+  SPPC_LAUNCH_CHECK();
+}
 
 void fill_block_zero(int64_t n, int b, double* Y, int64_t ldy, hipStream_t s) {
   if (n * b == 0) return;
