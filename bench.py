@@ -1,12 +1,17 @@
 #!/usr/bin/env python3
-"""Benchmark: time to the k lowest eigenpairs at relative residual 1e-6 on one MI355X.
+"""Benchmark: time to the k lowest eigenpairs at relative residual 1e-6 on one MI355X, against
+plain float64 SPPC on the same GPU.
 
 One step = sppc_setup (device format, H0hat eigenpairs, p = 0) + sppc_solve (SPPC steps,
 continuation, final float64 check) on the level-structured workload
 L4-2k/20k/150k/1M-d200-k8 (n = 1,172,000, ~118M stored upper entries), with H already
-resident in HBM as an upper-triangular CSR.  Prints one JSON line.
+resident in HBM as an upper-triangular CSR.  The timed form (--mode, default mixed+mpnn:
+float32 products with float64 accumulation, float64 refinement, learned preconditioner in the
+continuation) is followed by the same number of plain float64 steps with the diagonal
+preconditioner (--no-compare skips them).  Prints one JSON line.
 
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload 1] [--mode plain|mixed]
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload 1]
+                  [--mode plain|mixed|plain+mpnn|mixed+mpnn] [--no-compare]
                   [--no-cpu-baseline] [--calibrate-copy] [--spmm-only R]
 """
 from __future__ import annotations
@@ -23,6 +28,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+MODES = ("plain", "mixed", "plain+mpnn", "mixed+mpnn")
 
 
 def parse():
@@ -31,12 +37,14 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", type=int, default=1)
-    ap.add_argument("--mode", default="plain", choices=["plain", "mixed"])
+    ap.add_argument("--mode", default="mixed+mpnn", choices=MODES)
+    ap.add_argument("--no-compare", action="store_true", help="do not time plain float64 SPPC as well")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of known size (HBM counter calibration)")
     ap.add_argument("--spmm-only", type=int, default=0,
                     help="only time this many block products with H (profiling runs)")
+    ap.add_argument("--spmm-f32", action="store_true", help="with --spmm-only: float32 X (mixed form)")
     ap.add_argument("--verbose", action="store_true")
     return ap.parse_args()
 
@@ -73,48 +81,62 @@ def main():
     t_gen = time.time() - t0
     rp, col, val = P.upload(A, dtype=torch.float64)
     torch.cuda.synchronize()
-    mixed = args.mode == "mixed"
-    opts = P.sppc_default_opts(precision=P.SPPC_PREC_MIXED if mixed else P.SPPC_PREC_FP64,
-                               verbose=1 if args.verbose else 0)
-    stream = torch.cuda.current_stream()
 
     if args.spmm_only:
+        opts = P.sppc_default_opts(precision=P.SPPC_PREC_MIXED if args.spmm_f32 else P.SPPC_PREC_FP64)
         ctx = P.sppc_setup(rp, col, val, A.level_offsets, w.n_small_levels, w.k, opts)
         X = torch.randn(A.n, w.k, dtype=torch.float64, device="cuda")
-        Y = torch.empty_like(X)
+        if args.spmm_f32:
+            X = X.float()
+        Y = torch.empty(A.n, w.k, dtype=torch.float64, device="cuda")
         for _ in range(args.spmm_only):
             P.sppc_spmm(ctx, X, Y)
         torch.cuda.synchronize()
-        print(json.dumps({"spmm_launches": args.spmm_only, "n": A.n, "b": w.k}))
+        print(json.dumps({"spmm_launches": args.spmm_only, "n": A.n, "b": w.k,
+                          "x": "f32" if args.spmm_f32 else "f64"}))
         return
 
-    def one_step():
-        ctx = P.sppc_setup(rp, col, val, A.level_offsets, w.n_small_levels, w.k, opts)
-        ev, Z, rrn, st, status = P.sppc_solve(ctx, want_vectors=True)
-        P.sppc_destroy(ctx)
-        return ev, rrn, st, status
+    weights = None
+    if "mpnn" in args.mode:
+        from paper_2407_08901_amd import mpnn_train
+        weights = mpnn_train.load()
 
-    for _ in range(args.warmup):
-        one_step()
-    torch.cuda.synchronize()
-    results = []
-    t_start = time.perf_counter()
-    for _ in range(args.steps):
-        results.append(one_step())
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t_start
-    per = elapsed / args.steps
+    def make_step(mode):
+        mixed = mode.startswith("mixed")
+        mpnn = mode.endswith("mpnn")
+        opts = P.sppc_default_opts(precision=P.SPPC_PREC_MIXED if mixed else P.SPPC_PREC_FP64,
+                                   precond=P.SPPC_CORR_MPNN if mpnn else P.SPPC_CORR_JACOBI,
+                                   verbose=1 if args.verbose else 0)
+
+        def one_step():
+            ctx = P.sppc_setup(rp, col, val, A.level_offsets, w.n_small_levels, w.k, opts)
+            if mpnn:
+                P.sppc_mpnn_set_weights(ctx, weights)
+            ev, Z, rrn, st, status = P.sppc_solve(ctx, want_vectors=True)
+            P.sppc_destroy(ctx)
+            return ev, rrn, st, status
+        return one_step
+
+    def timed(mode):
+        one_step = make_step(mode)
+        for _ in range(args.warmup):
+            one_step()
+        torch.cuda.synchronize()
+        results = []
+        t_start = time.perf_counter()
+        for _ in range(args.steps):
+            results.append(one_step())
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t_start) / args.steps, results
+
+    per, results = timed(args.mode)
     ev, rrn, st, status = results[-1]
 
-    # roofline of the dominant kernel: the block product with H, from the library's own
-    # HIP events on its stream over the timed steps
+    # roofline of the dominant kernel: the block product with H, from the library's own HIP
+    # events on its stream (kernel launches only) and its algorithmic byte count
     spmm_ms = sum(r[2]["t_spmm_ms"] for r in results)
     spmm_calls = sum(r[2]["spmm_calls"] for r in results)
-    spmm_cols = sum(r[2]["spmm_cols"] for r in results)
-    nnz_up = A.nnz
-    mat_bytes = nnz_up * (8 + 4) + (A.n + 1) * 8          # upper triangle once: f64 value, i32 col, i64 row ptr
-    vec_bytes_per_col = A.n * 8 * 2                        # X read + Y written (float64)
-    alg_bytes = spmm_calls * mat_bytes + spmm_cols * vec_bytes_per_col
+    alg_bytes = sum(r[2]["spmm_alg_bytes"] for r in results)
     achieved = alg_bytes / (spmm_ms * 1e-3) / 1e9 if spmm_ms > 0 else 0.0
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
@@ -122,22 +144,32 @@ def main():
             "avg_launch_ms": round(spmm_ms / max(spmm_calls, 1), 4),
             "alg_bytes_per_launch_avg": int(alg_bytes / max(spmm_calls, 1))}
 
+    mixed = args.mode.startswith("mixed")
     line = {
         "metric": "time to k eigenpairs at resid 1e-6 vs plain FP64 SPPC; SpMM HBM GB/s",
         "value": round(per, 4), "unit": "s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(per * 1e3, 2), "higher_is_better": False, "scaling": "strong",
-        "vs_baseline": None, "dtype": "f64" if not mixed else "f32+f64",
+        "vs_baseline": None, "dtype": "f32+f64" if mixed else "f64",
         "data": "synthetic",
-        "config": {"workload": w.name, "n": A.n, "n0": w.n0, "k": w.k, "nnz_upper": nnz_up,
-                   "tol": 1e-6, "mode": args.mode, "precond": "jacobi"},
+        "config": {"workload": w.name, "n": A.n, "n0": w.n0, "k": w.k, "nnz_upper": A.nnz,
+                   "tol": 1e-6, "mode": args.mode},
         "converged": bool(st["converged"]), "max_rrn": max(rrn), "evals": ev,
-        "iterations": st["iterations"], "cont_steps": st["cont_steps"], "n_spmv": st["n_spmv"],
+        "iterations": st["iterations"], "cont_steps": st["cont_steps"], "refine_steps": st["refine_steps"],
+        "mpnn_steps": st["mpnn_steps"], "n_spmv": st["n_spmv"],
         "breakdown_ms": {k: round(st[k], 2) for k in ("t_setup_ms", "t_solve_ms", "t_spmm_ms", "t_small_ms",
-                                                      "t_ortho_ms", "t_rr_ms")},
+                                                      "t_ortho_ms", "t_rr_ms", "t_h0_ms")},
         "cg_iterations": st["cg_iterations"], "h0_iterations": st["h0_iterations"],
         "roofline": roof,
         "generate_s": round(t_gen, 2),
     }
+    if not args.no_compare and args.mode != "plain":
+        per_p, res_p = timed("plain")
+        ev_p, rrn_p, st_p, _ = res_p[-1]
+        line["plain_fp64"] = {"s": round(per_p, 4), "speedup": round(per_p / per, 3),
+                              "iterations": st_p["iterations"], "cont_steps": st_p["cont_steps"],
+                              "n_spmv": st_p["n_spmv"], "max_rrn": max(rrn_p),
+                              "max_rel_eval_diff": float(np.max(np.abs(np.array(ev) - np.array(ev_p)) /
+                                                                np.abs(np.array(ev_p))))}
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(A, w, st)
     print(json.dumps(line))

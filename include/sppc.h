@@ -99,10 +99,14 @@ typedef struct {
   int converged;       /* 1 if every pair met tol (after the final check when enabled) */
   double t_setup_ms;   /* device format, H0hat extraction, zeroth order */
   double t_solve_ms;   /* iteration loop + final check */
-  double t_spmm_ms;    /* time inside the H products */
+  double t_spmm_ms;    /* time inside the block-product kernels with H (HIP events) */
   double t_small_ms;   /* time inside the small-space solves */
   double t_ortho_ms;   /* block Gram-Schmidt + Cholesky-QR */
   double t_rr_ms;      /* projected matrix, eigensolve, Ritz vectors, residuals */
+  double spmm_alg_bytes; /* algorithmic bytes of the counted products with H: the stored upper
+                            triangle once (values as read: float32 when lossless or mixed;
+                            int32 columns; int64 row pointers) + X read + Y written */
+  double t_h0_ms;      /* time inside products with H0hat outside the small solves */
 } sppc_stats;
 
 typedef struct sppc_ctx sppc_ctx;
@@ -211,31 +215,37 @@ sppc_status sppc_mpnn_set_weights(sppc_ctx* ctx, const float* w_host);
  *   w_host        289 parameters (host)
  *   R_dev, X_dev  n x S row-major: residuals and unit Ritz vectors (device)
  *   theta_host    [S] Ritz values
+ *   Q_dev, m      optional basis (n x m row-major, orthonormal columns spanning every x_s, device):
+ *                 the output is then projected as t - Q (Q^T t), the part that enlarges the basis.
+ *                 NULL / 0: t - x (x^T t).  m <= 512.
  *   E_dev         n x S targets, or NULL (then no loss / gradient)
- *   T_dev         n x S output t~ (device), or NULL
- *   loss_host     [S] per-sample loss 1 - cos^2(t~, e), or NULL
+ *   T_dev         n x S projected output (device), or NULL
+ *   loss_host     [S] per-sample loss 1 - cos^2(projected output, e), or NULL
  *   grad_host     [289] gradient of the mean loss, or NULL
  *   f64           1: float64 arithmetic and exact weights (gradient checks); 0: float32 arithmetic
  *                 with bfloat16-rounded weights (the solver's form)
+ * Errors: SPPC_E_ARG (S out of range, missing arrays, loss/grad requested without E).
  */
 sppc_status sppc_mpnn_eval(sppc_ctx* ctx, const float* w_host, int S, const double* R_dev, const double* X_dev,
-                           const double* theta_host, const double* E_dev, double* T_dev, double* loss_host,
-                           double* grad_host, int f64);
+                           const double* theta_host, const double* Q_dev, int m, const double* E_dev,
+                           double* T_dev, double* loss_host, double* grad_host, int f64);
 
 /*
  * One training step on the GPU: forward, backward (one more product with H), and an Adam update
- * (beta 0.9 / 0.999) of the float32 master weights.
+ * (beta 0.9 / 0.999) of the float32 master weights.  Arguments as in sppc_mpnn_eval.
  *   state_dev  device float[4 x 289]: weights | first moments | second moments | bfloat16 copy
  *   step       Adam step count (>= 1); loss_host: mean loss of the batch before the update (or NULL)
  */
 sppc_status sppc_mpnn_train_step(sppc_ctx* ctx, float* state_dev, int S, const double* R_dev, const double* X_dev,
-                                 const double* theta_host, const double* E_dev, float lr, int step,
-                                 double* loss_host);
+                                 const double* theta_host, const double* Q_dev, int m, const double* E_dev,
+                                 float lr, int step, double* loss_host);
 
-/* Training targets: E[:, s] = psi_s / (psi_s^T x_s) - x_s for unit Ritz vectors x_s and the exact
- * eigenvectors psi_s (all n x S, device): the exact Jacobi-Davidson correction in the limit where
- * theta reaches the eigenvalue. */
-sppc_status sppc_mpnn_target(sppc_ctx* ctx, int S, const double* X_dev, const double* Psi_dev, double* E_dev);
+/* Training targets E = (I - Q Q^T) Psi (n x S, device) for the exact eigenvectors Psi (n x S, device)
+ * and the basis Q (n x m, orthonormal columns, device): the part of each eigenvector that a
+ * subspace expansion still has to supply.  A direction that the Davidson step of Sec. V
+ * orthogonalises against Q adds psi_s to the span exactly when it is parallel to E[:, s]. */
+sppc_status sppc_mpnn_target(sppc_ctx* ctx, int S, const double* Q_dev, int m, const double* Psi_dev,
+                             double* E_dev);
 
 const char* sppc_last_error(const sppc_ctx* ctx);
 

@@ -47,8 +47,15 @@ def jacobi_step(d, theta, r):
     return r / den
 
 
-def forward(w, A, d, lev, theta, r, x):
-    """Returns t~ and the intermediate values used by the backward pass."""
+def project(t, x, Q=None):
+    """t - x (x^T t), or, with a basis Q (orthonormal columns, x in its span), t - Q (Q^T t)."""
+    if Q is None:
+        return t - x * (x @ t)
+    return t - Q @ (Q.T @ t)
+
+
+def forward(w, A, d, lev, theta, r, x, Q=None):
+    """Returns the projected output and the intermediate values used by the backward pass."""
     Ws, Wn, b1, ws, wn, b2 = unpack(w)
     n = r.shape[0]
     sr = np.sqrt(np.mean(r * r))
@@ -61,7 +68,7 @@ def forward(w, A, d, lev, theta, r, x):
     o = h @ ws + A @ u + b2
     tJ = jacobi_step(d, theta, r)
     t = tJ * (1.0 + o)
-    t_proj = t - x * (x @ t)
+    t_proj = project(t, x, Q)
     cache = dict(f=f, g=g, h=h, u=u, o=o, tJ=tJ, t=t)
     return t_proj, cache
 
@@ -73,14 +80,18 @@ def loss(t_proj, e):
     return 1.0 - c1 * c1 / (c2 * c3)
 
 
-def loss_and_grad(w, A, d, lev, theta, r, x, e):
-    """Loss of one sample and its gradient with respect to the 289 parameters."""
+def loss_and_grad(w, A, d, lev, theta, r, x, e, Q=None):
+    """Loss of one sample and its gradient with respect to the 289 parameters.
+
+    With a basis Q the output is projected onto the complement of span(Q) (only that part
+    enlarges the subspace) and compared with e = (I - Q Q^T) psi.
+    """
     Ws, Wn, b1, ws, wn, b2 = unpack(w)
-    tp, c = forward(w, A, d, lev, theta, r, x)
+    tp, c = forward(w, A, d, lev, theta, r, x, Q)
     c1, c2, c3 = tp @ e, tp @ tp, e @ e
     L = 1.0 - c1 * c1 / (c2 * c3)
     dtp = -(2.0 * c1 / (c2 * c3)) * e + (2.0 * c1 * c1 / (c2 * c2 * c3)) * tp
-    dt = dtp - x * (x @ dtp)                       # through t~ = (I - x x^T) t
+    dt = project(dtp, x, Q)                        # through the (symmetric) projection
     do = dt * c["tJ"]                              # t = tJ (1 + o)
     du = A @ do                                    # o contains A u, A symmetric
     h = c["h"]

@@ -51,7 +51,7 @@ class sppc_stats(ctypes.Structure):
                 ("basis_size", ctypes.c_int), ("cg_iterations", ctypes.c_int), ("h0_iterations", ctypes.c_int),
                 ("converged", ctypes.c_int), ("t_setup_ms", ctypes.c_double), ("t_solve_ms", ctypes.c_double),
                 ("t_spmm_ms", ctypes.c_double), ("t_small_ms", ctypes.c_double), ("t_ortho_ms", ctypes.c_double),
-                ("t_rr_ms", ctypes.c_double)]
+                ("t_rr_ms", ctypes.c_double), ("spmm_alg_bytes", ctypes.c_double), ("t_h0_ms", ctypes.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -89,9 +89,9 @@ def lib():
         L.sppc_destroy.restype = None
         fp = ctypes.POINTER(ctypes.c_float)
         L.sppc_mpnn_set_weights.argtypes = [vp, fp]
-        L.sppc_mpnn_eval.argtypes = [vp, fp, c_int, vp, vp, dp, vp, vp, dp, dp, c_int]
-        L.sppc_mpnn_train_step.argtypes = [vp, vp, c_int, vp, vp, dp, vp, ctypes.c_float, c_int, dp]
-        L.sppc_mpnn_target.argtypes = [vp, c_int, vp, vp, vp]
+        L.sppc_mpnn_eval.argtypes = [vp, fp, c_int, vp, vp, dp, vp, c_int, vp, vp, dp, dp, c_int]
+        L.sppc_mpnn_train_step.argtypes = [vp, vp, c_int, vp, vp, dp, vp, c_int, vp, ctypes.c_float, c_int, dp]
+        L.sppc_mpnn_target.argtypes = [vp, c_int, vp, c_int, vp, vp]
         for name in ("sppc_default_opts", "sppc_setup", "sppc_spmm", "sppc_correct", "sppc_rayleigh_ritz",
                      "sppc_solve", "sppc_get", "sppc_mpnn_set_weights", "sppc_mpnn_eval", "sppc_mpnn_train_step",
                      "sppc_mpnn_target"):
@@ -226,36 +226,50 @@ def sppc_mpnn_set_weights(ctx: Context, w) -> None:
     _check(lib().sppc_mpnn_set_weights(ctx.handle, p), ctx.handle)
 
 
+def _basis(ctx: Context, Q: Optional[torch.Tensor]):
+    if Q is None:
+        return None, 0
+    if Q.dim() != 2 or Q.shape[0] != ctx.n or Q.dtype != torch.float64 or not Q.is_contiguous():
+        raise ValueError("Q must be a contiguous float64 n x m tensor")
+    return _dptr(Q), Q.shape[1]
+
+
 def sppc_mpnn_eval(ctx: Context, w, R: torch.Tensor, X: torch.Tensor, theta, E: Optional[torch.Tensor] = None,
-                   want_output: bool = True, f64: bool = False):
-    """Returns (T or None, loss list or None, grad list or None).  R, X, E: n x S float64 GPU."""
+                   want_output: bool = True, f64: bool = False, Q: Optional[torch.Tensor] = None):
+    """Returns (T or None, loss list or None, grad list or None).  R, X, E: n x S float64 GPU;
+    Q: optional n x m basis for the output projection."""
     a, p = _fptr(w)
     S = R.shape[1]
     for t in (R, X, E):
         if t is not None and (t.shape != (ctx.n, S) or t.dtype != torch.float64 or not t.is_contiguous()):
             raise ValueError("R, X, E must be contiguous float64 n x S")
+    qp, m = _basis(ctx, Q)
     T = torch.empty_like(R) if want_output else None
     th = (ctypes.c_double * S)(*[float(x) for x in theta])
     loss = (ctypes.c_double * S)() if E is not None else None
     grad = (ctypes.c_double * SPPC_MPNN_NPARAM)() if E is not None else None
-    _check(lib().sppc_mpnn_eval(ctx.handle, p, S, _dptr(R), _dptr(X), th, _dptr(E), _dptr(T), loss, grad,
+    _check(lib().sppc_mpnn_eval(ctx.handle, p, S, _dptr(R), _dptr(X), th, qp, m, _dptr(E), _dptr(T), loss, grad,
                                 1 if f64 else 0), ctx.handle)
     return T, (list(loss) if loss is not None else None), (list(grad) if grad is not None else None)
 
 
-def sppc_mpnn_train_step(ctx: Context, state: torch.Tensor, R, X, theta, E, lr: float, step: int) -> float:
+def sppc_mpnn_train_step(ctx: Context, state: torch.Tensor, R, X, theta, E, lr: float, step: int,
+                         Q: Optional[torch.Tensor] = None) -> float:
     """state: float32 GPU tensor [4 * 289] (weights, Adam moments, bfloat16 copy)."""
     S = R.shape[1]
+    qp, m = _basis(ctx, Q)
     th = (ctypes.c_double * S)(*[float(x) for x in theta])
     loss = ctypes.c_double()
     _check(lib().sppc_mpnn_train_step(ctx.handle, ctypes.c_void_p(state.data_ptr()), S, _dptr(R), _dptr(X), th,
-                                      _dptr(E), ctypes.c_float(lr), step, ctypes.byref(loss)), ctx.handle)
+                                      qp, m, _dptr(E), ctypes.c_float(lr), step, ctypes.byref(loss)), ctx.handle)
     return loss.value
 
 
-def sppc_mpnn_target(ctx: Context, X: torch.Tensor, Psi: torch.Tensor) -> torch.Tensor:
-    E = torch.empty_like(X)
-    _check(lib().sppc_mpnn_target(ctx.handle, X.shape[1], _dptr(X), _dptr(Psi), _dptr(E)), ctx.handle)
+def sppc_mpnn_target(ctx: Context, Q: torch.Tensor, Psi: torch.Tensor) -> torch.Tensor:
+    """E = (I - Q Q^T) Psi on the GPU."""
+    qp, m = _basis(ctx, Q)
+    E = torch.empty_like(Psi)
+    _check(lib().sppc_mpnn_target(ctx.handle, Psi.shape[1], qp, m, _dptr(Psi), _dptr(E)), ctx.handle)
     return E
 
 

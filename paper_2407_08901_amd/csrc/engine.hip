@@ -58,7 +58,7 @@ struct Basis {
   double* T = nullptr;  // ldq x ldq
 };
 
-enum Cat { C_SPMM = 0, C_SMALL, C_ORTHO, C_RR, C_NCAT };
+enum Cat { C_SPMM = 0, C_SMALL, C_ORTHO, C_RR, C_H0, C_NCAT };
 
 struct EventTimer {
   std::vector<hipEvent_t> pool;
@@ -141,6 +141,8 @@ struct sppc_ctx {
   double *mp_sel = nullptr, *mp_th = nullptr, *mp_grad = nullptr, *mp_loss = nullptr, *mp_wd = nullptr;
   float *mp_w = nullptr, *mp_wq = nullptr;
   int mp_S = 0;
+  double* mp_bwork = nullptr;  // basis-projection workspace (training)
+  int64_t mp_bwork_cap = 0;
   std::vector<int> mp_fallback;     // per pair: 1 = use the diagonal step
   std::vector<double> mp_prev_rrn;  // residual when the learned step was last used (0 = not used)
   sppc_stats st{};
@@ -148,7 +150,8 @@ struct sppc_ctx {
   double* pin = nullptr;  // pinned host staging
   int* pin_i = nullptr;
   EventTimer tm;
-  double tacc[C_NCAT] = {0, 0, 0, 0};
+  double tacc[C_NCAT] = {0, 0, 0, 0, 0};
+  int64_t nnz_up = 0;  // stored upper-triangle entries of the input
 };
 
 namespace sppc {
@@ -158,28 +161,42 @@ thread_local std::string g_setup_err;
 
 inline double* Gh(sppc_ctx* c, int l) { return c->Ghist + (int64_t)l * c->gstride; }
 
-// Y = A X on the operator of the basis: the whole H (mixed or float64) or H0hat.
+// Algorithmic bytes of one block product with H: the upper triangle once (values as the kernel
+// reads them: float32 when stored losslessly or in mixed mode, int32 columns), the row pointers,
+// X read (float32 in mixed mode) and Y written (float64).
+double spmm_alg_bytes(const sppc_ctx* c, int b, bool xf32) {
+  const double vb = (xf32 || !c->H.val64) ? 4.0 : 8.0;
+  const double xb = xf32 ? 4.0 : 8.0;
+  return (double)c->nnz_up * (vb + 4.0) + (double)(c->n + 1) * 8.0 + (double)c->n * b * (xb + 8.0);
+}
+
+// Y = A X on the operator of the basis: the whole H (mixed or float64) or H0hat.  Products
+// with H are counted and timed (kernel only) in the statistics.
 struct Op {
+  sppc_ctx* c;
   const DevCSR* A;
   bool mixed;
-  float* X32;
-  sppc_stats* st;
-  void operator()(const double* X, int64_t ldx, double* Y, int64_t ldy, int b, hipStream_t s) const {
-    if (mixed) {
-      copy_to_f32(A->n, b, X, ldx, X32, b, s);
-      spmm_f32(*A, X32, b, Y, ldy, b, nullptr, s);
-    } else {
-      spmm_f64(*A, X, ldx, Y, ldy, b, nullptr, s);
-    }
-    if (st) {
-      st->n_spmv += b;
-      st->spmm_calls += 1;
-      st->spmm_cols += b;
-    }
-  }
+  bool isH;
+  void operator()(const double* X, int64_t ldx, double* Y, int64_t ldy, int b, hipStream_t s) const;
 };
 
 void sync(sppc_ctx* c) { SPPC_HIP(hipStreamSynchronize(c->s)); }
+
+void Op::operator()(const double* X, int64_t ldx, double* Y, int64_t ldy, int b, hipStream_t s) const {
+  if (mixed) copy_to_f32(A->n, b, X, ldx, c->X32, b, s);
+  const size_t t0 = c->tm.begin(isH ? C_SPMM : C_H0);
+  if (mixed)
+    spmm_f32(*A, c->X32, b, Y, ldy, b, nullptr, s);
+  else
+    spmm_f64(*A, X, ldx, Y, ldy, b, nullptr, s);
+  c->tm.end(t0);
+  if (isH) {
+    c->st.n_spmv += b;
+    c->st.spmm_calls += 1;
+    c->st.spmm_cols += b;
+    c->st.spmm_alg_bytes += spmm_alg_bytes(c, b, mixed);
+  }
+}
 
 void to_host(sppc_ctx* c, const double* dev, int count, double* host) {
   SPPC_HIP(hipMemcpyAsync(c->pin, dev, sizeof(double) * count, hipMemcpyDeviceToHost, c->s));
@@ -245,9 +262,7 @@ int ortho_append(sppc_ctx* c, Basis& b, const double* P, int bw, const Op& op, i
     cholqr_second(bw, c->Gm, c->M2, c->Rt, c->info, s);
     gemm_nn(n, kept, kept, c->Wb, kept, c->M2, bw, b.Q + m, b.ldq, 1.0, 0.0, s);
     c->tm.end(t0);
-    t0 = c->tm.begin(C_SPMM);
     op(b.Q + m, b.ldq, b.HQ + m, b.ldq, kept, s);
-    c->tm.end(t0);
     t0 = c->tm.begin(C_RR);
     gemm_tn(n, m + kept, kept, b.Q, b.ldq, b.HQ + m, b.ldq, c->Xt, kept, 1.0, 0.0, c->work, s);
     t_extend(m, kept, c->Xt, kept, b.T, b.ldq, s);
@@ -303,7 +318,7 @@ void zeroth_order(sppc_ctx* c) {
   SPPC_HIP(hipMemcpyAsync(c->pin, gtmp + n0, sizeof(double), hipMemcpyDeviceToHost, s));
   sync(c);
   bup = c->pin[0];
-  Op op{&c->H0, false, nullptr, nullptr};
+  Op op{c, &c->H0, false, false};
   select_smallest(n0, h0diag, nb, c->idx, s);
   unit_block(n0, nb, c->idx, c->Psi, nb, s);
   ortho_append(c, sb, c->Psi, nb, op, -1);
@@ -427,6 +442,19 @@ void mpnn_ensure(sppc_ctx* c, int S) {
   }
 }
 
+// Basis argument of the training entry points (NULL / m = 0: project against x only).
+const MpnnBasis* mpnn_basis(sppc_ctx* c, const double* Q_dev, int m, MpnnBasis& B) {
+  if (!Q_dev || m <= 0) return nullptr;
+  if (m > 512) throw Error(SPPC_E_ARG, "basis wider than 512 columns");
+  const int64_t need = mpnn_basis_work_doubles(c->n, m);
+  if (need > c->mp_bwork_cap) {  // sized once for the widest basis
+    c->mp_bwork_cap = mpnn_basis_work_doubles(c->n, 512);
+    c->mp_bwork = c->arena.alloc<double>((size_t)c->mp_bwork_cap);
+  }
+  B = MpnnBasis{Q_dev, m, m, c->mp_bwork};
+  return &B;
+}
+
 void upload_theta(sppc_ctx* c, const double* th, int S) {
   for (int i = 0; i < S; ++i) c->pin[3 * NWMAX + i] = th[i];
   SPPC_HIP(hipMemcpyAsync(c->mp_th, c->pin + 3 * NWMAX, sizeof(double) * S, hipMemcpyHostToDevice, c->s));
@@ -475,7 +503,7 @@ void correct_continuation(sppc_ctx* c, int kind) {
       for (int a = 0; a < S; ++a) th[a] = c->theta_h[sel[a]];
       upload_theta(c, th.data(), S);
       mpnn_run<float>(c->H, c->diag, c->mp_lev, c->mp_Ad, c->mp_A1, c->mp_Al, c->mp_wq, S, Rs, S, Zs, S,
-                      c->mp_th, nullptr, Ts, nullptr, nullptr, c->mp_work, s);
+                      c->mp_th, nullptr, Ts, nullptr, nullptr, c->mp_work, nullptr, s);
       // a non-finite or vanishing learned direction falls back to the diagonal step
       colsumsq(n, S, Ts, S, c->sumsq, c->work, s);
       SPPC_HIP(hipMemcpyAsync(c->pin + 2 * NWMAX, c->sumsq, sizeof(double) * S, hipMemcpyDeviceToHost, s));
@@ -503,7 +531,7 @@ void correct_continuation(sppc_ctx* c, int kind) {
 
 int append_and_rr(sppc_ctx* c) {
   Basis& b = c->B;
-  Op op{&c->H, c->o.precision == SPPC_PREC_MIXED && !c->refining, c->X32, &c->st};
+  Op op{c, &c->H, c->o.precision == SPPC_PREC_MIXED && !c->refining, true};
   int added = 0;
   if (c->pend_b > 0) {
     const bool pert = c->pend_kind == SPPC_CORR_PERTURBATIVE;
@@ -526,10 +554,11 @@ void final_check(sppc_ctx* c) {
   const int64_t n = c->n;
   size_t t0 = c->tm.begin(C_SPMM);
   spmm_f64(c->H, c->Z, k, c->Wb, k, k, nullptr, s);
+  c->tm.end(t0);
   c->st.n_spmv += k;
   c->st.spmm_calls += 1;
   c->st.spmm_cols += k;
-  c->tm.end(t0);
+  c->st.spmm_alg_bytes += spmm_alg_bytes(c, k, false);
   t0 = c->tm.begin(C_RR);
   gemm_tn(n, k, k, c->Z, k, c->Wb, k, c->Gm, k, 1.0, 0.0, c->work, s);
   t_from_full(k, c->Gm, k, c->Xt, k, s);
@@ -573,6 +602,7 @@ void setup_impl(sppc_ctx* c, const sppc_csr* Hin, const int64_t* loff, int L, in
   for (int l = 0; l < L; ++l)
     if (c->loff[l + 1] <= c->loff[l]) throw Error(SPPC_E_ARG, "levels must be non-empty and ascending");
   c->n = Hin->n;
+  c->nnz_up = Hin->nnz;
   c->n0 = c->loff[nsmall];
   c->k = k;
   sppc_opts& o = c->o;
@@ -696,10 +726,8 @@ void setup_impl(sppc_ctx* c, const sppc_csr* Hin, const int64_t* loff, int L, in
   Basis& b = c->B;
   fill_block_zero(n, k, b.Q, b.ldq, s);
   copy_block(n0, k, c->Psihat, c->D, b.Q, b.ldq, s);
-  Op op{&c->H, mixed, c->X32, &c->st};
-  size_t t0 = c->tm.begin(C_SPMM);
+  Op op{c, &c->H, mixed, true};
   op(b.Q, b.ldq, b.HQ, b.ldq, k, s);
-  c->tm.end(t0);
   gemm_tn(n, k, k, b.Q, b.ldq, b.HQ, b.ldq, c->Xt, k, 1.0, 0.0, c->work, s);
   t_from_full(k, c->Xt, k, b.T, b.ldq, s);
   b.m = k;
@@ -793,6 +821,7 @@ sppc_status solve_impl(sppc_ctx* c, double* evals, double* evecs, double* rrn, s
   c->st.t_small_ms = c->tacc[C_SMALL];
   c->st.t_ortho_ms = c->tacc[C_ORTHO];
   c->st.t_rr_ms = c->tacc[C_RR];
+  c->st.t_h0_ms = c->tacc[C_H0];
   if (st) *st = c->st;
   return conv ? SPPC_OK : SPPC_E_NOCONV;
 }
@@ -949,24 +978,29 @@ sppc_status sppc_mpnn_set_weights(sppc_ctx* c, const float* w_host) {
 }
 
 sppc_status sppc_mpnn_eval(sppc_ctx* c, const float* w_host, int S, const double* R_dev, const double* X_dev,
-                           const double* theta_host, const double* E_dev, double* T_dev, double* loss_host,
-                           double* grad_host, int f64) {
-  if (!c || !w_host || S < 1 || S > 64 || !R_dev || !X_dev || !theta_host) return SPPC_E_ARG;
+                           const double* theta_host, const double* Q_dev, int m, const double* E_dev,
+                           double* T_dev, double* loss_host, double* grad_host, int f64) {
+  if (!c || !w_host || S < 1 || S > 64 || !R_dev || !X_dev || !theta_host || m < 0) return SPPC_E_ARG;
   if ((loss_host || grad_host) && !E_dev) return SPPC_E_ARG;
   return guarded(c, [&]() {
     mpnn_ensure(c, S);
     hipStream_t s = c->s;
+    MpnnBasis B;
+    const MpnnBasis* bp = mpnn_basis(c, Q_dev, m, B);
     SPPC_HIP(hipMemcpy(c->mp_w, w_host, sizeof(float) * SPPC_MPNN_NPARAM, hipMemcpyHostToDevice));
     upload_theta(c, theta_host, S);
+    double* grad = grad_host ? c->mp_grad : nullptr;
+    double* lossd = loss_host ? c->mp_loss : nullptr;
+    const double* E = (grad || lossd) ? E_dev : nullptr;
     if (f64) {
       std::vector<double> wd(w_host, w_host + SPPC_MPNN_NPARAM);
       SPPC_HIP(hipMemcpy(c->mp_wd, wd.data(), sizeof(double) * SPPC_MPNN_NPARAM, hipMemcpyHostToDevice));
       mpnn_run<double>(c->H, c->diag, c->mp_lev, c->mp_Ad, c->mp_A1, c->mp_Al, c->mp_wd, S, R_dev, S, X_dev, S,
-                       c->mp_th, E_dev, T_dev, c->mp_grad, c->mp_loss, c->mp_work, s);
+                       c->mp_th, E, T_dev, c->mp_grad, c->mp_loss, c->mp_work, bp, s);
     } else {
       mpnn_round_bf16(SPPC_MPNN_NPARAM, c->mp_w, c->mp_wq, nullptr, s);
       mpnn_run<float>(c->H, c->diag, c->mp_lev, c->mp_Ad, c->mp_A1, c->mp_Al, c->mp_wq, S, R_dev, S, X_dev, S,
-                      c->mp_th, E_dev, T_dev, c->mp_grad, c->mp_loss, c->mp_work, s);
+                      c->mp_th, E, T_dev, c->mp_grad, c->mp_loss, c->mp_work, bp, s);
     }
     sync(c);
     if (loss_host) SPPC_HIP(hipMemcpy(loss_host, c->mp_loss, sizeof(double) * S, hipMemcpyDeviceToHost));
@@ -976,22 +1010,24 @@ sppc_status sppc_mpnn_eval(sppc_ctx* c, const float* w_host, int S, const double
 }
 
 sppc_status sppc_mpnn_train_step(sppc_ctx* c, float* state_dev, int S, const double* R_dev, const double* X_dev,
-                                 const double* theta_host, const double* E_dev, float lr, int step,
-                                 double* loss_host) {
-  if (!c || !state_dev || S < 1 || S > 64 || !R_dev || !X_dev || !theta_host || !E_dev || step < 1)
+                                 const double* theta_host, const double* Q_dev, int m, const double* E_dev,
+                                 float lr, int step, double* loss_host) {
+  if (!c || !state_dev || S < 1 || S > 64 || !R_dev || !X_dev || !theta_host || !E_dev || step < 1 || m < 0)
     return SPPC_E_ARG;
   return guarded(c, [&]() {
     mpnn_ensure(c, S);
     hipStream_t s = c->s;
+    MpnnBasis B;
+    const MpnnBasis* bp = mpnn_basis(c, Q_dev, m, B);
     float* w = state_dev;
-    float* m = w + SPPC_MPNN_NPARAM;
-    float* v = m + SPPC_MPNN_NPARAM;
+    float* mo = w + SPPC_MPNN_NPARAM;
+    float* v = mo + SPPC_MPNN_NPARAM;
     float* wq = v + SPPC_MPNN_NPARAM;
     upload_theta(c, theta_host, S);
     mpnn_round_bf16(SPPC_MPNN_NPARAM, w, wq, nullptr, s);
     mpnn_run<float>(c->H, c->diag, c->mp_lev, c->mp_Ad, c->mp_A1, c->mp_Al, wq, S, R_dev, S, X_dev, S, c->mp_th,
-                    E_dev, nullptr, c->mp_grad, c->mp_loss, c->mp_work, s);
-    mpnn_adam(w, m, v, c->mp_grad, lr, step, wq, s);
+                    E_dev, nullptr, c->mp_grad, c->mp_loss, c->mp_work, bp, s);
+    mpnn_adam(w, mo, v, c->mp_grad, lr, step, wq, s);
     if (loss_host) {
       std::vector<double> lv(S);
       SPPC_HIP(hipMemcpyAsync(lv.data(), c->mp_loss, sizeof(double) * S, hipMemcpyDeviceToHost, s));
@@ -1004,11 +1040,13 @@ sppc_status sppc_mpnn_train_step(sppc_ctx* c, float* state_dev, int S, const dou
   });
 }
 
-sppc_status sppc_mpnn_target(sppc_ctx* c, int S, const double* X_dev, const double* Psi_dev, double* E_dev) {
-  if (!c || S < 1 || S > 64 || !X_dev || !Psi_dev || !E_dev) return SPPC_E_ARG;
+sppc_status sppc_mpnn_target(sppc_ctx* c, int S, const double* Q_dev, int m, const double* Psi_dev,
+                             double* E_dev) {
+  if (!c || S < 1 || S > 64 || !Q_dev || m < 1 || !Psi_dev || !E_dev) return SPPC_E_ARG;
   return guarded(c, [&]() {
     mpnn_ensure(c, S);
-    mpnn_target(c->n, S, X_dev, Psi_dev, E_dev, c->mp_loss, c->work, c->s);
+    MpnnBasis B;
+    mpnn_target(c->n, S, *mpnn_basis(c, Q_dev, m, B), Psi_dev, E_dev, c->s);
     sync(c);
     return SPPC_OK;
   });

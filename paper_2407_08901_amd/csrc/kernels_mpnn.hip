@@ -19,26 +19,6 @@ namespace {
 constexpr int HID = 32;
 constexpr int NPAR = 289;
 
-template <typename T>
-struct W {
-  T Ws[HID][3], Wn[HID][3], b1[HID], ws[HID], wn[HID], b2;
-};
-
-template <typename T>
-__device__ inline void load_w(const T* __restrict__ w, W<T>& o) {
-  for (int j = 0; j < HID; ++j)
-    for (int q = 0; q < 3; ++q) {
-      o.Ws[j][q] = w[j * 3 + q];
-      o.Wn[j][q] = w[96 + j * 3 + q];
-    }
-  for (int j = 0; j < HID; ++j) {
-    o.b1[j] = w[192 + j];
-    o.ws[j] = w[224 + j];
-    o.wn[j] = w[256 + j];
-  }
-  o.b2 = w[288];
-}
-
 __device__ inline double clamp_den(double den, double theta) {
   const double fl = 1e-2 * fmax(1.0, fabs(theta));
   return fabs(den) < fl ? (den >= 0.0 ? fl : -fl) : den;
@@ -244,15 +224,6 @@ __global__ void k_round_bf16(int cnt, const float* __restrict__ w, float* __rest
   if (wd) wd[i] = (double)q;
 }
 
-// e = psi / (psi.x) - x  (per column; dots precomputed)
-__global__ void k_target(int64_t n, int S, const double* __restrict__ X, const double* __restrict__ Psi,
-                         const double* __restrict__ dots, double* __restrict__ E) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n * S) return;
-  const int s = (int)(e % S);
-  E[e] = Psi[e] / dots[s] - X[e];
-}
-
 // static inputs: lev, and the row sums A d, A 1, A lev from full products
 __global__ void k_static(int64_t n, const double* __restrict__ d, const double* __restrict__ lev,
                          const double* __restrict__ P, double* __restrict__ Ad, double* __restrict__ A1,
@@ -325,11 +296,24 @@ int64_t mpnn_work_doubles(int64_t n, int S) {
 // Forward (and, with E, the loss gradient) for S samples.  R, X: n x S (leading dims ldr, ldx),
 // theta_dev[S].  T_out (n x S, ld S): the projected output t~ (or nullptr).  grad_out (device,
 // 289 doubles, mean over samples) and loss_dev (S doubles) when E != nullptr.
+// Y := Y - Q (Q^T Y) for Y n x S (ld S) and a basis Q n x m (ld ldq) with orthonormal columns.
+static void project_basis(int64_t n, int S, const MpnnBasis& B, double* Y, hipStream_t s) {
+  double* C = B.work;
+  double* gw = B.work + (int64_t)B.m * 32;
+  for (int c0 = 0; c0 < S; c0 += 32) {
+    const int bs = S - c0 < 32 ? S - c0 : 32;
+    gemm_tn(n, B.m, bs, B.Q, B.ldq, Y + c0, S, C, bs, 1.0, 0.0, gw, s);
+    gemm_nn(n, B.m, bs, B.Q, B.ldq, C, bs, Y + c0, S, -1.0, 1.0, s);
+  }
+}
+
+int64_t mpnn_basis_work_doubles(int64_t n, int m) { return (int64_t)m * 32 + gemm_tn_work(n, m, 32); }
+
 template <typename T>
 void mpnn_run(const DevCSR& H, const double* diag, const double* lev, const double* Ad, const double* A1,
               const double* Al, const T* w, int S, const double* R, int64_t ldr, const double* X, int64_t ldx,
               const double* theta_dev, const double* E, double* T_out, double* grad_out, double* loss_dev,
-              double* work, hipStream_t s) {
+              double* work, const MpnnBasis* basis, hipStream_t s) {
   const int64_t n = H.n;
   const int64_t items = n * S;
   double* fr = work;
@@ -360,11 +344,15 @@ void mpnn_run(const DevCSR& H, const double* diag, const double* lev, const doub
   k_mpnn_layer1<T><<<gg(items), 256, 0, s>>>(n, S, st, w, fr, HF, theta_dev, u, hs);
   spmm_f64(H, u, S, Hu, S, S, nullptr, s);
   k_mpnn_out<T><<<gg(items), 256, 0, s>>>(n, S, diag, w, R, ldr, theta_dev, hs, u, Hu, t, tJ);
-  // t~ = t - x (x.t)
-  coldots(n, S, X, ldx, t, S, xdt, part, s);
+  // t~ = t - x (x.t), or t - Q (Q^T t) with a basis
   k_fill_const<<<1, 64, 0, s>>>(S, 1.0, one);
-  k_neg<<<1, 64, 0, s>>>(S, xdt, mxdt);
-  k_comb_cols<<<gg(items), 256, 0, s>>>(n, S, one, t, S, mxdt, X, ldx, t, S);
+  if (basis) {
+    project_basis(n, S, *basis, t, s);
+  } else {
+    coldots(n, S, X, ldx, t, S, xdt, part, s);
+    k_neg<<<1, 64, 0, s>>>(S, xdt, mxdt);
+    k_comb_cols<<<gg(items), 256, 0, s>>>(n, S, one, t, S, mxdt, X, ldx, t, S);
+  }
   if (T_out) copy_block(n, S, t, S, T_out, S, s);
   if (E) {
     coldots(n, S, t, S, E, S, c1, part, s);
@@ -373,9 +361,13 @@ void mpnn_run(const DevCSR& H, const double* diag, const double* lev, const doub
     k_loss_coef<<<1, 64, 0, s>>>(S, c1, c2, c3, ca, cb, lossv, 1.0 / S);
     // dL/dt~ = ca e + cb t~ -> dO ; then through the projection and t = tJ (1 + o)
     k_comb_cols<<<gg(items), 256, 0, s>>>(n, S, ca, E, S, cb, t, S, dO, S);
-    coldots(n, S, X, ldx, dO, S, xdt, part, s);
-    k_neg<<<1, 64, 0, s>>>(S, xdt, mxdt);
-    k_comb_cols<<<gg(items), 256, 0, s>>>(n, S, one, dO, S, mxdt, X, ldx, dO, S);
+    if (basis) {
+      project_basis(n, S, *basis, dO, s);
+    } else {
+      coldots(n, S, X, ldx, dO, S, xdt, part, s);
+      k_neg<<<1, 64, 0, s>>>(S, xdt, mxdt);
+      k_comb_cols<<<gg(items), 256, 0, s>>>(n, S, one, dO, S, mxdt, X, ldx, dO, S);
+    }
     k_mul<<<gg(items), 256, 0, s>>>(items, tJ, dO);
     spmm_f64(H, dO, S, HdO, S, S, nullptr, s);
     const int64_t ipb = 8 * 64;
@@ -389,11 +381,12 @@ void mpnn_run(const DevCSR& H, const double* diag, const double* lev, const doub
 
 template void mpnn_run<float>(const DevCSR&, const double*, const double*, const double*, const double*,
                               const double*, const float*, int, const double*, int64_t, const double*, int64_t,
-                              const double*, const double*, double*, double*, double*, double*, hipStream_t);
+                              const double*, const double*, double*, double*, double*, double*,
+                              const MpnnBasis*, hipStream_t);
 template void mpnn_run<double>(const DevCSR&, const double*, const double*, const double*, const double*,
                                const double*, const double*, int, const double*, int64_t, const double*,
                                int64_t, const double*, const double*, double*, double*, double*, double*,
-                               hipStream_t);
+                               const MpnnBasis*, hipStream_t);
 
 void mpnn_adam(float* w, float* m, float* v, const double* g, float lr, int step, float* wq, hipStream_t s) {
   k_adam<<<cdiv(NPAR, 256), 256, 0, s>>>(w, m, v, g, lr, 0.9f, 0.999f, 1e-8f, step, wq);
@@ -405,11 +398,10 @@ void mpnn_round_bf16(int cnt, const float* w, float* wq, double* wd, hipStream_t
   SPPC_LAUNCH_CHECK();
 }
 
-void mpnn_target(int64_t n, int S, const double* X, const double* Psi, double* E, double* dots, double* work,
-                 hipStream_t s) {
-  coldots(n, S, Psi, S, X, S, dots, work, s);
-  k_target<<<gg(n * S), 256, 0, s>>>(n, S, X, Psi, dots, E);
-  SPPC_LAUNCH_CHECK();
+// E = (I - Q Q^T) Psi  (n x S, ld S): the part of each exact eigenvector outside the basis.
+void mpnn_target(int64_t n, int S, const MpnnBasis& B, const double* Psi, double* E, hipStream_t s) {
+  copy_block(n, S, Psi, S, E, S, s);
+  project_basis(n, S, B, E, s);
 }
 
 }  // namespace sppc

@@ -1,0 +1,151 @@
+"""Training of the learned preconditioner on the GPU (data generation and optimisation).
+
+Data: for each training matrix (the n = 4900 three-level shape, seeds 1000..1019) the GPU
+solver is run twice.  A tight solve (rrn <= 1e-11) gives the exact eigenvectors psi_i.  A
+solve at the working tolerance is stepped through the C ABI (perturbative steps, then the
+diagonal-step continuation of Sec. V); after every step p >= 2 the unconverged Ritz pairs
+(x, theta, r = H x - theta x) of that step form one batch, together with the basis Q of
+the step.  The target of a pair is e = (I - Q Q^T) psi: the next basis vector is the
+continuation direction orthogonalised against Q, and it adds psi to the span exactly when
+it is parallel to e.  The network output is compared after the same projection.
+(The exact correction (H - theta I)^-1 r that a literal reading suggests equals x itself,
+and the Jacobi-Davidson limit psi / (psi^T x) - x lies mostly inside the basis.)
+
+Optimisation: Adam on the float32 master weights with bfloat16-rounded copies in the forward
+pass (sppc_mpnn_train_step: forward, backward and update all run in the library's kernels).
+
+    python -m paper_2407_08901_amd.mpnn_train [--out weights.json] [--epochs 30]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import time
+
+import numpy as np
+import torch
+
+import paper_2407_08901_amd as P
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+DEFAULT_WEIGHTS = os.path.join(HERE, "mpnn_weights.json")
+FORMAT = "sppc-mpnn-v1"
+
+
+def build_dataset(seeds, k=4, log=print):
+    import levelgen
+    data = []
+    for sd in seeds:
+        w = levelgen.train_workload(sd)
+        A = w.generate()
+        rp, col, val = P.upload(A)
+        exact = P.sppc_setup(rp, col, val, A.level_offsets, w.n_small_levels, k, P.sppc_default_opts(tol=1e-11))
+        lam, psi, _, _, status = P.sppc_solve(exact)
+        P.sppc_destroy(exact)
+        if status != P.SPPC_OK:
+            raise RuntimeError("reference solve did not converge for seed %d" % sd)
+        ctx = P.sppc_setup(rp, col, val, A.level_offsets, w.n_small_levels, k, P.sppc_default_opts())
+        groups = []
+        for step in range(1, 15 + 12 + 1):
+            kind = P.SPPC_CORR_PERTURBATIVE if step <= 15 else P.SPPC_CORR_JACOBI
+            P.sppc_correct(ctx, kind)
+            theta, rrn, added = P.sppc_rayleigh_ritz(ctx)
+            if step >= 2:
+                # skip converged pairs and Ritz values not yet closer to their own eigenvalue
+                # than to a neighbour (the pairing with psi_i would be wrong)
+                sel = [i for i in range(k)
+                       if rrn[i] >= 1e-6 and abs(theta[i] - lam[i]) <= 0.5 * min(
+                           abs(lam[i] - lam[j]) for j in range(k) if j != i)]
+                if sel:
+                    m = int(P.sppc_get(ctx, 2, 1)[0])
+                    Q = P.sppc_get(ctx, 3, A.n * m, device=True).view(A.n, m).clone()
+                    Z = P.sppc_get(ctx, 10, A.n * k, device=True).view(A.n, k)
+                    R = P.sppc_get(ctx, 11, A.n * k, device=True).view(A.n, k)
+                    ix = torch.tensor(sel, device="cuda")
+                    X = Z[:, ix].contiguous()
+                    Psi = psi[:, ix].contiguous()
+                    E = P.sppc_mpnn_target(ctx, Q, Psi)
+                    groups.append(dict(step=step, Q=Q, X=X, R=R[:, ix].contiguous(), E=E,
+                                       theta=np.array([theta[i] for i in sel])))
+            if max(rrn) < 1e-6 or added == 0:
+                break
+        data.append(dict(seed=sd, ctx=ctx, groups=groups, keep=(rp, col, val)))
+        log("seed %d: %d batches, %d samples" % (sd, len(groups), sum(g["X"].shape[1] for g in groups)))
+    return data
+
+
+def train(data, epochs=30, lr=3e-3, seed=0, log=print):
+    """One Adam step per (matrix, step) batch; cosine learning-rate decay to lr/10."""
+    rng = np.random.default_rng(seed)
+    state = torch.zeros(4 * P.SPPC_MPNN_NPARAM, dtype=torch.float32, device="cuda")
+    # zero weights are a stationary point (tanh(0) = 0 and the loss ignores the output scale):
+    # random first layer, small second layer, so training starts near the diagonal step
+    w0 = np.zeros(P.SPPC_MPNN_NPARAM, np.float32)
+    w0[0:192] = rng.standard_normal(192) * 0.5
+    w0[224:288] = rng.standard_normal(64) * 0.05
+    state[:P.SPPC_MPNN_NPARAM] = torch.from_numpy(w0).cuda()
+    items = [(di, gi) for di, d in enumerate(data) for gi in range(len(d["groups"]))]
+    step = 0
+    hist = []
+    for ep in range(epochs):
+        lr_t = lr * (0.1 + 0.9 * 0.5 * (1.0 + np.cos(np.pi * ep / max(1, epochs))))
+        tot, cnt = 0.0, 0
+        for it in rng.permutation(len(items)):
+            di, gi = items[it]
+            d = data[di]
+            g = d["groups"][gi]
+            step += 1
+            loss = P.sppc_mpnn_train_step(d["ctx"], state, g["R"], g["X"], g["theta"], g["E"], lr_t, step, Q=g["Q"])
+            S = g["X"].shape[1]
+            tot += loss * S
+            cnt += S
+        hist.append(tot / cnt)
+        log("epoch %d loss %.5f" % (ep, tot / cnt))
+    w = state[:P.SPPC_MPNN_NPARAM].cpu().numpy().astype(np.float32)
+    return w, hist
+
+
+def save(w, path, meta):
+    payload = {"format": FORMAT, "nparam": int(w.size), "weights": [float(x) for x in w], **meta}
+    payload["sha256"] = hashlib.sha256(np.asarray(w, np.float32).tobytes()).hexdigest()
+    with open(path, "w") as f:
+        json.dump(payload, f, indent=1)
+
+
+def load(path=DEFAULT_WEIGHTS) -> np.ndarray:
+    with open(path) as f:
+        payload = json.load(f)
+    if payload.get("format") != FORMAT or payload.get("nparam") != P.SPPC_MPNN_NPARAM:
+        raise ValueError("not a weights file of this network")
+    w = np.asarray(payload["weights"], dtype=np.float32)
+    if hashlib.sha256(w.tobytes()).hexdigest() != payload.get("sha256"):
+        raise ValueError("weights file hash mismatch")
+    return w
+
+
+def main():
+    import levelgen
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", default=DEFAULT_WEIGHTS)
+    ap.add_argument("--epochs", type=int, default=30)
+    ap.add_argument("--lr", type=float, default=3e-3)
+    ap.add_argument("--nseeds", type=int, default=20)
+    args = ap.parse_args()
+    P.lib()
+    t0 = time.time()
+    data = build_dataset(levelgen.TRAIN_SEEDS[: args.nseeds], log=lambda m: print(m, flush=True))
+    t1 = time.time()
+    w, hist = train(data, epochs=args.epochs, lr=args.lr, log=lambda m: print(m, flush=True))
+    t2 = time.time()
+    nsamp = sum(g["X"].shape[1] for d in data for g in d["groups"])
+    save(w, args.out, {"train_seeds": list(levelgen.TRAIN_SEEDS[: args.nseeds]), "samples": nsamp,
+                       "epochs": args.epochs, "lr": args.lr, "loss_history": hist,
+                       "data_s": round(t1 - t0, 2), "train_s": round(t2 - t1, 2)})
+    print(json.dumps({"samples": nsamp, "final_loss": hist[-1], "first_loss": hist[0], "data_s": t1 - t0,
+                      "train_s": t2 - t1}))
+
+
+if __name__ == "__main__":
+    main()

@@ -42,3 +42,28 @@ def test_binding_names_match_abi():
         if n in ("sppc_last_error", "sppc_setup_error"):
             continue
         assert hasattr(P, n), n
+
+
+def _header_struct(name):
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    body = re.search(r"typedef struct \{([^}]*)\}\s*%s;" % name, text).group(1)
+    fields = []
+    for decl in body.split(";"):
+        decl = decl.strip()
+        if decl:
+            typ, nm = decl.rsplit(None, 1)
+            fields.append((nm.lstrip("*"), "ptr" if "*" in decl else typ.split()[-1]))
+    return fields
+
+
+CTYPE = {"int": "c_int", "int64_t": "c_int64", "double": "c_double", "sppc_dtype": "c_int", "ptr": "c_void_p"}
+
+
+@pytest.mark.parametrize("name", ["sppc_csr", "sppc_opts", "sppc_stats"])
+def test_binding_structs_match_header_layout(name):
+    import paper_2407_08901_amd as P
+    want = _header_struct(name)
+    have = getattr(P, name)._fields_
+    assert [f for f, _ in have] == [f for f, _ in want]
+    for (f, t), (_, ht) in zip(have, want):
+        assert t is getattr(ctypes, CTYPE[ht]), (name, f, t, ht)

@@ -65,6 +65,30 @@ def test_forward_and_gradient_match_reference(P):
     assert np.max(np.abs(np.array(grad32) - g_q)) < 2e-4 * np.max(np.abs(g_q))
 
 
+def test_basis_projection_and_target_match_reference(P):
+    S, m = 3, 9
+    A, H, Aoff, dg, lev, X, th, R, E, w = _problem(13, S)
+    print("case mpnn basis n=%d S=%d m=%d" % (A.n, S, m), flush=True)
+    rng = np.random.default_rng(2)
+    Q, _ = np.linalg.qr(np.column_stack([X, rng.standard_normal((A.n, m - S))]))
+    Psi = rng.standard_normal((A.n, S))
+    ctx = _ctx(P, A)
+    Eg = P.sppc_mpnn_target(ctx, _cu(Q), _cu(Psi)).cpu().numpy()
+    E_ref = Psi - Q @ (Q.T @ Psi)
+    assert np.max(np.abs(Eg - E_ref)) < 1e-13 * np.max(np.abs(Psi))
+    T, loss, grad = P.sppc_mpnn_eval(ctx, w, _cu(R), _cu(X), th, _cu(E_ref), f64=True, Q=_cu(Q))
+    T = T.cpu().numpy()
+    w64 = w.astype(np.float64)
+    g_ref = np.zeros(ompnn.NPARAM)
+    for s in range(S):
+        tp, _ = ompnn.forward(w64, Aoff, dg, lev, th[s], R[:, s], X[:, s], Q)
+        assert np.max(np.abs(T[:, s] - tp)) < 1e-11 * np.max(np.abs(tp))
+        L, g = ompnn.loss_and_grad(w64, Aoff, dg, lev, th[s], R[:, s], X[:, s], E_ref[:, s], Q)
+        assert abs(loss[s] - L) < 1e-11
+        g_ref += g / S
+    assert np.max(np.abs(np.array(grad) - g_ref)) < 1e-10 * np.max(np.abs(g_ref))
+
+
 def ompnn_bf16(w):
     b = np.ascontiguousarray(w, dtype=np.float32).view(np.uint32).astype(np.uint64)
     b = (b + 0x7FFF + ((b >> 16) & 1)) & 0xFFFF0000
@@ -112,6 +136,10 @@ def test_training_step_lowers_the_loss(P):
     state = torch.zeros(4 * 289, dtype=torch.float32, device="cuda")
     state[:289] = torch.from_numpy(w * 0.1).cuda()
     Rg, Xg, Eg = _cu(R), _cu(X), _cu(E)
-    losses = [P.sppc_mpnn_train_step(ctx, state, Rg, Xg, th, Eg, 1e-2, it + 1) for it in range(40)]
+    rng = np.random.default_rng(4)
+    Q, _ = np.linalg.qr(np.column_stack([X, rng.standard_normal((A.n, 4))]))
+    Qg = _cu(Q)
+    Eg = P.sppc_mpnn_target(ctx, Qg, Eg)
+    losses = [P.sppc_mpnn_train_step(ctx, state, Rg, Xg, th, Eg, 1e-2, it + 1, Q=Qg) for it in range(40)]
     assert losses[-1] < losses[0] - 1e-3
     assert np.all(np.isfinite(losses))

@@ -43,6 +43,22 @@ def test_gradient_matches_central_differences():
     assert np.max(np.abs(num - g)) < 1e-6 * max(1.0, np.abs(g).max())
 
 
+def test_gradient_with_basis_projection_matches_central_differences():
+    H, Aoff, d, lev, theta, r, x, e, w = _setup(7)
+    rng = np.random.default_rng(1)
+    Q, _ = np.linalg.qr(np.column_stack([x, rng.standard_normal((x.size, 6))]))
+    e = e - Q @ (Q.T @ e)
+    L, g = mpnn.loss_and_grad(w, Aoff, d, lev, theta, r, x, e, Q)
+    h = 1e-6
+    idx = rng.choice(mpnn.NPARAM, 60, replace=False)
+    for i in idx:
+        wp = w.copy(); wp[i] += h
+        wm = w.copy(); wm[i] -= h
+        num = (mpnn.loss_and_grad(wp, Aoff, d, lev, theta, r, x, e, Q)[0] -
+               mpnn.loss_and_grad(wm, Aoff, d, lev, theta, r, x, e, Q)[0]) / (2 * h)
+        assert abs(num - g[i]) < 1e-6 * max(1.0, np.abs(g).max())
+
+
 def test_loss_is_zero_for_the_target_direction_and_scale_free():
     H, Aoff, d, lev, theta, r, x, e, w = _setup()
     tp, _ = mpnn.forward(w, Aoff, d, lev, theta, r, x)
