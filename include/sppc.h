@@ -83,6 +83,9 @@ typedef struct {
   int precond;         /* sppc_corr_kind used by the continuation (JACOBI or MPNN) */
   int final_check;     /* explicit float64 H Z, Rayleigh-Ritz on span Z, true residual */
   int verbose;         /* per-iteration line on stderr */
+  int panel_width;     /* block products with H over column panels of this many columns (<= 65536),
+                          so that the gathered rows of X stay in L2: -1 = automatic (when a k-column
+                          block of X exceeds 8 MiB), 0 = off */
 } sppc_opts;
 
 typedef struct {
@@ -211,7 +214,7 @@ sppc_status sppc_get(sppc_ctx* ctx, int what, double* dst, int64_t count);
 sppc_status sppc_mpnn_set_weights(sppc_ctx* ctx, const float* w_host);
 
 /*
- * Evaluates the network for S (1..64) samples on the matrix of the context.
+ * Evaluates the network for S (1..32) samples on the matrix of the context.
  *   w_host        289 parameters (host)
  *   R_dev, X_dev  n x S row-major: residuals and unit Ritz vectors (device)
  *   theta_host    [S] Ritz values

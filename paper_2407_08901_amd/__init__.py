@@ -41,7 +41,7 @@ class sppc_opts(ctypes.Structure):
                 ("max_cont", ctypes.c_int), ("m_max", ctypes.c_int), ("n_deflate", ctypes.c_int),
                 ("tau_drop", ctypes.c_double), ("inner_tol", ctypes.c_double), ("h0_tol", ctypes.c_double),
                 ("precision", ctypes.c_int), ("precond", ctypes.c_int), ("final_check", ctypes.c_int),
-                ("verbose", ctypes.c_int)]
+                ("verbose", ctypes.c_int), ("panel_width", ctypes.c_int)]
 
 
 class sppc_stats(ctypes.Structure):

@@ -33,6 +33,23 @@ __host__ __device__ inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 
 // ---------------------------------------------------------------- sparse (kernels_sparse.hip)
 
 // Full symmetric CSR on the device (both triangles, columns ascending in each row).
+// Row-block x column-panel copy of H for the block product with large n.  Rows are cut into
+// blocks of RB (one workgroup each) and columns into panels of PW (a panel of X is small enough
+// to stay in one XCD's L2).  Within a block the entries are stored panel by panel, and within
+// a panel row by row with ascending columns; columns are stored relative to the panel start.
+struct PanelH {
+  int64_t n = 0;
+  int nblocks = 0;
+  int RB = 0;                 // rows per block
+  int P = 0;                  // panels
+  int PW = 0;                 // columns per panel (<= 65536)
+  int32_t* off = nullptr;     // [nblocks][P*RB + 1]: start of (panel, row) relative to the block
+  int64_t* bstart = nullptr;  // [nblocks + 1]: first entry of each block
+  uint16_t* col = nullptr;    // column - panel * PW
+  float* val32 = nullptr;
+  double* val64 = nullptr;
+};
+
 struct DevCSR {
   int64_t n = 0;
   int64_t nnz = 0;
@@ -41,6 +58,7 @@ struct DevCSR {
   int32_t* col = nullptr;
   double* val64 = nullptr;     // float64 values (nullptr when val32 is exact and enough)
   float* val32 = nullptr;      // float32 values
+  const PanelH* panel = nullptr;  // optional panel copy used by the plain products (b <= 16)
 };
 
 // Setup: build the full CSR from the upper triangle.  Returns nnz of the full matrix.
@@ -49,6 +67,10 @@ void build_full_csr(int64_t n, int64_t nnz_up, const int64_t* up_rp, const int32
                     bool want64, bool want32, bool& exact32, hipStream_t s);
 // Row ends of the leading n0 x n0 block (columns < n0) of the full CSR.
 void build_block_view(const DevCSR& full, int64_t n0, int64_t* rend, hipStream_t s);
+// Panel copy of a full CSR (ascending columns per row); values as stored in the CSR.
+// Device memory is allocated with hipMalloc and owned by the caller (release_panel).
+void build_panel(const DevCSR& H, int PW, int RB, PanelH& out, hipStream_t s);
+void release_panel(PanelH& p);
 // diag(H) from the full CSR.
 void extract_diag(const DevCSR& H, double* diag, hipStream_t s);
 

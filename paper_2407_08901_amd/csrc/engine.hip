@@ -105,6 +105,7 @@ struct sppc_ctx {
   std::vector<int64_t> loff;
   Arena arena;
   DevCSR H, H0;
+  PanelH panel;
   double* diag = nullptr;
   bool exact32 = false;
   double* E0 = nullptr;      // [D]
@@ -611,6 +612,7 @@ void setup_impl(sppc_ctx* c, const sppc_csr* Hin, const int64_t* loff, int L, in
   if (o.n_deflate < k || o.n_deflate > 28 || o.n_deflate > c->n0) throw Error(SPPC_E_ARG, "n_deflate must be in [k, min(28, n0)]");
   c->D = o.n_deflate;
   if (o.m_max < 2 * k || o.m_max > 512) throw Error(SPPC_E_ARG, "m_max must be in [2k, 512]");
+  if (o.panel_width < -1 || o.panel_width > 65536) throw Error(SPPC_E_ARG, "panel_width must be -1, 0 or 1..65536");
   if (!(o.tol > 0) || !(o.tau_drop >= 0) || !(o.inner_tol >= 0) || !(o.h0_tol > 0)) throw Error(SPPC_E_ARG, "bad tolerances");
   if (o.precision != SPPC_PREC_FP64 && o.precision != SPPC_PREC_MIXED) throw Error(SPPC_E_ARG, "bad precision");
   const int last_p = (o.p_switch > 0) ? std::min(o.p_switch, o.maxiter) : o.maxiter;
@@ -650,6 +652,30 @@ void setup_impl(sppc_ctx* c, const sppc_csr* Hin, const int64_t* loff, int L, in
   c->exact32 = exact;
   c->H0 = c->H;
   c->H0.n = c->n0;
+  c->H0.panel = nullptr;
+  {
+    // column-panel copy for the block products with H
+    int pw = o.panel_width;
+    if (pw < 0) {
+      const int64_t xbytes = c->n * (int64_t)k * 8;
+      pw = 0;
+      if (xbytes > ((int64_t)8 << 20)) {
+        int64_t w = ((int64_t)1 << 20) / ((int64_t)k * 8);  // 1 MiB of float64 X per panel
+        int64_t p2 = 1024;
+        while (p2 * 2 <= w && p2 * 2 <= 65536) p2 *= 2;
+        pw = (int)p2;
+      }
+    }
+    if (pw > 0) {
+      build_panel(c->H, pw, 384, c->panel, s);
+      A.ptrs.push_back(c->panel.off);
+      A.ptrs.push_back(c->panel.bstart);
+      A.ptrs.push_back(c->panel.col);
+      if (c->panel.val64) A.ptrs.push_back(c->panel.val64);
+      if (c->panel.val32) A.ptrs.push_back(c->panel.val32);
+      c->H.panel = &c->panel;
+    }
+  }
   c->H0.rend = A.alloc<int64_t>(c->n0);
   build_block_view(c->H, c->n0, c->H0.rend, s);
   c->diag = A.alloc<double>(c->n);
@@ -861,6 +887,7 @@ sppc_status sppc_default_opts(sppc_opts* o) {
   o->precond = SPPC_CORR_JACOBI;
   o->final_check = 1;
   o->verbose = 0;
+  o->panel_width = -1;
   return SPPC_OK;
 }
 
@@ -980,7 +1007,7 @@ sppc_status sppc_mpnn_set_weights(sppc_ctx* c, const float* w_host) {
 sppc_status sppc_mpnn_eval(sppc_ctx* c, const float* w_host, int S, const double* R_dev, const double* X_dev,
                            const double* theta_host, const double* Q_dev, int m, const double* E_dev,
                            double* T_dev, double* loss_host, double* grad_host, int f64) {
-  if (!c || !w_host || S < 1 || S > 64 || !R_dev || !X_dev || !theta_host || m < 0) return SPPC_E_ARG;
+  if (!c || !w_host || S < 1 || S > 32 || !R_dev || !X_dev || !theta_host || m < 0) return SPPC_E_ARG;
   if ((loss_host || grad_host) && !E_dev) return SPPC_E_ARG;
   return guarded(c, [&]() {
     mpnn_ensure(c, S);
@@ -1012,7 +1039,7 @@ sppc_status sppc_mpnn_eval(sppc_ctx* c, const float* w_host, int S, const double
 sppc_status sppc_mpnn_train_step(sppc_ctx* c, float* state_dev, int S, const double* R_dev, const double* X_dev,
                                  const double* theta_host, const double* Q_dev, int m, const double* E_dev,
                                  float lr, int step, double* loss_host) {
-  if (!c || !state_dev || S < 1 || S > 64 || !R_dev || !X_dev || !theta_host || !E_dev || step < 1 || m < 0)
+  if (!c || !state_dev || S < 1 || S > 32 || !R_dev || !X_dev || !theta_host || !E_dev || step < 1 || m < 0)
     return SPPC_E_ARG;
   return guarded(c, [&]() {
     mpnn_ensure(c, S);
@@ -1042,7 +1069,7 @@ sppc_status sppc_mpnn_train_step(sppc_ctx* c, float* state_dev, int S, const dou
 
 sppc_status sppc_mpnn_target(sppc_ctx* c, int S, const double* Q_dev, int m, const double* Psi_dev,
                              double* E_dev) {
-  if (!c || S < 1 || S > 64 || !Q_dev || m < 1 || !Psi_dev || !E_dev) return SPPC_E_ARG;
+  if (!c || S < 1 || S > 32 || !Q_dev || m < 1 || !Psi_dev || !E_dev) return SPPC_E_ARG;
   return guarded(c, [&]() {
     mpnn_ensure(c, S);
     MpnnBasis B;

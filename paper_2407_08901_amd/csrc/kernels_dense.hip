@@ -15,56 +15,98 @@ inline int64_t tn_chunk(int64_t n) {
   int64_t c = (n / 512 + 31) / 32 * 32;
   return c < 32 ? 32 : (c > 2048 ? 2048 : c);
 }
-constexpr int TN_MT = 64;       // columns of A per block
-constexpr int TN_RT = 32;       // rows per LDS tile
+// ---------------------------------------------------------------- MFMA tall-skinny products
+// v_mfma_f64_16x16x4f64 (wave64): lane l supplies A[l%16][l/16] and B[l/16][l%16] of a
+// 16x4 by 4x16 product and holds D[l/16 + 4v][l%16], v = 0..3, of the 16x16 accumulator.
+typedef double v4d __attribute__((ext_vector_type(4)));
 
-// partial[chunk][i][j] = sum_{r in chunk} A[r][i0+i] B[r][j]
+__device__ inline v4d mfma16(double a, double b, v4d c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+constexpr int TN_COLS = 64;  // columns of A per workgroup (4 tiles of 16)
+
+// partial[chunk][i][j] = sum_{r in chunk} A[r][i] B[r][j] for the 64 columns i of blockIdx.y.
+// The reduction dimension of the MFMA is the row index: each wave takes 4 rows per step
+// (rows r0 + 16 t + 4 w .. +3 for wave w), 4 column tiles of A and NT column tiles of B.
+template <int NT>
 __global__ __launch_bounds__(256) void k_gemm_tn(int64_t n, int m, int b, const double* __restrict__ A,
                                                  int64_t lda, const double* __restrict__ B, int64_t ldb,
                                                  double* __restrict__ part, int64_t chunk) {
-  __shared__ double As[TN_RT][TN_MT];
-  __shared__ double Bs[TN_RT][33];
-  const int t = threadIdx.x;
-  const int i = t & 63;
-  const int jg = t >> 6;
-  const int i0 = blockIdx.y * TN_MT;
+  __shared__ double red[2][64][16 * NT];
+  const int lane = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6;
+  const int rl = lane >> 4, cl = lane & 15;
+  const int i0 = blockIdx.y * TN_COLS;
   const int64_t r0 = (int64_t)blockIdx.x * chunk;
   const int64_t r1 = min<int64_t>(n, r0 + chunk);
-  double acc[8];
+  v4d acc[4][NT];
 #pragma unroll
-  for (int q = 0; q < 8; ++q) acc[q] = 0.0;
-  for (int64_t rt = r0; rt < r1; rt += TN_RT) {
-    const int nr = (int)min<int64_t>(TN_RT, r1 - rt);
+  for (int ti = 0; ti < 4; ++ti)
 #pragma unroll
-    for (int q = 0; q < (TN_RT * TN_MT) / 256; ++q) {
-      const int e = t + 256 * q;
-      const int rr = e >> 6, ii = e & 63;
-      double v = 0.0;
-      if (rr < nr && i0 + ii < m) v = A[(rt + rr) * lda + i0 + ii];
-      As[rr][ii] = v;
-    }
-    for (int e = t; e < TN_RT * 32; e += 256) {
-      const int rr = e >> 5, jj = e & 31;
-      double v = 0.0;
-      if (rr < nr && jj < b) v = B[(rt + rr) * ldb + jj];
-      Bs[rr][jj] = v;
-    }
-    __syncthreads();
-#pragma unroll 8
-    for (int rr = 0; rr < TN_RT; ++rr) {
-      const double a = As[rr][i];
+    for (int tj = 0; tj < NT; ++tj) acc[ti][tj] = v4d{0.0, 0.0, 0.0, 0.0};
+  bool icol[4];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) acc[q] = fma(a, Bs[rr][jg + 4 * q], acc[q]);
+  for (int ti = 0; ti < 4; ++ti) icol[ti] = i0 + 16 * ti + cl < m;
+  bool jcol[NT];
+#pragma unroll
+  for (int tj = 0; tj < NT; ++tj) jcol[tj] = 16 * tj + cl < b;
+  for (int64_t rt = r0; rt < r1; rt += 32) {
+    double a[2][4], bv[2][NT];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int64_t r = rt + 16 * u + 4 * w + rl;
+      const bool rin = r < r1;
+      const double* ar = A + r * lda + i0 + cl;
+      const double* br = B + r * ldb + cl;
+#pragma unroll
+      for (int ti = 0; ti < 4; ++ti) a[u][ti] = (rin && icol[ti]) ? ar[16 * ti] : 0.0;
+#pragma unroll
+      for (int tj = 0; tj < NT; ++tj) bv[u][tj] = (rin && jcol[tj]) ? br[16 * tj] : 0.0;
     }
-    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int ti = 0; ti < 4; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < NT; ++tj) acc[ti][tj] = mfma16(a[u][ti], bv[u][tj], acc[ti][tj]);
   }
-  if (i0 + i < m) {
-    double* out = part + ((int64_t)blockIdx.x * m + i0 + i) * b;
+  // sum the 4 waves' accumulators in a fixed order: (w0 + w2) + (w1 + w3)
+  for (int ti = 0; ti < 4; ++ti) {
+    if (w >= 2) {
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int j = jg + 4 * q;
-      if (j < b) out[j] = acc[q];
+      for (int tj = 0; tj < NT; ++tj)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) red[w - 2][lane][tj * 4 + v] = acc[ti][tj][v];
     }
+    __syncthreads();
+    if (w < 2) {
+#pragma unroll
+      for (int tj = 0; tj < NT; ++tj)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[ti][tj][v] += red[w][lane][tj * 4 + v];
+    }
+    __syncthreads();
+    if (w == 1) {
+#pragma unroll
+      for (int tj = 0; tj < NT; ++tj)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) red[0][lane][tj * 4 + v] = acc[ti][tj][v];
+    }
+    __syncthreads();
+    if (w == 0) {
+#pragma unroll
+      for (int tj = 0; tj < NT; ++tj) {
+        const int j = 16 * tj + cl;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int i = i0 + 16 * ti + rl + 4 * v;
+          if (i < m && j < b)
+            part[((int64_t)blockIdx.x * m + i) * b + j] = acc[ti][tj][v] + red[0][lane][tj * 4 + v];
+        }
+      }
+    }
+    __syncthreads();
   }
 }
 
@@ -85,56 +127,69 @@ __global__ void k_reduce_partials(int64_t nchunks, int m, int b, const double* _
   }
 }
 
-constexpr int NN_RB = 64;  // rows per block
-constexpr int NN_IT = 64;  // inner tile
+constexpr int NN_ROWS = 128;  // rows per workgroup: 4 waves x 2 tiles of 16
 
+// Y = beta Y + alpha A C: the reduction dimension of the MFMA is the column index i of A.
+// In step s of a 16-column slab, k-slot q of the MFMA is column i0 + 4 s + q, so the 4 slots
+// of one row read 32 contiguous bytes.
+template <int NT>
 __global__ __launch_bounds__(256) void k_gemm_nn(int64_t n, int m, int b, const double* __restrict__ A,
                                                  int64_t lda, const double* __restrict__ C, int64_t ldc,
                                                  double* __restrict__ Y, int64_t ldy, double alpha,
                                                  double beta) {
-  __shared__ double As[NN_RB][NN_IT + 1];
-  __shared__ double Cs[NN_IT][33];
-  const int t = threadIdx.x;
-  const int r = t >> 2;
-  const int jq = t & 3;
-  const int64_t row0 = (int64_t)blockIdx.x * NN_RB;
-  const int nr = (int)min<int64_t>(NN_RB, n - row0);
-  double acc[8];
+  const int lane = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6;
+  const int q = lane >> 4, cl = lane & 15;
+  const int64_t rbase = (int64_t)blockIdx.x * NN_ROWS + 32 * w;
+  v4d acc[2][NT];
 #pragma unroll
-  for (int q = 0; q < 8; ++q) acc[q] = 0.0;
-  for (int i0 = 0; i0 < m; i0 += NN_IT) {
-    const int ni = min(NN_IT, m - i0);
+  for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
-    for (int q = 0; q < (NN_RB * NN_IT) / 256; ++q) {
-      const int e = t + 256 * q;
-      const int rr = e >> 6, ii = e & 63;
-      double v = 0.0;
-      if (rr < nr && ii < ni) v = A[(row0 + rr) * lda + i0 + ii];
-      As[rr][ii] = v;
-    }
-    for (int e = t; e < NN_IT * 32; e += 256) {
-      const int ii = e >> 5, jj = e & 31;
-      double v = 0.0;
-      if (ii < ni && jj < b) v = C[(int64_t)(i0 + ii) * ldc + jj];
-      Cs[ii][jj] = v;
-    }
-    __syncthreads();
-#pragma unroll 8
-    for (int ii = 0; ii < NN_IT; ++ii) {
-      const double a = As[r][ii];
+    for (int tj = 0; tj < NT; ++tj) acc[mt][tj] = v4d{0.0, 0.0, 0.0, 0.0};
+  bool rin[2];
+  const double* arow[2];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) acc[q] = fma(a, Cs[ii][jq + 4 * q], acc[q]);
-    }
-    __syncthreads();
+  for (int mt = 0; mt < 2; ++mt) {
+    const int64_t r = rbase + 16 * mt + cl;
+    rin[mt] = r < n;
+    arow[mt] = A + (rin[mt] ? r : 0) * lda;
   }
-  if (r < nr) {
-    double* y = Y + (row0 + r) * ldy;
+  bool jcol[NT];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int j = jq + 4 * q;
-      if (j < b) y[j] = beta == 0.0 ? alpha * acc[q] : beta * y[j] + alpha * acc[q];
+  for (int tj = 0; tj < NT; ++tj) jcol[tj] = 16 * tj + cl < b;
+  for (int i0 = 0; i0 < m; i0 += 16) {
+    double a[4][2], c[4][NT];
+#pragma unroll
+    for (int st = 0; st < 4; ++st) {
+      const int i = i0 + 4 * st + q;
+      const bool iin = i < m;
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt) a[st][mt] = (iin && rin[mt]) ? arow[mt][i] : 0.0;
+#pragma unroll
+      for (int tj = 0; tj < NT; ++tj) c[st][tj] = (iin && jcol[tj]) ? C[(int64_t)i * ldc + 16 * tj + cl] : 0.0;
     }
+#pragma unroll
+    for (int st = 0; st < 4; ++st)
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+        for (int tj = 0; tj < NT; ++tj) acc[mt][tj] = mfma16(a[st][mt], c[st][tj], acc[mt][tj]);
   }
+#pragma unroll
+  for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+    for (int tj = 0; tj < NT; ++tj) {
+      const int j = 16 * tj + cl;
+      if (j >= b) continue;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t r = rbase + 16 * mt + q + 4 * v;
+        if (r < n) {
+          double* y = Y + r * ldy + j;
+          *y = beta == 0.0 ? alpha * acc[mt][tj][v] : beta * (*y) + alpha * acc[mt][tj][v];
+        }
+      }
+    }
 }
 
 // ---------------------------------------------------------------- column reductions
@@ -275,8 +330,11 @@ void gemm_tn(int64_t n, int m, int b, const double* A, int64_t lda, const double
   const int64_t chunk = tn_chunk(n);
   const int64_t nch = cdiv(n > 0 ? n : 1, chunk);
   if (n > 0) {
-    dim3 grid((unsigned)nch, (unsigned)cdiv(m, TN_MT));
-    k_gemm_tn<<<grid, 256, 0, s>>>(n, m, b, A, lda, B, ldb, work, chunk);
+    dim3 grid((unsigned)nch, (unsigned)cdiv(m, TN_COLS));
+    if (b <= 16)
+      k_gemm_tn<1><<<grid, 256, 0, s>>>(n, m, b, A, lda, B, ldb, work, chunk);
+    else
+      k_gemm_tn<2><<<grid, 256, 0, s>>>(n, m, b, A, lda, B, ldb, work, chunk);
   } else {
     k_fill_zero<<<grid1((int64_t)m * b), 256, 0, s>>>((int64_t)m * b, work);
   }
@@ -288,7 +346,10 @@ void gemm_nn(int64_t n, int m, int b, const double* A, int64_t lda, const double
              double* Y, int64_t ldy, double alpha, double beta, hipStream_t s) {
   if (n <= 0 || b <= 0) return;
   if (b > 32) throw Error(1, "gemm_nn: b must be <= 32");
-  k_gemm_nn<<<cdiv(n, NN_RB), 256, 0, s>>>(n, m, b, A, lda, C, ldc, Y, ldy, alpha, beta);
+  if (b <= 16)
+    k_gemm_nn<1><<<cdiv(n, NN_ROWS), 256, 0, s>>>(n, m, b, A, lda, C, ldc, Y, ldy, alpha, beta);
+  else
+    k_gemm_nn<2><<<cdiv(n, NN_ROWS), 256, 0, s>>>(n, m, b, A, lda, C, ldc, Y, ldy, alpha, beta);
   SPPC_LAUNCH_CHECK();
 }
 

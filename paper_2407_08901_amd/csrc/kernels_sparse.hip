@@ -8,6 +8,9 @@
 // atomics in the arithmetic and a deterministic entry order.
 #include "common.h"
 
+#include <algorithm>
+#include <vector>
+
 namespace sppc {
 
 namespace {
@@ -267,6 +270,213 @@ void launch_spmm(const DevCSR& H, const VT* val, const XT* X, int64_t ldx, doubl
   SPPC_LAUNCH_CHECK();
 }
 
+// ------------------------------------------------------------------ panel format
+//
+// Block product over the row-block x column-panel copy (PanelH).  One workgroup per row
+// block; all workgroups sweep the panels in the same order, so the panel of X that the
+// resident workgroups gather from stays in L2.  Each wave owns RB/4 consecutive rows, whose
+// entries in one panel are contiguous; the wave streams them in windows of 64 (one coalesced
+// load of columns and values).  Group g of B lanes takes the B consecutive entries
+// g*B .. g*B+B-1 of the window, lane c reading column c of each gathered row of X, and sums runs
+// of entries of the same row in a register; a run is added to the row's LDS accumulator
+// when it ends.  Runs that straddle two groups meet in the same LDS add instruction.
+template <int B, typename VT, typename XT>
+__global__ __launch_bounds__(256) void k_spmm_panel(int64_t n, int RB, int P, int PW,
+                                                    const int32_t* __restrict__ off,
+                                                    const int64_t* __restrict__ bstart,
+                                                    const uint16_t* __restrict__ pcol,
+                                                    const VT* __restrict__ pval, const XT* __restrict__ X,
+                                                    int64_t ldx, double* __restrict__ Y, int64_t ldy, int b,
+                                                    int blk0) {
+  constexpr int E = B;  // entries per group and window: 64/B groups share the 64 entries
+  extern __shared__ double ysh[];  // RB * B accumulators, then RB + 1 ints
+  int* soff = (int*)(ysh + (size_t)RB * B);
+  const int t = threadIdx.x;
+  const int lane = t & 63, w = t >> 6;
+  const int g = lane / B, c = lane % B;
+  const int64_t blk = blk0 + (int64_t)blockIdx.x;
+  const int64_t row0 = blk * RB;
+  const int nr = (int)min<int64_t>(RB, n - row0);
+  const int32_t* boff = off + blk * ((int64_t)P * RB + 1);
+  const VT* bval = pval + bstart[blk];
+  const uint16_t* bcol = pcol + bstart[blk];
+  const int WR = RB / 4;
+  const int R0 = w * WR, R1 = R0 + WR;
+  const bool colok = c < b;
+  for (int i = t; i < RB * B; i += 256) ysh[i] = 0.0;
+  for (int p = 0; p < P; ++p) {
+    __syncthreads();  // previous panel's offsets are no longer read; accumulators zeroed
+    for (int i = t; i <= RB; i += 256) soff[i] = boff[(int64_t)p * RB + i];
+    __syncthreads();
+    const int a = soff[R0], z = soff[R1];
+    const XT* Xp = X + (int64_t)p * PW * ldx + c;
+    // the window after the current one is loaded while the current one is processed; the
+    // matrix is read once, streaming (nontemporal), so it does not evict the panel of X
+    int nc = 0;
+    VT nv = VT(0);
+    if (a + lane < z) {
+      nc = (int)__builtin_nontemporal_load(&bcol[a + lane]);
+      nv = __builtin_nontemporal_load(&bval[a + lane]);
+    }
+    for (int win = a; win < z; win += 64) {
+      const int e = win + lane;
+      const int mc = nc;
+      const VT mv = nv;
+      int mr = R0;
+      if (e < z) {
+        // row of entry e: last r in [R0, R1) with soff[r] <= e
+        int lo = R0, hi = R1 - 1;
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (soff[mid] <= e) lo = mid; else hi = mid - 1;
+        }
+        mr = lo;
+      }
+      XT xv[E];
+#pragma unroll
+      for (int q = 0; q < E; ++q) {
+        const int src = g * E + q;
+        const int cc = __shfl(mc, src);
+        xv[q] = (win + src < z && colok) ? Xp[(int64_t)cc * ldx] : XT(0);
+      }
+      // loads return in issue order: the next window is requested after the gathers, so
+      // waiting for the gathered values does not wait for the (HBM) window load
+      asm volatile("" ::: "memory");
+      if (e + 64 < z) {
+        nc = (int)__builtin_nontemporal_load(&bcol[e + 64]);
+        nv = __builtin_nontemporal_load(&bval[e + 64]);
+      }
+      int cur_r = __shfl(mr, g * E);
+      double cur = 0.0;
+#pragma unroll
+      for (int q = 0; q < E; ++q) {
+        const int src = g * E + q;
+        const VT vv = __shfl(mv, src);
+        const int rr = __shfl(mr, src);
+        if (win + src < z) {
+          if (rr != cur_r) {
+            atomicAdd(&ysh[cur_r * B + c], cur);
+            cur = 0.0;
+            cur_r = rr;
+          }
+          if constexpr (sizeof(XT) == 4) {
+            cur += (double)(vv * xv[q]);  // float32 product, float64 accumulation
+          } else {
+            cur = fma((double)vv, (double)xv[q], cur);
+          }
+        }
+      }
+      if (win + g * E < z) atomicAdd(&ysh[cur_r * B + c], cur);
+    }
+  }
+  __syncthreads();
+  for (int i = t; i < nr * B; i += 256) {
+    const int rr = i / B, cc = i % B;
+    if (cc < b) Y[(row0 + rr) * ldy + cc] = ysh[i];
+  }
+}
+
+// Workgroups of one launch start together and sweep the panels in step; when the blocks do
+// not all fit on the device at once they are split into rounds of at most the resident count,
+// one launch each, so that a later round does not start at staggered times.
+template <int B, typename VT, typename XT>
+void spmm_panel_rounds(const PanelH& P, const VT* val, const XT* X, int64_t ldx, double* Y, int64_t ldy, int b,
+                       hipStream_t s) {
+  const size_t lds = sizeof(double) * (size_t)P.RB * B + sizeof(int) * (size_t)(P.RB + 1);
+  static int resident = 0;  // per instantiation, computed once per process
+  if (resident == 0) {
+    int dev = 0, cus = 0, per_cu = 0;
+    SPPC_HIP(hipGetDevice(&dev));
+    SPPC_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    SPPC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_spmm_panel<B, VT, XT>, 256, lds));
+    resident = std::max(1, cus * std::max(1, per_cu));
+  }
+  const int cap = resident;
+  const int rounds = (int)cdiv(P.nblocks, cap);
+  const int per = (int)cdiv(P.nblocks, rounds);  // equal rounds
+  for (int r0 = 0; r0 < P.nblocks; r0 += per) {
+    const int nb = std::min(per, P.nblocks - r0);
+    k_spmm_panel<B, VT, XT><<<nb, 256, lds, s>>>(P.n, P.RB, P.P, P.PW, P.off, P.bstart, P.col, val, X, ldx, Y,
+                                                 ldy, b, r0);
+  }
+  SPPC_LAUNCH_CHECK();
+}
+
+template <typename VT, typename XT>
+void launch_spmm_panel(const PanelH& P, const VT* val, const XT* X, int64_t ldx, double* Y, int64_t ldy, int b,
+                       hipStream_t s) {
+  if (b <= 4)
+    spmm_panel_rounds<4, VT, XT>(P, val, X, ldx, Y, ldy, b, s);
+  else if (b <= 8)
+    spmm_panel_rounds<8, VT, XT>(P, val, X, ldx, Y, ldy, b, s);
+  else
+    spmm_panel_rounds<16, VT, XT>(P, val, X, ldx, Y, ldy, b, s);
+}
+
+// first entry of row [b, e) with column >= key (columns ascending)
+__device__ inline int64_t lower_col(const int32_t* __restrict__ col, int64_t b, int64_t e, int64_t key) {
+  while (b < e) {
+    const int64_t mid = (b + e) >> 1;
+    if (col[mid] < key) b = mid + 1; else e = mid;
+  }
+  return b;
+}
+
+// cnt[blk][p*RB + r] = entries of row r of block blk in panel p (one wave per row; the lane
+// that holds the last entry of a panel run writes its length)
+__global__ void k_panel_count(int64_t n, const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
+                              int RB, int P, int PW, int32_t* __restrict__ cnt) {
+  const int lane = threadIdx.x & 63;
+  const int64_t row = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (row >= n) return;
+  const int64_t b = rp[row], e = rp[row + 1];
+  const int64_t blk = row / RB;
+  const int rl = (int)(row - blk * RB);
+  for (int64_t t = b + lane; t < e; t += 64) {
+    const int p = col[t] / PW;
+    if (t + 1 == e || col[t + 1] / PW != p) {
+      const int64_t st = lower_col(col, b, t, (int64_t)p * PW);
+      cnt[blk * ((int64_t)P * RB) + (int64_t)p * RB + rl] = (int32_t)(t - st + 1);
+    }
+  }
+}
+
+// relative offsets per block from the global exclusive scan of the counts
+__global__ void k_panel_offsets(int nblocks, int64_t per_block, const int64_t* __restrict__ gscan,
+                                int32_t* __restrict__ off, int64_t* __restrict__ bstart) {
+  const int64_t blk = blockIdx.y;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i > per_block) return;
+  const int64_t base = gscan[blk * per_block];
+  off[blk * (per_block + 1) + i] = (int32_t)(gscan[blk * per_block + i] - base);
+  if (i == 0) {
+    bstart[blk] = base;
+    if (blk + 1 == nblocks) bstart[nblocks] = gscan[(int64_t)nblocks * per_block];
+  }
+}
+
+template <typename VT>
+__global__ void k_panel_fill(int64_t n, const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
+                             const VT* __restrict__ val, int RB, int P, int PW, const int32_t* __restrict__ off,
+                             const int64_t* __restrict__ bstart, uint16_t* __restrict__ pcol,
+                             VT* __restrict__ pval) {
+  const int lane = threadIdx.x & 63;
+  const int64_t row = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (row >= n) return;
+  const int64_t b = rp[row], e = rp[row + 1];
+  const int64_t blk = row / RB;
+  const int rl = (int)(row - blk * RB);
+  const int64_t per = (int64_t)P * RB + 1;
+  for (int64_t t = b + lane; t < e; t += 64) {
+    const int c = col[t];
+    const int p = c / PW;
+    const int64_t st = lower_col(col, b, t, (int64_t)p * PW);
+    const int64_t dst = bstart[blk] + off[blk * per + (int64_t)p * RB + rl] + (t - st);
+    pcol[dst] = (uint16_t)(c - p * PW);
+    pval[dst] = val[t];
+  }
+}
+
 // upper Gershgorin bound of each row: d_i + sum_{j != i} |a_ij|
 __global__ void k_gersh(int64_t n, const int64_t* __restrict__ rp, const int64_t* __restrict__ rend,
                         const int32_t* __restrict__ col, const double* __restrict__ v64,
@@ -385,8 +595,83 @@ void extract_diag(const DevCSR& H, double* diag, hipStream_t s) {
   SPPC_LAUNCH_CHECK();
 }
 
+void build_panel(const DevCSR& H, int PW, int RB, PanelH& out, hipStream_t s) {
+  if (PW < 1 || PW > 65536 || RB < 64 || RB % 64 != 0) throw Error(1, "panel: bad width or block size");
+  const int64_t n = H.n;
+  out.n = n;
+  out.RB = RB;
+  out.PW = PW;
+  out.P = (int)cdiv(n, PW);
+  out.nblocks = (int)cdiv(n, RB);
+  const int64_t per = (int64_t)out.P * RB;
+  const int64_t total = per * out.nblocks;
+  if (total >= ((int64_t)1 << 31)) throw Error(1, "panel: too many (row, panel) pairs");
+  int32_t* cnt = nullptr;
+  int64_t *gscan = nullptr, *bsum = nullptr;
+  auto cleanup = [&]() { hipFree(cnt); hipFree(gscan); hipFree(bsum); };
+  try {
+    SPPC_HIP(hipMalloc(&cnt, sizeof(int32_t) * total));
+    SPPC_HIP(hipMalloc(&gscan, sizeof(int64_t) * (total + 1)));
+    SPPC_HIP(hipMalloc(&bsum, sizeof(int64_t) * (cdiv(total, SCAN_BLOCK) + 1)));
+    SPPC_HIP(hipMemsetAsync(cnt, 0, sizeof(int32_t) * total, s));
+    const int64_t grid_w = cdiv(n, 4);
+    k_panel_count<<<grid_w, 256, 0, s>>>(n, H.rp, H.col, RB, out.P, PW, cnt);
+    scan_exclusive(total, cnt, gscan, bsum, s);
+    SPPC_HIP(hipMalloc(&out.off, sizeof(int32_t) * (per + 1) * out.nblocks));
+    SPPC_HIP(hipMalloc(&out.bstart, sizeof(int64_t) * (out.nblocks + 1)));
+    // a block holds fewer than 2^31 entries: RB rows of at most n columns each
+    if ((int64_t)RB * n >= ((int64_t)1 << 31)) {
+      int64_t big = 0;
+      // checked after the scan: the largest block
+      std::vector<int64_t> hs(out.nblocks + 1);
+      SPPC_HIP(hipStreamSynchronize(s));
+      for (int q = 0; q <= out.nblocks; ++q)
+        SPPC_HIP(hipMemcpy(&hs[q], gscan + (int64_t)q * per, sizeof(int64_t), hipMemcpyDeviceToHost));
+      for (int q = 0; q < out.nblocks; ++q) big = std::max(big, hs[q + 1] - hs[q]);
+      if (big >= ((int64_t)1 << 31)) throw Error(1, "panel: block with 2^31 entries");
+    }
+    dim3 g2((unsigned)cdiv(per + 1, 256), (unsigned)out.nblocks);
+    k_panel_offsets<<<g2, 256, 0, s>>>(out.nblocks, per, gscan, out.off, out.bstart);
+    const int64_t nnz = H.nnz;
+    SPPC_HIP(hipMalloc(&out.col, sizeof(uint16_t) * (nnz > 0 ? nnz : 1)));
+    if (H.val64) {
+      SPPC_HIP(hipMalloc(&out.val64, sizeof(double) * (nnz > 0 ? nnz : 1)));
+      k_panel_fill<double><<<grid_w, 256, 0, s>>>(n, H.rp, H.col, H.val64, RB, out.P, PW, out.off, out.bstart,
+                                                   out.col, out.val64);
+    }
+    if (H.val32) {
+      SPPC_HIP(hipMalloc(&out.val32, sizeof(float) * (nnz > 0 ? nnz : 1)));
+      k_panel_fill<float><<<grid_w, 256, 0, s>>>(n, H.rp, H.col, H.val32, RB, out.P, PW, out.off, out.bstart,
+                                                 out.col, out.val32);
+    }
+    SPPC_LAUNCH_CHECK();
+    SPPC_HIP(hipStreamSynchronize(s));
+  } catch (...) {
+    cleanup();
+    release_panel(out);
+    throw;
+  }
+  cleanup();
+}
+
+void release_panel(PanelH& p) {
+  (void)hipFree(p.off);
+  (void)hipFree(p.bstart);
+  (void)hipFree(p.col);
+  (void)hipFree(p.val32);
+  (void)hipFree(p.val64);
+  p = PanelH{};
+}
+
 void spmm_f64(const DevCSR& H, const double* X, int64_t ldx, double* Y, int64_t ldy, int b,
               const double* shift, hipStream_t s) {
+  if (H.panel && !shift && b >= 1 && b <= 16 && H.n > 0) {
+    if (H.val64)
+      launch_spmm_panel<double, double>(*H.panel, H.panel->val64, X, ldx, Y, ldy, b, s);
+    else
+      launch_spmm_panel<float, double>(*H.panel, H.panel->val32, X, ldx, Y, ldy, b, s);
+    return;
+  }
   if (H.val64)
     launch_spmm<double, double>(H, H.val64, X, ldx, Y, ldy, b, shift, s);
   else
@@ -396,6 +681,10 @@ void spmm_f64(const DevCSR& H, const double* X, int64_t ldx, double* Y, int64_t 
 void spmm_f32(const DevCSR& H, const float* X, int64_t ldx, double* Y, int64_t ldy, int b,
               const double* shift, hipStream_t s) {
   if (!H.val32) throw Error(1, "spmm_f32: no float32 values");
+  if (H.panel && !shift && b >= 1 && b <= 16 && H.n > 0) {
+    launch_spmm_panel<float, float>(*H.panel, H.panel->val32, X, ldx, Y, ldy, b, s);
+    return;
+  }
   launch_spmm<float, float>(H, H.val32, X, ldx, Y, ldy, b, shift, s);
 }
 

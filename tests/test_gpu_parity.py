@@ -64,6 +64,67 @@ def test_spmm_f32_products_accumulated_in_f64():
     assert np.max(np.abs(Y - ref) / scale) < 2.0 ** -24 * 1.01
 
 
+# column-panel copy: many panels, ragged last panel and last row block (n = 60,700)
+PANEL_A = None
+
+
+def _panel_matrix():
+    global PANEL_A
+    if PANEL_A is None:
+        PANEL_A = levelgen.generate((700, 6000, 54000), 40, 91)
+    return PANEL_A
+
+
+@pytest.mark.parametrize("pw", [0, 1000, 4096, 65536])
+def test_panel_spmm_f64_matches_scipy(pw):
+    A = _panel_matrix()
+    print("case panel spmm pw=%d n=%d" % (pw, A.n), flush=True)
+    H = _H(A)
+    ctx = _ctx(A, 1, 16, panel_width=pw)
+    rng = np.random.default_rng(pw)
+    for b in (1, 3, 4, 5, 8, 11, 16):
+        X = rng.standard_normal((A.n, b))
+        Yd = torch.empty((A.n, b), dtype=torch.float64, device="cuda")
+        P.sppc_spmm(ctx, torch.from_numpy(X).cuda(), Yd)
+        torch.cuda.synchronize()
+        Y = Yd.cpu().numpy()
+        ref = H @ X
+        scale = abs(H) @ np.abs(X)
+        assert np.max(np.abs(Y - ref) / scale) < 1e-14, b
+
+
+def test_panel_spmm_f32_products_accumulated_in_f64():
+    A = _panel_matrix()
+    print("case panel spmm f32 n=%d" % A.n, flush=True)
+    H = _H(A)
+    ctx = _ctx(A, 1, 8, panel_width=2048, precision=P.SPPC_PREC_MIXED)
+    rng = np.random.default_rng(6)
+    for b in (2, 8, 13):
+        X = rng.standard_normal((A.n, b)).astype(np.float32)
+        Yd = torch.empty((A.n, b), dtype=torch.float64, device="cuda")
+        P.sppc_spmm(ctx, torch.from_numpy(X).cuda(), Yd)
+        torch.cuda.synchronize()
+        Y = Yd.cpu().numpy()
+        X64 = X.astype(np.float64)
+        ref = H @ X64
+        scale = abs(H) @ np.abs(X64)
+        assert np.max(np.abs(Y - ref) / scale) < 2.0 ** -24 * 1.01, b
+
+
+def test_panel_solve_matches_csr_solve():
+    A = _panel_matrix()
+    print("case panel solve n=%d" % A.n, flush=True)
+    res = []
+    for pw in (0, 4096):
+        ctx = _ctx(A, 1, 4, panel_width=pw)
+        ev, Z, rrn, st, status = P.sppc_solve(ctx)
+        P.sppc_destroy(ctx)
+        assert status == P.SPPC_OK
+        res.append((np.array(ev), st))
+    assert np.max(np.abs(res[0][0] - res[1][0]) / np.abs(res[0][0])) < 1e-12
+    assert res[0][1]["iterations"] == res[1][1]["iterations"]
+
+
 # ---------------------------------------------------------------- zeroth order
 def test_zeroth_order_matches_dense():
     print("case zeroth order cfg0", flush=True)
