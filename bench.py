@@ -11,7 +11,7 @@ continuation) is followed by the same number of plain float64 steps with the dia
 preconditioner (--no-compare skips them).  Prints one JSON line.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload 1]
-                  [--mode plain|mixed|plain+mpnn|mixed+mpnn] [--no-compare]
+                  [--mode plain|mixed|plain+mpnn|mixed+mpnn|plain+small|mixed+small] [--no-compare]
                   [--no-cpu-baseline] [--calibrate-copy] [--spmm-only R]
 """
 from __future__ import annotations
@@ -28,7 +28,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
-MODES = ("plain", "mixed", "plain+mpnn", "mixed+mpnn")
+MODES = ("plain", "mixed", "plain+mpnn", "mixed+mpnn", "plain+small", "mixed+small")
 
 
 def parse():
@@ -111,8 +111,8 @@ def main():
     def make_step(mode):
         mixed = mode.startswith("mixed")
         mpnn = mode.endswith("mpnn")
-        opts = P.sppc_default_opts(precision=P.SPPC_PREC_MIXED if mixed else P.SPPC_PREC_FP64,
-                                   precond=P.SPPC_CORR_MPNN if mpnn else P.SPPC_CORR_JACOBI,
+        precond = P.SPPC_CORR_MPNN if mpnn else P.SPPC_CORR_SMALL if mode.endswith("small") else P.SPPC_CORR_JACOBI
+        opts = P.sppc_default_opts(precision=P.SPPC_PREC_MIXED if mixed else P.SPPC_PREC_FP64, precond=precond,
                                    verbose=1 if args.verbose else 0, panel_width=args.panel_width)
 
         def one_step():

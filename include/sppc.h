@@ -56,7 +56,10 @@ typedef enum {
 typedef enum {
   SPPC_CORR_PERTURBATIVE = 0, /* Psi^(p) of eq. exp_seq2 for every wanted pair (Alg. 2 step 6) */
   SPPC_CORR_JACOBI = 1,       /* continuation: t_i = -(I - z_i z_i^T) (diag(H) - theta_i)^-1 r_i */
-  SPPC_CORR_MPNN = 2          /* continuation: learned diagonal scaling of the Jacobi step */
+  SPPC_CORR_MPNN = 2,         /* continuation: learned diagonal scaling of the Jacobi step */
+  SPPC_CORR_SMALL = 3         /* continuation: t_i = -(I - z_i z_i^T) M_i r_i with M_i = (H0hat - theta_i)^-1
+                                 on the small-space rows (deflated CG to a loose tolerance plus the
+                                 exact deflated terms) and (diag(H) - theta_i)^-1 on the other rows */
 } sppc_corr_kind;
 
 /* Upper triangle (diagonal included) of the symmetric H, CSR, device memory. */
@@ -80,12 +83,14 @@ typedef struct {
   double inner_tol;    /* relative residual of the small-space solves; 0 = 1e-12 (FP64) / 1e-6 (MIXED) */
   double h0_tol;       /* residual of the H0hat eigenpairs, relative to max(1,|E|) */
   int precision;       /* sppc_precision; MIXED adds a float64 refinement when the final check fails */
-  int precond;         /* sppc_corr_kind used by the continuation (JACOBI or MPNN) */
+  int precond;         /* sppc_corr_kind used by the continuation (JACOBI, MPNN or SMALL); JACOBI */
   int final_check;     /* explicit float64 H Z, Rayleigh-Ritz on span Z, true residual */
   int verbose;         /* per-iteration line on stderr */
   int panel_width;     /* block products with H over column panels of this many columns (<= 65536),
                           so that the gathered rows of X stay in L2: -1 = automatic (when a k-column
                           block of X exceeds 8 MiB), 0 = off */
+  int refine_precond;  /* continuation kind of the float64 refinement after a mixed solve; SMALL */
+  double precond_tol;  /* relative residual of the small-space solve inside SMALL; 1e-3 */
 } sppc_opts;
 
 typedef struct {
@@ -153,8 +158,9 @@ sppc_status sppc_spmm(sppc_ctx* ctx, const void* X_dev, sppc_dtype xt, double* Y
  *     the stored H Q (eq. HPsip) and V Psi = H Psi - H0 Psi (eq. avoid_SpMV2);
  *     complement rows by eq. sm_first, small-space rows by eq. sm_lin_proj
  *     (minimum-norm solution orthogonal to psi_k).
- *   SPPC_CORR_JACOBI / SPPC_CORR_MPNN: preconditioned residuals of the current
- *     unconverged Ritz pairs.
+ *   SPPC_CORR_JACOBI / SPPC_CORR_MPNN / SPPC_CORR_SMALL: preconditioned residuals of
+ *     the current unconverged Ritz pairs (Sec. V continuation; the pending block is
+ *     n x (number of unconverged pairs)).
  * Errors: SPPC_E_ARG (e.g. PERTURBATIVE after the basis was restarted), SPPC_E_HIP.
  */
 sppc_status sppc_correct(sppc_ctx* ctx, int kind);

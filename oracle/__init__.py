@@ -17,5 +17,6 @@ from .core import (  # noqa: F401
     sppc,
     final_check,
     jacobi_correction,
+    small_space_correction,
     rayleigh_ritz,
 )

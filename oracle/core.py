@@ -230,6 +230,25 @@ def jacobi_correction(diag: np.ndarray, theta: float, r: np.ndarray, z: np.ndarr
     return -t
 
 
+def small_space_correction(H: sp.csr_matrix, n0: int, theta: float, r: np.ndarray,
+                           z: np.ndarray) -> np.ndarray:
+    """t = -(I - z z^T) M r with M = (H0hat - theta)^-1 on the rows of the small space and the
+    diagonal step (diag(H) - theta)^-1 (clamped as in jacobi_correction) on the other rows.
+
+    Preconditioner of the continuation that uses the zeroth-order block H0hat of the split
+    H = H0 + V (eq. split2); the small-space block is solved exactly (dense).
+    """
+    d = H.diagonal()
+    den = d - theta
+    floor = 1e-2 * max(1.0, abs(theta))
+    den = np.where(np.abs(den) < floor, np.where(den >= 0, floor, -floor), den)
+    t = r / den
+    H0 = H[:n0, :n0].toarray()
+    t[:n0] = np.linalg.solve(H0 - theta * np.eye(n0), r[:n0])
+    t = t - z * (z @ t)
+    return -t
+
+
 # --------------------------------------------------------------------------- driver
 
 

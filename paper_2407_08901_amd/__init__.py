@@ -20,7 +20,7 @@ SPPC_OK, SPPC_E_ARG, SPPC_E_HIP, SPPC_E_NOMEM, SPPC_E_SINGULAR_E0, SPPC_E_BREAKD
     SPPC_E_NAN = range(8)
 SPPC_F64, SPPC_F32 = 0, 1
 SPPC_PREC_FP64, SPPC_PREC_MIXED = 0, 1
-SPPC_CORR_PERTURBATIVE, SPPC_CORR_JACOBI, SPPC_CORR_MPNN = 0, 1, 2
+SPPC_CORR_PERTURBATIVE, SPPC_CORR_JACOBI, SPPC_CORR_MPNN, SPPC_CORR_SMALL = 0, 1, 2, 3
 
 STATUS_NAMES = {0: "SPPC_OK", 1: "SPPC_E_ARG", 2: "SPPC_E_HIP", 3: "SPPC_E_NOMEM",
                 4: "SPPC_E_SINGULAR_E0", 5: "SPPC_E_BREAKDOWN", 6: "SPPC_E_NOCONV", 7: "SPPC_E_NAN"}
@@ -41,7 +41,8 @@ class sppc_opts(ctypes.Structure):
                 ("max_cont", ctypes.c_int), ("m_max", ctypes.c_int), ("n_deflate", ctypes.c_int),
                 ("tau_drop", ctypes.c_double), ("inner_tol", ctypes.c_double), ("h0_tol", ctypes.c_double),
                 ("precision", ctypes.c_int), ("precond", ctypes.c_int), ("final_check", ctypes.c_int),
-                ("verbose", ctypes.c_int), ("panel_width", ctypes.c_int)]
+                ("verbose", ctypes.c_int), ("panel_width", ctypes.c_int), ("refine_precond", ctypes.c_int),
+                ("precond_tol", ctypes.c_double)]
 
 
 class sppc_stats(ctypes.Structure):

@@ -71,6 +71,10 @@ void build_block_view(const DevCSR& full, int64_t n0, int64_t* rend, hipStream_t
 // Device memory is allocated with hipMalloc and owned by the caller (release_panel).
 void build_panel(const DevCSR& H, int PW, int RB, PanelH& out, hipStream_t s);
 void release_panel(PanelH& p);
+// out[0..n] = exclusive prefix sums of a[0..n) (out[n] = total); bsum holds cdiv(n, 1024) + 1.
+void scan_exclusive(int64_t n, const int32_t* a, int64_t* out, int64_t* bsum, hipStream_t s);
+// Contiguous copy of a block view (rows [0, n0), columns < n0); hipMalloc'd arrays.
+void compact_view(const DevCSR& V, DevCSR& out, hipStream_t s);
 // diag(H) from the full CSR.
 void extract_diag(const DevCSR& H, double* diag, hipStream_t s);
 
@@ -155,6 +159,10 @@ void build_correction_coefs(int p, int k, int m, const double* Ghist, int64_t gs
                             const int* m_hist, double* Etab, const double* T, int64_t ldt,
                             const double* E0, double* A, double* B, hipStream_t s);
 // x1 add-back coefficients for the deflated small solves
+// out[j][a] = c[j][a] / (w[j] - theta[a]) (theta device, na values): deflated terms of the
+// theta-shifted small-space solve
+void deflate_shift(int D, int na, const double* w, const double* theta, const double* c, int64_t ldc, double* out,
+                   int64_t ldo, hipStream_t s);
 void deflate_coefs(int D, int k, const double* w, const double* c, int64_t ldc, double* out,
                    int64_t ldo, hipStream_t s);
 // element-wise small: C = C1 + C2 (m x b)
@@ -168,20 +176,13 @@ void unit_block(int64_t n, int b, const int* idx, double* X, int64_t ldx, hipStr
 
 // ---------------------------------------------------------------- small-space solver (kernels_cg.hip)
 int64_t cg_work_doubles(int64_t n0);
-// Deflated preconditioned CG for the k shifted small-space systems; b in r; returns iterations.
-int cg_solve(const DevCSR& H0, int64_t n0, int k, int D, const double* diag, const double* shift,
-             const double* Ps, double* x, double* r, double* z, double* p, double* q, double* work,
-             double* ccoef, int maxit, double tol, bool f32prod, int* host_flag, hipStream_t s);
-void cg_precond(int64_t n0, int k, const double* diag, const double* shift, const double* r,
-                double* z, hipStream_t s);
-void cg_dots(int64_t n0, int k, const double* a, const double* b, double* out, double* work, hipStream_t s);
-void cg_update_xr(int64_t n0, int k, double* x, double* r, const double* p, const double* q,
-                  const double* rz, const double* pq, const int* active, hipStream_t s);
-void cg_update_p(int64_t n0, int k, double* p, const double* z, const double* rz_new,
-                 const double* rz_old, const int* active, hipStream_t s);
-void cg_check(int k, const double* rr, const double* bb, double tol2, int* active, int* nactive,
-              double* rzn, double* rzo, hipStream_t s);
-void cg_init(int k, const double* bb, int* active, int* nactive, hipStream_t s);
+// Row bounds of the CG iteration blocks (once per H0hat); rowb has 257 entries, tmp 2 (n0 + 2)
+// doubles.
+void cg_prepare(const DevCSR& H0, int64_t n0, int64_t* rowb, double* tmp, hipStream_t s);
+// Deflated CG for the k small-space systems (b in r on entry, solution in x); ccoef = Ps^T b.
+int cg_solve(const DevCSR& H0, int64_t n0, int k, int D, const double* shift, const double* Ps,
+             const int64_t* rowb, double* x, double* r, double* work, double* ccoef, int maxit, double tol,
+             bool f32prod, int* host_flag, hipStream_t s);
 // out[c] = X[:, c]^T Y[:, c]
 void coldots(int64_t n, int b, const double* X, int64_t ldx, const double* Y, int64_t ldy, double* out,
              double* work, hipStream_t s);

@@ -119,10 +119,11 @@ struct sppc_ctx {
   double *Xt = nullptr, *Acoef = nullptr, *Bcoef = nullptr, *dots = nullptr, *work = nullptr;
   double* eigscr = nullptr;
   int *info = nullptr, *idx = nullptr, *mhist_dev = nullptr;
-  double *cx = nullptr, *cr = nullptr, *cz = nullptr, *cp = nullptr, *cp1 = nullptr, *cq = nullptr,
-         *ccoef = nullptr, *ctmp = nullptr, *cvec = nullptr, *cgpart = nullptr;
+  double *cx = nullptr, *cr = nullptr,
+         *ccoef = nullptr, *ctmp = nullptr, *cgpart = nullptr;
+  int64_t* cg_rowb = nullptr;
+  double* cshift = nullptr;  // shifts of the theta-shifted small-space solves
   int cg_blocks = 1;
-  int *cact = nullptr, *cnact = nullptr;
   double* Ghist = nullptr;
   int64_t gstride = 0;
   int maxhist = 0;
@@ -378,8 +379,8 @@ void small_solve(sppc_ctx* c) {
   const bool mixed = c->o.precision == SPPC_PREC_MIXED;
   double tol = c->o.inner_tol;
   if (tol <= 0.0) tol = mixed ? 1e-6 : 1e-12;
-  c->st.cg_iterations += cg_solve(c->H0, n0, k, D, c->diag, c->E0, c->Psihat, c->cx, c->cr, c->cz, c->cp,
-                                  c->cq, c->cgpart, c->ccoef, 5000, tol, mixed, c->pin_i + 4, s);
+  c->st.cg_iterations += cg_solve(c->H0, n0, k, D, c->E0, c->Psihat, c->cg_rowb, c->cx, c->cr, c->cgpart,
+                                  c->ccoef, 5000, tol, mixed, c->pin_i + 4, s);
   deflate_coefs(D, k, c->E0, c->ccoef, k, c->ctmp, k, s);
   gemm_nn(n0, D, k, c->Psihat, D, c->ctmp, k, c->cx, k, 1.0, 1.0, s);
   copy_block(n0, k, c->cx, k, c->Psi, k, s);
@@ -462,6 +463,34 @@ void upload_theta(sppc_ctx* c, const double* th, int S) {
   sync(c);
 }
 
+// Continuation step with the small-space preconditioner: t_a = -(I - z z^T) M_a r_a where M_a is
+// (H0hat - theta_a)^-1 on the rows of the small space (deflated CG to precond_tol, plus the exact
+// terms of the D deflated eigenvectors of H0hat) and the diagonal step (diag(H) - theta_a)^-1 on
+// the other rows.  On the complement of the deflated vectors H0hat - theta_a is positive
+// definite: a Ritz value theta_a >= lambda_a(H) <= E_a(H0hat) < E_{D+1} by interlacing.
+void small_expansion(sppc_ctx* c, const std::vector<int>& act) {
+  hipStream_t s = c->s;
+  const int na = (int)act.size(), k = c->k, D = c->D;
+  const int64_t n = c->n, n0 = c->n0;
+  for (int a = 0; a < na; ++a) {
+    c->pin_i[8 + a] = act[a];
+    c->pin[3 * NWMAX + a] = c->theta_h[act[a]];
+  }
+  SPPC_HIP(hipMemcpyAsync(c->idx, c->pin_i + 8, sizeof(int) * na, hipMemcpyHostToDevice, s));
+  SPPC_HIP(hipMemcpyAsync(c->cshift, c->pin + 3 * NWMAX, sizeof(double) * na, hipMemcpyHostToDevice, s));
+  jacobi_block(n, na, c->idx, c->R, k, c->diag, c->theta, c->Psi, na, s);
+  gather_cols(n0, na, c->idx, c->R, k, c->cr, na, s);
+  const bool f32 = c->o.precision == SPPC_PREC_MIXED && c->H0.val32 != nullptr;
+  c->st.cg_iterations += cg_solve(c->H0, n0, na, D, c->cshift, c->Psihat, c->cg_rowb, c->cx, c->cr, c->cgpart,
+                                  c->ccoef, 1000, c->o.precond_tol, f32, c->pin_i + 4, s);
+  deflate_shift(D, na, c->E0, c->cshift, c->ccoef, na, c->ctmp, na, s);
+  gemm_nn(n0, D, na, c->Psihat, D, c->ctmp, na, c->cx, na, 1.0, 1.0, s);
+  copy_block(n0, na, c->cx, na, c->Psi, na, s);
+  paired_dots(n, na, c->idx, c->Z, k, c->Psi, na, c->dots, c->work, s);
+  project_out_block(n, na, c->idx, c->Z, k, c->dots, c->Psi, na, s);
+  sync(c);
+}
+
 void correct_continuation(sppc_ctx* c, int kind) {
   if (kind == SPPC_CORR_MPNN && !c->mp_have_w) throw Error(SPPC_E_ARG, "no weights for the learned preconditioner");
   std::vector<int> act;
@@ -475,7 +504,10 @@ void correct_continuation(sppc_ctx* c, int kind) {
     restart_basis(c, b, c->k);
     c->restarted = true;
   }
-  jacobi_expansion(c, c->n, c->diag, act, c->k);
+  if (kind == SPPC_CORR_SMALL)
+    small_expansion(c, act);
+  else
+    jacobi_expansion(c, c->n, c->diag, act, c->k);
   if (kind == SPPC_CORR_MPNN && !c->mp_invalid) {
     // the true residual judges the learned step: a pair whose residual did not fall below 0.9x
     // its value at the previous learned step uses the diagonal step from then on
@@ -613,6 +645,10 @@ void setup_impl(sppc_ctx* c, const sppc_csr* Hin, const int64_t* loff, int L, in
   c->D = o.n_deflate;
   if (o.m_max < 2 * k || o.m_max > 512) throw Error(SPPC_E_ARG, "m_max must be in [2k, 512]");
   if (o.panel_width < -1 || o.panel_width > 65536) throw Error(SPPC_E_ARG, "panel_width must be -1, 0 or 1..65536");
+  for (int kind : {o.precond, o.refine_precond})
+    if (kind != SPPC_CORR_JACOBI && kind != SPPC_CORR_MPNN && kind != SPPC_CORR_SMALL)
+      throw Error(SPPC_E_ARG, "continuation preconditioner must be JACOBI, MPNN or SMALL");
+  if (!(o.precond_tol > 0.0) || o.precond_tol >= 1.0) throw Error(SPPC_E_ARG, "precond_tol must be in (0, 1)");
   if (!(o.tol > 0) || !(o.tau_drop >= 0) || !(o.inner_tol >= 0) || !(o.h0_tol > 0)) throw Error(SPPC_E_ARG, "bad tolerances");
   if (o.precision != SPPC_PREC_FP64 && o.precision != SPPC_PREC_MIXED) throw Error(SPPC_E_ARG, "bad precision");
   const int last_p = (o.p_switch > 0) ? std::min(o.p_switch, o.maxiter) : o.maxiter;
@@ -678,6 +714,15 @@ void setup_impl(sppc_ctx* c, const sppc_csr* Hin, const int64_t* loff, int L, in
   }
   c->H0.rend = A.alloc<int64_t>(c->n0);
   build_block_view(c->H, c->n0, c->H0.rend, s);
+  {
+    // H0hat as its own contiguous CSR (no gaps where the rows continue beyond column n0)
+    DevCSR v = c->H0;
+    compact_view(v, c->H0, s);
+    A.ptrs.push_back(c->H0.rp);
+    A.ptrs.push_back(c->H0.col);
+    if (c->H0.val64) A.ptrs.push_back(c->H0.val64);
+    if (c->H0.val32) A.ptrs.push_back(c->H0.val32);
+  }
   c->diag = A.alloc<double>(c->n);
   extract_diag(c->H, c->diag, s);
 
@@ -727,16 +772,12 @@ void setup_impl(sppc_ctx* c, const sppc_csr* Hin, const int64_t* loff, int L, in
   c->Psihat = A.alloc<double>((size_t)n0 * c->D);
   c->cx = A.alloc<double>((size_t)n0 * KB);
   c->cr = A.alloc<double>((size_t)n0 * KB);
-  c->cz = A.alloc<double>((size_t)n0 * KB);
-  c->cp = A.alloc<double>((size_t)n0 * KB);
-  c->cq = A.alloc<double>((size_t)n0 * KB);
-  c->cp1 = A.alloc<double>((size_t)n0 * KB);
   c->cgpart = A.alloc<double>((size_t)cg_work_doubles(n0));
+  c->cg_rowb = A.alloc<int64_t>(257);
+  c->cshift = A.alloc<double>(KB);
+  cg_prepare(c->H0, n0, c->cg_rowb, c->cgpart, s);
   c->ccoef = A.alloc<double>((size_t)KB * KB);
   c->ctmp = A.alloc<double>((size_t)KB * KB);
-  c->cvec = A.alloc<double>(8 * KB);
-  c->cact = A.alloc<int>(KB);
-  c->cnact = A.alloc<int>(4);
   SPPC_HIP(hipHostMalloc((void**)&c->pin, sizeof(double) * 4 * NWMAX, hipHostMallocDefault));
   SPPC_HIP(hipHostMalloc((void**)&c->pin_i, sizeof(int) * 128, hipHostMallocDefault));
   c->tm.s = s;
@@ -788,7 +829,7 @@ sppc_status solve_impl(sppc_ctx* c, double* evals, double* evecs, double* rrn, s
   c->st.iterations = c->p;
   int cont = 0;
   if (o.p_switch > 0) {
-    const int kind = o.precond == SPPC_CORR_MPNN ? SPPC_CORR_MPNN : SPPC_CORR_JACOBI;
+    const int kind = o.precond;
     while (!conv && cont < o.max_cont) {
       correct_continuation(c, kind);
       const int added = append_and_rr(c);
@@ -813,22 +854,25 @@ sppc_status solve_impl(sppc_ctx* c, double* evals, double* evecs, double* rrn, s
     // the checked Ritz vectors (float64 H Z) and continue with float64 products until the true
     // residual meets the tolerance
     if (!conv && o.precision == SPPC_PREC_MIXED && o.p_switch > 0) {
+      // New basis columns get float64 products.  The basis is kept (its float32-product columns
+      // still span the directions found so far); the loop's residuals carry the float32 noise,
+      // so each round ends with the float64 check, which decides convergence.
       c->refining = true;
-      restart_basis(c, c->B, c->k);
-      c->restarted = true;
       int ref = 0;
-      while (!conv && ref < o.max_cont) {
-        correct_continuation(c, SPPC_CORR_JACOBI);
-        const int added = append_and_rr(c);
-        ++ref;
-        ++cont;
-        log_step(c, "refine");
+      for (int round = 0; round < 4 && !conv && ref < o.max_cont; ++round) {
+        do {
+          correct_continuation(c, o.refine_precond);
+          const int added = append_and_rr(c);
+          ++ref;
+          ++cont;
+          log_step(c, "refine");
+          conv = all_converged(c);
+          if (added == 0) break;
+        } while (!conv && ref < o.max_cont);
+        final_check(c);
+        log_step(c, "final");
         conv = all_converged(c);
-        if (added == 0 && !conv) break;
       }
-      final_check(c);
-      log_step(c, "final");
-      conv = all_converged(c);
       c->st.refine_steps = ref;
     }
   }
@@ -885,6 +929,8 @@ sppc_status sppc_default_opts(sppc_opts* o) {
   o->h0_tol = 1e-12;
   o->precision = SPPC_PREC_FP64;
   o->precond = SPPC_CORR_JACOBI;
+  o->refine_precond = SPPC_CORR_SMALL;
+  o->precond_tol = 1e-3;
   o->final_check = 1;
   o->verbose = 0;
   o->panel_width = -1;
@@ -931,7 +977,8 @@ sppc_status sppc_correct(sppc_ctx* c, int kind) {
   if (!c) return SPPC_E_ARG;
   return guarded(c, [&]() {
     if (kind == SPPC_CORR_PERTURBATIVE) correct_perturbative(c);
-    else if (kind == SPPC_CORR_JACOBI || kind == SPPC_CORR_MPNN) correct_continuation(c, kind);
+    else if (kind == SPPC_CORR_JACOBI || kind == SPPC_CORR_MPNN || kind == SPPC_CORR_SMALL)
+      correct_continuation(c, kind);
     else throw Error(SPPC_E_ARG, "unknown correction kind");
     return SPPC_OK;
   });

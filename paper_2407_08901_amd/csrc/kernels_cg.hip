@@ -2,23 +2,22 @@
 //
 // For every wanted pair c the singular system (H0hat - E_c) x = b_c - (b_c^T psi_c) psi_c is
 // solved for its minimum-norm solution orthogonal to psi_c.  The D lowest eigenvectors of
-// H0hat (Ps, n0 x D) are deflated: preconditioned CG runs on the complement, where
-// H0hat - E_c is positive definite, and the deflated directions are added back exactly
-// by the caller.  All k systems advance together, sharing one product with H0hat per
-// iteration.
+// H0hat (Ps, n0 x D) are deflated: CG runs on the complement, where H0hat - E_c is positive
+// definite, and the deflated directions are added back exactly by the caller.  All k
+// systems advance together, sharing one product with H0hat per iteration.
 //
 // The right-hand side is projected once onto the complement; H0hat - E_c maps the complement
-// into itself (its deflated directions are eigenvectors), so plain CG iterates stay there and
-// need only the k-wide dot products p.q and r.r per iteration.  The final x is projected once
-// more to remove rounding drift.
+// into itself (its deflated directions are eigenvectors), so the CG iterates stay there.  The
+// final x is projected once more to remove rounding drift.
 //
-// One iteration is two kernels; the kernel boundaries are the only grid-wide barriers.  Every
-// block re-adds the previous kernel's per-block partial sums in the same fixed order, so the
-// CG scalars are identical on all blocks and bit-reproducible.  The product kernel forms the
-// new search direction p = r + beta p_old on the fly for every row it gathers (p is double
-// buffered), so no separate direction update is needed.  Scalars are double-buffered by
-// iteration parity; once no column is active every kernel returns at entry (the host polls
-// the count every few iterations).
+// The iteration is the single-reduction form of CG (Chronopoulos and Gear): with w = A r the
+// two inner products r.r and w.r of one iteration are formed together, so one kernel per
+// iteration suffices and the kernel boundary is the only grid-wide barrier.  The kernel
+// re-adds the previous kernel's per-block partial sums (same fixed order on every block, so
+// the CG scalars are identical everywhere and bit-reproducible), updates p, s, x, r of its own
+// rows and forms w = A r_new, evaluating r_new = r - alpha (w + beta s_old) at every gathered
+// row.  r, w and s are double-buffered by iteration parity.  Rows are split over the blocks by
+// nonzero count (level-0 rows of H0hat have far more entries than level-1 rows).
 #include "common.h"
 
 namespace sppc {
@@ -27,14 +26,16 @@ namespace {
 
 constexpr int CG_MAXK = 16;
 constexpr int CG_MAXD = 28;
-constexpr int PW = 1024;       // partial width of the reduction phase (>= 2k + 2Dk)
-constexpr int R1 = 16;         // rows per block of the product kernel
+constexpr int PW = 1024;       // partial width of the projection phase (>= 2Dk)
 constexpr int CH = 64;         // rows per LDS chunk of the projections
+constexpr int NB = 256;        // blocks of the iteration kernel
+constexpr int NT = 1024;       // threads per block of the iteration kernel
 
-// device scalars: [parity][...]
+// device scalars, double-buffered by iteration parity
 struct CGScal {
-  double rr[2][CG_MAXK];
-  double bb[CG_MAXK];
+  double gam[2][CG_MAXK];  // r.r of the iteration's residual
+  double alp[2][CG_MAXK];  // step length
+  double bb[CG_MAXK];      // r.r of the projected right-hand side
   int act[2][CG_MAXK];
   int nact[2];
   int iters;
@@ -48,16 +49,17 @@ struct CGArgs {
   const int32_t* col;
   const double* v64;
   const float* v32;
-  const double* diag;
   const double* shift;  // E_c
   const double* Ps;     // n0 x D
-  double *x, *r, *q;    // n0 x k
-  double *pa, *pb;      // search directions, double-buffered
-  double* part1;        // nb1 x k   (p.q)
-  double* part2;        // nb2 x k   (r.r)
-  double* partP;        // nb2 x Dk  (Ps^T y)
-  int nb1, nb2;
-  double* ccoef;        // D x k: Ps^T b (for the add-back)
+  const int64_t* rowb;  // [NB + 1] row bounds of the iteration blocks
+  double* x;            // n0 x k
+  double* r[2];         // residuals by parity
+  double* w[2];         // A r by parity
+  double* sv[2];        // A p by parity
+  double* p;
+  double* part[2];      // NB x 2*CG_MAXK partial (r.r, w.r) by parity
+  double* partP;        // nb2 x PW   (Ps^T y)
+  int nb2;
   CGScal* sc;
   double tol2;
 };
@@ -79,41 +81,7 @@ __device__ void reduce_parts(const double* __restrict__ part, int nb, int64_t st
   __syncthreads();
 }
 
-// tot[c] = sum_b part[b*CG_MAXK + c] for c < w <= CG_MAXK, all threads of the block: thread t
-// sums the blocks b = t/16, t/16 + nt/16, ... of column t%16, then a fixed-order tree.
-__device__ void reduce_cols(const double* __restrict__ part, int nb, int w, double* red, double* tot) {
-  const int t = threadIdx.x, nt = blockDim.x;
-  const int c = t % CG_MAXK;
-  double s = 0.0;
-  if (c < w)
-    for (int b2 = t / CG_MAXK; b2 < nb; b2 += nt / CG_MAXK) s += part[(int64_t)b2 * CG_MAXK + c];
-  red[t] = s;
-  __syncthreads();
-  for (int o = nt / 2; o >= CG_MAXK; o >>= 1) {
-    if (t < o) red[t] += red[t + o];
-    __syncthreads();
-  }
-  if (t < w) tot[t] = red[t];
-  __syncthreads();
-}
 
-// Column sums over rows [r0, r1) of X[r][c] * Y[r][c] -> out[c]; block of 1024 threads.
-__device__ void block_coldot(const double* __restrict__ X, const double* __restrict__ Y, int64_t r0,
-                             int64_t r1, int k, double* red, double* out) {
-  const int t = threadIdx.x, nt = blockDim.x;
-  const int tc = t % CG_MAXK, tr = t / CG_MAXK;
-  double s = 0.0;
-  if (tc < k)
-    for (int64_t r = r0 + tr; r < r1; r += nt / CG_MAXK) s = fma(X[r * k + tc], Y[r * k + tc], s);
-  red[t] = s;
-  __syncthreads();
-  for (int o = nt / 2; o >= CG_MAXK; o >>= 1) {
-    if (t < o) red[t] += red[t + o];
-    __syncthreads();
-  }
-  if (t < k) out[t] = red[t];
-  __syncthreads();
-}
 
 // Block partials over rows [r0, r1): Ps^T Y -> out[0 .. Dk) and, if psx, Ps^T X -> out[Dk .. 2Dk);
 // rows staged through LDS (one output per thread, 2Dk <= 896 < 1024 threads).
@@ -162,9 +130,10 @@ __global__ __launch_bounds__(1024) void k_cg_psT(CGArgs a, const double* Y) {
   block_psT(a.Ps, Y, Y, r0, r1, a.D, a.k, false, sh_ps, sh_x, sh_y, a.partP + (int64_t)blockIdx.x * PW);
 }
 
-// ---- Y -= Ps (Ps^T Y) from the partials; optionally also: coef = Ps^T Y, zero X, r.r partials
+// ---- Y -= Ps (Ps^T Y) from the partials; optionally also: coef = Ps^T Y, and (start) zero
+// x, p and s_{-1}
 __global__ __launch_bounds__(1024) void k_cg_project(CGArgs a, double* Y, double* coef, int start) {
-  __shared__ double tot[PW], red[1024];
+  __shared__ double tot[PW];
   const int k = a.k, D = a.D, Dk = D * k, t = threadIdx.x;
   reduce_parts(a.partP, a.nb2, PW, Dk, tot);
   if (coef && blockIdx.x == 0)
@@ -179,122 +148,290 @@ __global__ __launch_bounds__(1024) void k_cg_project(CGArgs a, double* Y, double
     Y[e] = v;
     if (start) {
       a.x[e] = 0.0;
-      a.pb[e] = 0.0;
+      a.p[e] = 0.0;
+      a.sv[1][e] = 0.0;
     }
-  }
-  if (start) {
-    __syncthreads();
-    block_coldot(Y, Y, r0, r1, k, red, a.part2 + (int64_t)blockIdx.x * CG_MAXK);
   }
 }
 
-// ---- iteration, K1: beta, convergence; p = r + beta p_old (on the fly); q = (H0hat - E) p ;
-//      partial p.q.  One wave per row.
+// ---- one CG iteration (j >= 0) or, with INIT, w_0 = A r_0 and the partials of (r.r, w.r).
+// Kernel j reads r_j, w_j (buffer j&1), s_{j-1} (buffer (j&1)^1), p_{j-1}, x_j and the partials
+// of kernel j-1; it writes p_j, s_j (buffer j&1), x_{j+1}, r_{j+1}, w_{j+1} (buffer (j&1)^1) and
+// its partials (buffer j&1).
+//
+// A block owns a row range (H0hat is a contiguous CSR) and takes it in chunks of RCH rows.  The
+// product is entry-parallel: each wave streams windows of 64 entries of the chunk (one coalesced
+// load), groups of B lanes take B consecutive entries, lane c gathers column c of the rows of
+// (r, w, s) named by the entries, and runs of entries of one row are summed in a register and
+// added to the row's LDS accumulator when the run ends.  Then every (row, column) of the chunk is
+// updated by one thread.
+constexpr int RCH = 128;
+
+// entries [win, win + 64) of a chunk: columns, values and the row (last r with soff[r] <= e)
+template <typename VT>
+__device__ inline void cg_window(const int32_t* __restrict__ col, const VT* __restrict__ val, int64_t e0,
+                                 const int* soff, int nr, int ne, int e, int& mc, VT& mv, int& mr) {
+  mc = 0;
+  mv = VT(0);
+  mr = 0;
+  if (e < ne) {
+    mc = col[e0 + e];
+    mv = val[e0 + e];
+    int lo = 0, hi = nr - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (soff[mid] <= e) lo = mid; else hi = mid - 1;
+    }
+    mr = lo;
+  }
+}
+
 template <int B, typename VT, bool F32P>
-__global__ __launch_bounds__(256) void k_cg_spmm(CGArgs a, int par, int first, const double* __restrict__ pold,
-                                                 double* __restrict__ pnew) {
+__device__ inline void cg_runs(int win, int ne, int g, int c, bool cok, int mr, VT mv, const double* xv,
+                               double* acc_s) {
+  int cur_r = __shfl(mr, g * B);
+  double cur = 0.0;
+#pragma unroll
+  for (int q = 0; q < B; ++q) {
+    const int src = g * B + q;
+    const VT vv = __shfl(mv, src);
+    const int rr = __shfl(mr, src);
+    if (win + src < ne) {
+      if (rr != cur_r) {
+        if (cok) atomicAdd(&acc_s[cur_r * CG_MAXK + c], cur);
+        cur = 0.0;
+        cur_r = rr;
+      }
+      if constexpr (F32P) {
+        cur += (double)((float)vv * (float)xv[q]);  // float32 product, float64 accumulation
+      } else {
+        cur = fma((double)vv, xv[q], cur);
+      }
+    }
+  }
+  if (win + g * B < ne && cok) atomicAdd(&acc_s[cur_r * CG_MAXK + c], cur);
+}
+
+template <int B, typename VT, bool F32P, bool INIT>
+__global__ __launch_bounds__(NT) void k_cg_iter(CGArgs a, int j) {
   const int t = threadIdx.x;
   const int k = a.k;
-  if (!first && a.sc->nact[par ^ 1] == 0) {
+  const int par = INIT ? 1 : (j & 1);
+  const double* __restrict__ partin = a.part[par ^ 1];
+  __shared__ double red[NT];
+  __shared__ double al[CG_MAXK], be[CG_MAXK];
+  __shared__ double acc_s[RCH * CG_MAXK];
+  __shared__ int soff[RCH + 1];
+  __shared__ int nact_s;
+  if (!INIT && j > 0 && a.sc->nact[par ^ 1] == 0) {
     if (blockIdx.x == 0 && t == 0) a.sc->nact[par] = 0;
     return;
   }
-  __shared__ double tot[CG_MAXK], be[CG_MAXK], pqw[4][CG_MAXK], red[256];
-  __shared__ int act[CG_MAXK];
-  reduce_cols(a.part2, a.nb2, k, red, tot);
-  if (t < k) {
-    const double rrn = tot[t];
-    const double rro = first ? rrn : a.sc->rr[par ^ 1][t];
-    const double bb = first ? rrn : a.sc->bb[t];
-    const int was = first ? (rrn > 0.0) : a.sc->act[par ^ 1][t];
-    const int now = was && (rrn > a.tol2 * bb);
-    act[t] = now;
-    be[t] = (now && rro != 0.0) ? rrn / rro : 0.0;
-    if (blockIdx.x == 0) {
-      a.sc->rr[par][t] = now ? rrn : rro;
-      a.sc->act[par][t] = now;
-      if (first) a.sc->bb[t] = rrn;
-    }
-  }
-  __syncthreads();
-  if (blockIdx.x == 0 && t == 0) {
-    int na = 0;
-    for (int c = 0; c < k; ++c) na += act[c];
-    a.sc->nact[par] = na;
-    if (first) a.sc->iters = 0;
-    if (na) a.sc->iters += 1;
-  }
-  constexpr int G = 64 / B;
-  const int lane = t & 63, g = lane / B, cc = lane % B, w = t >> 6;
-  const VT* val = sizeof(VT) == 8 ? (const VT*)a.v64 : (const VT*)a.v32;
-  const bool ca = cc < k && act[cc < k ? cc : 0];
-  const double bc = cc < k ? be[cc] : 0.0;
-  const int64_t r0 = (int64_t)blockIdx.x * R1, r1 = min<int64_t>(a.n0, r0 + R1);
-  double pq = 0.0;
-  for (int64_t row = r0 + w; row < r1; row += 4) {
-    const int64_t beg = a.rp[row], end = a.rend ? a.rend[row] : a.rp[row + 1];
-    double acc = 0.0;
-    for (int64_t base = beg; base < end; base += 64) {
-      const int cnt = (int)min<int64_t>(64, end - base);
-      int32_t mc = 0;
-      VT mv = VT(0);
-      if (lane < cnt) { mc = a.col[base + lane]; mv = val[base + lane]; }
-      for (int s0 = 0; s0 < cnt; s0 += G) {
-        const int e = s0 + g;
-        const int32_t cl = __shfl(mc, e);
-        const VT vv = __shfl(mv, e);
-        if (e < cnt && ca) {
-          const int64_t o = (int64_t)cl * k + cc;
-          const double pn = fma(bc, pold[o], a.r[o]);
-          if constexpr (F32P) {
-            acc += (double)((float)vv * (float)pn);  // float32 product, float64 accumulation
-          } else {
-            acc = fma((double)vv, pn, acc);
-          }
+  const int lane = t & 63, wv = t >> 6;
+  const int g = lane / B, c = lane % B;
+  const bool cok = c < k;
+  const double* __restrict__ rj = a.r[INIT ? 0 : par];
+  const double* __restrict__ wj = a.w[INIT ? 0 : par];
+  const double* __restrict__ sm = a.sv[INIT ? 1 : par ^ 1];
+  double* __restrict__ rn = a.r[INIT ? 0 : par ^ 1];
+  double* __restrict__ wn = a.w[INIT ? 0 : par ^ 1];
+  double* __restrict__ sj = a.sv[INIT ? 1 : par];
+  const VT* __restrict__ val = sizeof(VT) == 8 ? (const VT*)a.v64 : (const VT*)a.v32;
+  // own-row phase mapping: column oc, row slots os and os + NT/16 of each chunk
+  const int oc = t % CG_MAXK, os = t / CG_MAXK;
+  constexpr int OS = NT / CG_MAXK;
+  static_assert(2 * OS == RCH, "two row slots per thread and chunk");
+  double sg = 0.0, sd = 0.0;
+  double alpha = 0.0, beta = 0.0, oal = 0.0, obe = 0.0;
+  const double osh = oc < k ? a.shift[oc] : 0.0;
+  const int64_t rb0 = a.rowb[blockIdx.x], rb1 = a.rowb[blockIdx.x + 1];
+  bool first = true;
+  for (int64_t c0 = rb0; c0 < rb1 || (first && !INIT); c0 += RCH) {
+    const int nr = (int)max<int64_t>(0, min<int64_t>(RCH, rb1 - c0));
+    // operands that do not depend on this iteration's scalars are requested first
+    const int64_t e0 = nr > 0 ? a.rp[c0] : 0;
+    const int rpv = (t <= nr && nr > 0) ? (int)(a.rp[c0 + t] - e0) : 0;
+    double orj[2] = {0.0, 0.0}, owj[2] = {0.0, 0.0}, osm[2] = {0.0, 0.0};
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int rl = os + OS * u;
+      if (oc < k && rl < nr) {
+        const int64_t o = (c0 + rl) * k + oc;
+        orj[u] = rj[o];
+        if (!INIT) {
+          owj[u] = wj[o];
+          osm[u] = sm[o];
         }
       }
     }
-    for (int o = B; o < 64; o <<= 1) acc += __shfl_xor(acc, o);
-    if (g == 0 && cc < k) {
-      const int64_t o = row * k + cc;
-      if (ca) {
-        const double pv = fma(bc, pold[o], a.r[o]);
-        const double qv = acc - a.shift[cc] * pv;
-        pnew[o] = pv;
-        a.q[o] = qv;
-        pq = fma(pv, qv, pq);
-      } else {
-        pnew[o] = pold[o];
+    if (!INIT && first) {
+      // (r.r, w.r) of iteration j from the NB partials of the previous kernel, fixed order
+      const int v = t % (2 * CG_MAXK);
+      double sacc = 0.0;
+      for (int b2 = t / (2 * CG_MAXK); b2 < NB; b2 += NT / (2 * CG_MAXK))
+        sacc += partin[(int64_t)b2 * 2 * CG_MAXK + v];
+      red[t] = sacc;
+      __syncthreads();
+      for (int o = NT / 2; o >= 2 * CG_MAXK; o >>= 1) {
+        if (t < o) red[t] += red[t + o];
+        __syncthreads();
+      }
+      if (t < k) {
+        const double gg = red[t], d = red[CG_MAXK + t];
+        double al_ = 0.0, be_ = 0.0, gkeep;
+        int now;
+        if (j == 0) {
+          now = gg > 0.0 && d != 0.0;
+          al_ = now ? gg / d : 0.0;
+          gkeep = gg;
+          if (blockIdx.x == 0) a.sc->bb[t] = gg;
+        } else {
+          const double gold = a.sc->gam[par ^ 1][t];
+          const double aold = a.sc->alp[par ^ 1][t];
+          now = a.sc->act[par ^ 1][t] && gg > a.tol2 * a.sc->bb[t];
+          if (now) {
+            be_ = gg / gold;
+            const double den = d - be_ * gg / aold;
+            al_ = den != 0.0 ? gg / den : 0.0;
+            if (den == 0.0) {
+              now = 0;
+              be_ = 0.0;
+            }
+          }
+          gkeep = now ? gg : gold;
+        }
+        al[t] = al_;
+        be[t] = be_;
+        if (blockIdx.x == 0) {
+          a.sc->gam[par][t] = gkeep;
+          a.sc->alp[par][t] = now ? al_ : 0.0;
+          a.sc->act[par][t] = now;
+        }
+        red[t] = now;
+      }
+      __syncthreads();
+      if (t == 0) {
+        int na = 0;
+        for (int cc = 0; cc < k; ++cc) na += red[cc] != 0.0;
+        nact_s = na;
+        if (blockIdx.x == 0) {
+          a.sc->nact[par] = na;
+          if (j == 0) a.sc->iters = 0;
+          if (na) a.sc->iters += 1;
+        }
+      }
+      __syncthreads();
+      if (nact_s == 0) return;
+      alpha = cok ? al[c] : 0.0;
+      beta = cok ? be[c] : 0.0;
+      oal = oc < k ? al[oc] : 0.0;
+      obe = oc < k ? be[oc] : 0.0;
+    }
+    first = false;
+    if (nr == 0) break;
+    if (t <= nr) soff[t] = rpv;
+    for (int i = t; i < RCH * CG_MAXK; i += NT) acc_s[i] = 0.0;
+    __syncthreads();
+    const int ne = soff[nr];
+    // two windows per trip (one for 16-lane groups): their gathers are in flight together
+    constexpr int WT = B <= 8 ? 2 : 1;
+    for (int win = wv * 64; win < ne; win += WT * NT) {
+      const int win2 = WT == 2 ? win + NT : ne;  // ne: an empty second window
+      int mc1, mr1, mc2, mr2;
+      VT mv1, mv2;
+      cg_window<VT>(a.col, val, e0, soff, nr, ne, win + lane, mc1, mv1, mr1);
+      cg_window<VT>(a.col, val, e0, soff, nr, ne, win2 + lane, mc2, mv2, mr2);
+      double xv1[B], xv2[B];
+#pragma unroll
+      for (int q = 0; q < B; ++q) {
+        const int src = g * B + q;
+        const int cl1 = __shfl(mc1, src);
+        const int cl2 = __shfl(mc2, src);
+        double v1 = 0.0, v2 = 0.0;
+        if (win + src < ne && cok) {
+          const int64_t o = (int64_t)cl1 * k + c;
+          v1 = INIT ? rj[o] : rj[o] - alpha * (wj[o] + beta * sm[o]);
+        }
+        if (win2 + src < ne && cok) {
+          const int64_t o = (int64_t)cl2 * k + c;
+          v2 = INIT ? rj[o] : rj[o] - alpha * (wj[o] + beta * sm[o]);
+        }
+        xv1[q] = v1;
+        xv2[q] = v2;
+      }
+      cg_runs<B, VT, F32P>(win, ne, g, c, cok, mr1, mv1, xv1, acc_s);
+      cg_runs<B, VT, F32P>(win2, ne, g, c, cok, mr2, mv2, xv2, acc_s);
+    }
+    __syncthreads();
+    if (oc < k) {
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int rl = os + OS * u;
+        if (rl < nr) {
+          const int64_t o = (c0 + rl) * k + oc;
+          double rnew;
+          if (INIT) {
+            rnew = orj[u];
+          } else {
+            const double pv = orj[u] + obe * a.p[o];
+            const double sv = owj[u] + obe * osm[u];
+            a.p[o] = pv;
+            sj[o] = sv;
+            a.x[o] = fma(oal, pv, a.x[o]);
+            rnew = orj[u] - oal * sv;
+            rn[o] = rnew;
+          }
+          const double wv2 = acc_s[rl * CG_MAXK + oc] - osh * rnew;
+          wn[o] = wv2;
+          sg = fma(rnew, rnew, sg);
+          sd = fma(wv2, rnew, sd);
+        }
       }
     }
+    __syncthreads();
   }
-  if (g == 0) pqw[w][cc] = pq;
+  // block partials: fixed-order tree over the row slots of each column
+  red[t] = sg;
   __syncthreads();
-  if (t < k) a.part1[(int64_t)blockIdx.x * CG_MAXK + t] = (pqw[0][t] + pqw[1][t]) + (pqw[2][t] + pqw[3][t]);
+  for (int o = NT / 2; o >= CG_MAXK; o >>= 1) {
+    if (t < o) red[t] += red[t + o];
+    __syncthreads();
+  }
+  double gsum = 0.0;
+  if (t < CG_MAXK) gsum = red[t];
+  __syncthreads();
+  red[t] = sd;
+  __syncthreads();
+  for (int o = NT / 2; o >= CG_MAXK; o >>= 1) {
+    if (t < o) red[t] += red[t + o];
+    __syncthreads();
+  }
+  if (t < CG_MAXK) {
+    double* out = a.part[par] + (int64_t)blockIdx.x * 2 * CG_MAXK;
+    out[t] = gsum;
+    out[CG_MAXK + t] = red[t];
+  }
 }
 
-// ---- iteration, K2: alpha ; x += alpha p ; r -= alpha q ; partial r.r
-__global__ __launch_bounds__(1024) void k_cg_update(CGArgs a, int par, const double* __restrict__ p) {
-  if (a.sc->nact[par] == 0) return;
-  __shared__ double tot[CG_MAXK], red[1024], al[CG_MAXK];
-  const int k = a.k, t = threadIdx.x;
-  reduce_cols(a.part1, a.nb1, k, red, tot);
-  if (t < k) {
-    const double s = tot[t];
-    al[t] = (a.sc->act[par][t] && s != 0.0) ? a.sc->rr[par][t] / s : 0.0;
+// ---- row bounds of the iteration blocks: equal shares of (entries + 8 per row)
+__global__ void k_row_cost(int64_t n0, const int64_t* __restrict__ rp, const int64_t* __restrict__ rend,
+                           int32_t* __restrict__ cost) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n0) cost[i] = (int32_t)((rend ? rend[i] : rp[i + 1]) - rp[i] + 8);
+}
+
+__global__ void k_row_bounds(int64_t n0, const int64_t* __restrict__ pre, int64_t* __restrict__ rowb) {
+  const int b = threadIdx.x;
+  if (b > NB) return;
+  if (b == 0) { rowb[0] = 0; return; }
+  if (b == NB) { rowb[NB] = n0; return; }
+  const int64_t target = pre[n0] * b / NB;
+  int64_t lo = 0, hi = n0;  // first row whose prefix reaches the target
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (pre[mid] < target) lo = mid + 1; else hi = mid;
   }
-  __syncthreads();
-  int64_t r0, r1;
-  rows_of(a.n0, blockIdx.x, a.nb2, r0, r1);
-  for (int64_t e = r0 * k + t; e < r1 * k; e += blockDim.x) {
-    const double av = al[e % k];
-    if (av != 0.0) {
-      a.x[e] = fma(av, p[e], a.x[e]);
-      a.r[e] = fma(-av, a.q[e], a.r[e]);
-    }
-  }
-  __syncthreads();
-  block_coldot(a.r, a.r, r0, r1, k, red, a.part2 + (int64_t)blockIdx.x * CG_MAXK);
+  rowb[b] = lo;
 }
 
 }  // namespace
@@ -303,61 +440,72 @@ __global__ __launch_bounds__(1024) void k_cg_update(CGArgs a, int par, const dou
 constexpr int64_t SC_D = (int64_t)((sizeof(CGScal) + 63) / 64) * 8;
 
 int64_t cg_work_doubles(int64_t n0) {
-  const int64_t nb1 = cdiv(n0, R1), nb2 = std::min<int64_t>(256, cdiv(n0, 64));
-  return nb1 * CG_MAXK + nb2 * CG_MAXK + nb2 * PW + SC_D + 2 * n0 * CG_MAXK;
+  const int64_t nb2 = std::min<int64_t>(256, cdiv(n0, 64));
+  return 2 * NB * 2 * CG_MAXK + nb2 * PW + SC_D + 7 * n0 * CG_MAXK + (NB + 1) + 2 * (n0 + 2);
+}
+
+// Row bounds for the iteration blocks (once per H0hat); tmp holds 2 (n0 + 2) doubles.
+void cg_prepare(const DevCSR& H0, int64_t n0, int64_t* rowb, double* tmp, hipStream_t s) {
+  int32_t* cost = (int32_t*)tmp;
+  int64_t* pre = (int64_t*)(tmp + (n0 + 2) / 2 + 1);
+  int64_t* bsum = pre + n0 + 1;
+  (void)bsum;
+  k_row_cost<<<cdiv(n0 > 0 ? n0 : 1, 256), 256, 0, s>>>(n0, H0.rp, H0.rend, cost);
+  SPPC_LAUNCH_CHECK();
+  scan_exclusive(n0, cost, pre, bsum, s);
+  k_row_bounds<<<1, NB + 1 > 1024 ? 1024 : NB + 1, 0, s>>>(n0, pre, rowb);
+  SPPC_LAUNCH_CHECK();
 }
 
 // b in r (n0 x k) on entry; x returns the CG solution on the deflated complement and
 // ccoef = Ps^T b.  Returns the number of iterations (synchronises the stream).
-int cg_solve(const DevCSR& H0, int64_t n0, int k, int D, const double* diag, const double* shift,
-             const double* Ps, double* x, double* r, double* z, double* p, double* q, double* work,
-             double* ccoef, int maxit, double tol, bool f32prod, int* host_flag, hipStream_t s) {
-  (void)diag;
-  (void)z;
-  (void)p;
+int cg_solve(const DevCSR& H0, int64_t n0, int k, int D, const double* shift, const double* Ps,
+             const int64_t* rowb, double* x, double* r, double* work, double* ccoef, int maxit, double tol,
+             bool f32prod, int* host_flag, hipStream_t s) {
   if (k < 1 || k > CG_MAXK || D < 1 || D > CG_MAXD) throw Error(1, "cg: k <= 16 and D <= 28 required");
   if (f32prod && !H0.val32) throw Error(1, "cg: float32 products need float32 values");
-  const int nb1 = (int)cdiv(n0, R1);
+  if (H0.rend) throw Error(1, "cg: H0hat must be a contiguous CSR");
+  if (n0 * (int64_t)RCH >= ((int64_t)1 << 31)) throw Error(1, "cg: n0 too large for 32-bit chunk offsets");
   const int nb2 = (int)std::min<int64_t>(256, cdiv(n0, 64));
-  double* part1 = work;
-  double* part2 = part1 + (int64_t)nb1 * CG_MAXK;
-  double* partP = part2 + (int64_t)nb2 * CG_MAXK;
+  double* part0 = work;
+  double* part1 = part0 + NB * 2 * CG_MAXK;
+  double* partP = part1 + NB * 2 * CG_MAXK;
   CGScal* sc = (CGScal*)(partP + (int64_t)nb2 * PW);
-  double* pa = (double*)sc + SC_D;
-  double* pb = pa + n0 * CG_MAXK;
-  CGArgs a{n0, k, D, H0.rp, H0.rend, H0.col, H0.val64, H0.val32, diag, shift, Ps, x, r, q, pa, pb,
-           part1, part2, partP, nb1, nb2, ccoef, sc, tol * tol};
-  // r <- P b (ccoef = Ps^T b), x = 0, p_old = 0, partial r.r
+  double* vec = (double*)sc + SC_D;
+  const int64_t vs = n0 * CG_MAXK;
+  CGArgs a{n0, k, D, H0.rp, H0.rend, H0.col, H0.val64, H0.val32, shift, Ps, rowb, x,
+           {r, vec}, {vec + vs, vec + 2 * vs}, {vec + 3 * vs, vec + 4 * vs}, vec + 5 * vs,
+           {part0, part1}, partP, nb2, sc, tol * tol};
+  // r <- P b (ccoef = Ps^T b), x = p = s_{-1} = 0
   k_cg_psT<<<nb2, 1024, 0, s>>>(a, r);
   k_cg_project<<<nb2, 1024, 0, s>>>(a, r, ccoef, 1);
   SPPC_LAUNCH_CHECK();
   const bool f64 = H0.val64 != nullptr;
-  int it = 0;
-  for (it = 1; it <= maxit; ++it) {
-    const int par = it & 1;
-    const double* pold = (it & 1) ? pb : pa;
-    double* pnew = (it & 1) ? pa : pb;
-    const int first = it == 1;
-#define SPPC_CG_LAUNCH(BB)                                                                     \
-  if (f32prod) k_cg_spmm<BB, float, true><<<nb1, 256, 0, s>>>(a, par, first, pold, pnew);       \
-  else if (f64) k_cg_spmm<BB, double, false><<<nb1, 256, 0, s>>>(a, par, first, pold, pnew);    \
-  else k_cg_spmm<BB, float, false><<<nb1, 256, 0, s>>>(a, par, first, pold, pnew);
-    if (k <= 4) {
-      SPPC_CG_LAUNCH(4)
-    } else if (k <= 8) {
-      SPPC_CG_LAUNCH(8)
-    } else {
-      SPPC_CG_LAUNCH(16)
-    }
-#undef SPPC_CG_LAUNCH
-    k_cg_update<<<nb2, 1024, 0, s>>>(a, par, pnew);
-    if (it % 16 == 0 || it == maxit) {
+#define SPPC_CG_LAUNCH(BB, INIT, J)                                                         \
+  if (f32prod) k_cg_iter<BB, float, true, INIT><<<NB, NT, 0, s>>>(a, J);                     \
+  else if (f64) k_cg_iter<BB, double, false, INIT><<<NB, NT, 0, s>>>(a, J);                  \
+  else k_cg_iter<BB, float, false, INIT><<<NB, NT, 0, s>>>(a, J);
+#define SPPC_CG_STEP(INIT, J)      \
+  if (k <= 4) {                    \
+    SPPC_CG_LAUNCH(4, INIT, J)     \
+  } else if (k <= 8) {             \
+    SPPC_CG_LAUNCH(8, INIT, J)     \
+  } else {                         \
+    SPPC_CG_LAUNCH(16, INIT, J)    \
+  }
+  SPPC_CG_STEP(true, 0)
+  int j = 0;
+  for (j = 0; j < maxit; ++j) {
+    SPPC_CG_STEP(false, j)
+    if ((j + 1) % 16 == 0 || j + 1 == maxit) {
       SPPC_LAUNCH_CHECK();
-      SPPC_HIP(hipMemcpyAsync(host_flag, &sc->nact[par], sizeof(int), hipMemcpyDeviceToHost, s));
+      SPPC_HIP(hipMemcpyAsync(host_flag, &sc->nact[j & 1], sizeof(int), hipMemcpyDeviceToHost, s));
       SPPC_HIP(hipStreamSynchronize(s));
       if (*host_flag == 0) break;
     }
   }
+#undef SPPC_CG_STEP
+#undef SPPC_CG_LAUNCH
   // x <- P x (removes the drift into the deflated directions)
   k_cg_psT<<<nb2, 1024, 0, s>>>(a, x);
   k_cg_project<<<nb2, 1024, 0, s>>>(a, x, nullptr, 0);

@@ -444,66 +444,6 @@ __global__ __launch_bounds__(256) void k_coldots(int64_t n, int b, const double*
   if (t < b) part[(int64_t)blockIdx.x * b + t] = sh[t];
 }
 
-__global__ void k_cg_precond(int64_t n0, int k, const double* __restrict__ diag,
-                             const double* __restrict__ shift, const double* __restrict__ r,
-                             double* __restrict__ z) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n0 * k) return;
-  const int64_t i = e / k;
-  const int c = (int)(e % k);
-  const double sh = shift[c];
-  const double fl = 1e-2 * fmax(1.0, fabs(sh));
-  const double den = fmax(fabs(diag[i] - sh), fl);
-  z[e] = r[e] / den;
-}
-
-__global__ void k_cg_xr(int64_t n0, int k, double* __restrict__ x, double* __restrict__ r,
-                        const double* __restrict__ p, const double* __restrict__ q,
-                        const double* __restrict__ rz, const double* __restrict__ pq,
-                        const int* __restrict__ active) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n0 * k) return;
-  const int c = (int)(e % k);
-  if (!active[c]) return;
-  const double a = pq[c] != 0.0 ? rz[c] / pq[c] : 0.0;
-  x[e] = fma(a, p[e], x[e]);
-  r[e] = fma(-a, q[e], r[e]);
-}
-
-__global__ void k_cg_p(int64_t n0, int k, double* __restrict__ p, const double* __restrict__ z,
-                       const double* __restrict__ rzn, const double* __restrict__ rzo,
-                       const int* __restrict__ active) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n0 * k) return;
-  const int c = (int)(e % k);
-  if (!active[c]) return;
-  const double bt = rzo[c] != 0.0 ? rzn[c] / rzo[c] : 0.0;
-  p[e] = fma(bt, p[e], z[e]);
-}
-
-__global__ void k_cg_check(int k, const double* __restrict__ rr, const double* __restrict__ bb,
-                           double tol2, int* __restrict__ active, int* __restrict__ nactive,
-                           double* __restrict__ rzn, double* __restrict__ rzo) {
-  if (threadIdx.x != 0) return;
-  int na = 0;
-  for (int c = 0; c < k; ++c) {
-    if (active[c] && !(rr[c] > tol2 * bb[c])) active[c] = 0;
-    na += active[c];
-  }
-  *nactive = na;
-  if (rzn) for (int c = 0; c < k; ++c) rzo[c] = rzn[c];
-}
-
-__global__ void k_cg_init(int k, const double* __restrict__ bb, int* __restrict__ active,
-                          int* __restrict__ nactive) {
-  if (threadIdx.x != 0) return;
-  int na = 0;
-  for (int c = 0; c < k; ++c) {
-    active[c] = bb[c] > 0.0;
-    na += active[c];
-  }
-  *nactive = na;
-}
 
 }  // namespace
 
@@ -515,34 +455,6 @@ void coldots(int64_t n, int b, const double* X, int64_t ldx, const double* Y, in
   SPPC_LAUNCH_CHECK();
 }
 
-void cg_precond(int64_t n0, int k, const double* diag, const double* shift, const double* r, double* z,
-                hipStream_t s) {
-  k_cg_precond<<<grid1(n0 * k), 256, 0, s>>>(n0, k, diag, shift, r, z);
-  SPPC_LAUNCH_CHECK();
-}
-
-void cg_update_xr(int64_t n0, int k, double* x, double* r, const double* p, const double* q,
-                  const double* rz, const double* pq, const int* active, hipStream_t s) {
-  k_cg_xr<<<grid1(n0 * k), 256, 0, s>>>(n0, k, x, r, p, q, rz, pq, active);
-  SPPC_LAUNCH_CHECK();
-}
-
-void cg_update_p(int64_t n0, int k, double* p, const double* z, const double* rzn, const double* rzo,
-                 const int* active, hipStream_t s) {
-  k_cg_p<<<grid1(n0 * k), 256, 0, s>>>(n0, k, p, z, rzn, rzo, active);
-  SPPC_LAUNCH_CHECK();
-}
-
-void cg_check(int k, const double* rr, const double* bb, double tol2, int* active, int* nactive,
-              double* rzn, double* rzo, hipStream_t s) {
-  k_cg_check<<<1, 64, 0, s>>>(k, rr, bb, tol2, active, nactive, rzn, rzo);
-  SPPC_LAUNCH_CHECK();
-}
-
-void cg_init(int k, const double* bb, int* active, int* nactive, hipStream_t s) {
-  k_cg_init<<<1, 64, 0, s>>>(k, bb, active, nactive);
-  SPPC_LAUNCH_CHECK();
-}
 
 namespace {
 __global__ void k_gather_cols(int64_t n, int S, const int* __restrict__ idx, const double* __restrict__ X,

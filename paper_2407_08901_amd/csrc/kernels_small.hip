@@ -554,6 +554,20 @@ __global__ void k_deflate_coefs(int D, int k, const double* __restrict__ w, cons
   out[(int64_t)j * ldo + kk] = v;
 }
 
+// out[j][a] = c[j][a] / (w[j] - theta[a]) for every deflated j (shifted small-space solve)
+__global__ void k_deflate_shift(int D, int na, const double* __restrict__ w, const double* __restrict__ theta,
+                                const double* __restrict__ c, int64_t ldc, double* __restrict__ out,
+                                int64_t ldo) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= D * na) return;
+  const int j = e / na, a = e % na;
+  const double th = theta[a];
+  const double dj = w[j] - th;
+  double v = 0.0;
+  if (fabs(dj) > 1e-12 * fmax(1.0, fabs(th))) v = c[(int64_t)j * ldc + a] / dj;
+  out[(int64_t)j * ldo + a] = v;
+}
+
 __global__ void k_add(int count, const double* __restrict__ a, double* __restrict__ b) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e < count) b[e] += a[e];
@@ -718,6 +732,12 @@ void build_correction_coefs(int p, int k, int m, const double* Ghist, int64_t gs
 void deflate_coefs(int D, int k, const double* w, const double* c, int64_t ldc, double* out, int64_t ldo,
                    hipStream_t s) {
   k_deflate_coefs<<<g1((int64_t)D * k), 256, 0, s>>>(D, k, w, c, ldc, out, ldo);
+  SPPC_LAUNCH_CHECK();
+}
+
+void deflate_shift(int D, int na, const double* w, const double* theta, const double* c, int64_t ldc, double* out,
+                   int64_t ldo, hipStream_t s) {
+  k_deflate_shift<<<g1((int64_t)D * na), 256, 0, s>>>(D, na, w, theta, c, ldc, out, ldo);
   SPPC_LAUNCH_CHECK();
 }
 

@@ -97,7 +97,7 @@ __global__ void k_scan_final(int64_t n, const int32_t* __restrict__ a, const int
   if (i == n - 1) out[n] = bsum[blockIdx.x] + sh[threadIdx.x];
 }
 
-void scan_exclusive(int64_t n, const int32_t* a, int64_t* out, int64_t* bsum, hipStream_t s) {
+void scan_exclusive_impl(int64_t n, const int32_t* a, int64_t* out, int64_t* bsum, hipStream_t s) {
   const int64_t nb = cdiv(n, SCAN_BLOCK);
   k_scan_blocks<<<nb, SCAN_BLOCK, 0, s>>>(n, a, bsum);
   k_scan_sums<<<1, 1024, 0, s>>>(nb, bsum);
@@ -268,6 +268,28 @@ void launch_spmm(const DevCSR& H, const VT* val, const XT* X, int64_t ldx, doubl
   }
 #undef SPPC_SPMM_CASE
   SPPC_LAUNCH_CHECK();
+}
+
+// rows [0, n0) restricted to columns < n0 (the row ends of the view), copied contiguously
+__global__ void k_view_count(int64_t n0, const int64_t* __restrict__ rp, const int64_t* __restrict__ rend,
+                             int32_t* __restrict__ cnt) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n0) cnt[i] = (int32_t)(rend[i] - rp[i]);
+}
+
+__global__ void k_view_fill(int64_t n0, const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
+                            const double* __restrict__ v64, const float* __restrict__ v32,
+                            const int64_t* __restrict__ nrp, int32_t* __restrict__ ncol,
+                            double* __restrict__ n64, float* __restrict__ n32) {
+  const int lane = threadIdx.x & 63;
+  const int64_t row = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (row >= n0) return;
+  const int64_t b = rp[row], len = nrp[row + 1] - nrp[row], d = nrp[row];
+  for (int64_t t = lane; t < len; t += 64) {
+    ncol[d + t] = col[b + t];
+    if (n64) n64[d + t] = v64[b + t];
+    if (n32) n32[d + t] = v32[b + t];
+  }
 }
 
 // ------------------------------------------------------------------ panel format
@@ -553,7 +575,7 @@ void build_full_csr(int64_t n, int64_t nnz_up, const int64_t* up_rp, const int32
     if (h_flags[0]) throw Error(1, "H: upper CSR expected (columns >= row, < n, strictly ascending)");
     if (h_flags[2]) throw Error(7, "H: NaN or Inf among the values");
     exact32 = val_is_f32 || !h_flags[1];
-    scan_exclusive(n, lower_cnt, lower_rp, bsum, s);
+    scan_exclusive_impl(n, lower_cnt, lower_rp, bsum, s);
     int64_t nlow = 0;
     SPPC_HIP(hipMemcpyAsync(&nlow, lower_rp + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     SPPC_HIP(hipStreamSynchronize(s));
@@ -590,6 +612,41 @@ void build_block_view(const DevCSR& full, int64_t n0, int64_t* rend, hipStream_t
   SPPC_LAUNCH_CHECK();
 }
 
+void compact_view(const DevCSR& V, DevCSR& out, hipStream_t s) {
+  const int64_t n0 = V.n;
+  if (!V.rend) throw Error(1, "compact_view: not a block view");
+  int32_t* cnt = nullptr;
+  int64_t* bsum = nullptr;
+  auto cleanup = [&]() { hipFree(cnt); hipFree(bsum); };
+  try {
+    out = DevCSR{};
+    out.n = n0;
+    SPPC_HIP(hipMalloc(&cnt, sizeof(int32_t) * (n0 + 1)));
+    SPPC_HIP(hipMalloc(&bsum, sizeof(int64_t) * (cdiv(n0 + 1, SCAN_BLOCK) + 1)));
+    SPPC_HIP(hipMalloc(&out.rp, sizeof(int64_t) * (n0 + 1)));
+    k_view_count<<<cdiv(n0 > 0 ? n0 : 1, 256), 256, 0, s>>>(n0, V.rp, V.rend, cnt);
+    SPPC_LAUNCH_CHECK();
+    scan_exclusive_impl(n0, cnt, out.rp, bsum, s);
+    int64_t nnz = 0;
+    SPPC_HIP(hipMemcpyAsync(&nnz, out.rp + n0, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    SPPC_HIP(hipStreamSynchronize(s));
+    out.nnz = nnz;
+    SPPC_HIP(hipMalloc(&out.col, sizeof(int32_t) * (nnz > 0 ? nnz : 1)));
+    if (V.val64) SPPC_HIP(hipMalloc(&out.val64, sizeof(double) * (nnz > 0 ? nnz : 1)));
+    if (V.val32) SPPC_HIP(hipMalloc(&out.val32, sizeof(float) * (nnz > 0 ? nnz : 1)));
+    k_view_fill<<<cdiv(n0 > 0 ? n0 : 1, 4), 256, 0, s>>>(n0, V.rp, V.col, V.val64, V.val32, out.rp, out.col,
+                                                          out.val64, out.val32);
+    SPPC_LAUNCH_CHECK();
+    SPPC_HIP(hipStreamSynchronize(s));
+  } catch (...) {
+    cleanup();
+    (void)hipFree(out.rp); (void)hipFree(out.col); (void)hipFree(out.val64); (void)hipFree(out.val32);
+    out = DevCSR{};
+    throw;
+  }
+  cleanup();
+}
+
 void extract_diag(const DevCSR& H, double* diag, hipStream_t s) {
   k_diag<<<cdiv(H.n, 256), 256, 0, s>>>(H.n, H.rp, H.col, H.val64, H.val32, diag);
   SPPC_LAUNCH_CHECK();
@@ -616,7 +673,7 @@ void build_panel(const DevCSR& H, int PW, int RB, PanelH& out, hipStream_t s) {
     SPPC_HIP(hipMemsetAsync(cnt, 0, sizeof(int32_t) * total, s));
     const int64_t grid_w = cdiv(n, 4);
     k_panel_count<<<grid_w, 256, 0, s>>>(n, H.rp, H.col, RB, out.P, PW, cnt);
-    scan_exclusive(total, cnt, gscan, bsum, s);
+    scan_exclusive_impl(total, cnt, gscan, bsum, s);
     SPPC_HIP(hipMalloc(&out.off, sizeof(int32_t) * (per + 1) * out.nblocks));
     SPPC_HIP(hipMalloc(&out.bstart, sizeof(int64_t) * (out.nblocks + 1)));
     // a block holds fewer than 2^31 entries: RB rows of at most n columns each
@@ -652,6 +709,10 @@ void build_panel(const DevCSR& H, int PW, int RB, PanelH& out, hipStream_t s) {
     throw;
   }
   cleanup();
+}
+
+void scan_exclusive(int64_t n, const int32_t* a, int64_t* out, int64_t* bsum, hipStream_t s) {
+  scan_exclusive_impl(n, a, out, bsum, s);
 }
 
 void release_panel(PanelH& p) {

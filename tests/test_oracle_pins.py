@@ -247,3 +247,39 @@ def test_zero_E0_refused():
     Hd[0, 2] = Hd[2, 0] = 0.3
     with pytest.raises(ZeroDivisionError):
         oracle.sppc(sp.csr_matrix(Hd), 2, 1, oracle.Options())
+
+
+# ---------------------------------------------------------------- small-space preconditioner
+def test_small_space_correction_vanishes_for_rayleigh_quotient_when_the_small_space_is_everything():
+    # with n0 = n the preconditioner is (H - theta)^-1 and (H - theta)^-1 (H z - theta z) = z, so
+    # the projected correction -(I - z z^T) z is exactly zero (Rayleigh quotient iteration)
+    A = levelgen.generate((30, 60), 12, 5)
+    H = oracle.symmetric_from_upper(A.row_ptr, A.col, A.val, A.n)
+    rng = np.random.default_rng(0)
+    z = rng.standard_normal(A.n)
+    z /= np.linalg.norm(z)
+    theta = float(z @ (H @ z))
+    r = H @ z - theta * z
+    t = oracle.small_space_correction(H, A.n, theta, r, z)
+    # |t| ~ eps * cond(H - theta) * |z|, cond ~ 1e2 here
+    assert np.linalg.norm(t) < 1e-12
+
+
+def test_small_space_correction_is_the_diagonal_step_off_the_small_space():
+    # decoupled H (no entries between the first n0 rows and the rest) and z supported off the
+    # small space: the small-space rows of r vanish, the step is the diagonal one
+    A = levelgen.generate((20, 80), 10, 6)
+    H = oracle.symmetric_from_upper(A.row_ptr, A.col, A.val, A.n).tolil()
+    n0 = 20
+    H[:n0, n0:] = 0.0
+    H[n0:, :n0] = 0.0
+    H = H.tocsr()
+    rng = np.random.default_rng(1)
+    z = np.zeros(A.n)
+    z[n0:] = rng.standard_normal(A.n - n0)
+    z /= np.linalg.norm(z)
+    theta = float(z @ (H @ z))
+    r = H @ z - theta * z
+    t = oracle.small_space_correction(H, n0, theta, r, z)
+    ref = oracle.jacobi_correction(H.diagonal(), theta, r, z)
+    assert np.allclose(t, ref, rtol=0, atol=1e-14 * np.abs(ref).max())
