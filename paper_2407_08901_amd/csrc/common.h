@@ -87,9 +87,12 @@ void spmm_cheb(const DevCSR& H, const double* X, int64_t ldx, double* Y, int64_t
                double ec, double eb, const double* Zo, int64_t ldz, hipStream_t s);
 // max_i (h_ii + sum_{j != i} |h_ij|) into *out (device); tmp holds n doubles
 void gershgorin_upper(const DevCSR& H, double* tmp, double* out, hipStream_t s);
-// Mixed: float32 values and float32 X, float32 products accumulated in float64.
+// Mixed: float32 values and float32 X, float32 products accumulated in float64.  With diag
+// (the diagonal of H) and X64 (float64 X) the diagonal entries are skipped in the float32 sum and
+// diag * X64 is added in float64: the diagonal product is the largest term of a row.
 void spmm_f32(const DevCSR& H, const float* X, int64_t ldx, double* Y, int64_t ldy, int b,
-              const double* shift, hipStream_t s);
+              const double* shift, hipStream_t s, const double* diag = nullptr, const double* X64 = nullptr,
+              int64_t ldx64 = 0);
 
 // ---------------------------------------------------------------- dense (kernels_dense.hip)
 

@@ -165,10 +165,10 @@ inline double* Gh(sppc_ctx* c, int l) { return c->Ghist + (int64_t)l * c->gstrid
 
 // Algorithmic bytes of one block product with H: the upper triangle once (values as the kernel
 // reads them: float32 when stored losslessly or in mixed mode, int32 columns), the row pointers,
-// X read (float32 in mixed mode) and Y written (float64).
+// X read (in mixed mode float32 X for the sum and float64 X for the diagonal) and Y written.
 double spmm_alg_bytes(const sppc_ctx* c, int b, bool xf32) {
   const double vb = (xf32 || !c->H.val64) ? 4.0 : 8.0;
-  const double xb = xf32 ? 4.0 : 8.0;
+  const double xb = xf32 ? 4.0 + 8.0 : 8.0;  // mixed: float32 X gathered, float64 X for the diagonal
   return (double)c->nnz_up * (vb + 4.0) + (double)(c->n + 1) * 8.0 + (double)c->n * b * (xb + 8.0);
 }
 
@@ -188,7 +188,7 @@ void Op::operator()(const double* X, int64_t ldx, double* Y, int64_t ldy, int b,
   if (mixed) copy_to_f32(A->n, b, X, ldx, c->X32, b, s);
   const size_t t0 = c->tm.begin(isH ? C_SPMM : C_H0);
   if (mixed)
-    spmm_f32(*A, c->X32, b, Y, ldy, b, nullptr, s);
+    spmm_f32(*A, c->X32, b, Y, ldy, b, nullptr, s, isH ? c->diag : nullptr, isH ? X : nullptr, ldx);
   else
     spmm_f64(*A, X, ldx, Y, ldy, b, nullptr, s);
   c->tm.end(t0);
@@ -830,6 +830,7 @@ sppc_status solve_impl(sppc_ctx* c, double* evals, double* evecs, double* rrn, s
   int cont = 0;
   if (o.p_switch > 0) {
     const int kind = o.precond;
+    std::vector<double> hist;  // max residual per continuation step (mixed hand-over test)
     while (!conv && cont < o.max_cont) {
       correct_continuation(c, kind);
       const int added = append_and_rr(c);
@@ -837,12 +838,14 @@ sppc_status solve_impl(sppc_ctx* c, double* evals, double* evecs, double* rrn, s
       log_step(c, "cont");
       conv = all_converged(c);
       if (added == 0 && !conv) break;
-      // mixed precision: within 10x of the tolerance the float32 noise (~3e-7 relative)
-      // dominates the loop's residuals; hand over to the float64 refinement
+      // mixed precision: within 10x of the tolerance, or once the residuals stop falling (the
+      // float32 noise floor), hand over to the float64 refinement
       if (!conv && o.precision == SPPC_PREC_MIXED && o.final_check) {
         double mx = 0.0;
         for (int i = 0; i < c->k; ++i) mx = std::max(mx, c->rrn_h[i]);
-        if (mx < 10.0 * o.tol) break;
+        hist.push_back(mx);
+        const size_t h = hist.size();
+        if (mx < 10.0 * o.tol || (h > 4 && !(mx < 0.5 * hist[h - 5]))) break;
       }
     }
   }
@@ -854,24 +857,42 @@ sppc_status solve_impl(sppc_ctx* c, double* evals, double* evecs, double* rrn, s
     // the checked Ritz vectors (float64 H Z) and continue with float64 products until the true
     // residual meets the tolerance
     if (!conv && o.precision == SPPC_PREC_MIXED && o.p_switch > 0) {
-      // New basis columns get float64 products.  The basis is kept (its float32-product columns
-      // still span the directions found so far); the loop's residuals carry the float32 noise,
-      // so each round ends with the float64 check, which decides convergence.
+      // New basis columns get float64 products.  The basis is kept at first (its float32-product
+      // columns still span the directions found so far); the loop's residuals carry the float32
+      // noise, so each round ends with the float64 check, which decides convergence.  The
+      // float32 columns also bound the accuracy the kept basis can reach: once a round fails to
+      // halve the checked residual (or after two rounds) the basis restarts on the checked Ritz
+      // vectors, whose H Z is exact, and continues with float64 products only.
       c->refining = true;
       int ref = 0;
-      for (int round = 0; round < 4 && !conv && ref < o.max_cont; ++round) {
-        do {
+      bool clean = false, stalled = false;
+      double last = 0.0;
+      for (int i = 0; i < c->k; ++i) last = std::max(last, c->rrn_h[i]);
+      for (int round = 0; !conv && ref < o.max_cont; ++round) {
+        if (!clean && (stalled || round >= 2)) {
+          restart_basis(c, c->B, c->k);
+          c->restarted = true;
+          clean = true;
+        }
+        // a kept-basis round cannot see below the float32 noise: at most 4 steps before checking
+        const int cap = clean ? o.max_cont : 4;
+        for (int st = 0; st < cap && ref < o.max_cont; ++st) {
           correct_continuation(c, o.refine_precond);
           const int added = append_and_rr(c);
           ++ref;
           ++cont;
           log_step(c, "refine");
           conv = all_converged(c);
-          if (added == 0) break;
-        } while (!conv && ref < o.max_cont);
+          if (conv || added == 0) break;
+        }
         final_check(c);
         log_step(c, "final");
         conv = all_converged(c);
+        double now = 0.0;
+        for (int i = 0; i < c->k; ++i) now = std::max(now, c->rrn_h[i]);
+        stalled = !(now < 0.5 * last);
+        last = now;
+        if (clean && stalled && !conv) break;
       }
       c->st.refine_steps = ref;
     }

@@ -204,7 +204,9 @@ __global__ __launch_bounds__(256) void k_spmm(int64_t n, const int64_t* __restri
                                               const VT* __restrict__ val, const XT* __restrict__ X,
                                               int64_t ldx, double* __restrict__ Y, int64_t ldy, int b,
                                               const double* __restrict__ shift, double ea, double ec,
-                                              double eb, const double* __restrict__ Zo, int64_t ldz) {
+                                              double eb, const double* __restrict__ Zo, int64_t ldz,
+                                              const double* __restrict__ dg, const double* __restrict__ X64,
+                                              int64_t ldx64) {
   constexpr int G = 64 / B;
   const int lane = threadIdx.x & 63;
   const int g = lane / B;
@@ -228,7 +230,7 @@ __global__ __launch_bounds__(256) void k_spmm(int64_t n, const int64_t* __restri
       const int e = s0 + g;
       const int32_t cc = __shfl(mc, e);
       const VT vv = __shfl(mv, e);
-      if (e < cnt && colok) {
+      if (e < cnt && colok && !(dg && cc == row)) {
         const XT xv = X[(int64_t)cc * ldx + c];
         if constexpr (sizeof(XT) == 4) {
           acc += (double)(vv * xv);            // float32 product, float64 accumulation
@@ -241,6 +243,7 @@ __global__ __launch_bounds__(256) void k_spmm(int64_t n, const int64_t* __restri
 #pragma unroll
   for (int o = B; o < 64; o <<= 1) acc += __shfl_xor(acc, o);
   if (g == 0 && colok) {
+    if (dg) acc = fma(dg[row], X64[row * ldx64 + c], acc);  // diagonal term in float64
     if (shift) acc -= shift[c] * (double)X[row * ldx + c];
     if (Zo) acc = ea * (acc - ec * (double)X[row * ldx + c]) + eb * Zo[row * ldz + c];
     Y[row * ldy + c] = acc;
@@ -250,13 +253,14 @@ __global__ __launch_bounds__(256) void k_spmm(int64_t n, const int64_t* __restri
 template <typename VT, typename XT>
 void launch_spmm(const DevCSR& H, const VT* val, const XT* X, int64_t ldx, double* Y, int64_t ldy,
                  int b, const double* shift, hipStream_t s, double ea = 0.0, double ec = 0.0,
-                 double eb = 0.0, const double* Zo = nullptr, int64_t ldz = 0) {
+                 double eb = 0.0, const double* Zo = nullptr, int64_t ldz = 0, const double* dg = nullptr,
+                 const double* X64 = nullptr, int64_t ldx64 = 0) {
   if (b < 1 || b > 32) throw Error(1, "spmm: block width must be 1..32");
   if (H.n == 0) return;
   const int64_t grid = cdiv(H.n, 4);
 #define SPPC_SPMM_CASE(BB)                                                                        \
   k_spmm<BB, VT, XT><<<grid, 256, 0, s>>>(H.n, H.rp, H.rend, H.col, val, X, ldx, Y, ldy, b, shift, ea, ec, \
-                                          eb, Zo, ldz);                                                     \
+                                          eb, Zo, ldz, dg, X64, ldx64);                                     \
   break;
   switch (b <= 1 ? 1 : b <= 2 ? 2 : b <= 4 ? 4 : b <= 8 ? 8 : b <= 16 ? 16 : 32) {
     case 1: SPPC_SPMM_CASE(1)
@@ -309,7 +313,8 @@ __global__ __launch_bounds__(256) void k_spmm_panel(int64_t n, int RB, int P, in
                                                     const uint16_t* __restrict__ pcol,
                                                     const VT* __restrict__ pval, const XT* __restrict__ X,
                                                     int64_t ldx, double* __restrict__ Y, int64_t ldy, int b,
-                                                    int blk0) {
+                                                    int blk0, const double* __restrict__ dg,
+                                                    const double* __restrict__ X64, int64_t ldx64) {
   constexpr int E = B;  // entries per group and window: 64/B groups share the 64 entries
   extern __shared__ double ysh[];  // RB * B accumulators, then RB + 1 ints
   int* soff = (int*)(ysh + (size_t)RB * B);
@@ -359,7 +364,9 @@ __global__ __launch_bounds__(256) void k_spmm_panel(int64_t n, int RB, int P, in
       for (int q = 0; q < E; ++q) {
         const int src = g * E + q;
         const int cc = __shfl(mc, src);
-        xv[q] = (win + src < z && colok) ? Xp[(int64_t)cc * ldx] : XT(0);
+        bool use = win + src < z && colok;
+        if (dg && use) use = (int64_t)p * PW + cc != row0 + __shfl(mr, src);  // diagonal: float64 below
+        xv[q] = use ? Xp[(int64_t)cc * ldx] : XT(0);
       }
       // loads return in issue order: the next window is requested after the gathers, so
       // waiting for the gathered values does not wait for the (HBM) window load
@@ -394,7 +401,11 @@ __global__ __launch_bounds__(256) void k_spmm_panel(int64_t n, int RB, int P, in
   __syncthreads();
   for (int i = t; i < nr * B; i += 256) {
     const int rr = i / B, cc = i % B;
-    if (cc < b) Y[(row0 + rr) * ldy + cc] = ysh[i];
+    if (cc < b) {
+      double y = ysh[i];
+      if (dg) y = fma(dg[row0 + rr], X64[(row0 + rr) * ldx64 + cc], y);
+      Y[(row0 + rr) * ldy + cc] = y;
+    }
   }
 }
 
@@ -403,7 +414,7 @@ __global__ __launch_bounds__(256) void k_spmm_panel(int64_t n, int RB, int P, in
 // one launch each, so that a later round does not start at staggered times.
 template <int B, typename VT, typename XT>
 void spmm_panel_rounds(const PanelH& P, const VT* val, const XT* X, int64_t ldx, double* Y, int64_t ldy, int b,
-                       hipStream_t s) {
+                       hipStream_t s, const double* dg, const double* X64, int64_t ldx64) {
   const size_t lds = sizeof(double) * (size_t)P.RB * B + sizeof(int) * (size_t)(P.RB + 1);
   static int resident = 0;  // per instantiation, computed once per process
   if (resident == 0) {
@@ -419,20 +430,21 @@ void spmm_panel_rounds(const PanelH& P, const VT* val, const XT* X, int64_t ldx,
   for (int r0 = 0; r0 < P.nblocks; r0 += per) {
     const int nb = std::min(per, P.nblocks - r0);
     k_spmm_panel<B, VT, XT><<<nb, 256, lds, s>>>(P.n, P.RB, P.P, P.PW, P.off, P.bstart, P.col, val, X, ldx, Y,
-                                                 ldy, b, r0);
+                                                 ldy, b, r0, dg, X64, ldx64);
   }
   SPPC_LAUNCH_CHECK();
 }
 
 template <typename VT, typename XT>
 void launch_spmm_panel(const PanelH& P, const VT* val, const XT* X, int64_t ldx, double* Y, int64_t ldy, int b,
-                       hipStream_t s) {
+                       hipStream_t s, const double* dg = nullptr, const double* X64 = nullptr,
+                       int64_t ldx64 = 0) {
   if (b <= 4)
-    spmm_panel_rounds<4, VT, XT>(P, val, X, ldx, Y, ldy, b, s);
+    spmm_panel_rounds<4, VT, XT>(P, val, X, ldx, Y, ldy, b, s, dg, X64, ldx64);
   else if (b <= 8)
-    spmm_panel_rounds<8, VT, XT>(P, val, X, ldx, Y, ldy, b, s);
+    spmm_panel_rounds<8, VT, XT>(P, val, X, ldx, Y, ldy, b, s, dg, X64, ldx64);
   else
-    spmm_panel_rounds<16, VT, XT>(P, val, X, ldx, Y, ldy, b, s);
+    spmm_panel_rounds<16, VT, XT>(P, val, X, ldx, Y, ldy, b, s, dg, X64, ldx64);
 }
 
 // first entry of row [b, e) with column >= key (columns ascending)
@@ -740,13 +752,14 @@ void spmm_f64(const DevCSR& H, const double* X, int64_t ldx, double* Y, int64_t 
 }
 
 void spmm_f32(const DevCSR& H, const float* X, int64_t ldx, double* Y, int64_t ldy, int b,
-              const double* shift, hipStream_t s) {
+              const double* shift, hipStream_t s, const double* diag, const double* X64, int64_t ldx64) {
   if (!H.val32) throw Error(1, "spmm_f32: no float32 values");
+  if (diag && !X64) throw Error(1, "spmm_f32: the float64 diagonal term needs float64 X");
   if (H.panel && !shift && b >= 1 && b <= 16 && H.n > 0) {
-    launch_spmm_panel<float, float>(*H.panel, H.panel->val32, X, ldx, Y, ldy, b, s);
+    launch_spmm_panel<float, float>(*H.panel, H.panel->val32, X, ldx, Y, ldy, b, s, diag, X64, ldx64);
     return;
   }
-  launch_spmm<float, float>(H, H.val32, X, ldx, Y, ldy, b, shift, s);
+  launch_spmm<float, float>(H, H.val32, X, ldx, Y, ldy, b, shift, s, 0.0, 0.0, 0.0, nullptr, 0, diag, X64, ldx64);
 }
 
 }  // namespace sppc
