@@ -102,7 +102,7 @@ __global__ __launch_bounds__(EIG_THREADS) void k_sym_eig(int m, int nw, const do
   __shared__ double sc[4];
   __shared__ double Alds[EIG_LDS_M * EIG_LDS_M];  // the working matrix when it fits
   const int t = threadIdx.x;
-  double* A = m <= EIG_LDS_M ? Alds : scr;
+  double* A = scr;  // the working matrix in global memory (ld m) while it does not fit in LDS
   double* d = scr + (int64_t)m * m;
   double* e = d + m;
   double* e2 = e + m;
@@ -114,19 +114,40 @@ __global__ __launch_bounds__(EIG_THREADS) void k_sym_eig(int m, int nw, const do
   double* lm = u2 + (int64_t)nw * m;
   unsigned char* piv = (unsigned char*)(lm + (int64_t)nw * m);
 
-  for (int64_t x = t; x < (int64_t)m * m; x += EIG_THREADS) A[x] = S[(x / m) * lds + (x % m)];
+  // Rows and columns >= o live in LDS (stride EIG_LDS_M); the rest in global memory (stride m).
+  // Step j of the reduction touches only [j, m)^2, so the trailing block moves to LDS once it fits
+  // and every later step (and the Householder vectors it stores) stays there.
+  int o = m;
+  if (m <= EIG_LDS_M) {
+    for (int64_t x = t; x < (int64_t)m * m; x += EIG_THREADS)
+      Alds[(x / m) * EIG_LDS_M + (x % m)] = S[(x / m) * lds + (x % m)];
+    o = 0;
+  } else {
+    for (int64_t x = t; x < (int64_t)m * m; x += EIG_THREADS) A[x] = S[(x / m) * lds + (x % m)];
+  }
   __syncthreads();
 
   // ---- Householder tridiagonalisation (the lower part; A stays symmetric)
   for (int j = 0; j + 2 < m; ++j) {
+    if (o > j && m - j <= EIG_LDS_M) {
+      const int len0 = m - j;
+      for (int64_t x = t; x < (int64_t)len0 * len0; x += EIG_THREADS)
+        Alds[(x / len0) * EIG_LDS_M + (x % len0)] = A[(int64_t)(j + x / len0) * m + j + (x % len0)];
+      __syncthreads();
+      o = j;
+    }
+    double* const base = j >= o ? Alds : A;
+    const int ld = j >= o ? EIG_LDS_M : m;
+    const int off = j >= o ? o : 0;
     const int len = m - 1 - j;
-    const double* xr = A + (int64_t)j * m + j + 1;  // row j, columns j+1.. == column j below diag
+    // row j, columns j+1.. == column j below the diagonal
+    const double* xr = base + (int64_t)(j - off) * ld + (j + 1 - off);
     double part = 0.0;
     for (int i = 1 + t; i < len; i += EIG_THREADS) part += xr[i] * xr[i];
     const double sigma = block_sum(part, red);
     if (t == 0) {
       const double alpha = xr[0];
-      d[j] = A[(int64_t)j * m + j];
+      d[j] = base[(int64_t)(j - off) * ld + (j - off)];
       double b = 0.0, v0 = 1.0, ej = alpha;
       if (sigma > 0.0) {
         const double mu = sqrt(alpha * alpha + sigma);
@@ -144,22 +165,22 @@ __global__ __launch_bounds__(EIG_THREADS) void k_sym_eig(int m, int nw, const do
     for (int i = t; i < len; i += EIG_THREADS) vsh[i] = i == 0 ? 1.0 : (b == 0.0 ? 0.0 : xr[i] / v0);
     __syncthreads();
     // keep v for the back-transformation in row j (no longer needed otherwise)
-    for (int i = t; i < len; i += EIG_THREADS) A[(int64_t)j * m + j + 1 + i] = vsh[i];
+    for (int i = t; i < len; i += EIG_THREADS) base[(int64_t)(j - off) * ld + (j + 1 - off) + i] = vsh[i];
     if (b != 0.0) {
       // p = b * A_tr v, A_tr = A[j+1.., j+1..]; 4 row groups x 256 columns
       const int grp = t >> 8, tl = t & 255;
       const int l0 = (len * grp) / 4, l1 = (len * (grp + 1)) / 4;
       for (int i = tl; i < len; i += 256) {
-        const double* col = A + (int64_t)(j + 1) * m + j + 1 + i;
+        const double* col = base + (int64_t)(j + 1 - off) * ld + (j + 1 - off) + i;
         double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
         int l = l0;
         for (; l + 3 < l1; l += 4) {
-          s0 += col[(int64_t)l * m] * vsh[l];
-          s1 += col[(int64_t)(l + 1) * m] * vsh[l + 1];
-          s2 += col[(int64_t)(l + 2) * m] * vsh[l + 2];
-          s3 += col[(int64_t)(l + 3) * m] * vsh[l + 3];
+          s0 += col[(int64_t)l * ld] * vsh[l];
+          s1 += col[(int64_t)(l + 1) * ld] * vsh[l + 1];
+          s2 += col[(int64_t)(l + 2) * ld] * vsh[l + 2];
+          s3 += col[(int64_t)(l + 3) * ld] * vsh[l + 3];
         }
-        for (; l < l1; ++l) s0 += col[(int64_t)l * m] * vsh[l];
+        for (; l < l1; ++l) s0 += col[(int64_t)l * ld] * vsh[l];
         psh[grp][i] = (s0 + s1) + (s2 + s3);
       }
       __syncthreads();
@@ -174,19 +195,21 @@ __global__ __launch_bounds__(EIG_THREADS) void k_sym_eig(int m, int nw, const do
       __syncthreads();
       for (int64_t x = t; x < (int64_t)len * len; x += EIG_THREADS) {
         const int l = (int)(x / len), i = (int)(x % len);
-        A[(int64_t)(j + 1 + l) * m + j + 1 + i] -= vsh[l] * wsh[i] + wsh[l] * vsh[i];
+        base[(int64_t)(j + 1 + l - off) * ld + (j + 1 + i - off)] -= vsh[l] * wsh[i] + wsh[l] * vsh[i];
       }
     }
     __syncthreads();
   }
   if (t == 0) {
+    // the last 2 x 2 block is in LDS (o <= m - 2 whenever m >= 3; o = 0 when m <= EIG_LDS_M)
+    const double* lb = Alds + (int64_t)(m >= 2 ? m - 2 - o : 0) * EIG_LDS_M + (m >= 2 ? m - 2 - o : 0);
     if (m >= 2) {
-      d[m - 2] = A[(int64_t)(m - 2) * m + m - 2];
-      d[m - 1] = A[(int64_t)(m - 1) * m + m - 1];
-      e[m - 2] = A[(int64_t)(m - 1) * m + m - 2];
+      d[m - 2] = lb[0];
+      d[m - 1] = lb[EIG_LDS_M + 1];
+      e[m - 2] = lb[EIG_LDS_M];
       beta[m - 2] = 0.0;
     } else {
-      d[0] = A[0];
+      d[0] = lb[0];
     }
     e[m - 1] = 0.0;
     beta[m - 1] = 0.0;
@@ -212,7 +235,10 @@ __global__ __launch_bounds__(EIG_THREADS) void k_sym_eig(int m, int nw, const do
   }
   __syncthreads();
   const double tn = sc[2];
-  if (t < nw) {
+  // Multisection: one wave per wanted eigenvalue; in each round the 64 lanes evaluate the Sturm
+  // count at 64 interior points of the current interval, which shrinks 65-fold (counts are
+  // monotone in x, so the crossing is found by a ballot).
+  {
     double lo = dl[0], hi = dl[0], maxe2 = 0.0;
     for (int i = 0; i < m; ++i) {
       const double r = (i > 0 ? fabs(el[i - 1]) : 0.0) + (i < m - 1 ? fabs(el[i]) : 0.0);
@@ -221,13 +247,25 @@ __global__ __launch_bounds__(EIG_THREADS) void k_sym_eig(int m, int nw, const do
       if (i < m - 1) maxe2 = fmax(maxe2, e2l[i]);
     }
     const double pivmin = 2.2250738585072014e-308 * fmax(1.0, maxe2);
-    double a = lo - 1e-14 * tn - 1e-300, bb = hi + 1e-14 * tn + 1e-300;
-    for (int it = 0; it < 200; ++it) {
-      const double mid = 0.5 * (a + bb);
-      if (bb - a <= 2.220446049250313e-16 * fmax(fabs(a), fabs(bb)) + pivmin || mid == a || mid == bb) break;
-      if (sturm_count(m, dl, e2l, mid, pivmin) <= t) a = mid; else bb = mid;
+    const int wv0 = t >> 6, ln0 = t & 63;
+    for (int idx = wv0; idx < nw; idx += EIG_THREADS / 64) {
+      double a = lo - 1e-14 * tn - 1e-300, bb = hi + 1e-14 * tn + 1e-300;
+      for (int it = 0; it < 40; ++it) {
+        if (bb - a <= 2.220446049250313e-16 * fmax(fabs(a), fabs(bb)) + pivmin) break;
+        const double h = (bb - a) / 65.0;
+        const double x = a + (ln0 + 1) * h;
+        const bool le = x < bb && sturm_count(m, dl, e2l, x, pivmin) <= idx;
+        const unsigned long long bal = __ballot(le);
+        // lanes 0..L-1 have count <= idx (monotone); the eigenvalue lies in [x_{L-1}, x_L]
+        const int L = __popcll(bal);
+        const double na = L > 0 ? a + L * h : a;
+        const double nbv = L < 64 ? a + (L + 1) * h : bb;
+        if (!(na < nbv) || (na == a && nbv == bb)) break;
+        a = na;
+        bb = fmin(nbv, bb);
+      }
+      if (ln0 == 0) wsh[idx] = 0.5 * (a + bb);
     }
-    wsh[t] = 0.5 * (a + bb);
   }
   __syncthreads();
 
@@ -298,7 +336,7 @@ __global__ __launch_bounds__(EIG_THREADS) void k_sym_eig(int m, int nw, const do
     const double b = beta[j];
     if (b != 0.0) {
       const int len = m - 1 - j;
-      const double* v = A + (int64_t)j * m + j + 1;
+      const double* v = j >= o ? Alds + (int64_t)(j - o) * EIG_LDS_M + (j + 1 - o) : A + (int64_t)j * m + j + 1;
       for (int c = wv; c < nw; c += EIG_THREADS / 64) {
         double* y = Y + (int64_t)c * m + j + 1;
         double s = 0.0;

@@ -213,3 +213,19 @@ def test_full_solve_cfg0_matches_dense():
     ref = _oracle_run(A, w.n0, w.k)
     assert np.max(np.abs(np.array(ev) - ref.theta) / np.abs(ref.theta)) < 1e-10
     assert st["n_spmv"] >= w.k * (st["iterations"] + 1)
+
+
+@pytest.mark.parametrize("extra", [2, 12])
+def test_projected_eigensolver_beyond_the_lds_tile(extra):
+    # m = 8 (p = 0) + 15 * 8 + extra continuation blocks > 128: the eigensolver starts in global
+    # memory and moves the trailing block to LDS; its Ritz values must be those of T itself
+    A = levelgen.generate((150, 1500, 12000), 60, 33)
+    print("case eig m>128 extra=%d" % extra, flush=True)
+    ctx = _ctx(A, 1, 8, tol=1e-15, max_cont=extra, final_check=0)
+    P.sppc_solve(ctx)
+    m = int(P.sppc_get(ctx, 2, 1)[0])
+    assert m > 128
+    T = np.array(P.sppc_get(ctx, 6, m * m)).reshape(m, m)
+    theta = np.array(P.sppc_get(ctx, 1, 8))
+    lam = np.linalg.eigvalsh(0.5 * (T + T.T))[:8]
+    assert np.max(np.abs(theta - lam) / np.abs(lam)) < 1e-13
