@@ -265,17 +265,23 @@ __global__ __launch_bounds__(NT) void k_cg_iter(CGArgs a, int j) {
       }
     }
     if (!INIT && first) {
-      // (r.r, w.r) of iteration j from the NB partials of the previous kernel, fixed order
+      // (r.r, w.r) of iteration j from the NB partials of the previous kernel, in a fixed order:
+      // lane sums over blocks, the two half-waves, then the 16 waves in turn
       const int v = t % (2 * CG_MAXK);
       double sacc = 0.0;
       for (int b2 = t / (2 * CG_MAXK); b2 < NB; b2 += NT / (2 * CG_MAXK))
         sacc += partin[(int64_t)b2 * 2 * CG_MAXK + v];
-      red[t] = sacc;
+      sacc += __shfl_xor(sacc, 32);
+      if ((t & 63) < 2 * CG_MAXK) red[(t >> 6) * 2 * CG_MAXK + v] = sacc;
       __syncthreads();
-      for (int o = NT / 2; o >= 2 * CG_MAXK; o >>= 1) {
-        if (t < o) red[t] += red[t + o];
-        __syncthreads();
+      if (t < 2 * CG_MAXK) {
+        double tot = 0.0;
+        for (int w2 = 0; w2 < NT / 64; ++w2) tot += red[w2 * 2 * CG_MAXK + t];
+        red[NT - 2 * CG_MAXK + t] = tot;
       }
+      __syncthreads();
+      if (t < 2 * CG_MAXK) red[t] = red[NT - 2 * CG_MAXK + t];
+      __syncthreads();
       if (t < k) {
         const double gg = red[t], d = red[CG_MAXK + t];
         double al_ = 0.0, be_ = 0.0, gkeep;
@@ -390,26 +396,20 @@ __global__ __launch_bounds__(NT) void k_cg_iter(CGArgs a, int j) {
     }
     __syncthreads();
   }
-  // block partials: fixed-order tree over the row slots of each column
-  red[t] = sg;
-  __syncthreads();
-  for (int o = NT / 2; o >= CG_MAXK; o >>= 1) {
-    if (t < o) red[t] += red[t + o];
-    __syncthreads();
+  // block partials in a fixed order: the four lanes of a column within a wave, then the waves
+  sg += __shfl_xor(sg, 16);
+  sg += __shfl_xor(sg, 32);
+  sd += __shfl_xor(sd, 16);
+  sd += __shfl_xor(sd, 32);
+  if ((t & 63) < CG_MAXK) {
+    red[(t >> 6) * 2 * CG_MAXK + oc] = sg;
+    red[(t >> 6) * 2 * CG_MAXK + CG_MAXK + oc] = sd;
   }
-  double gsum = 0.0;
-  if (t < CG_MAXK) gsum = red[t];
   __syncthreads();
-  red[t] = sd;
-  __syncthreads();
-  for (int o = NT / 2; o >= CG_MAXK; o >>= 1) {
-    if (t < o) red[t] += red[t + o];
-    __syncthreads();
-  }
-  if (t < CG_MAXK) {
-    double* out = a.part[par] + (int64_t)blockIdx.x * 2 * CG_MAXK;
-    out[t] = gsum;
-    out[CG_MAXK + t] = red[t];
+  if (t < 2 * CG_MAXK) {
+    double tot = 0.0;
+    for (int w2 = 0; w2 < NT / 64; ++w2) tot += red[w2 * 2 * CG_MAXK + t];
+    a.part[par][(int64_t)blockIdx.x * 2 * CG_MAXK + t] = tot;
   }
 }
 
