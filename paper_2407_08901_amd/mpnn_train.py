@@ -34,11 +34,12 @@ DEFAULT_WEIGHTS = os.path.join(HERE, "mpnn_weights.json")
 FORMAT = "sppc-mpnn-v1"
 
 
-def build_dataset(seeds, k=4, log=print):
+def build_dataset(seeds, shape="L3", log=print):
     import levelgen
     data = []
     for sd in seeds:
-        w = levelgen.train_workload(sd)
+        w = levelgen.train_workload(sd, shape)
+        k = w.k
         A = w.generate()
         rp, col, val = P.upload(A)
         exact = P.sppc_setup(rp, col, val, A.level_offsets, w.n_small_levels, k, P.sppc_default_opts(tol=1e-11))
@@ -132,15 +133,18 @@ def main():
     ap.add_argument("--epochs", type=int, default=30)
     ap.add_argument("--lr", type=float, default=3e-3)
     ap.add_argument("--nseeds", type=int, default=20)
+    ap.add_argument("--shape", default="L3", choices=["L3", "L4"],
+                    help="training matrices: the n = 4900 three-level shape or the four-level n = 117,200 one")
     args = ap.parse_args()
     P.lib()
     t0 = time.time()
-    data = build_dataset(levelgen.TRAIN_SEEDS[: args.nseeds], log=lambda m: print(m, flush=True))
+    seeds = (levelgen.TRAIN_SEEDS if args.shape == "L3" else levelgen.TRAIN_SEEDS_L4)[: args.nseeds]
+    data = build_dataset(seeds, args.shape, log=lambda m: print(m, flush=True))
     t1 = time.time()
     w, hist = train(data, epochs=args.epochs, lr=args.lr, log=lambda m: print(m, flush=True))
     t2 = time.time()
     nsamp = sum(g["X"].shape[1] for d in data for g in d["groups"])
-    save(w, args.out, {"train_seeds": list(levelgen.TRAIN_SEEDS[: args.nseeds]), "samples": nsamp,
+    save(w, args.out, {"train_seeds": list(seeds), "shape": args.shape, "samples": nsamp,
                        "epochs": args.epochs, "lr": args.lr, "loss_history": hist,
                        "data_s": round(t1 - t0, 2), "train_s": round(t2 - t1, 2)})
     print(json.dumps({"samples": nsamp, "final_loss": hist[-1], "first_loss": hist[0], "data_s": t1 - t0,
