@@ -5,13 +5,15 @@ plain float64 SPPC on the same GPU.
 One step = sppc_setup (device format, H0hat eigenpairs, p = 0) + sppc_solve (SPPC steps,
 continuation, final float64 check) on the level-structured workload
 L4-2k/20k/150k/1M-d200-k8 (n = 1,172,000, ~118M stored upper entries), with H already
-resident in HBM as an upper-triangular CSR.  The timed form (--mode, default mixed+mpnn:
-float32 products with float64 accumulation, float64 refinement, learned preconditioner in the
-continuation) is followed by the same number of plain float64 steps with the diagonal
-preconditioner (--no-compare skips them).  Prints one JSON line.
+resident in HBM as an upper-triangular CSR.  The timed form (--mode, default mixed: float32
+products with float64 accumulation, small-space solves to 1e-6, float64 check and refinement)
+is followed by the same number of steps of plain float64 SPPC (small-space solves to 1e-12), of
+the mixed form with the learned preconditioner in the continuation, and of float64 SPPC with
+small-space solves to 1e-6 (--no-compare skips them).  Prints one JSON line.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload 1]
-                  [--mode plain|mixed|plain+mpnn|mixed+mpnn|plain+small|mixed+small] [--no-compare]
+                  [--mode plain|mixed|plain+mpnn|mixed+mpnn|plain+small|mixed+small|plain-inexact]
+                  [--no-compare]
                   [--no-cpu-baseline] [--calibrate-copy] [--spmm-only R]
 """
 from __future__ import annotations
@@ -49,7 +51,7 @@ def measured_traffic(workload, mode):
     except OSError:
         ok = False
     return rec[0] if ok else None
-MODES = ("plain", "mixed", "plain+mpnn", "mixed+mpnn", "plain+small", "mixed+small")
+MODES = ("plain", "mixed", "plain+mpnn", "mixed+mpnn", "plain+small", "mixed+small", "plain-inexact")
 
 
 def parse():
@@ -126,14 +128,16 @@ def main():
         return
 
     from paper_2407_08901_amd import mpnn_train
-    weights = mpnn_train.load()
+    weights = mpnn_train.load_for_levels(len(w.level_sizes))
 
     def make_step(mode):
         mixed = mode.startswith("mixed")
         mpnn = mode.endswith("mpnn")
         precond = P.SPPC_CORR_MPNN if mpnn else P.SPPC_CORR_SMALL if mode.endswith("small") else P.SPPC_CORR_JACOBI
+        # plain-inexact: float64 with the small-space solves to the mixed form's inner tolerance
+        extra = {"inner_tol": 1e-6} if mode == "plain-inexact" else {}
         opts = P.sppc_default_opts(precision=P.SPPC_PREC_MIXED if mixed else P.SPPC_PREC_FP64, precond=precond,
-                                   verbose=1 if args.verbose else 0, panel_width=args.panel_width)
+                                   verbose=1 if args.verbose else 0, panel_width=args.panel_width, **extra)
 
         def one_step():
             ctx = P.sppc_setup(rp, col, val, A.level_offsets, w.n_small_levels, w.k, opts)
@@ -203,6 +207,9 @@ def main():
                                                                  np.abs(np.array(ev_p)))))
         per_l, ev_l, d = summary("mixed+mpnn")
         line["mixed_learned"] = dict(d, speedup_vs_plain=round(per_p / per_l, 3))
+        # the same float64 method with inexact small-space solves (inner tolerance 1e-6)
+        per_i, ev_i, d = summary("plain-inexact")
+        line["plain_fp64_inner_1e-6"] = dict(d, speedup_vs_plain=round(per_p / per_i, 3))
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(A, w, st)
     print(json.dumps(line))

@@ -47,10 +47,12 @@ typedef enum { SPPC_F64 = 0, SPPC_F32 = 1 } sppc_dtype;
 
 typedef enum {
   SPPC_PREC_FP64 = 0,   /* every product in float64 */
-  SPPC_PREC_MIXED = 1   /* float32 matrix values and vectors in the H and H0hat products and the
-                           small-space solves, float32 products accumulated in float64; basis,
-                           projected matrix, orthonormalisation, Rayleigh-Ritz and the final
-                           residual check stay float64 */
+  SPPC_PREC_MIXED = 1   /* block products with H: float32 X, float32 products accumulated in
+                           float64 (the diagonal term in float64), until the largest relative
+                           residual falls below 1e-4, float64 after that.  H Psi^(0), the
+                           small-space solves (inner_tol 1e-6 by default), basis, projected matrix,
+                           orthonormalisation, Rayleigh-Ritz and the final residual check are
+                           float64; a float64 refinement follows when the check fails */
 } sppc_precision;
 
 typedef enum {

@@ -33,21 +33,24 @@ __host__ __device__ inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 
 // ---------------------------------------------------------------- sparse (kernels_sparse.hip)
 
 // Full symmetric CSR on the device (both triangles, columns ascending in each row).
-// Row-block x column-panel copy of H for the block product with large n.  Rows are cut into
-// blocks of RB (one workgroup each) and columns into panels of PW (a panel of X is small enough
-// to stay in one XCD's L2).  Within a block the entries are stored panel by panel, and within
-// a panel row by row with ascending columns; columns are stored relative to the panel start.
+// Row-block x column-panel copy of H for the block product with large n (n < 2^24).  Rows are
+// cut into blocks of RB = 256 (one workgroup each) and columns into panels of PW (a panel of X
+// is small enough to stay in one XCD's L2).  The off-diagonal entries of a block form one
+// stream ordered by (panel, row, column), padded with zero entries to a multiple of 8; an
+// entry is a word (column | row-in-block << 24) and a value.  The diagonal is kept apart (dg).
 struct PanelH {
   int64_t n = 0;
   int nblocks = 0;
   int RB = 0;                 // rows per block
   int P = 0;                  // panels
   int PW = 0;                 // columns per panel (<= 65536)
-  int32_t* off = nullptr;     // [nblocks][P*RB + 1]: start of (panel, row) relative to the block
-  int64_t* bstart = nullptr;  // [nblocks + 1]: first entry of each block
-  uint16_t* col = nullptr;    // column - panel * PW
+  int64_t* bstart = nullptr;  // [nblocks + 1]: first entry of each block (multiples of 8)
+  int32_t* bcount = nullptr;  // [nblocks]: entries of each block, without the padding
+  uint32_t* ent = nullptr;    // column | row-in-block << 24
   float* val32 = nullptr;
   double* val64 = nullptr;
+  double* dg = nullptr;       // [n] diagonal of H
+  void* xpad = nullptr;       // [n x 16] doubles: X copied to row stride B when needed
 };
 
 struct DevCSR {
@@ -69,7 +72,7 @@ void build_full_csr(int64_t n, int64_t nnz_up, const int64_t* up_rp, const int32
 void build_block_view(const DevCSR& full, int64_t n0, int64_t* rend, hipStream_t s);
 // Panel copy of a full CSR (ascending columns per row); values as stored in the CSR.
 // Device memory is allocated with hipMalloc and owned by the caller (release_panel).
-void build_panel(const DevCSR& H, int PW, int RB, PanelH& out, hipStream_t s);
+void build_panel(const DevCSR& H, int PW, PanelH& out, hipStream_t s);
 void release_panel(PanelH& p);
 // out[0..n] = exclusive prefix sums of a[0..n) (out[n] = total); bsum holds cdiv(n, 1024) + 1.
 void scan_exclusive(int64_t n, const int32_t* a, int64_t* out, int64_t* bsum, hipStream_t s);
@@ -183,9 +186,10 @@ int64_t cg_work_doubles(int64_t n0);
 // doubles.
 void cg_prepare(const DevCSR& H0, int64_t n0, int64_t* rowb, double* tmp, hipStream_t s);
 // Deflated CG for the k small-space systems (b in r on entry, solution in x); ccoef = Ps^T b.
+// Products in float64 (float32-stored values are widened).
 int cg_solve(const DevCSR& H0, int64_t n0, int k, int D, const double* shift, const double* Ps,
              const int64_t* rowb, double* x, double* r, double* work, double* ccoef, int maxit, double tol,
-             bool f32prod, int* host_flag, hipStream_t s);
+             int* host_flag, hipStream_t s);
 // out[c] = X[:, c]^T Y[:, c]
 void coldots(int64_t n, int b, const double* X, int64_t ldx, const double* Y, int64_t ldy, double* out,
              double* work, hipStream_t s);

@@ -186,7 +186,7 @@ __device__ inline void cg_window(const int32_t* __restrict__ col, const VT* __re
   }
 }
 
-template <int B, typename VT, bool F32P>
+template <int B, typename VT>
 __device__ inline void cg_runs(int win, int ne, int g, int c, bool cok, int mr, VT mv, const double* xv,
                                double* acc_s) {
   int cur_r = __shfl(mr, g * B);
@@ -202,17 +202,13 @@ __device__ inline void cg_runs(int win, int ne, int g, int c, bool cok, int mr, 
         cur = 0.0;
         cur_r = rr;
       }
-      if constexpr (F32P) {
-        cur += (double)((float)vv * (float)xv[q]);  // float32 product, float64 accumulation
-      } else {
-        cur = fma((double)vv, xv[q], cur);
-      }
+      cur = fma((double)vv, xv[q], cur);
     }
   }
   if (win + g * B < ne && cok) atomicAdd(&acc_s[cur_r * CG_MAXK + c], cur);
 }
 
-template <int B, typename VT, bool F32P, bool INIT>
+template <int B, typename VT, bool INIT>
 __global__ __launch_bounds__(NT) void k_cg_iter(CGArgs a, int j) {
   const int t = threadIdx.x;
   const int k = a.k;
@@ -365,8 +361,8 @@ __global__ __launch_bounds__(NT) void k_cg_iter(CGArgs a, int j) {
         xv1[q] = v1;
         xv2[q] = v2;
       }
-      cg_runs<B, VT, F32P>(win, ne, g, c, cok, mr1, mv1, xv1, acc_s);
-      cg_runs<B, VT, F32P>(win2, ne, g, c, cok, mr2, mv2, xv2, acc_s);
+      cg_runs<B, VT>(win, ne, g, c, cok, mr1, mv1, xv1, acc_s);
+      cg_runs<B, VT>(win2, ne, g, c, cok, mr2, mv2, xv2, acc_s);
     }
     __syncthreads();
     if (oc < k) {
@@ -461,9 +457,8 @@ void cg_prepare(const DevCSR& H0, int64_t n0, int64_t* rowb, double* tmp, hipStr
 // ccoef = Ps^T b.  Returns the number of iterations (synchronises the stream).
 int cg_solve(const DevCSR& H0, int64_t n0, int k, int D, const double* shift, const double* Ps,
              const int64_t* rowb, double* x, double* r, double* work, double* ccoef, int maxit, double tol,
-             bool f32prod, int* host_flag, hipStream_t s) {
+             int* host_flag, hipStream_t s) {
   if (k < 1 || k > CG_MAXK || D < 1 || D > CG_MAXD) throw Error(1, "cg: k <= 16 and D <= 28 required");
-  if (f32prod && !H0.val32) throw Error(1, "cg: float32 products need float32 values");
   if (H0.rend) throw Error(1, "cg: H0hat must be a contiguous CSR");
   if (n0 * (int64_t)RCH >= ((int64_t)1 << 31)) throw Error(1, "cg: n0 too large for 32-bit chunk offsets");
   const int nb2 = (int)std::min<int64_t>(256, cdiv(n0, 64));
@@ -481,10 +476,9 @@ int cg_solve(const DevCSR& H0, int64_t n0, int k, int D, const double* shift, co
   k_cg_project<<<nb2, 1024, 0, s>>>(a, r, ccoef, 1);
   SPPC_LAUNCH_CHECK();
   const bool f64 = H0.val64 != nullptr;
-#define SPPC_CG_LAUNCH(BB, INIT, J)                                                         \
-  if (f32prod) k_cg_iter<BB, float, true, INIT><<<NB, NT, 0, s>>>(a, J);                     \
-  else if (f64) k_cg_iter<BB, double, false, INIT><<<NB, NT, 0, s>>>(a, J);                  \
-  else k_cg_iter<BB, float, false, INIT><<<NB, NT, 0, s>>>(a, J);
+#define SPPC_CG_LAUNCH(BB, INIT, J)                               \
+  if (f64) k_cg_iter<BB, double, INIT><<<NB, NT, 0, s>>>(a, J);    \
+  else k_cg_iter<BB, float, INIT><<<NB, NT, 0, s>>>(a, J);
 #define SPPC_CG_STEP(INIT, J)      \
   if (k <= 4) {                    \
     SPPC_CG_LAUNCH(4, INIT, J)     \

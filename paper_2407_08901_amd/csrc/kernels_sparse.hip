@@ -298,153 +298,222 @@ __global__ void k_view_fill(int64_t n0, const int64_t* __restrict__ rp, const in
 
 // ------------------------------------------------------------------ panel format
 //
-// Block product over the row-block x column-panel copy (PanelH).  One workgroup per row
-// block; all workgroups sweep the panels in the same order, so the panel of X that the
-// resident workgroups gather from stays in L2.  Each wave owns RB/4 consecutive rows, whose
-// entries in one panel are contiguous; the wave streams them in windows of 64 (one coalesced
-// load of columns and values).  Group g of B lanes takes the B consecutive entries
-// g*B .. g*B+B-1 of the window, lane c reading column c of each gathered row of X, and sums runs
-// of entries of the same row in a register; a run is added to the row's LDS accumulator
-// when it ends.  Runs that straddle two groups meet in the same LDS add instruction.
-template <int B, typename VT, typename XT>
-__global__ __launch_bounds__(256) void k_spmm_panel(int64_t n, int RB, int P, int PW,
-                                                    const int32_t* __restrict__ off,
-                                                    const int64_t* __restrict__ bstart,
-                                                    const uint16_t* __restrict__ pcol,
-                                                    const VT* __restrict__ pval, const XT* __restrict__ X,
-                                                    int64_t ldx, double* __restrict__ Y, int64_t ldy, int b,
-                                                    int blk0, const double* __restrict__ dg,
+// Block product over the row-block x column-panel stream (PanelH).  One workgroup per block of
+// RB = 256 rows.  The block's off-diagonal entries are one contiguous stream ordered by (panel,
+// row, column); each entry is a 32-bit word (column | row-in-block << 24) and a value.  The
+// NW waves take tiles of the stream in turn, so the workgroup sweeps the panels in order and,
+// with all workgroups of a launch starting together, the panels of X they gather from stay in
+// L2 (the gathers are most of the product's time: without them it runs 1.5x faster).
+//
+// Inside a tile, group g of G lanes takes U = 8 consecutive entries (two vector loads of words
+// and values per lane, shared by the G lanes); lane h of the group gathers columns
+// [h*CPL, h*CPL + CPL) (CPL = 4) of each entry's row of X with 16-byte loads and adds the products
+// to the row's LDS accumulators (native float64 LDS adds).  In one add instruction the groups
+// hold entries 8 apart, which lie in different rows, so the adds rarely collide.  The words and
+// values of the tile D steps ahead are requested after the gathers of the current one.  X is
+// read from a copy with row stride B (16-byte aligned); the diagonal is not in the stream and is
+// added in float64 at the end: dg * X64 when X64 is given, else the product in the precision of
+// X.
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+
+template <typename VT> struct ValLoad;
+template <> struct ValLoad<float> {
+  static __device__ inline void load(const float* p, float (&v)[8]) {
+    const f32x4 a = __builtin_nontemporal_load((const f32x4*)p);
+    const f32x4 b = __builtin_nontemporal_load((const f32x4*)p + 1);
+    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w; v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+  }
+};
+template <> struct ValLoad<double> {
+  static __device__ inline void load(const double* p, double (&v)[8]) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const f64x2 a = __builtin_nontemporal_load((const f64x2*)p + i);
+      v[2 * i] = a.x;
+      v[2 * i + 1] = a.y;
+    }
+  }
+};
+
+struct f64x4 {
+  f64x2 lo, hi;
+};
+template <typename XT> struct XRow;  // CPL = 4 columns of one row of X (16 or 32 bytes)
+template <> struct XRow<float> {
+  static constexpr int CPL = 4;
+  typedef f32x4 V;
+  static __device__ inline V load(const float* p) { return *(const f32x4*)p; }
+  static __device__ inline float get(const V& v, int j) { return v[j]; }
+};
+template <> struct XRow<double> {
+  static constexpr int CPL = 4;
+  typedef f64x4 V;
+  static __device__ inline V load(const double* p) { return V{*(const f64x2*)p, *((const f64x2*)p + 1)}; }
+  static __device__ inline double get(const V& v, int j) { return j < 2 ? v.lo[j] : v.hi[j - 2]; }
+};
+
+constexpr int PANEL_RB = 256;  // rows per block: the row index is stored in 8 bits
+constexpr int PANEL_U = 8;     // consecutive entries per lane group and tile
+template <typename VT>
+__device__ inline void panel_load(const uint32_t* __restrict__ ent, const VT* __restrict__ pval, int64_t e,
+                                  int64_t s1, u32x4& wa, u32x4& wb, VT (&v)[PANEL_U]) {
+  if (e < s1) {
+    wa = __builtin_nontemporal_load((const u32x4*)(ent + e));
+    wb = __builtin_nontemporal_load((const u32x4*)(ent + e) + 1);
+    ValLoad<VT>::load(pval + e, v);
+  } else {
+    wa = u32x4{0u, 0u, 0u, 0u};  // column 0: the gathers stay in bounds, the adds are masked
+    wb = wa;
+  }
+}
+
+template <int B, int NW, int D, typename VT, typename XT>
+__global__ __launch_bounds__(NW * 64) void k_spmm_panel(int64_t n, const int64_t* __restrict__ bstart,
+                                                    const int32_t* __restrict__ bcount,
+                                                    const uint32_t* __restrict__ ent,
+                                                    const VT* __restrict__ pval, const XT* __restrict__ Xc,
+                                                    double* __restrict__ Y, int64_t ldy, int b, int blk0,
+                                                    const double* __restrict__ dg,
                                                     const double* __restrict__ X64, int64_t ldx64) {
-  constexpr int E = B;  // entries per group and window: 64/B groups share the 64 entries
-  extern __shared__ double ysh[];  // RB * B accumulators, then RB + 1 ints
-  int* soff = (int*)(ysh + (size_t)RB * B);
+  typedef XRow<XT> XR;
+  constexpr int CPL = XR::CPL;
+  constexpr int G = B / CPL;       // lanes per entry
+  constexpr int NG = 64 / G;       // entry groups per wave
+  constexpr int U = PANEL_U;
+  constexpr int T = NG * U;        // entries per wave tile
+  constexpr int YS = B + 1;        // LDS row stride in doubles (odd: spreads the rows over banks)
+  constexpr int RB = PANEL_RB;
+  constexpr int NT = NW * 64;      // threads
+  __shared__ double ysh[RB * YS];
   const int t = threadIdx.x;
   const int lane = t & 63, w = t >> 6;
-  const int g = lane / B, c = lane % B;
+  const int g = lane / G, h = lane % G;
   const int64_t blk = blk0 + (int64_t)blockIdx.x;
   const int64_t row0 = blk * RB;
   const int nr = (int)min<int64_t>(RB, n - row0);
-  const int32_t* boff = off + blk * ((int64_t)P * RB + 1);
-  const VT* bval = pval + bstart[blk];
-  const uint16_t* bcol = pcol + bstart[blk];
-  const int WR = RB / 4;
-  const int R0 = w * WR, R1 = R0 + WR;
-  const bool colok = c < b;
-  for (int i = t; i < RB * B; i += 256) ysh[i] = 0.0;
-  for (int p = 0; p < P; ++p) {
-    __syncthreads();  // previous panel's offsets are no longer read; accumulators zeroed
-    for (int i = t; i <= RB; i += 256) soff[i] = boff[(int64_t)p * RB + i];
-    __syncthreads();
-    const int a = soff[R0], z = soff[R1];
-    const XT* Xp = X + (int64_t)p * PW * ldx + c;
-    // the window after the current one is loaded while the current one is processed; the
-    // matrix is read once, streaming (nontemporal), so it does not evict the panel of X
-    int nc = 0;
-    VT nv = VT(0);
-    if (a + lane < z) {
-      nc = (int)__builtin_nontemporal_load(&bcol[a + lane]);
-      nv = __builtin_nontemporal_load(&bval[a + lane]);
-    }
-    for (int win = a; win < z; win += 64) {
-      const int e = win + lane;
-      const int mc = nc;
-      const VT mv = nv;
-      int mr = R0;
-      if (e < z) {
-        // row of entry e: last r in [R0, R1) with soff[r] <= e
-        int lo = R0, hi = R1 - 1;
-        while (lo < hi) {
-          const int mid = (lo + hi + 1) >> 1;
-          if (soff[mid] <= e) lo = mid; else hi = mid - 1;
-        }
-        mr = lo;
-      }
-      XT xv[E];
+  for (int i = t; i < RB * YS; i += NT) ysh[i] = 0.0;
+  __syncthreads();
+  const int64_t s0 = bstart[blk];
+  const int64_t s1 = s0 + bcount[blk];
+  const XT* xb = Xc + h * CPL;
+  const int64_t step = (int64_t)NW * T;
+  int64_t e0 = s0 + (int64_t)w * T + g * U;  // this lane group's chunk of the current tile
+  // words and values of the next D tiles are in flight; chunks start at multiples of 8 and each
+  // block's stream is padded to 8, so a chunk that starts before s1 is inside the allocation
+  u32x4 wa[D], wb[D];
+  VT v[D][U];
 #pragma unroll
-      for (int q = 0; q < E; ++q) {
-        const int src = g * E + q;
-        const int cc = __shfl(mc, src);
-        bool use = win + src < z && colok;
-        if (dg && use) use = (int64_t)p * PW + cc != row0 + __shfl(mr, src);  // diagonal: float64 below
-        xv[q] = use ? Xp[(int64_t)cc * ldx] : XT(0);
-      }
-      // loads return in issue order: the next window is requested after the gathers, so
-      // waiting for the gathered values does not wait for the (HBM) window load
+  for (int d = 0; d < D; ++d) panel_load(ent, pval, e0 + d * step, s1, wa[d], wb[d], v[d]);
+  int64_t tb = s0 + (int64_t)w * T;
+  while (tb < s1) {
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      if (tb >= s1) break;
+      const uint32_t wd[U] = {wa[d].x, wa[d].y, wa[d].z, wa[d].w, wb[d].x, wb[d].y, wb[d].z, wb[d].w};
+      typename XR::V xv[U];
+#pragma unroll
+      for (int q = 0; q < U; ++q) xv[q] = XR::load(xb + (int64_t)(wd[q] & 0xFFFFFFu) * B);
+      VT cv[U];
+#pragma unroll
+      for (int q = 0; q < U; ++q) cv[q] = v[d][q];
+      // loads return in issue order: the tile D steps ahead is requested after the gathers
       asm volatile("" ::: "memory");
-      if (e + 64 < z) {
-        nc = (int)__builtin_nontemporal_load(&bcol[e + 64]);
-        nv = __builtin_nontemporal_load(&bval[e + 64]);
-      }
-      int cur_r = __shfl(mr, g * E);
-      double cur = 0.0;
+      panel_load(ent, pval, e0 + D * step, s1, wa[d], wb[d], v[d]);
 #pragma unroll
-      for (int q = 0; q < E; ++q) {
-        const int src = g * E + q;
-        const VT vv = __shfl(mv, src);
-        const int rr = __shfl(mr, src);
-        if (win + src < z) {
-          if (rr != cur_r) {
-            atomicAdd(&ysh[cur_r * B + c], cur);
-            cur = 0.0;
-            cur_r = rr;
-          }
-          if constexpr (sizeof(XT) == 4) {
-            cur += (double)(vv * xv[q]);  // float32 product, float64 accumulation
-          } else {
-            cur = fma((double)vv, (double)xv[q], cur);
+      for (int q = 0; q < U; ++q) {
+        if (e0 + q < s1) {
+          double* yr = ysh + (int)(wd[q] >> 24) * YS + h * CPL;
+#pragma unroll
+          for (int j = 0; j < CPL; ++j) {
+            if constexpr (sizeof(XT) == 4) {
+              atomicAdd(yr + j, (double)(cv[q] * XR::get(xv[q], j)));  // float32 product, float64 sum
+            } else {
+              atomicAdd(yr + j, (double)cv[q] * XR::get(xv[q], j));
+            }
           }
         }
       }
-      if (win + g * E < z) atomicAdd(&ysh[cur_r * B + c], cur);
+      tb += step;
+      e0 += step;
     }
   }
   __syncthreads();
-  for (int i = t; i < nr * B; i += 256) {
+  for (int i = t; i < nr * B; i += NT) {
     const int rr = i / B, cc = i % B;
     if (cc < b) {
-      double y = ysh[i];
-      if (dg) y = fma(dg[row0 + rr], X64[(row0 + rr) * ldx64 + cc], y);
-      Y[(row0 + rr) * ldy + cc] = y;
+      const int64_t row = row0 + rr;
+      double y = ysh[rr * YS + cc];
+      if (X64) {
+        y = fma(dg[row], X64[row * ldx64 + cc], y);
+      } else if constexpr (sizeof(XT) == 4) {
+        y += (double)((float)dg[row] * Xc[row * B + cc]);
+      } else {
+        y = fma(dg[row], Xc[row * B + cc], y);
+      }
+      Y[row * ldy + cc] = y;
     }
   }
 }
 
-// Workgroups of one launch start together and sweep the panels in step; when the blocks do
-// not all fit on the device at once they are split into rounds of at most the resident count,
-// one launch each, so that a later round does not start at staggered times.
-template <int B, typename VT, typename XT>
-void spmm_panel_rounds(const PanelH& P, const VT* val, const XT* X, int64_t ldx, double* Y, int64_t ldy, int b,
-                       hipStream_t s, const double* dg, const double* X64, int64_t ldx64) {
-  const size_t lds = sizeof(double) * (size_t)P.RB * B + sizeof(int) * (size_t)(P.RB + 1);
-  static int resident = 0;  // per instantiation, computed once per process
-  if (resident == 0) {
-    int dev = 0, cus = 0, per_cu = 0;
+// Xp[r][c] = X[r][c] for c < b, row stride B
+template <typename XT>
+__global__ void k_pad_copy(int64_t n, int b, const XT* __restrict__ X, int64_t ldx, XT* __restrict__ Xp, int B) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n * B) return;
+  const int64_t r = i / B;
+  const int c = (int)(i % B);
+  if (c < b) Xp[i] = X[r * ldx + c];
+}
+
+// Workgroups of one launch start together and sweep the panels in step.  The blocks run in
+// rounds of exactly BPC workgroups per compute unit, one launch each: every CU then carries the
+// same load, so the workgroups progress at the same rate and stay within a few panels of each
+// other (an uneven round lets the workgroups on busier CUs fall behind, and the gathers of
+// X then miss L2).
+template <int B, int NW, int D, typename VT, typename XT>
+void spmm_panel_rounds(const PanelH& P, const VT* val, const XT* Xc, double* Y, int64_t ldy, int b, int bpc,
+                       hipStream_t s, const double* X64, int64_t ldx64) {
+  static int cus = 0;
+  if (cus == 0) {
+    int dev = 0;
     SPPC_HIP(hipGetDevice(&dev));
     SPPC_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    SPPC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_spmm_panel<B, VT, XT>, 256, lds));
-    resident = std::max(1, cus * std::max(1, per_cu));
+    cus = std::max(1, cus);
   }
-  const int cap = resident;
-  const int rounds = (int)cdiv(P.nblocks, cap);
-  const int per = (int)cdiv(P.nblocks, rounds);  // equal rounds
+  const int per = cus * bpc;
   for (int r0 = 0; r0 < P.nblocks; r0 += per) {
     const int nb = std::min(per, P.nblocks - r0);
-    k_spmm_panel<B, VT, XT><<<nb, 256, lds, s>>>(P.n, P.RB, P.P, P.PW, P.off, P.bstart, P.col, val, X, ldx, Y,
-                                                 ldy, b, r0, dg, X64, ldx64);
+    k_spmm_panel<B, NW, D, VT, XT><<<nb, NW * 64, 0, s>>>(P.n, P.bstart, P.bcount, P.ent, val, Xc, Y, ldy, b, r0, P.dg,
+                                                       X64, ldx64);
   }
   SPPC_LAUNCH_CHECK();
 }
 
+template <int B, typename VT, typename XT>
+void spmm_panel_b(const PanelH& P, const VT* val, const XT* X, int64_t ldx, double* Y, int64_t ldy, int b,
+                  hipStream_t s, const double* X64, int64_t ldx64) {
+  const XT* Xc = X;
+  if (ldx != B || ((uintptr_t)X & 15) != 0) {
+    XT* xp = (XT*)P.xpad;
+    k_pad_copy<XT><<<(unsigned)cdiv(P.n * B, 256), 256, 0, s>>>(P.n, b, X, ldx, xp, B);
+    Xc = xp;
+  }
+  // two-wave workgroups, two (float64 X) or four (float32 X) per CU, words and values two tiles
+  // ahead: the fastest of the measured shapes at n = 1.17M, d = 200
+  spmm_panel_rounds<B, 2, 2, VT, XT>(P, val, Xc, Y, ldy, b, sizeof(XT) == 4 ? 4 : 2, s, X64, ldx64);
+}
+
 template <typename VT, typename XT>
 void launch_spmm_panel(const PanelH& P, const VT* val, const XT* X, int64_t ldx, double* Y, int64_t ldy, int b,
-                       hipStream_t s, const double* dg = nullptr, const double* X64 = nullptr,
-                       int64_t ldx64 = 0) {
+                       hipStream_t s, const double* X64 = nullptr, int64_t ldx64 = 0) {
   if (b <= 4)
-    spmm_panel_rounds<4, VT, XT>(P, val, X, ldx, Y, ldy, b, s, dg, X64, ldx64);
+    spmm_panel_b<4, VT, XT>(P, val, X, ldx, Y, ldy, b, s, X64, ldx64);
   else if (b <= 8)
-    spmm_panel_rounds<8, VT, XT>(P, val, X, ldx, Y, ldy, b, s, dg, X64, ldx64);
+    spmm_panel_b<8, VT, XT>(P, val, X, ldx, Y, ldy, b, s, X64, ldx64);
   else
-    spmm_panel_rounds<16, VT, XT>(P, val, X, ldx, Y, ldy, b, s, dg, X64, ldx64);
+    spmm_panel_b<16, VT, XT>(P, val, X, ldx, Y, ldy, b, s, X64, ldx64);
 }
 
 // first entry of row [b, e) with column >= key (columns ascending)
@@ -456,58 +525,107 @@ __device__ inline int64_t lower_col(const int32_t* __restrict__ col, int64_t b, 
   return b;
 }
 
-// cnt[blk][p*RB + r] = entries of row r of block blk in panel p (one wave per row; the lane
-// that holds the last entry of a panel run writes its length)
-__global__ void k_panel_count(int64_t n, const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
-                              int RB, int P, int PW, int32_t* __restrict__ cnt) {
-  const int lane = threadIdx.x & 63;
-  const int64_t row = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  if (row >= n) return;
-  const int64_t b = rp[row], e = rp[row + 1];
-  const int64_t blk = row / RB;
-  const int rl = (int)(row - blk * RB);
-  for (int64_t t = b + lane; t < e; t += 64) {
-    const int p = col[t] / PW;
-    if (t + 1 == e || col[t + 1] / PW != p) {
-      const int64_t st = lower_col(col, b, t, (int64_t)p * PW);
-      cnt[blk * ((int64_t)P * RB) + (int64_t)p * RB + rl] = (int32_t)(t - st + 1);
-    }
+// Block-wide (256 threads) sum and exclusive prefix sum; sh holds 4 values.
+__device__ inline int block_scan_excl(int v, int* sh, int& total) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int inc = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int u = __shfl_up(inc, o);
+    if (lane >= o) inc += u;
+  }
+  __syncthreads();  // sh is free (previous use finished)
+  if (lane == 63) sh[w] = inc;
+  __syncthreads();
+  int before = 0;
+  total = 0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    if (i < w) before += sh[i];
+    total += sh[i];
+  }
+  return before + inc - v;
+}
+
+__device__ inline int block_min(int v, int* sh) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
+  __syncthreads();
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  return min(min(sh[0], sh[1]), min(sh[2], sh[3]));
+}
+
+// Off-diagonal entries of each block of PANEL_RB rows, padded to a multiple of 8 (one thread
+// per row, one workgroup per block); flags[0] is set when a block holds 2^31 - 8 or more.
+__global__ __launch_bounds__(256) void k_panel_bcount(int64_t n, const int64_t* __restrict__ rp,
+                                                      const int32_t* __restrict__ col, int32_t* __restrict__ bcount,
+                                                      int32_t* __restrict__ padded, int* __restrict__ flags) {
+  __shared__ int64_t sh[4];
+  const int64_t row = (int64_t)blockIdx.x * PANEL_RB + threadIdx.x;
+  int64_t len = 0;
+  if (row < n) {
+    const int64_t b = rp[row], e = rp[row + 1];
+    const int64_t d = lower_col(col, b, e, row);
+    len = (e - b) - ((d < e && col[d] == row) ? 1 : 0);
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) len += __shfl_xor(len, o);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = len;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int64_t tot = sh[0] + sh[1] + sh[2] + sh[3];
+    if (tot >= ((int64_t)1 << 31) - 8) atomicOr(&flags[0], 1);
+    bcount[blockIdx.x] = (int32_t)min<int64_t>(tot, ((int64_t)1 << 31) - 8);
+    padded[blockIdx.x] = (bcount[blockIdx.x] + 7) & ~7;
   }
 }
 
-// relative offsets per block from the global exclusive scan of the counts
-__global__ void k_panel_offsets(int nblocks, int64_t per_block, const int64_t* __restrict__ gscan,
-                                int32_t* __restrict__ off, int64_t* __restrict__ bstart) {
-  const int64_t blk = blockIdx.y;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i > per_block) return;
-  const int64_t base = gscan[blk * per_block];
-  off[blk * (per_block + 1) + i] = (int32_t)(gscan[blk * per_block + i] - base);
-  if (i == 0) {
-    bstart[blk] = base;
-    if (blk + 1 == nblocks) bstart[nblocks] = gscan[(int64_t)nblocks * per_block];
-  }
-}
-
+// Writes the stream of one block (one thread per row): the panels that hold entries of the
+// block are visited in order (the next one is the smallest panel among the rows' next
+// entries); in each, the rows' runs are placed row by row after a block-wide prefix sum of
+// their lengths.  The diagonal goes to dg instead.
 template <typename VT>
-__global__ void k_panel_fill(int64_t n, const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
-                             const VT* __restrict__ val, int RB, int P, int PW, const int32_t* __restrict__ off,
-                             const int64_t* __restrict__ bstart, uint16_t* __restrict__ pcol,
-                             VT* __restrict__ pval) {
-  const int lane = threadIdx.x & 63;
-  const int64_t row = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  if (row >= n) return;
-  const int64_t b = rp[row], e = rp[row + 1];
-  const int64_t blk = row / RB;
-  const int rl = (int)(row - blk * RB);
-  const int64_t per = (int64_t)P * RB + 1;
-  for (int64_t t = b + lane; t < e; t += 64) {
-    const int c = col[t];
-    const int p = c / PW;
-    const int64_t st = lower_col(col, b, t, (int64_t)p * PW);
-    const int64_t dst = bstart[blk] + off[blk * per + (int64_t)p * RB + rl] + (t - st);
-    pcol[dst] = (uint16_t)(c - p * PW);
-    pval[dst] = val[t];
+__global__ __launch_bounds__(256) void k_panel_fill(int64_t n, const int64_t* __restrict__ rp,
+                                                    const int32_t* __restrict__ col, const VT* __restrict__ val,
+                                                    int PW, const int64_t* __restrict__ bstart,
+                                                    uint32_t* __restrict__ ent, VT* __restrict__ pval,
+                                                    double* __restrict__ dg) {
+  __shared__ int sh[4];
+  const int r = threadIdx.x;
+  const int64_t row = (int64_t)blockIdx.x * PANEL_RB + r;
+  int64_t q = 0, e = 0;
+  if (row < n) {
+    q = rp[row];
+    e = rp[row + 1];
+  }
+  int64_t base = bstart[blockIdx.x];
+  constexpr int NONE = 0x7fffffff;
+  for (;;) {
+    const int mine = q < e ? col[q] / PW : NONE;
+    const int p = block_min(mine, sh);
+    if (p == NONE) break;
+    int len = 0;
+    int64_t q1 = q;
+    while (q1 < e && col[q1] / PW == p) {
+      if (col[q1] != row) ++len;
+      ++q1;
+    }
+    int tot = 0;
+    const int off = block_scan_excl(len, sh, tot);
+    int64_t dst = base + off;
+    for (; q < q1; ++q) {
+      const int c = col[q];
+      if (c == row) {
+        if (dg) dg[row] = (double)val[q];
+      } else {
+        ent[dst] = (uint32_t)c | ((uint32_t)r << 24);
+        pval[dst] = val[q];
+        ++dst;
+      }
+    }
+    base += tot;
   }
 }
 
@@ -664,54 +782,51 @@ void extract_diag(const DevCSR& H, double* diag, hipStream_t s) {
   SPPC_LAUNCH_CHECK();
 }
 
-void build_panel(const DevCSR& H, int PW, int RB, PanelH& out, hipStream_t s) {
-  if (PW < 1 || PW > 65536 || RB < 64 || RB % 64 != 0) throw Error(1, "panel: bad width or block size");
+void build_panel(const DevCSR& H, int PW, PanelH& out, hipStream_t s) {
   const int64_t n = H.n;
+  if (PW < 1 || PW > 65536) throw Error(1, "panel: bad width");
+  if (n < 1 || n >= ((int64_t)1 << 24)) throw Error(1, "panel: n must be in [1, 2^24)");
   out.n = n;
-  out.RB = RB;
+  out.RB = PANEL_RB;
   out.PW = PW;
   out.P = (int)cdiv(n, PW);
-  out.nblocks = (int)cdiv(n, RB);
-  const int64_t per = (int64_t)out.P * RB;
-  const int64_t total = per * out.nblocks;
-  if (total >= ((int64_t)1 << 31)) throw Error(1, "panel: too many (row, panel) pairs");
-  int32_t* cnt = nullptr;
-  int64_t *gscan = nullptr, *bsum = nullptr;
-  auto cleanup = [&]() { hipFree(cnt); hipFree(gscan); hipFree(bsum); };
+  out.nblocks = (int)cdiv(n, PANEL_RB);
+  int32_t* padded = nullptr;
+  int64_t* bsum = nullptr;
+  int* flags = nullptr;
+  auto cleanup = [&]() { (void)hipFree(padded); (void)hipFree(bsum); (void)hipFree(flags); };
   try {
-    SPPC_HIP(hipMalloc(&cnt, sizeof(int32_t) * total));
-    SPPC_HIP(hipMalloc(&gscan, sizeof(int64_t) * (total + 1)));
-    SPPC_HIP(hipMalloc(&bsum, sizeof(int64_t) * (cdiv(total, SCAN_BLOCK) + 1)));
-    SPPC_HIP(hipMemsetAsync(cnt, 0, sizeof(int32_t) * total, s));
-    const int64_t grid_w = cdiv(n, 4);
-    k_panel_count<<<grid_w, 256, 0, s>>>(n, H.rp, H.col, RB, out.P, PW, cnt);
-    scan_exclusive_impl(total, cnt, gscan, bsum, s);
-    SPPC_HIP(hipMalloc(&out.off, sizeof(int32_t) * (per + 1) * out.nblocks));
-    SPPC_HIP(hipMalloc(&out.bstart, sizeof(int64_t) * (out.nblocks + 1)));
-    // a block holds fewer than 2^31 entries: RB rows of at most n columns each
-    if ((int64_t)RB * n >= ((int64_t)1 << 31)) {
-      int64_t big = 0;
-      // checked after the scan: the largest block
-      std::vector<int64_t> hs(out.nblocks + 1);
-      SPPC_HIP(hipStreamSynchronize(s));
-      for (int q = 0; q <= out.nblocks; ++q)
-        SPPC_HIP(hipMemcpy(&hs[q], gscan + (int64_t)q * per, sizeof(int64_t), hipMemcpyDeviceToHost));
-      for (int q = 0; q < out.nblocks; ++q) big = std::max(big, hs[q + 1] - hs[q]);
-      if (big >= ((int64_t)1 << 31)) throw Error(1, "panel: block with 2^31 entries");
-    }
-    dim3 g2((unsigned)cdiv(per + 1, 256), (unsigned)out.nblocks);
-    k_panel_offsets<<<g2, 256, 0, s>>>(out.nblocks, per, gscan, out.off, out.bstart);
-    const int64_t nnz = H.nnz;
-    SPPC_HIP(hipMalloc(&out.col, sizeof(uint16_t) * (nnz > 0 ? nnz : 1)));
+    const int nb = out.nblocks;
+    SPPC_HIP(hipMalloc(&padded, sizeof(int32_t) * nb));
+    SPPC_HIP(hipMalloc(&bsum, sizeof(int64_t) * (cdiv(nb, SCAN_BLOCK) + 1)));
+    SPPC_HIP(hipMalloc(&out.bcount, sizeof(int32_t) * nb));
+    SPPC_HIP(hipMalloc(&out.bstart, sizeof(int64_t) * (nb + 1)));
+    SPPC_HIP(hipMalloc(&out.dg, sizeof(double) * n));
+    SPPC_HIP(hipMalloc(&out.xpad, sizeof(double) * 16 * n));
+    SPPC_HIP(hipMemsetAsync(out.dg, 0, sizeof(double) * n, s));
+    SPPC_HIP(hipMalloc(&flags, sizeof(int)));
+    SPPC_HIP(hipMemsetAsync(flags, 0, sizeof(int), s));
+    k_panel_bcount<<<nb, 256, 0, s>>>(n, H.rp, H.col, out.bcount, padded, flags);
+    scan_exclusive_impl(nb, padded, out.bstart, bsum, s);
+    int64_t total = 0;
+    int flag = 0;
+    SPPC_HIP(hipMemcpyAsync(&total, out.bstart + nb, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    SPPC_HIP(hipMemcpyAsync(&flag, flags, sizeof(int), hipMemcpyDeviceToHost, s));
+    SPPC_HIP(hipStreamSynchronize(s));
+    if (flag) throw Error(1, "panel: a block of rows holds 2^31 entries or more");
+    const int64_t cap = std::max<int64_t>(total, 8);
+    SPPC_HIP(hipMalloc(&out.ent, sizeof(uint32_t) * cap));
+    SPPC_HIP(hipMemsetAsync(out.ent, 0, sizeof(uint32_t) * cap, s));  // padding: column 0, row 0
     if (H.val64) {
-      SPPC_HIP(hipMalloc(&out.val64, sizeof(double) * (nnz > 0 ? nnz : 1)));
-      k_panel_fill<double><<<grid_w, 256, 0, s>>>(n, H.rp, H.col, H.val64, RB, out.P, PW, out.off, out.bstart,
-                                                   out.col, out.val64);
+      SPPC_HIP(hipMalloc(&out.val64, sizeof(double) * cap));
+      SPPC_HIP(hipMemsetAsync(out.val64, 0, sizeof(double) * cap, s));
+      k_panel_fill<double><<<nb, 256, 0, s>>>(n, H.rp, H.col, H.val64, PW, out.bstart, out.ent, out.val64, out.dg);
     }
     if (H.val32) {
-      SPPC_HIP(hipMalloc(&out.val32, sizeof(float) * (nnz > 0 ? nnz : 1)));
-      k_panel_fill<float><<<grid_w, 256, 0, s>>>(n, H.rp, H.col, H.val32, RB, out.P, PW, out.off, out.bstart,
-                                                 out.col, out.val32);
+      SPPC_HIP(hipMalloc(&out.val32, sizeof(float) * cap));
+      SPPC_HIP(hipMemsetAsync(out.val32, 0, sizeof(float) * cap, s));
+      k_panel_fill<float><<<nb, 256, 0, s>>>(n, H.rp, H.col, H.val32, PW, out.bstart, out.ent, out.val32,
+                                             H.val64 ? nullptr : out.dg);
     }
     SPPC_LAUNCH_CHECK();
     SPPC_HIP(hipStreamSynchronize(s));
@@ -728,11 +843,13 @@ void scan_exclusive(int64_t n, const int32_t* a, int64_t* out, int64_t* bsum, hi
 }
 
 void release_panel(PanelH& p) {
-  (void)hipFree(p.off);
   (void)hipFree(p.bstart);
-  (void)hipFree(p.col);
+  (void)hipFree(p.bcount);
+  (void)hipFree(p.ent);
   (void)hipFree(p.val32);
   (void)hipFree(p.val64);
+  (void)hipFree(p.dg);
+  (void)hipFree(p.xpad);
   p = PanelH{};
 }
 
@@ -756,7 +873,10 @@ void spmm_f32(const DevCSR& H, const float* X, int64_t ldx, double* Y, int64_t l
   if (!H.val32) throw Error(1, "spmm_f32: no float32 values");
   if (diag && !X64) throw Error(1, "spmm_f32: the float64 diagonal term needs float64 X");
   if (H.panel && !shift && b >= 1 && b <= 16 && H.n > 0) {
-    launch_spmm_panel<float, float>(*H.panel, H.panel->val32, X, ldx, Y, ldy, b, s, diag, X64, ldx64);
+    // the panel stream holds the diagonal apart: diag * X64 in float64 when given, else the
+    // float32 product as for the other entries
+    launch_spmm_panel<float, float>(*H.panel, H.panel->val32, X, ldx, Y, ldy, b, s, diag ? X64 : nullptr,
+                                    ldx64);
     return;
   }
   launch_spmm<float, float>(H, H.val32, X, ldx, Y, ldy, b, shift, s, 0.0, 0.0, 0.0, nullptr, 0, diag, X64, ldx64);

@@ -14,7 +14,7 @@ and the Jacobi-Davidson limit psi / (psi^T x) - x lies mostly inside the basis.)
 Optimisation: Adam on the float32 master weights with bfloat16-rounded copies in the forward
 pass (sppc_mpnn_train_step: forward, backward and update all run in the library's kernels).
 
-    python -m paper_2407_08901_amd.mpnn_train [--out weights.json] [--epochs 30]
+    python -m paper_2407_08901_amd.mpnn_train [--shape L3|L4] [--out weights.json] [--epochs 30]
 """
 from __future__ import annotations
 
@@ -30,7 +30,8 @@ import torch
 import paper_2407_08901_amd as P
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-DEFAULT_WEIGHTS = os.path.join(HERE, "mpnn_weights.json")
+DEFAULT_WEIGHTS = os.path.join(HERE, "mpnn_weights.json")          # three-level training shape
+WEIGHTS_L4 = os.path.join(HERE, "mpnn_weights_L4.json")           # four-level training shape
 FORMAT = "sppc-mpnn-v1"
 
 
@@ -126,6 +127,12 @@ def load(path=DEFAULT_WEIGHTS) -> np.ndarray:
     return w
 
 
+def load_for_levels(n_levels: int) -> np.ndarray:
+    """Weights trained on matrices with the same number of levels (the level feature is
+    level / (L - 1), so its meaning depends on L): four-level weights for L >= 4."""
+    return load(WEIGHTS_L4 if n_levels >= 4 else DEFAULT_WEIGHTS)
+
+
 def main():
     import levelgen
     ap = argparse.ArgumentParser()
@@ -144,7 +151,9 @@ def main():
     w, hist = train(data, epochs=args.epochs, lr=args.lr, log=lambda m: print(m, flush=True))
     t2 = time.time()
     nsamp = sum(g["X"].shape[1] for d in data for g in d["groups"])
-    save(w, args.out, {"train_seeds": list(seeds), "shape": args.shape, "samples": nsamp,
+    cmd = "python -m paper_2407_08901_amd.mpnn_train --shape %s --epochs %d --lr %g --nseeds %d" % (
+        args.shape, args.epochs, args.lr, args.nseeds)
+    save(w, args.out, {"command": cmd, "train_seeds": list(seeds), "shape": args.shape, "samples": nsamp,
                        "epochs": args.epochs, "lr": args.lr, "loss_history": hist,
                        "data_s": round(t1 - t0, 2), "train_s": round(t2 - t1, 2)})
     print(json.dumps({"samples": nsamp, "final_loss": hist[-1], "first_loss": hist[0], "data_s": t1 - t0,

@@ -43,8 +43,8 @@ def test_small_space_correction_matches_reference(P, mixed):
     for a, i in enumerate(act):
         ref = oracle.small_space_correction(H, n0, theta[i], R[:, i], Z[:, i])
         err = np.max(np.abs(T[:, a] - ref)) / np.max(np.abs(ref))
-        # float64: the small solve to 1e-13; mixed: float32 products inside the solve
-        assert err < (1e-9 if not mixed else 1e-5), (i, err)
+        # the small solve to 1e-13, with float64 products in both precisions
+        assert err < 1e-9, (i, err)
     P.sppc_destroy(ctx)
 
 

@@ -111,18 +111,24 @@ def test_panel_spmm_f32_products_accumulated_in_f64():
         assert np.max(np.abs(Y - ref) / scale) < 2.0 ** -24 * 1.01, b
 
 
-def test_panel_solve_matches_csr_solve():
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_panel_solve_matches_csr_solve(prec):
     A = _panel_matrix()
-    print("case panel solve n=%d" % A.n, flush=True)
+    print("case panel solve %s n=%d" % (prec, A.n), flush=True)
+    precision = P.SPPC_PREC_MIXED if prec == "mixed" else P.SPPC_PREC_FP64
     res = []
     for pw in (0, 4096):
-        ctx = _ctx(A, 1, 4, panel_width=pw)
+        ctx = _ctx(A, 1, 4, panel_width=pw, precision=precision)
         ev, Z, rrn, st, status = P.sppc_solve(ctx)
         P.sppc_destroy(ctx)
         assert status == P.SPPC_OK
+        assert max(rrn) <= 1e-6
         res.append((np.array(ev), st))
-    assert np.max(np.abs(res[0][0] - res[1][0]) / np.abs(res[0][0])) < 1e-12
-    assert res[0][1]["iterations"] == res[1][1]["iterations"]
+    # the float32 sums of the mixed form differ in order between the two layouts; the float64
+    # refinement brings both to the same eigenpairs
+    assert np.max(np.abs(res[0][0] - res[1][0]) / np.abs(res[0][0])) < (1e-12 if prec == "fp64" else 1e-10)
+    if prec == "fp64":
+        assert res[0][1]["iterations"] == res[1][1]["iterations"]
 
 
 # ---------------------------------------------------------------- zeroth order
