@@ -333,7 +333,6 @@ void zeroth_order(sppc_ctx* c) {
   unit_block(n0, nb, c->idx, c->Psi, nb, s);
   ortho_append(c, sb, c->Psi, nb, op, -1);
   const double tol = c->o.h0_tol;
-  const int deg = 24;
   int it = 0;
   for (;; ++it) {
     const int nw = sb.m;
@@ -349,6 +348,10 @@ void zeroth_order(sppc_ctx* c) {
     const double e = 0.5 * (bb - a), cc = 0.5 * (bb + a);
     double sigma = e / (a0 - cc);
     const double tau = 2.0 / sigma;
+    // degree: the lowest Ritz value grows by T_deg(y0) against the damped interval; keep that
+    // below e^25 (~7e10) so the block keeps the accuracy of its slowest wanted directions
+    const double y0 = std::max(1.0 + 1e-12, (cc - a0) / e);
+    const int deg = std::max(12, std::min(40, (int)(25.0 / std::acosh(y0))));
     double* buf[4] = {c->Z, c->Psi, c->R, c->HZ};
     int i0 = 0, i1 = 1;  // Y_{j-1}, Y_j
     // Y_1 = sigma/e (H - cc) Y_0  (Z holds the Ritz vectors, ld nw)

@@ -140,14 +140,15 @@ __global__ __launch_bounds__(EIG_THREADS) void k_sym_eig(int m, int nw, const do
     const int ld = j >= o ? EIG_LDS_M : m;
     const int off = j >= o ? o : 0;
     const int len = m - 1 - j;
-    // row j, columns j+1.. == column j below the diagonal
+    // row j, columns j+1.. == column j below the diagonal.  Wave 0 forms the Householder vector
+    // alone (no block-wide reduction), the other waves wait at the barrier.
     const double* xr = base + (int64_t)(j - off) * ld + (j + 1 - off);
-    double part = 0.0;
-    for (int i = 1 + t; i < len; i += EIG_THREADS) part += xr[i] * xr[i];
-    const double sigma = block_sum(part, red);
-    if (t == 0) {
+    if (t < 64) {
+      double part = 0.0;
+      for (int i = 1 + t; i < len; i += 64) part += xr[i] * xr[i];
+      for (int o2 = 32; o2 > 0; o2 >>= 1) part += __shfl_xor(part, o2);
+      const double sigma = part;
       const double alpha = xr[0];
-      d[j] = base[(int64_t)(j - off) * ld + (j - off)];
       double b = 0.0, v0 = 1.0, ej = alpha;
       if (sigma > 0.0) {
         const double mu = sqrt(alpha * alpha + sigma);
@@ -155,15 +156,16 @@ __global__ __launch_bounds__(EIG_THREADS) void k_sym_eig(int m, int nw, const do
         b = 2.0 * v0 * v0 / (sigma + v0 * v0);
         ej = mu;
       }
-      sc[0] = b;
-      sc[1] = v0;
-      e[j] = ej;
-      beta[j] = b;
+      if (t == 0) {
+        d[j] = base[(int64_t)(j - off) * ld + (j - off)];
+        e[j] = ej;
+        beta[j] = b;
+        sc[0] = b;
+      }
+      for (int i = t; i < len; i += 64) vsh[i] = i == 0 ? 1.0 : (b == 0.0 ? 0.0 : xr[i] / v0);
     }
     __syncthreads();
-    const double b = sc[0], v0 = sc[1];
-    for (int i = t; i < len; i += EIG_THREADS) vsh[i] = i == 0 ? 1.0 : (b == 0.0 ? 0.0 : xr[i] / v0);
-    __syncthreads();
+    const double b = sc[0];
     // keep v for the back-transformation in row j (no longer needed otherwise)
     for (int i = t; i < len; i += EIG_THREADS) base[(int64_t)(j - off) * ld + (j + 1 - off) + i] = vsh[i];
     if (b != 0.0) {
@@ -184,14 +186,18 @@ __global__ __launch_bounds__(EIG_THREADS) void k_sym_eig(int m, int nw, const do
         psh[grp][i] = (s0 + s1) + (s2 + s3);
       }
       __syncthreads();
-      double kp = 0.0;
-      for (int i = t; i < len; i += EIG_THREADS) {
-        const double pi = b * (psh[0][i] + psh[1][i] + psh[2][i] + psh[3][i]);
-        wsh[i] = pi;
-        kp += pi * vsh[i];
+      // w = p - (b/2)(v^T p) v, by wave 0
+      if (t < 64) {
+        double kp = 0.0;
+        for (int i = t; i < len; i += 64) {
+          const double pi = b * (psh[0][i] + psh[1][i] + psh[2][i] + psh[3][i]);
+          wsh[i] = pi;
+          kp += pi * vsh[i];
+        }
+        for (int o2 = 32; o2 > 0; o2 >>= 1) kp += __shfl_xor(kp, o2);
+        const double K = 0.5 * b * kp;
+        for (int i = t; i < len; i += 64) wsh[i] -= K * vsh[i];
       }
-      const double K = 0.5 * b * block_sum(kp, red);
-      for (int i = t; i < len; i += EIG_THREADS) wsh[i] -= K * vsh[i];
       __syncthreads();
       for (int64_t x = t; x < (int64_t)len * len; x += EIG_THREADS) {
         const int l = (int)(x / len), i = (int)(x % len);
@@ -216,7 +222,23 @@ __global__ __launch_bounds__(EIG_THREADS) void k_sym_eig(int m, int nw, const do
   }
   __syncthreads();
   for (int i = t; i < m; i += EIG_THREADS) e2[i] = e[i] * e[i];
+  // the Householder vectors held in LDS (rows j >= o) move to A, so that LDS can hold the
+  // inverse-iteration work arrays
+  for (int j = o; j + 2 < m; ++j) {
+    const int len = m - 1 - j;
+    for (int i = t; i < len; i += EIG_THREADS)
+      A[(int64_t)j * m + j + 1 + i] = Alds[(int64_t)(j - o) * EIG_LDS_M + (j + 1 - o) + i];
+  }
+  o = m;
   __syncthreads();
+  if ((int64_t)nw * m * 41 <= (int64_t)sizeof(Alds)) {
+    Y = Alds;
+    u0 = Y + (int64_t)nw * m;
+    u1 = u0 + (int64_t)nw * m;
+    u2 = u1 + (int64_t)nw * m;
+    lm = u2 + (int64_t)nw * m;
+    piv = (unsigned char*)(lm + (int64_t)nw * m);
+  }
 
   // ---- eigenvalues by bisection (one thread per wanted eigenvalue); d, e, e2 copied to LDS
   double* dl = psh[0];

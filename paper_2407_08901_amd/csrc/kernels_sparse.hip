@@ -15,6 +15,10 @@ namespace sppc {
 
 namespace {
 
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+
 // -------------------------------------------------------------------------- setup
 
 template <typename VT>
@@ -141,21 +145,36 @@ __global__ void k_fill(int64_t n, const int64_t* __restrict__ up_rp, const int32
 }
 
 // The mirrored entries of a row arrive in arbitrary order; place each at its rank
-// (column indices in a row are unique), which is deterministic.
-__global__ void k_sort_lower(int64_t n, const int64_t* __restrict__ lower_rp,
-                             const int64_t* __restrict__ full_rp, const int32_t* __restrict__ tmp_col,
-                             const double* __restrict__ tmp_val, int32_t* __restrict__ full_col,
-                             double* __restrict__ full_v64, float* __restrict__ full_v32) {
-  const int lane = threadIdx.x & 63;
-  const int64_t row = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  if (row >= n) return;
-  const int64_t b = lower_rp[row], e = lower_rp[row + 1];
+// (column indices in a row are unique), which is deterministic.  One wave per row; a row of up to
+// SORT_CAP mirrored entries is staged in LDS, so the rank loop reads broadcast LDS words.
+constexpr int SORT_CAP = 1024;
+
+__global__ __launch_bounds__(256) void k_sort_lower(int64_t n, const int64_t* __restrict__ lower_rp,
+                                                    const int64_t* __restrict__ full_rp,
+                                                    const int32_t* __restrict__ tmp_col,
+                                                    const double* __restrict__ tmp_val,
+                                                    int32_t* __restrict__ full_col, double* __restrict__ full_v64,
+                                                    float* __restrict__ full_v32) {
+  __shared__ int32_t keys[4][SORT_CAP];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t row = (int64_t)blockIdx.x * 4 + wv;
+  const int64_t b = row < n ? lower_rp[row] : 0, e = row < n ? lower_rp[row + 1] : 0;
   const int64_t L = e - b;
+  const bool staged = L <= SORT_CAP;
+  if (staged)
+    for (int64_t t = lane; t < L; t += 64) keys[wv][t] = tmp_col[b + t];
+  __syncthreads();  // every thread of the block reaches this (no early return)
+  if (row >= n) return;
   const int64_t dst = full_rp[row];
   for (int64_t t = lane; t < L; t += 64) {
     const int32_t key = tmp_col[b + t];
     int64_t rank = 0;
-    for (int64_t f = 0; f < L; ++f) rank += tmp_col[b + f] < key;
+    if (staged) {
+      const int32_t* kw = keys[wv];
+      for (int f = 0; f < (int)L; ++f) rank += kw[f] < key;
+    } else {
+      for (int64_t f = 0; f < L; ++f) rank += tmp_col[b + f] < key;
+    }
     full_col[dst + rank] = key;
     const double v = tmp_val[b + t];
     if (full_v64) full_v64[dst + rank] = v;
@@ -250,6 +269,67 @@ __global__ __launch_bounds__(256) void k_spmm(int64_t n, const int64_t* __restri
   }
 }
 
+// Wide blocks of float64 X (B = 16 or 32; b and ld even, X 16-byte aligned): groups of B/2
+// lanes take one nonzero each and read two columns per lane (16-byte loads), so a wave holds
+// 128/B nonzeros per step, twice as many as k_spmm.  Same epilogues as k_spmm (no diagonal term).
+template <int B, typename VT>
+__global__ __launch_bounds__(256) void k_spmm_wide(int64_t n, const int64_t* __restrict__ rp,
+                                                   const int64_t* __restrict__ rend,
+                                                   const int32_t* __restrict__ col,
+                                                   const VT* __restrict__ val, const double* __restrict__ X,
+                                                   int64_t ldx, double* __restrict__ Y, int64_t ldy, int b,
+                                                   const double* __restrict__ shift, double ea, double ec,
+                                                   double eb, const double* __restrict__ Zo, int64_t ldz) {
+  constexpr int L = B / 2;   // lanes per nonzero
+  constexpr int G = 64 / L;  // nonzeros per step
+  const int lane = threadIdx.x & 63;
+  const int g = lane / L;
+  const int c = (lane % L) * 2;
+  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= n) return;
+  const int64_t beg = rp[row];
+  const int64_t end = rend ? rend[row] : rp[row + 1];
+  double a0 = 0.0, a1 = 0.0;
+  for (int64_t base = beg; base < end; base += 64) {
+    const int cnt = (int)min<int64_t>(64, end - base);
+    int32_t mc = 0;
+    VT mv = VT(0);
+    if (lane < cnt) {
+      mc = __builtin_nontemporal_load(&col[base + lane]);
+      mv = __builtin_nontemporal_load(&val[base + lane]);
+    }
+#pragma unroll 4
+    for (int s0 = 0; s0 < cnt; s0 += G) {
+      const int e = s0 + g;
+      const int32_t cc = __shfl(mc, e);
+      const VT vv = __shfl(mv, e);
+      if (e < cnt && c < b) {  // b even: c < b covers both columns
+        const f64x2 xv = *(const f64x2*)(X + (int64_t)cc * ldx + c);
+        a0 = fma((double)vv, xv.x, a0);
+        a1 = fma((double)vv, xv.y, a1);
+      }
+    }
+  }
+#pragma unroll
+  for (int o = L; o < 64; o <<= 1) {
+    a0 += __shfl_xor(a0, o);
+    a1 += __shfl_xor(a1, o);
+  }
+  if (g == 0) {
+    double acc[2] = {a0, a1};
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int cq = c + q;
+      if (cq < b) {
+        double y = acc[q];
+        if (shift) y -= shift[cq] * X[row * ldx + cq];
+        if (Zo) y = ea * (y - ec * X[row * ldx + cq]) + eb * Zo[row * ldz + cq];
+        Y[row * ldy + cq] = y;
+      }
+    }
+  }
+}
+
 template <typename VT, typename XT>
 void launch_spmm(const DevCSR& H, const VT* val, const XT* X, int64_t ldx, double* Y, int64_t ldy,
                  int b, const double* shift, hipStream_t s, double ea = 0.0, double ec = 0.0,
@@ -258,6 +338,18 @@ void launch_spmm(const DevCSR& H, const VT* val, const XT* X, int64_t ldx, doubl
   if (b < 1 || b > 32) throw Error(1, "spmm: block width must be 1..32");
   if (H.n == 0) return;
   const int64_t grid = cdiv(H.n, 4);
+  if constexpr (sizeof(XT) == 8) {
+    if (b > 8 && b % 2 == 0 && !dg && ldx % 2 == 0 && ((uintptr_t)X & 15) == 0) {
+      if (b <= 16)
+        k_spmm_wide<16, VT><<<grid, 256, 0, s>>>(H.n, H.rp, H.rend, H.col, val, X, ldx, Y, ldy, b, shift, ea, ec,
+                                                 eb, Zo, ldz);
+      else
+        k_spmm_wide<32, VT><<<grid, 256, 0, s>>>(H.n, H.rp, H.rend, H.col, val, X, ldx, Y, ldy, b, shift, ea, ec,
+                                                 eb, Zo, ldz);
+      SPPC_LAUNCH_CHECK();
+      return;
+    }
+  }
 #define SPPC_SPMM_CASE(BB)                                                                        \
   k_spmm<BB, VT, XT><<<grid, 256, 0, s>>>(H.n, H.rp, H.rend, H.col, val, X, ldx, Y, ldy, b, shift, ea, ec, \
                                           eb, Zo, ldz, dg, X64, ldx64);                                     \
@@ -314,9 +406,6 @@ __global__ void k_view_fill(int64_t n0, const int64_t* __restrict__ rp, const in
 // read from a copy with row stride B (16-byte aligned); the diagonal is not in the stream and is
 // added in float64 at the end: dg * X64 when X64 is given, else the product in the precision of
 // X.
-typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-typedef double f64x2 __attribute__((ext_vector_type(2)));
 
 template <typename VT> struct ValLoad;
 template <> struct ValLoad<float> {
@@ -525,38 +614,6 @@ __device__ inline int64_t lower_col(const int32_t* __restrict__ col, int64_t b, 
   return b;
 }
 
-// Block-wide (256 threads) sum and exclusive prefix sum; sh holds 4 values.
-__device__ inline int block_scan_excl(int v, int* sh, int& total) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  int inc = v;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const int u = __shfl_up(inc, o);
-    if (lane >= o) inc += u;
-  }
-  __syncthreads();  // sh is free (previous use finished)
-  if (lane == 63) sh[w] = inc;
-  __syncthreads();
-  int before = 0;
-  total = 0;
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    if (i < w) before += sh[i];
-    total += sh[i];
-  }
-  return before + inc - v;
-}
-
-__device__ inline int block_min(int v, int* sh) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
-  __syncthreads();
-  if (lane == 0) sh[w] = v;
-  __syncthreads();
-  return min(min(sh[0], sh[1]), min(sh[2], sh[3]));
-}
-
 // Off-diagonal entries of each block of PANEL_RB rows, padded to a multiple of 8 (one thread
 // per row, one workgroup per block); flags[0] is set when a block holds 2^31 - 8 or more.
 __global__ __launch_bounds__(256) void k_panel_bcount(int64_t n, const int64_t* __restrict__ rp,
@@ -582,49 +639,118 @@ __global__ __launch_bounds__(256) void k_panel_bcount(int64_t n, const int64_t* 
   }
 }
 
-// Writes the stream of one block (one thread per row): the panels that hold entries of the
-// block are visited in order (the next one is the smallest panel among the rows' next
-// entries); in each, the rows' runs are placed row by row after a block-wide prefix sum of
-// their lengths.  The diagonal goes to dg instead.
+// Writes the stream of one block (one workgroup of 16 waves per block; a wave takes every 16th
+// row, 64 consecutive entries at a time), in chunks of PANEL_PC panels: (1) the off-diagonal
+// entries of each (panel, row) of the chunk are counted in LDS, (2) a block-wide exclusive scan
+// in (panel, row) order gives each run's offset, (3) every entry goes to its run's offset plus
+// its index in the run (the run start comes from a ballot over the window, carried across
+// windows).  Each row keeps a cursor in LDS, so no row is searched.  The diagonal goes to dg
+// instead (when dg is given).
+constexpr int PANEL_PC = 32;
+constexpr int PANEL_FT = 1024;  // threads of the fill kernel
+
 template <typename VT>
-__global__ __launch_bounds__(256) void k_panel_fill(int64_t n, const int64_t* __restrict__ rp,
-                                                    const int32_t* __restrict__ col, const VT* __restrict__ val,
-                                                    int PW, const int64_t* __restrict__ bstart,
-                                                    uint32_t* __restrict__ ent, VT* __restrict__ pval,
-                                                    double* __restrict__ dg) {
-  __shared__ int sh[4];
-  const int r = threadIdx.x;
-  const int64_t row = (int64_t)blockIdx.x * PANEL_RB + r;
-  int64_t q = 0, e = 0;
-  if (row < n) {
-    q = rp[row];
-    e = rp[row + 1];
+__global__ __launch_bounds__(PANEL_FT) void k_panel_fill(int64_t n, const int64_t* __restrict__ rp,
+                                                         const int32_t* __restrict__ col,
+                                                         const VT* __restrict__ val, int PW, int P,
+                                                         const int64_t* __restrict__ bstart,
+                                                         uint32_t* __restrict__ ent, VT* __restrict__ pval,
+                                                         double* __restrict__ dg) {
+  constexpr int NWV = PANEL_FT / 64;
+  constexpr int PER = PANEL_PC * PANEL_RB / PANEL_FT;  // counters per thread in the scan
+  __shared__ int cnt[PANEL_PC * PANEL_RB];
+  __shared__ int64_t cur[PANEL_RB];   // next entry of each row
+  __shared__ int64_t dpos[PANEL_RB];  // position of the row's diagonal entry (or -1)
+  __shared__ int sh[NWV];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t row0 = (int64_t)blockIdx.x * PANEL_RB;
+  const int nr = (int)min<int64_t>(PANEL_RB, n - row0);
+  for (int r = threadIdx.x; r < PANEL_RB; r += PANEL_FT) {
+    cur[r] = r < nr ? rp[row0 + r] : 0;
+    if (r < nr) {
+      const int64_t b = rp[row0 + r], e = rp[row0 + r + 1];
+      const int64_t d = lower_col(col, b, e, row0 + r);
+      dpos[r] = (d < e && col[d] == row0 + r) ? d : -1;
+    }
   }
   int64_t base = bstart[blockIdx.x];
-  constexpr int NONE = 0x7fffffff;
-  for (;;) {
-    const int mine = q < e ? col[q] / PW : NONE;
-    const int p = block_min(mine, sh);
-    if (p == NONE) break;
-    int len = 0;
-    int64_t q1 = q;
-    while (q1 < e && col[q1] / PW == p) {
-      if (col[q1] != row) ++len;
-      ++q1;
-    }
-    int tot = 0;
-    const int off = block_scan_excl(len, sh, tot);
-    int64_t dst = base + off;
-    for (; q < q1; ++q) {
-      const int c = col[q];
-      if (c == row) {
-        if (dg) dg[row] = (double)val[q];
-      } else {
-        ent[dst] = (uint32_t)c | ((uint32_t)r << 24);
-        pval[dst] = val[q];
-        ++dst;
+  for (int p0 = 0; p0 < P; p0 += PANEL_PC) {
+    const int64_t c1 = min<int64_t>((int64_t)(p0 + PANEL_PC) * PW, n);
+    for (int i = threadIdx.x; i < PANEL_PC * PANEL_RB; i += PANEL_FT) cnt[i] = 0;
+    __syncthreads();
+    // (1) counts; the chunk of a row is [cur, first entry with column >= c1)
+    for (int r = w; r < nr; r += NWV) {
+      const int64_t row = row0 + r, e = rp[row + 1];
+      for (int64_t t0 = cur[r]; t0 < e; t0 += 64) {
+        const int64_t t = t0 + lane;
+        const int c = t < e ? col[t] : (int)n;
+        const bool in = c < c1;
+        if (in && c != row) atomicAdd(&cnt[(c / PW - p0) * PANEL_RB + r], 1);
+        if (__ballot(!in)) break;  // columns ascend: the chunk ends in this window
       }
     }
+    __syncthreads();
+    // (2) exclusive scan in (panel, row) order: thread i owns PER consecutive counters
+    int* mine = cnt + threadIdx.x * PER;
+    int loc = 0;
+    for (int q = 0; q < PER; ++q) loc += mine[q];
+    int inc = loc;
+    for (int o = 1; o < 64; o <<= 1) {
+      const int u = __shfl_up(inc, o);
+      if (lane >= o) inc += u;
+    }
+    if (lane == 63) sh[w] = inc;
+    __syncthreads();
+    int before = 0, tot = 0;
+    for (int i = 0; i < NWV; ++i) {
+      if (i < w) before += sh[i];
+      tot += sh[i];
+    }
+    int run = before + inc - loc;
+    for (int q = 0; q < PER; ++q) {
+      const int v = mine[q];
+      mine[q] = run;
+      run += v;
+    }
+    __syncthreads();
+    // (3) placement
+    for (int r = w; r < nr; r += NWV) {
+      const int64_t row = row0 + r, e = rp[row + 1];
+      const int64_t dp = dpos[r];
+      int64_t rs = cur[r];  // start of the run that continues into the next window
+      int pr = -1;          // its panel
+      int64_t t0 = cur[r];
+      for (; t0 < e; t0 += 64) {
+        const int64_t t = t0 + lane;
+        const int c = t < e ? col[t] : (int)n;
+        const bool in = c < c1;
+        const int p = in ? c / PW : 0x7fffffff;
+        const int pprev = __shfl_up(p, 1);
+        const bool start = in && (lane == 0 ? p != pr : p != pprev);
+        const unsigned long long m = __ballot(start);
+        const unsigned long long mm = m & (lane == 63 ? ~0ull : ((2ull << lane) - 1ull));
+        const int64_t st = mm ? t0 + (63 - __builtin_clzll(mm)) : rs;
+        if (in) {
+          if (c == row) {
+            if (dg) dg[row] = (double)val[t];
+          } else {
+            const int64_t idx = t - st - ((dp >= st && dp < t) ? 1 : 0);
+            const int64_t dst = base + cnt[(p - p0) * PANEL_RB + r] + idx;
+            ent[dst] = (uint32_t)c | ((uint32_t)r << 24);
+            pval[dst] = val[t];
+          }
+        }
+        const unsigned long long nin = __ballot(in);
+        if (nin != ~0ull) {  // the chunk ends in this window: next chunk starts at the first lane out
+          if (lane == 0) cur[r] = t0 + __builtin_popcountll(nin);
+          break;
+        }
+        rs = __shfl(st, 63);
+        pr = __shfl(p, 63);
+      }
+      if (t0 >= e && lane == 0) cur[r] = e;
+    }
+    __syncthreads();  // cnt and cur are rewritten by the next chunk
     base += tot;
   }
 }
@@ -820,13 +946,14 @@ void build_panel(const DevCSR& H, int PW, PanelH& out, hipStream_t s) {
     if (H.val64) {
       SPPC_HIP(hipMalloc(&out.val64, sizeof(double) * cap));
       SPPC_HIP(hipMemsetAsync(out.val64, 0, sizeof(double) * cap, s));
-      k_panel_fill<double><<<nb, 256, 0, s>>>(n, H.rp, H.col, H.val64, PW, out.bstart, out.ent, out.val64, out.dg);
+      k_panel_fill<double><<<nb, PANEL_FT, 0, s>>>(n, H.rp, H.col, H.val64, PW, out.P, out.bstart, out.ent,
+                                                    out.val64, out.dg);
     }
     if (H.val32) {
       SPPC_HIP(hipMalloc(&out.val32, sizeof(float) * cap));
       SPPC_HIP(hipMemsetAsync(out.val32, 0, sizeof(float) * cap, s));
-      k_panel_fill<float><<<nb, 256, 0, s>>>(n, H.rp, H.col, H.val32, PW, out.bstart, out.ent, out.val32,
-                                             H.val64 ? nullptr : out.dg);
+      k_panel_fill<float><<<nb, PANEL_FT, 0, s>>>(n, H.rp, H.col, H.val32, PW, out.P, out.bstart, out.ent,
+                                                   out.val32, H.val64 ? nullptr : out.dg);
     }
     SPPC_LAUNCH_CHECK();
     SPPC_HIP(hipStreamSynchronize(s));

@@ -29,7 +29,7 @@ def _H(A):
 
 
 # ---------------------------------------------------------------- block product
-@pytest.mark.parametrize("b", [1, 3, 4, 8, 16])
+@pytest.mark.parametrize("b", [1, 3, 4, 8, 10, 13, 16, 24, 32])
 def test_spmm_f64_matches_scipy(b):
     print("case spmm_f64 b=%d" % b, flush=True)
     A = levelgen.generate((300, 3000, 20000), 60, 77)      # n = 23300: many waves, ragged tail
