@@ -168,7 +168,44 @@ __global__ __launch_bounds__(EIG_THREADS) void k_sym_eig(int m, int nw, const do
     const double b = sc[0];
     // keep v for the back-transformation in row j (no longer needed otherwise)
     for (int i = t; i < len; i += EIG_THREADS) base[(int64_t)(j - off) * ld + (j + 1 - off) + i] = vsh[i];
-    if (b != 0.0) {
+    if (b != 0.0 && j >= o) {
+      // trailing block in LDS (len <= 128): thread (lg, i) owns column i and the rows l = lg mod 8,
+      // with v_i and w_i in registers; p_i in 8 partial sums
+      const int i = t & 127, lg = t >> 7;
+      double* pp = &psh[0][0];  // [8][128]
+      const double vi = i < len ? vsh[i] : 0.0;
+      double* ci = base + (int64_t)(j + 1 - off) * ld + (j + 1 - off) + i;
+      if (i < len) {
+        double s0 = 0.0, s1 = 0.0;
+        int l = lg;
+        for (; l + 8 < len; l += 16) {
+          s0 += ci[(int64_t)l * ld] * vsh[l];
+          s1 += ci[(int64_t)(l + 8) * ld] * vsh[l + 8];
+        }
+        if (l < len) s0 += ci[(int64_t)l * ld] * vsh[l];
+        pp[lg * 128 + i] = s0 + s1;
+      }
+      __syncthreads();
+      if (t < 64) {
+        double kp = 0.0;
+        for (int i2 = t; i2 < len; i2 += 64) {
+          double pi = 0.0;
+#pragma unroll
+          for (int g8 = 0; g8 < 8; ++g8) pi += pp[g8 * 128 + i2];
+          pi *= b;
+          wsh[i2] = pi;
+          kp += pi * vsh[i2];
+        }
+        for (int o2 = 32; o2 > 0; o2 >>= 1) kp += __shfl_xor(kp, o2);
+        const double K = 0.5 * b * kp;
+        for (int i2 = t; i2 < len; i2 += 64) wsh[i2] -= K * vsh[i2];
+      }
+      __syncthreads();
+      if (i < len) {
+        const double wi = wsh[i];
+        for (int l = lg; l < len; l += 8) ci[(int64_t)l * ld] -= vsh[l] * wi + wsh[l] * vi;
+      }
+    } else if (b != 0.0) {
       // p = b * A_tr v, A_tr = A[j+1.., j+1..]; 4 row groups x 256 columns
       const int grp = t >> 8, tl = t & 255;
       const int l0 = (len * grp) / 4, l1 = (len * (grp + 1)) / 4;
@@ -695,15 +732,16 @@ __global__ void k_colscale(int64_t n, int b, double* __restrict__ X, int64_t ldx
 __global__ void k_select_smallest(int64_t n, const double* __restrict__ d, int nsel, int* __restrict__ idx) {
   __shared__ double sv[1024];
   __shared__ int si[1024];
+  // pass q takes the smallest (value, index) pair above the one taken by pass q - 1
+  double pv = -INFINITY;
+  int pi = -1;
   for (int q = 0; q < nsel; ++q) {
     double best = INFINITY;
     int bi = 0x7fffffff;
     for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
-      bool used = false;
-      for (int u = 0; u < q; ++u) used |= (idx[u] == (int)i);
-      if (used) continue;
       const double v = d[i];
-      if (v < best || (v == best && (int)i < bi)) { best = v; bi = (int)i; }
+      const bool above = v > pv || (v == pv && (int)i > pi);
+      if (above && (v < best || (v == best && (int)i < bi))) { best = v; bi = (int)i; }
     }
     sv[threadIdx.x] = best;
     si[threadIdx.x] = bi;
@@ -720,6 +758,8 @@ __global__ void k_select_smallest(int64_t n, const double* __restrict__ d, int n
       __syncthreads();
     }
     if (threadIdx.x == 0) idx[q] = si[0];
+    pv = sv[0];
+    pi = si[0];
     __syncthreads();
   }
 }

@@ -115,13 +115,14 @@ __global__ void k_full_rowptr(int64_t n, const int64_t* __restrict__ lower_rp,
   if (i <= n) full_rp[i] = lower_rp[i] + up_rp[i];
 }
 
-template <typename VT>
+// TT: type of the staged mirrored values (float when only float32 values are kept)
+template <typename VT, typename TT>
 __global__ void k_fill(int64_t n, const int64_t* __restrict__ up_rp, const int32_t* __restrict__ up_col,
                        const VT* __restrict__ up_val, const int64_t* __restrict__ lower_rp,
                        const int64_t* __restrict__ full_rp, int32_t* __restrict__ fillc,
                        int32_t* __restrict__ full_col, double* __restrict__ full_v64,
                        float* __restrict__ full_v32, int32_t* __restrict__ tmp_col,
-                       double* __restrict__ tmp_val) {
+                       TT* __restrict__ tmp_val) {
   const int lane = threadIdx.x & 63;
   const int64_t row = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (row >= n) return;
@@ -139,7 +140,7 @@ __global__ void k_fill(int64_t n, const int64_t* __restrict__ up_rp, const int32
       const int32_t slot = atomicAdd(&fillc[c], 1);
       const int64_t q = lower_rp[c] + slot;
       tmp_col[q] = (int32_t)row;
-      tmp_val[q] = v;
+      tmp_val[q] = (TT)v;
     }
   }
 }
@@ -149,10 +150,11 @@ __global__ void k_fill(int64_t n, const int64_t* __restrict__ up_rp, const int32
 // SORT_CAP mirrored entries is staged in LDS, so the rank loop reads broadcast LDS words.
 constexpr int SORT_CAP = 1024;
 
+template <typename TT>
 __global__ __launch_bounds__(256) void k_sort_lower(int64_t n, const int64_t* __restrict__ lower_rp,
                                                     const int64_t* __restrict__ full_rp,
                                                     const int32_t* __restrict__ tmp_col,
-                                                    const double* __restrict__ tmp_val,
+                                                    const TT* __restrict__ tmp_val,
                                                     int32_t* __restrict__ full_col, double* __restrict__ full_v64,
                                                     float* __restrict__ full_v32) {
   __shared__ int32_t keys[4][SORT_CAP];
@@ -176,7 +178,7 @@ __global__ __launch_bounds__(256) void k_sort_lower(int64_t n, const int64_t* __
       for (int64_t f = 0; f < L; ++f) rank += tmp_col[b + f] < key;
     }
     full_col[dst + rank] = key;
-    const double v = tmp_val[b + t];
+    const double v = (double)tmp_val[b + t];
     if (full_v64) full_v64[dst + rank] = v;
     if (full_v32) full_v32[dst + rank] = (float)v;
   }
@@ -843,16 +845,29 @@ void build_full_csr(int64_t n, int64_t nnz_up, const int64_t* up_rp, const int32
     if (want64) SPPC_HIP(hipMalloc(&out.val64, sizeof(double) * (nnz > 0 ? nnz : 1)));
     if (want32) SPPC_HIP(hipMalloc(&out.val32, sizeof(float) * (nnz > 0 ? nnz : 1)));
     SPPC_HIP(hipMalloc(&tmp_col, sizeof(int32_t) * (nlow > 0 ? nlow : 1)));
-    SPPC_HIP(hipMalloc(&tmp_val, sizeof(double) * (nlow > 0 ? nlow : 1)));
+    // staged mirrored values: float32 suffice when only float32 values are kept
+    SPPC_HIP(hipMalloc(&tmp_val, (want64 ? sizeof(double) : sizeof(float)) * (nlow > 0 ? nlow : 1)));
     k_full_rowptr<<<cdiv(n + 1, 256), 256, 0, s>>>(n, lower_rp, up_rp, out.rp);
-    if (val_is_f32)
-      k_fill<float><<<grid_w, 256, 0, s>>>(n, up_rp, up_col, (const float*)up_val, lower_rp, out.rp, fillc,
-                                           out.col, out.val64, out.val32, tmp_col, tmp_val);
-    else
-      k_fill<double><<<grid_w, 256, 0, s>>>(n, up_rp, up_col, (const double*)up_val, lower_rp, out.rp,
-                                            fillc, out.col, out.val64, out.val32, tmp_col, tmp_val);
-    k_sort_lower<<<grid_w, 256, 0, s>>>(n, lower_rp, out.rp, tmp_col, tmp_val, out.col, out.val64,
-                                        out.val32);
+    if (want64) {
+      if (val_is_f32)
+        k_fill<float, double><<<grid_w, 256, 0, s>>>(n, up_rp, up_col, (const float*)up_val, lower_rp, out.rp,
+                                                     fillc, out.col, out.val64, out.val32, tmp_col, tmp_val);
+      else
+        k_fill<double, double><<<grid_w, 256, 0, s>>>(n, up_rp, up_col, (const double*)up_val, lower_rp, out.rp,
+                                                      fillc, out.col, out.val64, out.val32, tmp_col, tmp_val);
+      k_sort_lower<double><<<grid_w, 256, 0, s>>>(n, lower_rp, out.rp, tmp_col, tmp_val, out.col, out.val64,
+                                                  out.val32);
+    } else {
+      float* tv = (float*)tmp_val;
+      if (val_is_f32)
+        k_fill<float, float><<<grid_w, 256, 0, s>>>(n, up_rp, up_col, (const float*)up_val, lower_rp, out.rp,
+                                                    fillc, out.col, out.val64, out.val32, tmp_col, tv);
+      else
+        k_fill<double, float><<<grid_w, 256, 0, s>>>(n, up_rp, up_col, (const double*)up_val, lower_rp, out.rp,
+                                                     fillc, out.col, out.val64, out.val32, tmp_col, tv);
+      k_sort_lower<float><<<grid_w, 256, 0, s>>>(n, lower_rp, out.rp, tmp_col, tv, out.col, out.val64,
+                                                 out.val32);
+    }
     SPPC_LAUNCH_CHECK();
     SPPC_HIP(hipStreamSynchronize(s));
   } catch (...) {
