@@ -11,6 +11,7 @@ from .core import (  # noqa: F401
     Options,
     Result,
     symmetric_from_upper,
+    product_from_upper,
     small_space_matrix,
     zeroth_order,
     rs_corrections,

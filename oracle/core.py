@@ -60,6 +60,16 @@ def symmetric_from_upper(row_ptr, col, val, n) -> sp.csr_matrix:
     return H
 
 
+def product_from_upper(row_ptr, col, val, n, X) -> np.ndarray:
+    """Y = H X for the symmetric H given by its upper triangle (diagonal included): the block
+    product with H that Sec. IV.C counts as the cost unit.  Y = U X + U^T X - diag(U) X, in
+    float64, without forming the lower triangle."""
+    U = sp.csr_matrix((np.asarray(val, dtype=np.float64), np.asarray(col), np.asarray(row_ptr)),
+                      shape=(n, n))
+    X = np.asarray(X, dtype=np.float64)
+    return U @ X + U.T @ X - U.diagonal()[:, None] * X
+
+
 def small_space_matrix(H: sp.csr_matrix, n0: int) -> np.ndarray:
     """H0hat: the leading n0 x n0 block of H, dense (eq. split2)."""
     return H[:n0, :n0].toarray()

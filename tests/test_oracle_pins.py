@@ -283,3 +283,29 @@ def test_small_space_correction_is_the_diagonal_step_off_the_small_space():
     t = oracle.small_space_correction(H, n0, theta, r, z)
     ref = oracle.jacobi_correction(H.diagonal(), theta, r, z)
     assert np.allclose(t, ref, rtol=0, atol=1e-14 * np.abs(ref).max())
+
+
+def test_product_from_upper_matches_the_dense_symmetric_matrix():
+    # the block product from the upper triangle equals the product with the full symmetric matrix
+    # written out entry by entry (brute force on a small ragged case, diagonal entries present
+    # and absent)
+    rng = np.random.default_rng(11)
+    n = 37
+    rows, cols, vals = [], [], []
+    for i in range(n):
+        js = sorted(set([i] * (i % 3 != 0) + list(rng.integers(i, n, size=4))))
+        for j in js:
+            rows.append(i)
+            cols.append(j)
+            vals.append(rng.standard_normal())
+    rp = np.zeros(n + 1, dtype=np.int64)
+    for i in rows:
+        rp[i + 1] += 1
+    rp = np.cumsum(rp)
+    Hd = np.zeros((n, n))
+    for i, j, v in zip(rows, cols, vals):
+        Hd[i, j] = v
+        Hd[j, i] = v
+    X = rng.standard_normal((n, 5))
+    Y = oracle.product_from_upper(rp, np.array(cols), np.array(vals), n, X)
+    assert np.max(np.abs(Y - Hd @ X)) < 1e-13
