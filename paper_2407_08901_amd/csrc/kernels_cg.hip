@@ -53,9 +53,8 @@ struct CGArgs {
   const double* Ps;     // n0 x D
   const int64_t* rowb;  // [NB + 1] row bounds of the iteration blocks
   double* x;            // n0 x k
-  double* r[2];         // residuals by parity
-  double* w[2];         // A r by parity
-  double* sv[2];        // A p by parity
+  double* r0;           // n0 x k: the right-hand side, projected in place
+  double* G[2];         // by iteration parity: per row (r_j, w_j = A r_j, s_{j-1} = A p_{j-1}), 3k values
   double* p;
   double* part[2];      // NB x 2*CG_MAXK partial (r.r, w.r) by parity
   double* partP;        // nb2 x PW   (Ps^T y)
@@ -149,7 +148,9 @@ __global__ __launch_bounds__(1024) void k_cg_project(CGArgs a, double* Y, double
     if (start) {
       a.x[e] = 0.0;
       a.p[e] = 0.0;
-      a.sv[1][e] = 0.0;
+      const int64_t g = row * 3 * k + c;
+      a.G[0][g] = v;          // r_0
+      a.G[0][g + 2 * k] = 0.0;  // s_{-1}
     }
   }
 }
@@ -226,12 +227,14 @@ __global__ __launch_bounds__(NT) void k_cg_iter(CGArgs a, int j) {
   const int lane = t & 63, wv = t >> 6;
   const int g = lane / B, c = lane % B;
   const bool cok = c < k;
-  const double* __restrict__ rj = a.r[INIT ? 0 : par];
-  const double* __restrict__ wj = a.w[INIT ? 0 : par];
-  const double* __restrict__ sm = a.sv[INIT ? 1 : par ^ 1];
-  double* __restrict__ rn = a.r[INIT ? 0 : par ^ 1];
-  double* __restrict__ wn = a.w[INIT ? 0 : par ^ 1];
-  double* __restrict__ sj = a.sv[INIT ? 1 : par];
+  // the triple (r, w, s) of a row is contiguous, so a gathered row of the three is one segment
+  const int k3 = 3 * k;
+  const double* __restrict__ rj = a.G[INIT ? 0 : par];
+  const double* __restrict__ wj = rj + k;
+  const double* __restrict__ sm = rj + 2 * k;
+  double* __restrict__ rn = a.G[INIT ? 0 : par ^ 1];
+  double* __restrict__ wn = rn + k;
+  double* __restrict__ sj = rn + 2 * k;
   const VT* __restrict__ val = sizeof(VT) == 8 ? (const VT*)a.v64 : (const VT*)a.v32;
   // own-row phase mapping: column oc, row slots os and os + NT/16 of each chunk
   const int oc = t % CG_MAXK, os = t / CG_MAXK;
@@ -252,11 +255,11 @@ __global__ __launch_bounds__(NT) void k_cg_iter(CGArgs a, int j) {
     for (int u = 0; u < 2; ++u) {
       const int rl = os + OS * u;
       if (oc < k && rl < nr) {
-        const int64_t o = (c0 + rl) * k + oc;
-        orj[u] = rj[o];
+        const int64_t og = (c0 + rl) * k3 + oc;
+        orj[u] = rj[og];
         if (!INIT) {
-          owj[u] = wj[o];
-          osm[u] = sm[o];
+          owj[u] = wj[og];
+          osm[u] = sm[og];
         }
       }
     }
@@ -351,12 +354,12 @@ __global__ __launch_bounds__(NT) void k_cg_iter(CGArgs a, int j) {
         const int cl2 = __shfl(mc2, src);
         double v1 = 0.0, v2 = 0.0;
         if (win + src < ne && cok) {
-          const int64_t o = (int64_t)cl1 * k + c;
-          v1 = INIT ? rj[o] : rj[o] - alpha * (wj[o] + beta * sm[o]);
+          const int64_t og = (int64_t)cl1 * k3 + c;
+          v1 = INIT ? rj[og] : rj[og] - alpha * (wj[og] + beta * sm[og]);
         }
         if (win2 + src < ne && cok) {
-          const int64_t o = (int64_t)cl2 * k + c;
-          v2 = INIT ? rj[o] : rj[o] - alpha * (wj[o] + beta * sm[o]);
+          const int64_t og = (int64_t)cl2 * k3 + c;
+          v2 = INIT ? rj[og] : rj[og] - alpha * (wj[og] + beta * sm[og]);
         }
         xv1[q] = v1;
         xv2[q] = v2;
@@ -371,6 +374,7 @@ __global__ __launch_bounds__(NT) void k_cg_iter(CGArgs a, int j) {
         const int rl = os + OS * u;
         if (rl < nr) {
           const int64_t o = (c0 + rl) * k + oc;
+          const int64_t og = (c0 + rl) * k3 + oc;
           double rnew;
           if (INIT) {
             rnew = orj[u];
@@ -378,13 +382,13 @@ __global__ __launch_bounds__(NT) void k_cg_iter(CGArgs a, int j) {
             const double pv = orj[u] + obe * a.p[o];
             const double sv = owj[u] + obe * osm[u];
             a.p[o] = pv;
-            sj[o] = sv;
+            sj[og] = sv;
             a.x[o] = fma(oal, pv, a.x[o]);
             rnew = orj[u] - oal * sv;
-            rn[o] = rnew;
+            rn[og] = rnew;
           }
           const double wv2 = acc_s[rl * CG_MAXK + oc] - osh * rnew;
-          wn[o] = wv2;
+          wn[og] = wv2;
           sg = fma(rnew, rnew, sg);
           sd = fma(wv2, rnew, sd);
         }
@@ -469,8 +473,7 @@ int cg_solve(const DevCSR& H0, int64_t n0, int k, int D, const double* shift, co
   double* vec = (double*)sc + SC_D;
   const int64_t vs = n0 * CG_MAXK;
   CGArgs a{n0, k, D, H0.rp, H0.rend, H0.col, H0.val64, H0.val32, shift, Ps, rowb, x,
-           {r, vec}, {vec + vs, vec + 2 * vs}, {vec + 3 * vs, vec + 4 * vs}, vec + 5 * vs,
-           {part0, part1}, partP, nb2, sc, tol * tol};
+           r, {vec, vec + 3 * vs}, vec + 6 * vs, {part0, part1}, partP, nb2, sc, tol * tol};
   // r <- P b (ccoef = Ps^T b), x = p = s_{-1} = 0
   k_cg_psT<<<nb2, 1024, 0, s>>>(a, r);
   k_cg_project<<<nb2, 1024, 0, s>>>(a, r, ccoef, 1);
