@@ -56,6 +56,7 @@ struct CGArgs {
   double* r0;           // n0 x k: the right-hand side, projected in place
   double* G[2];         // by iteration parity: per row (r_j, w_j = A r_j, s_{j-1} = A p_{j-1}), 3k values
   double* p;
+  double* z;            // n0 x k: A s (pipelined form only)
   double* part[2];      // NB x 2*CG_MAXK partial (r.r, w.r) by parity
   double* partP;        // nb2 x PW   (Ps^T y)
   int nb2;
@@ -151,6 +152,7 @@ __global__ __launch_bounds__(1024) void k_cg_project(CGArgs a, double* Y, double
       const int64_t g = row * 3 * k + c;
       a.G[0][g] = v;          // r_0
       a.G[0][g + 2 * k] = 0.0;  // s_{-1}
+      a.z[e] = 0.0;
     }
   }
 }
@@ -209,7 +211,7 @@ __device__ inline void cg_runs(int win, int ne, int g, int c, bool cok, int mr, 
   if (win + g * B < ne && cok) atomicAdd(&acc_s[cur_r * CG_MAXK + c], cur);
 }
 
-template <int B, typename VT, bool INIT>
+template <int B, typename VT, bool INIT, bool PIPE>
 __global__ __launch_bounds__(NT) void k_cg_iter(CGArgs a, int j) {
   const int t = threadIdx.x;
   const int k = a.k;
@@ -353,13 +355,14 @@ __global__ __launch_bounds__(NT) void k_cg_iter(CGArgs a, int j) {
         const int cl1 = __shfl(mc1, src);
         const int cl2 = __shfl(mc2, src);
         double v1 = 0.0, v2 = 0.0;
+        // pipelined form: the product is A w_j, which needs no scalar of this iteration
         if (win + src < ne && cok) {
           const int64_t og = (int64_t)cl1 * k3 + c;
-          v1 = INIT ? rj[og] : rj[og] - alpha * (wj[og] + beta * sm[og]);
+          v1 = INIT ? rj[og] : PIPE ? wj[og] : rj[og] - alpha * (wj[og] + beta * sm[og]);
         }
         if (win2 + src < ne && cok) {
           const int64_t og = (int64_t)cl2 * k3 + c;
-          v2 = INIT ? rj[og] : rj[og] - alpha * (wj[og] + beta * sm[og]);
+          v2 = INIT ? rj[og] : PIPE ? wj[og] : rj[og] - alpha * (wj[og] + beta * sm[og]);
         }
         xv1[q] = v1;
         xv2[q] = v2;
@@ -375,10 +378,11 @@ __global__ __launch_bounds__(NT) void k_cg_iter(CGArgs a, int j) {
         if (rl < nr) {
           const int64_t o = (c0 + rl) * k + oc;
           const int64_t og = (c0 + rl) * k3 + oc;
-          double rnew;
+          double rnew, wv2;
           if (INIT) {
             rnew = orj[u];
-          } else {
+            wv2 = acc_s[rl * CG_MAXK + oc] - osh * rnew;
+          } else if (!PIPE) {
             const double pv = orj[u] + obe * a.p[o];
             const double sv = owj[u] + obe * osm[u];
             a.p[o] = pv;
@@ -386,8 +390,22 @@ __global__ __launch_bounds__(NT) void k_cg_iter(CGArgs a, int j) {
             a.x[o] = fma(oal, pv, a.x[o]);
             rnew = orj[u] - oal * sv;
             rn[og] = rnew;
+            wv2 = acc_s[rl * CG_MAXK + oc] - osh * rnew;
+          } else {
+            // pipelined CG: q = A w_j, z = q + beta z, s = w + beta s, p = r + beta p,
+            // x += alpha p, r -= alpha s, w -= alpha z
+            const double q = acc_s[rl * CG_MAXK + oc] - osh * owj[u];
+            const double zv = q + obe * a.z[o];
+            const double sv = owj[u] + obe * osm[u];
+            const double pv = orj[u] + obe * a.p[o];
+            a.z[o] = zv;
+            a.p[o] = pv;
+            sj[og] = sv;
+            a.x[o] = fma(oal, pv, a.x[o]);
+            rnew = orj[u] - oal * sv;
+            rn[og] = rnew;
+            wv2 = owj[u] - oal * zv;
           }
-          const double wv2 = acc_s[rl * CG_MAXK + oc] - osh * rnew;
           wn[og] = wv2;
           sg = fma(rnew, rnew, sg);
           sd = fma(wv2, rnew, sd);
@@ -441,7 +459,7 @@ constexpr int64_t SC_D = (int64_t)((sizeof(CGScal) + 63) / 64) * 8;
 
 int64_t cg_work_doubles(int64_t n0) {
   const int64_t nb2 = std::min<int64_t>(256, cdiv(n0, 64));
-  return 2 * NB * 2 * CG_MAXK + nb2 * PW + SC_D + 7 * n0 * CG_MAXK + (NB + 1) + 2 * (n0 + 2);
+  return 2 * NB * 2 * CG_MAXK + nb2 * PW + SC_D + 8 * n0 * CG_MAXK + (NB + 1) + 2 * (n0 + 2);
 }
 
 // Row bounds for the iteration blocks (once per H0hat); tmp holds 2 (n0 + 2) doubles.
@@ -473,15 +491,26 @@ int cg_solve(const DevCSR& H0, int64_t n0, int k, int D, const double* shift, co
   double* vec = (double*)sc + SC_D;
   const int64_t vs = n0 * CG_MAXK;
   CGArgs a{n0, k, D, H0.rp, H0.rend, H0.col, H0.val64, H0.val32, shift, Ps, rowb, x,
-           r, {vec, vec + 3 * vs}, vec + 6 * vs, {part0, part1}, partP, nb2, sc, tol * tol};
+           r, {vec, vec + 3 * vs}, vec + 6 * vs, vec + 7 * vs, {part0, part1}, partP, nb2, sc, tol * tol};
   // r <- P b (ccoef = Ps^T b), x = p = s_{-1} = 0
   k_cg_psT<<<nb2, 1024, 0, s>>>(a, r);
   k_cg_project<<<nb2, 1024, 0, s>>>(a, r, ccoef, 1);
   SPPC_LAUNCH_CHECK();
   const bool f64 = H0.val64 != nullptr;
-#define SPPC_CG_LAUNCH(BB, INIT, J)                               \
-  if (f64) k_cg_iter<BB, double, INIT><<<NB, NT, 0, s>>>(a, J);    \
-  else k_cg_iter<BB, float, INIT><<<NB, NT, 0, s>>>(a, J);
+  // the pipelined form (one gathered vector per entry) for loose tolerances; its recursively
+  // updated residual drifts from the true one, so tight tolerances keep the classical form
+  const bool pipe = tol >= 1e-9;
+#define SPPC_CG_LAUNCH(BB, INIT, J)                                                \
+  if (INIT) {                                                                       \
+    if (f64) k_cg_iter<BB, double, true, false><<<NB, NT, 0, s>>>(a, J);            \
+    else k_cg_iter<BB, float, true, false><<<NB, NT, 0, s>>>(a, J);                 \
+  } else if (pipe) {                                                                \
+    if (f64) k_cg_iter<BB, double, false, true><<<NB, NT, 0, s>>>(a, J);            \
+    else k_cg_iter<BB, float, false, true><<<NB, NT, 0, s>>>(a, J);                 \
+  } else {                                                                          \
+    if (f64) k_cg_iter<BB, double, false, false><<<NB, NT, 0, s>>>(a, J);           \
+    else k_cg_iter<BB, float, false, false><<<NB, NT, 0, s>>>(a, J);                \
+  }
 #define SPPC_CG_STEP(INIT, J)      \
   if (k <= 4) {                    \
     SPPC_CG_LAUNCH(4, INIT, J)     \

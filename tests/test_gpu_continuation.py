@@ -20,15 +20,16 @@ def _H(A):
     return oracle.symmetric_from_upper(A.row_ptr, A.col, A.val, A.n)
 
 
-@pytest.mark.parametrize("mixed", [False, True])
-def test_small_space_correction_matches_reference(P, mixed):
+@pytest.mark.parametrize("mixed,ptol", [(False, 1e-13), (True, 1e-13), (False, 1e-8)])
+def test_small_space_correction_matches_reference(P, mixed, ptol):
+    # ptol 1e-13: the classical single-reduction CG; 1e-8: its pipelined form (loose tolerances)
     A = levelgen.generate((37, 411, 2999), 44, 19)
     k, ns = 3, 1
     n0 = int(A.level_offsets[ns])
-    print("case small correction mixed=%d n=%d" % (mixed, A.n), flush=True)
+    print("case small correction mixed=%d ptol=%g n=%d" % (mixed, ptol, A.n), flush=True)
     H = _H(A)
     rp, col, val = P.upload(A)
-    opts = P.sppc_default_opts(precond_tol=1e-13,
+    opts = P.sppc_default_opts(precond_tol=ptol,
                                precision=P.SPPC_PREC_MIXED if mixed else P.SPPC_PREC_FP64)
     ctx = P.sppc_setup(rp, col, val, A.level_offsets, ns, k, opts)
     for _ in range(3):
@@ -43,8 +44,9 @@ def test_small_space_correction_matches_reference(P, mixed):
     for a, i in enumerate(act):
         ref = oracle.small_space_correction(H, n0, theta[i], R[:, i], Z[:, i])
         err = np.max(np.abs(T[:, a] - ref)) / np.max(np.abs(ref))
-        # the small solve to 1e-13, with float64 products in both precisions
-        assert err < 1e-9, (i, err)
+        # the small solve to ptol with float64 products in both precisions; the error of the
+        # solution is at most the condition of the deflated operator (~1e2 here) times ptol
+        assert err < (1e-9 if ptol < 1e-12 else 1e-5), (i, err)
     P.sppc_destroy(ctx)
 
 
