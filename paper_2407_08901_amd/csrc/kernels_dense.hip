@@ -18,6 +18,7 @@ inline int64_t tn_chunk(int64_t n) {
 // ---------------------------------------------------------------- MFMA tall-skinny products
 // v_mfma_f64_16x16x4f64 (wave64): lane l supplies A[l%16][l/16] and B[l/16][l%16] of a
 // 16x4 by 4x16 product and holds D[l/16 + 4v][l%16], v = 0..3, of the 16x16 accumulator.
+typedef double v2d __attribute__((ext_vector_type(2)));
 typedef double v4d __attribute__((ext_vector_type(4)));
 
 __device__ inline v4d mfma16(double a, double b, v4d c) {
@@ -132,7 +133,7 @@ constexpr int NN_ROWS = 128;  // rows per workgroup: 4 waves x 2 tiles of 16
 // Y = beta Y + alpha A C: the reduction dimension of the MFMA is the column index i of A.
 // In step s of a 16-column slab, k-slot q of the MFMA is column i0 + 4 s + q, so the 4 slots
 // of one row read 32 contiguous bytes.
-template <int NT>
+template <int NT, bool VEC>
 __global__ __launch_bounds__(256) void k_gemm_nn(int64_t n, int m, int b, const double* __restrict__ A,
                                                  int64_t lda, const double* __restrict__ C, int64_t ldc,
                                                  double* __restrict__ Y, int64_t ldy, double alpha,
@@ -159,14 +160,39 @@ __global__ __launch_bounds__(256) void k_gemm_nn(int64_t n, int m, int b, const 
   for (int tj = 0; tj < NT; ++tj) jcol[tj] = 16 * tj + cl < b;
   for (int i0 = 0; i0 < m; i0 += 16) {
     double a[4][2], c[4][NT];
+    if constexpr (VEC) {
+      // slot q of step st is column i0 + 4 q + st: a lane's 4 columns of a row are one 32-byte
+      // load, and the 16 columns of a row one 128-byte segment (lda >= m rounded up to 16)
 #pragma unroll
-    for (int st = 0; st < 4; ++st) {
-      const int i = i0 + 4 * st + q;
-      const bool iin = i < m;
+      for (int mt = 0; mt < 2; ++mt) {
+        const v2d lo = rin[mt] ? *(const v2d*)(arow[mt] + i0 + 4 * q) : v2d{0.0, 0.0};
+        const v2d hi = rin[mt] ? *(const v2d*)(arow[mt] + i0 + 4 * q + 2) : v2d{0.0, 0.0};
+        a[0][mt] = lo.x;
+        a[1][mt] = lo.y;
+        a[2][mt] = hi.x;
+        a[3][mt] = hi.y;
+      }
 #pragma unroll
-      for (int mt = 0; mt < 2; ++mt) a[st][mt] = (iin && rin[mt]) ? arow[mt][i] : 0.0;
+      for (int st = 0; st < 4; ++st) {
+        const int i = i0 + 4 * q + st;
+        const bool iin = i < m;
 #pragma unroll
-      for (int tj = 0; tj < NT; ++tj) c[st][tj] = (iin && jcol[tj]) ? C[(int64_t)i * ldc + 16 * tj + cl] : 0.0;
+        for (int mt = 0; mt < 2; ++mt) a[st][mt] = iin ? a[st][mt] : 0.0;
+#pragma unroll
+        for (int tj = 0; tj < NT; ++tj)
+          c[st][tj] = (iin && jcol[tj]) ? C[(int64_t)i * ldc + 16 * tj + cl] : 0.0;
+      }
+    } else {
+#pragma unroll
+      for (int st = 0; st < 4; ++st) {
+        const int i = i0 + 4 * st + q;
+        const bool iin = i < m;
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt) a[st][mt] = (iin && rin[mt]) ? arow[mt][i] : 0.0;
+#pragma unroll
+        for (int tj = 0; tj < NT; ++tj)
+          c[st][tj] = (iin && jcol[tj]) ? C[(int64_t)i * ldc + 16 * tj + cl] : 0.0;
+      }
     }
 #pragma unroll
     for (int st = 0; st < 4; ++st)
@@ -346,10 +372,16 @@ void gemm_nn(int64_t n, int m, int b, const double* A, int64_t lda, const double
              double* Y, int64_t ldy, double alpha, double beta, hipStream_t s) {
   if (n <= 0 || b <= 0) return;
   if (b > 32) throw Error(1, "gemm_nn: b must be <= 32");
-  if (b <= 16)
-    k_gemm_nn<1><<<cdiv(n, NN_ROWS), 256, 0, s>>>(n, m, b, A, lda, C, ldc, Y, ldy, alpha, beta);
-  else
-    k_gemm_nn<2><<<cdiv(n, NN_ROWS), 256, 0, s>>>(n, m, b, A, lda, C, ldc, Y, ldy, alpha, beta);
+  // 32-byte row loads when the rows of A are 32-byte aligned and hold m rounded up to 16 columns
+  const bool vec = lda % 4 == 0 && ((uintptr_t)A & 31) == 0 && lda >= (int64_t)((m + 15) / 16) * 16;
+  const unsigned g = (unsigned)cdiv(n, NN_ROWS);
+  if (b <= 16) {
+    if (vec) k_gemm_nn<1, true><<<g, 256, 0, s>>>(n, m, b, A, lda, C, ldc, Y, ldy, alpha, beta);
+    else k_gemm_nn<1, false><<<g, 256, 0, s>>>(n, m, b, A, lda, C, ldc, Y, ldy, alpha, beta);
+  } else {
+    if (vec) k_gemm_nn<2, true><<<g, 256, 0, s>>>(n, m, b, A, lda, C, ldc, Y, ldy, alpha, beta);
+    else k_gemm_nn<2, false><<<g, 256, 0, s>>>(n, m, b, A, lda, C, ldc, Y, ldy, alpha, beta);
+  }
   SPPC_LAUNCH_CHECK();
 }
 
