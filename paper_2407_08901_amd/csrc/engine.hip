@@ -351,7 +351,7 @@ void zeroth_order(sppc_ctx* c) {
     // degree: the lowest Ritz value grows by T_deg(y0) against the damped interval; keep that
     // below e^25 (~7e10) so the block keeps the accuracy of its slowest wanted directions
     const double y0 = std::max(1.0 + 1e-12, (cc - a0) / e);
-    const int deg = std::max(12, std::min(40, (int)(25.0 / std::acosh(y0))));
+    const int deg = std::max(12, std::min(64, (int)(25.0 / std::acosh(y0))));
     double* buf[4] = {c->Z, c->Psi, c->R, c->HZ};
     int i0 = 0, i1 = 1;  // Y_{j-1}, Y_j
     // Y_1 = sigma/e (H - cc) Y_0  (Z holds the Ritz vectors, ld nw)
