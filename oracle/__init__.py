@@ -12,6 +12,7 @@ from .core import (  # noqa: F401
     Result,
     symmetric_from_upper,
     product_from_upper,
+    product_rows_from_upper,
     small_space_matrix,
     zeroth_order,
     rs_corrections,

@@ -70,6 +70,31 @@ def product_from_upper(row_ptr, col, val, n, X) -> np.ndarray:
     return U @ X + U.T @ X - U.diagonal()[:, None] * X
 
 
+def product_rows_from_upper(row_ptr, col, val, n, X, rows) -> np.ndarray:
+    """Rows `rows` of H X, each from its definition (H X)_i = sum_j H_ij X_j with H_ij = U_ij for
+    j >= i and U_ji for j < i, in float64.  The entries of row i below the diagonal are the stored
+    entries of column i, found by one pass over the column indices, so the cost is one pass over
+    the matrix however many rows are asked for (the check of sampled rows at sizes where the full
+    product is too slow on the CPU)."""
+    rows, back = np.unique(np.asarray(rows, dtype=np.int64), return_inverse=True)
+    row_ptr = np.asarray(row_ptr)
+    X = np.asarray(X, dtype=np.float64)
+    out = np.zeros((rows.size, X.shape[1]))
+    for a, i in enumerate(rows):          # j >= i: row i of the upper triangle
+        s, e = int(row_ptr[i]), int(row_ptr[i + 1])
+        out[a] = np.asarray(val[s:e], dtype=np.float64) @ X[np.asarray(col[s:e], dtype=np.int64)]
+    wanted = np.zeros(n, dtype=bool)       # j < i: stored entries (j, i) with j < i
+    wanted[rows] = True
+    slot = np.full(n, -1, dtype=np.int64)
+    slot[rows] = np.arange(rows.size)
+    hit = np.flatnonzero(wanted[col])
+    owner = np.searchsorted(row_ptr, hit, side="right") - 1
+    below = owner < np.asarray(col)[hit]
+    hit, owner = hit[below], owner[below]
+    np.add.at(out, slot[np.asarray(col)[hit]], np.asarray(val, dtype=np.float64)[hit][:, None] * X[owner])
+    return out[back.ravel()]
+
+
 def small_space_matrix(H: sp.csr_matrix, n0: int) -> np.ndarray:
     """H0hat: the leading n0 x n0 block of H, dense (eq. split2)."""
     return H[:n0, :n0].toarray()

@@ -1,12 +1,19 @@
-"""Full-size checks on the bench workload L4-2k/20k/150k/1M-d200-k8 (n = 1,172,000), in the
-launch configuration the benchmark times (panel stream, automatic panel width).
+"""Full-size checks at the sizes of the benchmark workloads, in the launch configuration the
+benchmark times (panel stream, automatic panel width).
 
-* every row of the block product with H against the oracle's float64 product from the upper
-  triangle (both precisions of X, full and partial blocks);
-* the mixed solve's eigenpairs against properties that hold at any size: the true residual
-  computed on the CPU by the oracle's product, orthonormality, and agreement with the float64
-  solve's eigenvalues.
+* L4-2k/20k/150k/1M-d200-k8 (n = 1,172,000): every row of the block product with H against the
+  oracle's float64 product from the upper triangle (both precisions of X, full and partial
+  blocks); the mixed and float64 solves against properties that hold at any size: the true
+  residual computed on the CPU by the oracle's product, orthonormality, agreement of the
+  eigenvalues.
+* The same shape with k = 16 (mixed and float64) and with the learned preconditioner in the
+  continuation: the same properties.
+* L5-2k/20k/200k/1.5M/6M-d300-k16 (n = 7,722,000, 1.17e9 stored entries, float32 values): the
+  block product on sampled rows against the oracle's row-by-row definition, then the mixed +
+  learned and float64 solves, with the true residual formed by that verified product.
 """
+import time
+
 import numpy as np
 import pytest
 import torch
@@ -28,11 +35,13 @@ def setup_module(module):
     P = _P
 
 
-def _matrix():
+def _matrix(wi=1):
+    # one matrix at a time: the largest takes 9 GB of host memory
     global _A
-    if _A is None:
-        _A = W.generate()
-    return _A
+    if _A is None or _A[0] != wi:
+        _A = None
+        _A = (wi, levelgen.WORKLOADS[wi].generate())
+    return _A[1]
 
 
 def _ctx(A, **kw):
@@ -82,3 +91,106 @@ def test_mixed_solve_true_residual_and_plain_agreement():
         assert np.max(np.abs(Z.T @ Z - np.eye(W.k))) < 1e-12
         assert np.all(np.diff(ev) >= 0)
     assert np.max(np.abs(res["mixed"][0] - res["plain"][0]) / np.abs(res["plain"][0])) < 1e-10
+
+
+def _solve_forms(A, w, forms, dtype=torch.float64):
+    """Solves A with each form (a fresh context each); returns {name: (ev, Z on the host, rrn)}."""
+    from paper_2407_08901_amd import mpnn_train
+    rp, col, val = P.upload(A, dtype=dtype)
+    out = {}
+    for name, kw in forms.items():
+        ctx = P.sppc_setup(rp, col, val, A.level_offsets, w.n_small_levels, w.k, P.sppc_default_opts(**kw))
+        if kw.get("precond") == P.SPPC_CORR_MPNN:
+            P.sppc_mpnn_set_weights(ctx, mpnn_train.load_for_levels(len(w.level_sizes)))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ev, Z, rrn, st, status = P.sppc_solve(ctx)
+        torch.cuda.synchronize()
+        print("%s %s: %.3f s, %d + %d steps (%d refinement, %d learned)" % (
+            w.name, name, time.perf_counter() - t0, st["iterations"], st["cont_steps"], st["refine_steps"],
+            st["mpnn_steps"]), flush=True)
+        P.sppc_destroy(ctx)
+        assert status == P.SPPC_OK and st["converged"] == 1, name
+        if kw.get("precond") == P.SPPC_CORR_MPNN:
+            assert st["mpnn_steps"] > 0
+        out[name] = (np.array(ev), Z.cpu().numpy(), np.array(rrn))
+        del Z
+    return out
+
+
+def _check_pairs(res, HZ_of, k):
+    for name, (ev, Z, rrn) in res.items():
+        R = HZ_of(name, Z) - Z * ev[None, :]
+        true = np.linalg.norm(R, axis=0) / np.abs(ev)
+        assert np.max(true) < 1e-6, (name, true)
+        assert np.max(np.abs(true - rrn)) < 1e-9, (name, true, rrn)
+        assert np.max(np.abs(Z.T @ Z - np.eye(k))) < 1e-12, name
+        assert np.all(np.diff(ev) >= 0), name
+    ref = res["plain"][0]
+    for name, (ev, Z, rrn) in res.items():
+        assert np.max(np.abs(ev - ref) / np.abs(ref)) < 1e-10, name
+
+
+@pytest.mark.parametrize("wi", [2, 3])
+def test_k16_and_learned_solves_at_full_size(wi):
+    # k = 16 (mixed and float64), and the learned preconditioner in the continuation (k = 8)
+    w = levelgen.WORKLOADS[wi]
+    A = _matrix(wi)
+    print("case fullsize solves %s" % w.name, flush=True)
+    forms = {"mixed": dict(precision=P.SPPC_PREC_MIXED), "plain": dict(precision=P.SPPC_PREC_FP64)}
+    if wi == 3:
+        forms = {"mixed+learned": dict(precision=P.SPPC_PREC_MIXED, precond=P.SPPC_CORR_MPNN),
+                 "plain+learned": dict(precision=P.SPPC_PREC_FP64, precond=P.SPPC_CORR_MPNN),
+                 "plain": dict(precision=P.SPPC_PREC_FP64)}
+    res = _solve_forms(A, w, forms)
+    names = list(res)
+    Zall = np.concatenate([res[nm][1] for nm in names], axis=1)
+    HZall = oracle.product_from_upper(A.row_ptr, A.col, A.val, A.n, Zall)
+    cols = {nm: slice(i * w.k, (i + 1) * w.k) for i, nm in enumerate(names)}
+    _check_pairs(res, lambda nm, Z: HZall[:, cols[nm]], w.k)
+
+
+def test_n7722000_sampled_product_and_solves():
+    w = levelgen.WORKLOADS[4]
+    A = _matrix(4)
+    print("case fullsize n=%d nnz=%d" % (A.n, A.nnz), flush=True)
+    rng = np.random.default_rng(404)
+    offs = np.asarray(A.level_offsets)
+    rows = np.unique(np.concatenate([rng.choice(A.n, 2000, replace=False), np.arange(64),
+                                     np.arange(A.n - 64, A.n), offs[1:-1], offs[1:-1] - 1]))
+    X = rng.standard_normal((A.n, 16))
+    ref = oracle.product_rows_from_upper(A.row_ptr, A.col, A.val, A.n, X, rows)
+    scale = oracle.product_rows_from_upper(A.row_ptr, A.col, np.abs(A.val), A.n, np.abs(X), rows)
+    X32 = X.astype(np.float32)
+    ref32 = oracle.product_rows_from_upper(A.row_ptr, A.col, A.val, A.n, X32.astype(np.float64), rows)
+    rp, col, val = P.upload(A, dtype=torch.float32)
+    from paper_2407_08901_amd import mpnn_train
+    res = {}
+    for name, kw in (("mixed+learned", dict(precision=P.SPPC_PREC_MIXED, precond=P.SPPC_CORR_MPNN)),
+                     ("plain", dict(precision=P.SPPC_PREC_FP64))):
+        ctx = P.sppc_setup(rp, col, val, A.level_offsets, w.n_small_levels, w.k, P.sppc_default_opts(**kw))
+        Yd = torch.empty((A.n, 16), dtype=torch.float64, device="cuda")
+        P.sppc_spmm(ctx, torch.from_numpy(X).cuda(), Yd)
+        torch.cuda.synchronize()
+        assert np.max(np.abs(Yd.cpu().numpy()[rows] - ref) / scale) < 1e-14, name
+        P.sppc_spmm(ctx, torch.from_numpy(X32).cuda(), Yd)
+        torch.cuda.synchronize()
+        assert np.max(np.abs(Yd.cpu().numpy()[rows] - ref32) / scale) < 2.0 ** -24 * 1.01, name
+        if kw.get("precond") == P.SPPC_CORR_MPNN:
+            P.sppc_mpnn_set_weights(ctx, mpnn_train.load_for_levels(len(w.level_sizes)))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ev, Z, rrn, st, status = P.sppc_solve(ctx)
+        torch.cuda.synchronize()
+        print("%s %s: %.3f s, %d + %d steps (%d refinement, %d learned)" % (
+            w.name, name, time.perf_counter() - t0, st["iterations"], st["cont_steps"], st["refine_steps"],
+            st["mpnn_steps"]), flush=True)
+        assert status == P.SPPC_OK and st["converged"] == 1, name
+        # the residual through the float64 product just checked on sampled rows
+        HZ = torch.empty_like(Z)
+        P.sppc_spmm(ctx, Z, HZ)
+        torch.cuda.synchronize()
+        P.sppc_destroy(ctx)
+        res[name] = (np.array(ev), Z.cpu().numpy(), np.array(rrn), HZ.cpu().numpy())
+        del Z, HZ, Yd
+    _check_pairs({nm: r[:3] for nm, r in res.items()}, lambda nm, Z: res[nm][3], w.k)

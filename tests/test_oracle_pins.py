@@ -309,3 +309,7 @@ def test_product_from_upper_matches_the_dense_symmetric_matrix():
     X = rng.standard_normal((n, 5))
     Y = oracle.product_from_upper(rp, np.array(cols), np.array(vals), n, X)
     assert np.max(np.abs(Y - Hd @ X)) < 1e-13
+    # single rows from the definition: every row, a repeated row, and unsorted order
+    rows = np.concatenate([np.arange(n), [5, 5, 36, 0]])[::-1]
+    Yr = oracle.product_rows_from_upper(rp, np.array(cols, dtype=np.int32), np.array(vals), n, X, rows)
+    assert np.max(np.abs(Yr - (Hd @ X)[rows])) < 1e-13
