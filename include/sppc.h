@@ -263,8 +263,22 @@ const char* sppc_last_error(const sppc_ctx* ctx);
 /* Message of the last failure in sppc_setup (no context exists then). */
 const char* sppc_setup_error(void);
 
-/* Frees every device allocation of the context.  NULL is ignored. */
+/* Waits for the context's stream, then gives every device and pinned allocation of the context
+ * back to the library's memory cache.  NULL is ignored. */
 void sppc_destroy(sppc_ctx* ctx);
+
+/*
+ * Device memory of the library (context arrays and setup temporaries, including those of the
+ * float64 and float32 device copies of H) comes from a process-wide cache: a block given back by
+ * sppc_destroy or by setup is kept and handed to the next request of the same rounded size
+ * (2 MiB granules) on the same device.  Repeated setups of one problem size then allocate
+ * nothing; hipMalloc/hipFree stall the host, and VRAM that was freed recently is cleared by the
+ * driver before it is handed out again (about a second per 100 GB).  The cache keeps at most 3/4
+ * of a device's memory, and an allocation that fails empties the cache of its device and is
+ * tried once more.  This call frees every cached block (of every device) now and returns the
+ * number of bytes freed.  Thread-safe; blocks in use by live contexts are not affected.
+ */
+size_t sppc_release_cached_memory(void);
 
 #ifdef __cplusplus
 }

@@ -27,7 +27,7 @@ STATUS_NAMES = {0: "SPPC_OK", 1: "SPPC_E_ARG", 2: "SPPC_E_HIP", 3: "SPPC_E_NOMEM
 
 EXPORTS = ("sppc_default_opts", "sppc_setup", "sppc_spmm", "sppc_correct", "sppc_rayleigh_ritz",
            "sppc_solve", "sppc_get", "sppc_last_error", "sppc_setup_error", "sppc_destroy",
-           "sppc_mpnn_set_weights", "sppc_mpnn_eval", "sppc_mpnn_train_step", "sppc_mpnn_target")
+           "sppc_release_cached_memory", "sppc_mpnn_set_weights", "sppc_mpnn_eval", "sppc_mpnn_train_step", "sppc_mpnn_target")
 SPPC_MPNN_NPARAM = 289
 
 
@@ -88,6 +88,8 @@ def lib():
         L.sppc_setup_error.restype = ctypes.c_char_p
         L.sppc_destroy.argtypes = [vp]
         L.sppc_destroy.restype = None
+        L.sppc_release_cached_memory.argtypes = []
+        L.sppc_release_cached_memory.restype = ctypes.c_size_t
         fp = ctypes.POINTER(ctypes.c_float)
         L.sppc_mpnn_set_weights.argtypes = [vp, fp]
         L.sppc_mpnn_eval.argtypes = [vp, fp, c_int, vp, vp, dp, vp, c_int, vp, vp, dp, dp, c_int]
@@ -278,6 +280,11 @@ def sppc_destroy(ctx: Context) -> None:
     if ctx is not None and ctx.handle:
         lib().sppc_destroy(ctx.handle)
         ctx.handle = None
+
+
+def sppc_release_cached_memory() -> int:
+    """Frees the library's cached device memory; returns the bytes freed."""
+    return int(lib().sppc_release_cached_memory())
 
 
 def upload(A, dtype=torch.float64, device="cuda"):

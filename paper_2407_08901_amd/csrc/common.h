@@ -30,6 +30,19 @@ constexpr int WAVE = 64;
 
 __host__ __device__ inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+// ---------------------------------------------------------------- memory (memory.hip)
+
+// Device and pinned host memory from the library's process-wide cache of freed blocks.  A block
+// may be given back only once the stream that last used it has been synchronised.
+hipError_t dev_alloc(void** p, size_t bytes);
+void dev_free(void* p);
+hipError_t pinned_alloc(void** p, size_t bytes);
+void pinned_free(void* p);
+template <class T>
+inline hipError_t dev_malloc(T** p, size_t bytes) {
+  return dev_alloc((void**)p, bytes);
+}
+
 // ---------------------------------------------------------------- sparse (kernels_sparse.hip)
 
 // Full symmetric CSR on the device (both triangles, columns ascending in each row).
@@ -186,7 +199,7 @@ int64_t cg_work_doubles(int64_t n0);
 // doubles.
 void cg_prepare(const DevCSR& H0, int64_t n0, int64_t* rowb, double* tmp, hipStream_t s);
 // Deflated CG for the k small-space systems (b in r on entry, solution in x); ccoef = Ps^T b.
-// Products in float64 (float32-stored values are widened).
+// Products in float64 (float32-stored values are widened).  host_flag: two ints of pinned memory.
 int cg_solve(const DevCSR& H0, int64_t n0, int k, int D, const double* shift, const double* Ps,
              const int64_t* rowb, double* x, double* r, double* work, double* ccoef, int maxit, double tol,
              int* host_flag, hipStream_t s);

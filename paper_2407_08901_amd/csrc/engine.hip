@@ -34,16 +34,16 @@ struct Arena {
   T* alloc(size_t count) {
     void* p = nullptr;
     const size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
-    hipError_t e = hipMalloc(&p, bytes);
+    hipError_t e = dev_alloc(&p, bytes);
     if (e != hipSuccess) {
       (void)hipGetLastError();
-      throw Error(SPPC_E_NOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+      throw Error(SPPC_E_NOMEM, "allocation of " + std::to_string(bytes) + " bytes of device memory failed");
     }
     ptrs.push_back(p);
     return (T*)p;
   }
   void release() {
-    for (void* p : ptrs) (void)hipFree(p);
+    for (void* p : ptrs) dev_free(p);
     ptrs.clear();
   }
   ~Arena() { release(); }
@@ -695,10 +695,10 @@ void setup_impl(sppc_ctx* c, const sppc_csr* Hin, const int64_t* loff, int L, in
     if (exact) {
       c->H = tmp;
     } else {
-      (void)hipFree(tmp.val32);
+      dev_free(tmp.val32);
       tmp.val32 = nullptr;
-      (void)hipFree(tmp.rp);
-      (void)hipFree(tmp.col);
+      dev_free(tmp.rp);
+      dev_free(tmp.col);
       DevCSR t2;
       build_full_csr(c->n, Hin->nnz, Hin->row_ptr_dev, Hin->col_dev, Hin->val_dev, 0, t2, dflags, true, mixed,
                      exact, s);
@@ -800,8 +800,8 @@ void setup_impl(sppc_ctx* c, const sppc_csr* Hin, const int64_t* loff, int L, in
   cg_prepare(c->H0, n0, c->cg_rowb, c->cgpart, s);
   c->ccoef = A.alloc<double>((size_t)KB * KB);
   c->ctmp = A.alloc<double>((size_t)KB * KB);
-  SPPC_HIP(hipHostMalloc((void**)&c->pin, sizeof(double) * 4 * NWMAX, hipHostMallocDefault));
-  SPPC_HIP(hipHostMalloc((void**)&c->pin_i, sizeof(int) * 128, hipHostMallocDefault));
+  SPPC_HIP(pinned_alloc((void**)&c->pin, sizeof(double) * 4 * NWMAX));
+  SPPC_HIP(pinned_alloc((void**)&c->pin_i, sizeof(int) * 128));
   c->tm.s = s;
 
   // zeroth order
@@ -1177,8 +1177,8 @@ const char* sppc_setup_error(void) { return g_setup_err.c_str(); }
 void sppc_destroy(sppc_ctx* c) {
   if (!c) return;
   if (c->s) (void)hipStreamSynchronize(c->s); else (void)hipDeviceSynchronize();
-  if (c->pin) (void)hipHostFree(c->pin);
-  if (c->pin_i) (void)hipHostFree(c->pin_i);
+  pinned_free(c->pin);
+  pinned_free(c->pin_i);
   c->arena.release();
   delete c;
 }

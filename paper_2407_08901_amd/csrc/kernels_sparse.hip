@@ -810,14 +810,14 @@ void build_full_csr(int64_t n, int64_t nnz_up, const int64_t* up_rp, const int32
   int64_t *lower_rp = nullptr, *bsum = nullptr;
   double* tmp_val = nullptr;
   auto cleanup = [&]() {
-    hipFree(lower_cnt); hipFree(fillc); hipFree(tmp_col); hipFree(lower_rp); hipFree(bsum);
-    hipFree(tmp_val);
+    dev_free(lower_cnt); dev_free(fillc); dev_free(tmp_col); dev_free(lower_rp); dev_free(bsum);
+    dev_free(tmp_val);
   };
   try {
-    SPPC_HIP(hipMalloc(&lower_cnt, sizeof(int32_t) * (n + 1)));
-    SPPC_HIP(hipMalloc(&fillc, sizeof(int32_t) * (n + 1)));
-    SPPC_HIP(hipMalloc(&lower_rp, sizeof(int64_t) * (n + 1)));
-    SPPC_HIP(hipMalloc(&bsum, sizeof(int64_t) * (cdiv(n, SCAN_BLOCK) + 1)));
+    SPPC_HIP(dev_malloc(&lower_cnt, sizeof(int32_t) * (n + 1)));
+    SPPC_HIP(dev_malloc(&fillc, sizeof(int32_t) * (n + 1)));
+    SPPC_HIP(dev_malloc(&lower_rp, sizeof(int64_t) * (n + 1)));
+    SPPC_HIP(dev_malloc(&bsum, sizeof(int64_t) * (cdiv(n, SCAN_BLOCK) + 1)));
     SPPC_HIP(hipMemsetAsync(lower_cnt, 0, sizeof(int32_t) * (n + 1), s));
     SPPC_HIP(hipMemsetAsync(fillc, 0, sizeof(int32_t) * (n + 1), s));
     SPPC_HIP(hipMemsetAsync(d_flags, 0, sizeof(int) * 4, s));
@@ -840,13 +840,13 @@ void build_full_csr(int64_t n, int64_t nnz_up, const int64_t* up_rp, const int32
     const int64_t nnz = nnz_up + nlow;
     out.n = n;
     out.nnz = nnz;
-    SPPC_HIP(hipMalloc(&out.rp, sizeof(int64_t) * (n + 1)));
-    SPPC_HIP(hipMalloc(&out.col, sizeof(int32_t) * (nnz > 0 ? nnz : 1)));
-    if (want64) SPPC_HIP(hipMalloc(&out.val64, sizeof(double) * (nnz > 0 ? nnz : 1)));
-    if (want32) SPPC_HIP(hipMalloc(&out.val32, sizeof(float) * (nnz > 0 ? nnz : 1)));
-    SPPC_HIP(hipMalloc(&tmp_col, sizeof(int32_t) * (nlow > 0 ? nlow : 1)));
+    SPPC_HIP(dev_malloc(&out.rp, sizeof(int64_t) * (n + 1)));
+    SPPC_HIP(dev_malloc(&out.col, sizeof(int32_t) * (nnz > 0 ? nnz : 1)));
+    if (want64) SPPC_HIP(dev_malloc(&out.val64, sizeof(double) * (nnz > 0 ? nnz : 1)));
+    if (want32) SPPC_HIP(dev_malloc(&out.val32, sizeof(float) * (nnz > 0 ? nnz : 1)));
+    SPPC_HIP(dev_malloc(&tmp_col, sizeof(int32_t) * (nlow > 0 ? nlow : 1)));
     // staged mirrored values: float32 suffice when only float32 values are kept
-    SPPC_HIP(hipMalloc(&tmp_val, (want64 ? sizeof(double) : sizeof(float)) * (nlow > 0 ? nlow : 1)));
+    SPPC_HIP(dev_malloc(&tmp_val, (want64 ? sizeof(double) : sizeof(float)) * (nlow > 0 ? nlow : 1)));
     k_full_rowptr<<<cdiv(n + 1, 256), 256, 0, s>>>(n, lower_rp, up_rp, out.rp);
     if (want64) {
       if (val_is_f32)
@@ -871,6 +871,7 @@ void build_full_csr(int64_t n, int64_t nnz_up, const int64_t* up_rp, const int32
     SPPC_LAUNCH_CHECK();
     SPPC_HIP(hipStreamSynchronize(s));
   } catch (...) {
+    (void)hipStreamSynchronize(s);
     cleanup();
     throw;
   }
@@ -888,13 +889,13 @@ void compact_view(const DevCSR& V, DevCSR& out, hipStream_t s) {
   if (!V.rend) throw Error(1, "compact_view: not a block view");
   int32_t* cnt = nullptr;
   int64_t* bsum = nullptr;
-  auto cleanup = [&]() { hipFree(cnt); hipFree(bsum); };
+  auto cleanup = [&]() { dev_free(cnt); dev_free(bsum); };
   try {
     out = DevCSR{};
     out.n = n0;
-    SPPC_HIP(hipMalloc(&cnt, sizeof(int32_t) * (n0 + 1)));
-    SPPC_HIP(hipMalloc(&bsum, sizeof(int64_t) * (cdiv(n0 + 1, SCAN_BLOCK) + 1)));
-    SPPC_HIP(hipMalloc(&out.rp, sizeof(int64_t) * (n0 + 1)));
+    SPPC_HIP(dev_malloc(&cnt, sizeof(int32_t) * (n0 + 1)));
+    SPPC_HIP(dev_malloc(&bsum, sizeof(int64_t) * (cdiv(n0 + 1, SCAN_BLOCK) + 1)));
+    SPPC_HIP(dev_malloc(&out.rp, sizeof(int64_t) * (n0 + 1)));
     k_view_count<<<cdiv(n0 > 0 ? n0 : 1, 256), 256, 0, s>>>(n0, V.rp, V.rend, cnt);
     SPPC_LAUNCH_CHECK();
     scan_exclusive_impl(n0, cnt, out.rp, bsum, s);
@@ -902,16 +903,17 @@ void compact_view(const DevCSR& V, DevCSR& out, hipStream_t s) {
     SPPC_HIP(hipMemcpyAsync(&nnz, out.rp + n0, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     SPPC_HIP(hipStreamSynchronize(s));
     out.nnz = nnz;
-    SPPC_HIP(hipMalloc(&out.col, sizeof(int32_t) * (nnz > 0 ? nnz : 1)));
-    if (V.val64) SPPC_HIP(hipMalloc(&out.val64, sizeof(double) * (nnz > 0 ? nnz : 1)));
-    if (V.val32) SPPC_HIP(hipMalloc(&out.val32, sizeof(float) * (nnz > 0 ? nnz : 1)));
+    SPPC_HIP(dev_malloc(&out.col, sizeof(int32_t) * (nnz > 0 ? nnz : 1)));
+    if (V.val64) SPPC_HIP(dev_malloc(&out.val64, sizeof(double) * (nnz > 0 ? nnz : 1)));
+    if (V.val32) SPPC_HIP(dev_malloc(&out.val32, sizeof(float) * (nnz > 0 ? nnz : 1)));
     k_view_fill<<<cdiv(n0 > 0 ? n0 : 1, 4), 256, 0, s>>>(n0, V.rp, V.col, V.val64, V.val32, out.rp, out.col,
                                                           out.val64, out.val32);
     SPPC_LAUNCH_CHECK();
     SPPC_HIP(hipStreamSynchronize(s));
   } catch (...) {
+    (void)hipStreamSynchronize(s);
     cleanup();
-    (void)hipFree(out.rp); (void)hipFree(out.col); (void)hipFree(out.val64); (void)hipFree(out.val32);
+    (void)dev_free(out.rp); (void)dev_free(out.col); (void)dev_free(out.val64); (void)dev_free(out.val32);
     out = DevCSR{};
     throw;
   }
@@ -935,17 +937,17 @@ void build_panel(const DevCSR& H, int PW, PanelH& out, hipStream_t s) {
   int32_t* padded = nullptr;
   int64_t* bsum = nullptr;
   int* flags = nullptr;
-  auto cleanup = [&]() { (void)hipFree(padded); (void)hipFree(bsum); (void)hipFree(flags); };
+  auto cleanup = [&]() { (void)dev_free(padded); (void)dev_free(bsum); (void)dev_free(flags); };
   try {
     const int nb = out.nblocks;
-    SPPC_HIP(hipMalloc(&padded, sizeof(int32_t) * nb));
-    SPPC_HIP(hipMalloc(&bsum, sizeof(int64_t) * (cdiv(nb, SCAN_BLOCK) + 1)));
-    SPPC_HIP(hipMalloc(&out.bcount, sizeof(int32_t) * nb));
-    SPPC_HIP(hipMalloc(&out.bstart, sizeof(int64_t) * (nb + 1)));
-    SPPC_HIP(hipMalloc(&out.dg, sizeof(double) * n));
-    SPPC_HIP(hipMalloc(&out.xpad, sizeof(double) * 16 * n));
+    SPPC_HIP(dev_malloc(&padded, sizeof(int32_t) * nb));
+    SPPC_HIP(dev_malloc(&bsum, sizeof(int64_t) * (cdiv(nb, SCAN_BLOCK) + 1)));
+    SPPC_HIP(dev_malloc(&out.bcount, sizeof(int32_t) * nb));
+    SPPC_HIP(dev_malloc(&out.bstart, sizeof(int64_t) * (nb + 1)));
+    SPPC_HIP(dev_malloc(&out.dg, sizeof(double) * n));
+    SPPC_HIP(dev_malloc(&out.xpad, sizeof(double) * 16 * n));
     SPPC_HIP(hipMemsetAsync(out.dg, 0, sizeof(double) * n, s));
-    SPPC_HIP(hipMalloc(&flags, sizeof(int)));
+    SPPC_HIP(dev_malloc(&flags, sizeof(int)));
     SPPC_HIP(hipMemsetAsync(flags, 0, sizeof(int), s));
     k_panel_bcount<<<nb, 256, 0, s>>>(n, H.rp, H.col, out.bcount, padded, flags);
     scan_exclusive_impl(nb, padded, out.bstart, bsum, s);
@@ -956,16 +958,16 @@ void build_panel(const DevCSR& H, int PW, PanelH& out, hipStream_t s) {
     SPPC_HIP(hipStreamSynchronize(s));
     if (flag) throw Error(1, "panel: a block of rows holds 2^31 entries or more");
     const int64_t cap = std::max<int64_t>(total, 8);
-    SPPC_HIP(hipMalloc(&out.ent, sizeof(uint32_t) * cap));
+    SPPC_HIP(dev_malloc(&out.ent, sizeof(uint32_t) * cap));
     SPPC_HIP(hipMemsetAsync(out.ent, 0, sizeof(uint32_t) * cap, s));  // padding: column 0, row 0
     if (H.val64) {
-      SPPC_HIP(hipMalloc(&out.val64, sizeof(double) * cap));
+      SPPC_HIP(dev_malloc(&out.val64, sizeof(double) * cap));
       SPPC_HIP(hipMemsetAsync(out.val64, 0, sizeof(double) * cap, s));
       k_panel_fill<double><<<nb, PANEL_FT, 0, s>>>(n, H.rp, H.col, H.val64, PW, out.P, out.bstart, out.ent,
                                                     out.val64, out.dg);
     }
     if (H.val32) {
-      SPPC_HIP(hipMalloc(&out.val32, sizeof(float) * cap));
+      SPPC_HIP(dev_malloc(&out.val32, sizeof(float) * cap));
       SPPC_HIP(hipMemsetAsync(out.val32, 0, sizeof(float) * cap, s));
       k_panel_fill<float><<<nb, PANEL_FT, 0, s>>>(n, H.rp, H.col, H.val32, PW, out.P, out.bstart, out.ent,
                                                    out.val32, H.val64 ? nullptr : out.dg);
@@ -973,6 +975,7 @@ void build_panel(const DevCSR& H, int PW, PanelH& out, hipStream_t s) {
     SPPC_LAUNCH_CHECK();
     SPPC_HIP(hipStreamSynchronize(s));
   } catch (...) {
+    (void)hipStreamSynchronize(s);
     cleanup();
     release_panel(out);
     throw;
@@ -985,13 +988,13 @@ void scan_exclusive(int64_t n, const int32_t* a, int64_t* out, int64_t* bsum, hi
 }
 
 void release_panel(PanelH& p) {
-  (void)hipFree(p.bstart);
-  (void)hipFree(p.bcount);
-  (void)hipFree(p.ent);
-  (void)hipFree(p.val32);
-  (void)hipFree(p.val64);
-  (void)hipFree(p.dg);
-  (void)hipFree(p.xpad);
+  (void)dev_free(p.bstart);
+  (void)dev_free(p.bcount);
+  (void)dev_free(p.ent);
+  (void)dev_free(p.val32);
+  (void)dev_free(p.val64);
+  (void)dev_free(p.dg);
+  (void)dev_free(p.xpad);
   p = PanelH{};
 }
 
