@@ -520,16 +520,37 @@ int cg_solve(const DevCSR& H0, int64_t n0, int k, int D, const double* shift, co
     SPPC_CG_LAUNCH(16, INIT, J)    \
   }
   SPPC_CG_STEP(true, 0)
-  int j = 0;
-  for (j = 0; j < maxit; ++j) {
-    SPPC_CG_STEP(false, j)
-    if ((j + 1) % 16 == 0 || j + 1 == maxit) {
-      SPPC_LAUNCH_CHECK();
-      SPPC_HIP(hipMemcpyAsync(host_flag, &sc->nact[j & 1], sizeof(int), hipMemcpyDeviceToHost, s));
-      SPPC_HIP(hipStreamSynchronize(s));
-      if (*host_flag == 0) break;
+  // The active count is read back after every 16 iterations without draining the stream: the
+  // host waits for the count of the batch before the one just queued, so the GPU always has a
+  // batch to run.  Iterations queued after convergence return at once.
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  auto cleanup = [&]() {
+    for (hipEvent_t e : ev)
+      if (e) (void)hipEventDestroy(e);
+  };
+  try {
+    SPPC_HIP(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
+    SPPC_HIP(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
+    int batch = 0;
+    for (int j = 0; j < maxit; ++j) {
+      SPPC_CG_STEP(false, j)
+      if ((j + 1) % 16 == 0 || j + 1 == maxit) {
+        SPPC_LAUNCH_CHECK();
+        SPPC_HIP(hipMemcpyAsync(host_flag + (batch & 1), &sc->nact[j & 1], sizeof(int), hipMemcpyDeviceToHost, s));
+        SPPC_HIP(hipEventRecord(ev[batch & 1], s));
+        if (batch > 0) {
+          SPPC_HIP(hipEventSynchronize(ev[(batch - 1) & 1]));
+          if (host_flag[(batch - 1) & 1] == 0) break;
+        }
+        ++batch;
+      }
     }
+  } catch (...) {
+    (void)hipStreamSynchronize(s);
+    cleanup();
+    throw;
   }
+  cleanup();
 #undef SPPC_CG_STEP
 #undef SPPC_CG_LAUNCH
   // x <- P x (removes the drift into the deflated directions)
