@@ -21,25 +21,27 @@ typedef double f64x2 __attribute__((ext_vector_type(2)));
 
 // -------------------------------------------------------------------------- setup
 
+// One wave per row: checks the upper CSR (columns >= row, < n, strictly ascending), whether
+// every value is float32-exact and finite, and counts the row's strict-upper entries.
 template <typename VT>
 __global__ void k_validate_count(int64_t n, const int64_t* __restrict__ rp,
                                  const int32_t* __restrict__ col, const VT* __restrict__ val,
-                                 int32_t* __restrict__ lower_cnt, int* __restrict__ flags) {
+                                 int32_t* __restrict__ su_cnt, int* __restrict__ flags) {
   const int lane = threadIdx.x & 63;
   const int64_t row = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (row >= n) return;
   const int64_t b = rp[row], e = rp[row + 1];
   int bad = 0, inexact = 0, nonfinite = 0;
-  if (e < b) bad = 1;
-  for (int64_t t = b + lane; t < e; t += 64) {
+  if (e < b || e - b > n - row) bad = 1;
+  for (int64_t t = b + lane; t < e && !bad; t += 64) {
     const int32_t c = col[t];
     if (c < row || c >= n) bad = 1;
     if (t > b && col[t - 1] >= c) bad = 1;
     const double v = (double)val[t];
     if (!isfinite(v)) nonfinite = 1;
     if ((double)(float)v != v) inexact = 1;
-    if (c != row && c < n && c > row) atomicAdd(&lower_cnt[c], 1);
   }
+  if (lane == 0) su_cnt[row] = bad ? 0 : (int32_t)((e - b) - ((e > b && col[b] == row) ? 1 : 0));
   if (bad) atomicOr(&flags[0], 1);
   if (inexact) atomicOr(&flags[1], 1);
   if (nonfinite) atomicOr(&flags[2], 1);
@@ -115,72 +117,176 @@ __global__ void k_full_rowptr(int64_t n, const int64_t* __restrict__ lower_rp,
   if (i <= n) full_rp[i] = lower_rp[i] + up_rp[i];
 }
 
-// TT: type of the staged mirrored values (float when only float32 values are kept)
+// The mirror of the strict upper triangle is a stable sort of its entries by column: entry (r, c)
+// of the upper triangle becomes entry (c, r) of the lower one, and a stable sort of the entries,
+// taken in row order, by column leaves every lower row with its columns ascending.  The sort is
+// a least-significant-digit radix sort (digits of at most 8 bits): per pass, a histogram of
+// each tile of RS_TILE entries, an exclusive scan of the (digit, tile) counts in digit-major
+// order, and a scatter in which one wave ranks its tile's entries round by round (a digit's
+// peers in a round come from ballots over the digit's bits), so every entry keeps its order
+// among equal digits.  No global atomics, and the result does not depend on scheduling.
+constexpr int RS_TILE = 2048;
+constexpr int RS_ROUNDS = RS_TILE / 64;
+
+// strict-upper entries in row order: key = column, row, value (TT: float when only float32 values
+// are kept)
 template <typename VT, typename TT>
-__global__ void k_fill(int64_t n, const int64_t* __restrict__ up_rp, const int32_t* __restrict__ up_col,
-                       const VT* __restrict__ up_val, const int64_t* __restrict__ lower_rp,
-                       const int64_t* __restrict__ full_rp, int32_t* __restrict__ fillc,
-                       int32_t* __restrict__ full_col, double* __restrict__ full_v64,
-                       float* __restrict__ full_v32, int32_t* __restrict__ tmp_col,
-                       TT* __restrict__ tmp_val) {
+__global__ void k_extract_upper(int64_t n, const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
+                                const VT* __restrict__ val, const int64_t* __restrict__ su_off,
+                                int32_t* __restrict__ key, int32_t* __restrict__ rowi, TT* __restrict__ v) {
   const int lane = threadIdx.x & 63;
   const int64_t row = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (row >= n) return;
-  const int64_t b = up_rp[row], e = up_rp[row + 1];
-  const int64_t nlow = lower_rp[row + 1] - lower_rp[row];
-  const int64_t dst = full_rp[row] + nlow;
+  const int64_t e = rp[row + 1];
+  int64_t b = rp[row];
+  if (e > b && col[b] == row) ++b;  // the diagonal (first, since columns ascend from row)
+  const int64_t o = su_off[row];
+  if (su_off[row + 1] - o != e - b) return;  // (cannot happen for a valid input)
   for (int64_t t = b + lane; t < e; t += 64) {
-    const int32_t c = up_col[t];
-    const double v = (double)up_val[t];
-    const int64_t o = dst + (t - b);
-    full_col[o] = c;
-    if (full_v64) full_v64[o] = v;
-    if (full_v32) full_v32[o] = (float)v;
-    if (c != row) {
-      const int32_t slot = atomicAdd(&fillc[c], 1);
-      const int64_t q = lower_rp[c] + slot;
-      tmp_col[q] = (int32_t)row;
-      tmp_val[q] = (TT)v;
-    }
+    key[o + (t - b)] = col[t];
+    rowi[o + (t - b)] = (int32_t)row;
+    v[o + (t - b)] = (TT)val[t];
   }
 }
 
-// The mirrored entries of a row arrive in arbitrary order; place each at its rank
-// (column indices in a row are unique), which is deterministic.  One wave per row; a row of up to
-// SORT_CAP mirrored entries is staged in LDS, so the rank loop reads broadcast LDS words.
-constexpr int SORT_CAP = 1024;
+// counts of digit (key >> shift) & mask per tile, digit-major: cnt[d * ntile + tile]
+__global__ __launch_bounds__(256) void k_rs_hist(int64_t m, const int32_t* __restrict__ key, int shift, int mask,
+                                                 int64_t ntile, int32_t* __restrict__ cnt) {
+  __shared__ int h[256];
+  const int t = threadIdx.x;
+  h[t] = 0;
+  __syncthreads();
+  const int64_t i0 = (int64_t)blockIdx.x * RS_TILE;
+  const int64_t i1 = min<int64_t>(m, i0 + RS_TILE);
+  for (int64_t i = i0 + t; i < i1; i += 256) atomicAdd(&h[((uint32_t)key[i] >> shift) & mask], 1);
+  __syncthreads();
+  if (t <= mask) cnt[(int64_t)t * ntile + blockIdx.x] = h[t];
+}
 
+// One wave per tile.  Entry i of the tile goes to off[d * ntile + tile] + (its rank among the
+// tile's entries with digit d), ranks taken in rounds of 64 entries in order.  The tile is first
+// reordered by digit in LDS (stable), then written out in that order, so consecutive lanes write
+// consecutive positions of one digit's run and the stores coalesce.
 template <typename TT>
-__global__ __launch_bounds__(256) void k_sort_lower(int64_t n, const int64_t* __restrict__ lower_rp,
-                                                    const int64_t* __restrict__ full_rp,
-                                                    const int32_t* __restrict__ tmp_col,
-                                                    const TT* __restrict__ tmp_val,
-                                                    int32_t* __restrict__ full_col, double* __restrict__ full_v64,
-                                                    float* __restrict__ full_v32) {
-  __shared__ int32_t keys[4][SORT_CAP];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int64_t row = (int64_t)blockIdx.x * 4 + wv;
-  const int64_t b = row < n ? lower_rp[row] : 0, e = row < n ? lower_rp[row + 1] : 0;
-  const int64_t L = e - b;
-  const bool staged = L <= SORT_CAP;
-  if (staged)
-    for (int64_t t = lane; t < L; t += 64) keys[wv][t] = tmp_col[b + t];
-  __syncthreads();  // every thread of the block reaches this (no early return)
-  if (row >= n) return;
-  const int64_t dst = full_rp[row];
-  for (int64_t t = lane; t < L; t += 64) {
-    const int32_t key = tmp_col[b + t];
-    int64_t rank = 0;
-    if (staged) {
-      const int32_t* kw = keys[wv];
-      for (int f = 0; f < (int)L; ++f) rank += kw[f] < key;
-    } else {
-      for (int64_t f = 0; f < L; ++f) rank += tmp_col[b + f] < key;
+__global__ __launch_bounds__(64) void k_rs_scatter(int64_t m, const int32_t* __restrict__ kin,
+                                                   const int32_t* __restrict__ rin, const TT* __restrict__ vin,
+                                                   int32_t* __restrict__ kout, int32_t* __restrict__ rout,
+                                                   TT* __restrict__ vout, int shift, int bits, int64_t ntile,
+                                                   const int32_t* __restrict__ cnt,
+                                                   const int64_t* __restrict__ off) {
+  __shared__ int64_t gbase[256];  // first global position of each digit's run of this tile
+  __shared__ int lbase[256];      // first position of each digit's run in the reordered tile
+  __shared__ int lnext[256];      // next free position of each digit's run (ranking)
+  __shared__ int32_t sk[RS_TILE], sr[RS_TILE];
+  __shared__ TT sv[RS_TILE];
+  const int lane = threadIdx.x;
+  const int mask = (1 << bits) - 1;
+  const int64_t i0 = (int64_t)blockIdx.x * RS_TILE;
+  const int nt = (int)min<int64_t>(RS_TILE, m - i0);
+  int32_t kk[RS_ROUNDS], rr[RS_ROUNDS];
+  TT vv[RS_ROUNDS];
+#pragma unroll
+  for (int q = 0; q < RS_ROUNDS; ++q) {
+    const int i = q * 64 + lane;
+    const bool ok = i < nt;
+    kk[q] = ok ? kin[i0 + i] : 0;
+    rr[q] = ok ? rin[i0 + i] : 0;
+    vv[q] = ok ? vin[i0 + i] : TT(0);
+  }
+  // exclusive prefix of this tile's digit counts: lane owns digits 4 lane .. 4 lane + 3
+  {
+    int c4[4], sum = 0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int d = 4 * lane + u;
+      c4[u] = d <= mask ? cnt[(int64_t)d * ntile + blockIdx.x] : 0;
+      sum += c4[u];
     }
-    full_col[dst + rank] = key;
-    const double v = (double)tmp_val[b + t];
-    if (full_v64) full_v64[dst + rank] = v;
-    if (full_v32) full_v32[dst + rank] = (float)v;
+    int inc = sum;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int y = __shfl_up(inc, o);
+      if (lane >= o) inc += y;
+    }
+    int run = inc - sum;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int d = 4 * lane + u;
+      lbase[d] = run;
+      lnext[d] = run;
+      gbase[d] = d <= mask ? off[(int64_t)d * ntile + blockIdx.x] : 0;
+      run += c4[u];
+    }
+  }
+  __syncthreads();
+  const unsigned long long below = (1ull << lane) - 1ull;
+#pragma unroll
+  for (int q = 0; q < RS_ROUNDS; ++q) {
+    const bool ok = q * 64 + lane < nt;
+    const int d = ((uint32_t)kk[q] >> shift) & mask;
+    unsigned long long peers = __ballot(ok);
+#pragma unroll
+    for (int bb = 0; bb < 8; ++bb) {
+      if (bb < bits) {
+        const unsigned long long bal = __ballot((d >> bb) & 1);
+        peers &= ((d >> bb) & 1) ? bal : ~bal;
+      }
+    }
+    // the lowest peer advances the digit's cursor after every lane has read it (one wave: its
+    // LDS accesses take effect in program order)
+    const int lp = lnext[d] + __popcll(peers & below);
+    if (ok) {
+      sk[lp] = kk[q];
+      sr[lp] = rr[q];
+      sv[lp] = vv[q];
+      if ((peers & below) == 0) lnext[d] += __popcll(peers);
+    }
+  }
+  __syncthreads();
+  for (int i = lane; i < nt; i += 64) {
+    const int32_t k = sk[i];
+    const int d = ((uint32_t)k >> shift) & mask;
+    const int64_t pos = gbase[d] + (i - lbase[d]);
+    kout[pos] = k;
+    rout[pos] = sr[i];
+    vout[pos] = sv[i];
+  }
+}
+
+// first index of each column's run in the sorted keys: lower_rp[c] for c in [0, n]
+__global__ void k_run_starts(int64_t m, int64_t n, const int32_t* __restrict__ key, int64_t* __restrict__ lrp) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i > m) return;
+  const int64_t lo = i == 0 ? 0 : (int64_t)key[i - 1] + 1;  // columns whose run starts at i
+  const int64_t hi = i == m ? n : (int64_t)key[i];
+  for (int64_t c = lo; c <= hi; ++c) lrp[c] = i;
+}
+
+// full row = mirrored entries (columns ascending, all < row) followed by the upper row
+template <typename VT, typename TT>
+__global__ void k_fill(int64_t n, const int64_t* __restrict__ up_rp, const int32_t* __restrict__ up_col,
+                       const VT* __restrict__ up_val, const int64_t* __restrict__ lower_rp,
+                       const int32_t* __restrict__ lrow, const TT* __restrict__ lval,
+                       const int64_t* __restrict__ full_rp, int32_t* __restrict__ full_col,
+                       double* __restrict__ full_v64, float* __restrict__ full_v32) {
+  const int lane = threadIdx.x & 63;
+  const int64_t row = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (row >= n) return;
+  const int64_t lb = lower_rp[row], nl = lower_rp[row + 1] - lb;
+  const int64_t dst = full_rp[row];
+  for (int64_t t = lane; t < nl; t += 64) {
+    full_col[dst + t] = lrow[lb + t];
+    const double v = (double)lval[lb + t];
+    if (full_v64) full_v64[dst + t] = v;
+    if (full_v32) full_v32[dst + t] = (float)v;
+  }
+  const int64_t b = up_rp[row], e = up_rp[row + 1];
+  for (int64_t t = b + lane; t < e; t += 64) {
+    const int64_t o = dst + nl + (t - b);
+    full_col[o] = up_col[t];
+    const double v = (double)up_val[t];
+    if (full_v64) full_v64[o] = v;
+    if (full_v32) full_v32[o] = (float)v;
   }
 }
 
@@ -803,29 +909,57 @@ void spmm_cheb(const DevCSR& H, const double* X, int64_t ldx, double* Y, int64_t
     launch_spmm<float, double>(H, H.val32, X, ldx, Y, ldy, b, nullptr, s, ea, ec, eb, Zo, ldz);
 }
 
+template <typename VT, typename TT>
+void mirror_and_fill(int64_t n, int64_t m, const int64_t* up_rp, const int32_t* up_col, const VT* up_val,
+                     const int64_t* su_off, DevCSR& out, int64_t* lower_rp, int32_t* key[2], int32_t* rowi[2],
+                     TT* v[2], int32_t* cnt, int64_t* off, int64_t* bsum, hipStream_t s) {
+  const int64_t grid_w = cdiv(n, 4);
+  k_extract_upper<VT, TT><<<grid_w, 256, 0, s>>>(n, up_rp, up_col, up_val, su_off, key[0], rowi[0], v[0]);
+  int cur = 0;
+  if (m > 0) {
+    int kb = 1;  // bits of the largest column index
+    while (kb < 31 && ((int64_t)1 << kb) < n) ++kb;
+    const int passes = (kb + 7) / 8;
+    const int64_t ntile = cdiv(m, RS_TILE);
+    for (int p = 0, shift = 0; p < passes; ++p) {
+      const int bits = std::min(8, (kb - shift + (passes - p) - 1) / (passes - p));
+      k_rs_hist<<<ntile, 256, 0, s>>>(m, key[cur], shift, (1 << bits) - 1, ntile, cnt);
+      scan_exclusive_impl(ntile << bits, cnt, off, bsum, s);
+      k_rs_scatter<TT><<<ntile, 64, 0, s>>>(m, key[cur], rowi[cur], v[cur], key[cur ^ 1], rowi[cur ^ 1], v[cur ^ 1],
+                                            shift, bits, ntile, cnt, off);
+      cur ^= 1;
+      shift += bits;
+    }
+  }
+  k_run_starts<<<cdiv(m + 1, 256), 256, 0, s>>>(m, n, key[cur], lower_rp);
+  k_full_rowptr<<<cdiv(n + 1, 256), 256, 0, s>>>(n, lower_rp, up_rp, out.rp);
+  k_fill<VT, TT><<<grid_w, 256, 0, s>>>(n, up_rp, up_col, up_val, lower_rp, rowi[cur], v[cur], out.rp, out.col,
+                                        out.val64, out.val32);
+  SPPC_LAUNCH_CHECK();
+}
+
 void build_full_csr(int64_t n, int64_t nnz_up, const int64_t* up_rp, const int32_t* up_col,
                     const void* up_val, int val_is_f32, DevCSR& out, int* d_flags, bool want64,
                     bool want32, bool& exact32, hipStream_t s) {
-  int32_t *lower_cnt = nullptr, *fillc = nullptr, *tmp_col = nullptr;
-  int64_t *lower_rp = nullptr, *bsum = nullptr;
-  double* tmp_val = nullptr;
+  int32_t *su_cnt = nullptr, *cnt = nullptr;
+  int64_t *su_off = nullptr, *lower_rp = nullptr, *bsum = nullptr, *off = nullptr;
+  int32_t* key[2] = {nullptr, nullptr};
+  int32_t* rowi[2] = {nullptr, nullptr};
+  void* v[2] = {nullptr, nullptr};
   auto cleanup = [&]() {
-    dev_free(lower_cnt); dev_free(fillc); dev_free(tmp_col); dev_free(lower_rp); dev_free(bsum);
-    dev_free(tmp_val);
+    dev_free(su_cnt); dev_free(cnt); dev_free(su_off); dev_free(lower_rp); dev_free(bsum); dev_free(off);
+    for (int i = 0; i < 2; ++i) { dev_free(key[i]); dev_free(rowi[i]); dev_free(v[i]); }
   };
   try {
-    SPPC_HIP(dev_malloc(&lower_cnt, sizeof(int32_t) * (n + 1)));
-    SPPC_HIP(dev_malloc(&fillc, sizeof(int32_t) * (n + 1)));
+    SPPC_HIP(dev_malloc(&su_cnt, sizeof(int32_t) * (n + 1)));
+    SPPC_HIP(dev_malloc(&su_off, sizeof(int64_t) * (n + 1)));
     SPPC_HIP(dev_malloc(&lower_rp, sizeof(int64_t) * (n + 1)));
-    SPPC_HIP(dev_malloc(&bsum, sizeof(int64_t) * (cdiv(n, SCAN_BLOCK) + 1)));
-    SPPC_HIP(hipMemsetAsync(lower_cnt, 0, sizeof(int32_t) * (n + 1), s));
-    SPPC_HIP(hipMemsetAsync(fillc, 0, sizeof(int32_t) * (n + 1), s));
     SPPC_HIP(hipMemsetAsync(d_flags, 0, sizeof(int) * 4, s));
     const int64_t grid_w = cdiv(n, 4);
     if (val_is_f32)
-      k_validate_count<float><<<grid_w, 256, 0, s>>>(n, up_rp, up_col, (const float*)up_val, lower_cnt, d_flags);
+      k_validate_count<float><<<grid_w, 256, 0, s>>>(n, up_rp, up_col, (const float*)up_val, su_cnt, d_flags);
     else
-      k_validate_count<double><<<grid_w, 256, 0, s>>>(n, up_rp, up_col, (const double*)up_val, lower_cnt, d_flags);
+      k_validate_count<double><<<grid_w, 256, 0, s>>>(n, up_rp, up_col, (const double*)up_val, su_cnt, d_flags);
     SPPC_LAUNCH_CHECK();
     int h_flags[4];
     SPPC_HIP(hipMemcpyAsync(h_flags, d_flags, sizeof(h_flags), hipMemcpyDeviceToHost, s));
@@ -833,42 +967,49 @@ void build_full_csr(int64_t n, int64_t nnz_up, const int64_t* up_rp, const int32
     if (h_flags[0]) throw Error(1, "H: upper CSR expected (columns >= row, < n, strictly ascending)");
     if (h_flags[2]) throw Error(7, "H: NaN or Inf among the values");
     exact32 = val_is_f32 || !h_flags[1];
-    scan_exclusive_impl(n, lower_cnt, lower_rp, bsum, s);
-    int64_t nlow = 0;
-    SPPC_HIP(hipMemcpyAsync(&nlow, lower_rp + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    SPPC_HIP(dev_malloc(&bsum, sizeof(int64_t) * (cdiv(n, SCAN_BLOCK) + 1)));
+    scan_exclusive_impl(n, su_cnt, su_off, bsum, s);
+    int64_t m = 0;  // strict-upper entries = mirrored entries
+    SPPC_HIP(hipMemcpyAsync(&m, su_off + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     SPPC_HIP(hipStreamSynchronize(s));
-    const int64_t nnz = nnz_up + nlow;
+    const int64_t nnz = nnz_up + m;
     out.n = n;
     out.nnz = nnz;
     SPPC_HIP(dev_malloc(&out.rp, sizeof(int64_t) * (n + 1)));
     SPPC_HIP(dev_malloc(&out.col, sizeof(int32_t) * (nnz > 0 ? nnz : 1)));
     if (want64) SPPC_HIP(dev_malloc(&out.val64, sizeof(double) * (nnz > 0 ? nnz : 1)));
     if (want32) SPPC_HIP(dev_malloc(&out.val32, sizeof(float) * (nnz > 0 ? nnz : 1)));
-    SPPC_HIP(dev_malloc(&tmp_col, sizeof(int32_t) * (nlow > 0 ? nlow : 1)));
-    // staged mirrored values: float32 suffice when only float32 values are kept
-    SPPC_HIP(dev_malloc(&tmp_val, (want64 ? sizeof(double) : sizeof(float)) * (nlow > 0 ? nlow : 1)));
-    k_full_rowptr<<<cdiv(n + 1, 256), 256, 0, s>>>(n, lower_rp, up_rp, out.rp);
-    if (want64) {
-      if (val_is_f32)
-        k_fill<float, double><<<grid_w, 256, 0, s>>>(n, up_rp, up_col, (const float*)up_val, lower_rp, out.rp,
-                                                     fillc, out.col, out.val64, out.val32, tmp_col, tmp_val);
-      else
-        k_fill<double, double><<<grid_w, 256, 0, s>>>(n, up_rp, up_col, (const double*)up_val, lower_rp, out.rp,
-                                                      fillc, out.col, out.val64, out.val32, tmp_col, tmp_val);
-      k_sort_lower<double><<<grid_w, 256, 0, s>>>(n, lower_rp, out.rp, tmp_col, tmp_val, out.col, out.val64,
-                                                  out.val32);
-    } else {
-      float* tv = (float*)tmp_val;
-      if (val_is_f32)
-        k_fill<float, float><<<grid_w, 256, 0, s>>>(n, up_rp, up_col, (const float*)up_val, lower_rp, out.rp,
-                                                    fillc, out.col, out.val64, out.val32, tmp_col, tv);
-      else
-        k_fill<double, float><<<grid_w, 256, 0, s>>>(n, up_rp, up_col, (const double*)up_val, lower_rp, out.rp,
-                                                     fillc, out.col, out.val64, out.val32, tmp_col, tv);
-      k_sort_lower<float><<<grid_w, 256, 0, s>>>(n, lower_rp, out.rp, tmp_col, tv, out.col, out.val64,
-                                                 out.val32);
+    // sort buffers (twice: the passes alternate between them) and the digit counts
+    const int64_t ms = m > 0 ? m : 1;
+    const size_t vb = want64 ? sizeof(double) : sizeof(float);
+    for (int i = 0; i < 2; ++i) {
+      SPPC_HIP(dev_malloc(&key[i], sizeof(int32_t) * ms));
+      SPPC_HIP(dev_malloc(&rowi[i], sizeof(int32_t) * ms));
+      SPPC_HIP(dev_alloc(&v[i], vb * ms));
     }
-    SPPC_LAUNCH_CHECK();
+    const int64_t ncnt = (cdiv(ms, RS_TILE) << 8) + 1;
+    SPPC_HIP(dev_malloc(&cnt, sizeof(int32_t) * ncnt));
+    SPPC_HIP(dev_malloc(&off, sizeof(int64_t) * (ncnt + 1)));
+    dev_free(bsum);
+    bsum = nullptr;
+    SPPC_HIP(dev_malloc(&bsum, sizeof(int64_t) * (cdiv(std::max(ncnt, n + 1), SCAN_BLOCK) + 1)));
+    if (want64) {
+      double* vv[2] = {(double*)v[0], (double*)v[1]};
+      if (val_is_f32)
+        mirror_and_fill<float, double>(n, m, up_rp, up_col, (const float*)up_val, su_off, out, lower_rp, key, rowi,
+                                       vv, cnt, off, bsum, s);
+      else
+        mirror_and_fill<double, double>(n, m, up_rp, up_col, (const double*)up_val, su_off, out, lower_rp, key,
+                                        rowi, vv, cnt, off, bsum, s);
+    } else {
+      float* vv[2] = {(float*)v[0], (float*)v[1]};
+      if (val_is_f32)
+        mirror_and_fill<float, float>(n, m, up_rp, up_col, (const float*)up_val, su_off, out, lower_rp, key, rowi,
+                                      vv, cnt, off, bsum, s);
+      else
+        mirror_and_fill<double, float>(n, m, up_rp, up_col, (const double*)up_val, su_off, out, lower_rp, key,
+                                       rowi, vv, cnt, off, bsum, s);
+    }
     SPPC_HIP(hipStreamSynchronize(s));
   } catch (...) {
     (void)hipStreamSynchronize(s);
