@@ -130,9 +130,9 @@ __global__ void k_reduce_partials(int64_t nchunks, int m, int b, const double* _
 
 constexpr int NN_ROWS = 128;  // rows per workgroup: 4 waves x 2 tiles of 16
 
-// Y = beta Y + alpha A C: the reduction dimension of the MFMA is the column index i of A.
-// In step s of a 16-column slab, k-slot q of the MFMA is column i0 + 4 s + q, so the 4 slots
-// of one row read 32 contiguous bytes.
+// Y = beta Y + alpha A C: the reduction dimension of the MFMA is the column index i of A.  In
+// step st of a 16-column slab, k-slot q of the MFMA is column i0 + 4 q + st when the rows of A
+// allow 32-byte loads (VEC: a lane reads its 4 columns of a row at once), else i0 + 4 st + q.
 template <int NT, bool VEC>
 __global__ __launch_bounds__(256) void k_gemm_nn(int64_t n, int m, int b, const double* __restrict__ A,
                                                  int64_t lda, const double* __restrict__ C, int64_t ldc,

@@ -96,6 +96,7 @@ __global__ __launch_bounds__(EIG_THREADS) void k_sym_eig(int m, int nw, const do
                                                          double* __restrict__ V, int64_t ldv,
                                                          double* __restrict__ scr) {
   __shared__ double vsh[512];
+  __shared__ double vsh2[512];
   __shared__ double psh[4][512];
   __shared__ double wsh[512];
   __shared__ double red[16];
@@ -117,38 +118,58 @@ __global__ __launch_bounds__(EIG_THREADS) void k_sym_eig(int m, int nw, const do
   // Rows and columns >= o live in LDS (stride EIG_LDS_M); the rest in global memory (stride m).
   // Step j of the reduction touches only [j, m)^2, so the trailing block moves to LDS once it fits
   // and every later step (and the Householder vectors it stores) stays there.
+  // (2-D loops throughout: rows by thread group, columns by lane, so no index is divided)
+  const int tg = t >> 8, tc = t & 255;
   int o = m;
   if (m <= EIG_LDS_M) {
-    for (int64_t x = t; x < (int64_t)m * m; x += EIG_THREADS)
-      Alds[(x / m) * EIG_LDS_M + (x % m)] = S[(x / m) * lds + (x % m)];
+    for (int r = tg; r < m; r += EIG_THREADS / 256)
+      for (int c = tc; c < m; c += 256) Alds[r * EIG_LDS_M + c] = S[(int64_t)r * lds + c];
     o = 0;
   } else {
-    for (int64_t x = t; x < (int64_t)m * m; x += EIG_THREADS) A[x] = S[(x / m) * lds + (x % m)];
+    for (int r = tg; r < m; r += EIG_THREADS / 256)
+      for (int c = tc; c < m; c += 256) A[(int64_t)r * m + c] = S[(int64_t)r * lds + c];
   }
   __syncthreads();
 
   // ---- Householder tridiagonalisation (the lower part; A stays symmetric)
+  // While the trailing block is in global memory, the rank-2 update of step j - 1 is not applied
+  // in a pass of its own: step j applies it to row j as it forms its Householder vector, and to
+  // the rest of the block in the same pass that forms A v (each element read and written once
+  // per step instead of read twice and written once).  up/wp hold v and w of step j - 1 (index 0
+  // = row j), vc the vector of step j.
+  bool pend = false;
   for (int j = 0; j + 2 < m; ++j) {
+    double* const vc = (j & 1) ? vsh2 : vsh;
+    const double* const up = (j & 1) ? vsh : vsh2;
     if (o > j && m - j <= EIG_LDS_M) {
+      // the trailing block moves to LDS, with the pending update of step j - 1
       const int len0 = m - j;
-      for (int64_t x = t; x < (int64_t)len0 * len0; x += EIG_THREADS)
-        Alds[(x / len0) * EIG_LDS_M + (x % len0)] = A[(int64_t)(j + x / len0) * m + j + (x % len0)];
+      for (int r = tg; r < len0; r += EIG_THREADS / 256) {
+        const double ur = pend ? up[r] : 0.0, wr = pend ? wsh[r] : 0.0;
+        for (int c = tc; c < len0; c += 256)
+          Alds[r * EIG_LDS_M + c] = A[(int64_t)(j + r) * m + j + c] - (ur * wsh[c] + wr * up[c]);
+      }
       __syncthreads();
       o = j;
+      pend = false;
     }
     double* const base = j >= o ? Alds : A;
     const int ld = j >= o ? EIG_LDS_M : m;
     const int off = j >= o ? o : 0;
     const int len = m - 1 - j;
-    // row j, columns j+1.. == column j below the diagonal.  Wave 0 forms the Householder vector
-    // alone (no block-wide reduction), the other waves wait at the barrier.
+    // row j, columns j+1.. == column j below the diagonal (with the pending update).  Wave 0 forms
+    // the Householder vector alone (no block-wide reduction), the other waves wait at the barrier.
     const double* xr = base + (int64_t)(j - off) * ld + (j + 1 - off);
     if (t < 64) {
+      const double u0 = pend ? up[0] : 0.0, w0 = pend ? wsh[0] : 0.0;
       double part = 0.0;
-      for (int i = 1 + t; i < len; i += 64) part += xr[i] * xr[i];
+      for (int i = 1 + t; i < len; i += 64) {
+        const double x = xr[i] - (u0 * wsh[1 + i] + w0 * up[1 + i]);
+        part += x * x;
+      }
       for (int o2 = 32; o2 > 0; o2 >>= 1) part += __shfl_xor(part, o2);
       const double sigma = part;
-      const double alpha = xr[0];
+      const double alpha = xr[0] - (u0 * wsh[1] + w0 * up[1]);
       double b = 0.0, v0 = 1.0, ej = alpha;
       if (sigma > 0.0) {
         const double mu = sqrt(alpha * alpha + sigma);
@@ -157,89 +178,106 @@ __global__ __launch_bounds__(EIG_THREADS) void k_sym_eig(int m, int nw, const do
         ej = mu;
       }
       if (t == 0) {
-        d[j] = base[(int64_t)(j - off) * ld + (j - off)];
+        d[j] = base[(int64_t)(j - off) * ld + (j - off)] - 2.0 * u0 * w0;
         e[j] = ej;
         beta[j] = b;
         sc[0] = b;
       }
-      for (int i = t; i < len; i += 64) vsh[i] = i == 0 ? 1.0 : (b == 0.0 ? 0.0 : xr[i] / v0);
+      for (int i = t; i < len; i += 64) {
+        const double x = i == 0 ? alpha : xr[i] - (u0 * wsh[1 + i] + w0 * up[1 + i]);
+        vc[i] = i == 0 ? 1.0 : (b == 0.0 ? 0.0 : x / v0);
+      }
     }
     __syncthreads();
     const double b = sc[0];
     // keep v for the back-transformation in row j (no longer needed otherwise)
-    for (int i = t; i < len; i += EIG_THREADS) base[(int64_t)(j - off) * ld + (j + 1 - off) + i] = vsh[i];
-    if (b != 0.0 && j >= o) {
-      // trailing block in LDS (len <= 128): thread (lg, i) owns column i and the rows l = lg mod 8,
-      // with v_i and w_i in registers; p_i in 8 partial sums
-      const int i = t & 127, lg = t >> 7;
-      double* pp = &psh[0][0];  // [8][128]
-      const double vi = i < len ? vsh[i] : 0.0;
-      double* ci = base + (int64_t)(j + 1 - off) * ld + (j + 1 - off) + i;
-      if (i < len) {
-        double s0 = 0.0, s1 = 0.0;
-        int l = lg;
-        for (; l + 8 < len; l += 16) {
-          s0 += ci[(int64_t)l * ld] * vsh[l];
-          s1 += ci[(int64_t)(l + 8) * ld] * vsh[l + 8];
+    for (int i = t; i < len; i += EIG_THREADS) base[(int64_t)(j - off) * ld + (j + 1 - off) + i] = vc[i];
+    if (j >= o) {
+      if (b != 0.0) {
+        // trailing block in LDS (len <= 128): thread (lg, i) owns column i and the rows l = lg mod
+        // 8, with v_i and w_i in registers; p_i in 8 partial sums
+        const int i = t & 127, lg = t >> 7;
+        double* pp = &psh[0][0];  // [8][128]
+        const double vi = i < len ? vc[i] : 0.0;
+        double* ci = base + (int64_t)(j + 1 - off) * ld + (j + 1 - off) + i;
+        if (i < len) {
+          double s0 = 0.0, s1 = 0.0;
+          int l = lg;
+          for (; l + 8 < len; l += 16) {
+            s0 += ci[(int64_t)l * ld] * vc[l];
+            s1 += ci[(int64_t)(l + 8) * ld] * vc[l + 8];
+          }
+          if (l < len) s0 += ci[(int64_t)l * ld] * vc[l];
+          pp[lg * 128 + i] = s0 + s1;
         }
-        if (l < len) s0 += ci[(int64_t)l * ld] * vsh[l];
-        pp[lg * 128 + i] = s0 + s1;
-      }
-      __syncthreads();
-      if (t < 64) {
-        double kp = 0.0;
-        for (int i2 = t; i2 < len; i2 += 64) {
-          double pi = 0.0;
+        __syncthreads();
+        if (t < 64) {
+          double kp = 0.0;
+          for (int i2 = t; i2 < len; i2 += 64) {
+            double pi = 0.0;
 #pragma unroll
-          for (int g8 = 0; g8 < 8; ++g8) pi += pp[g8 * 128 + i2];
-          pi *= b;
-          wsh[i2] = pi;
-          kp += pi * vsh[i2];
+            for (int g8 = 0; g8 < 8; ++g8) pi += pp[g8 * 128 + i2];
+            pi *= b;
+            wsh[i2] = pi;
+            kp += pi * vc[i2];
+          }
+          for (int o2 = 32; o2 > 0; o2 >>= 1) kp += __shfl_xor(kp, o2);
+          const double K = 0.5 * b * kp;
+          for (int i2 = t; i2 < len; i2 += 64) wsh[i2] -= K * vc[i2];
         }
-        for (int o2 = 32; o2 > 0; o2 >>= 1) kp += __shfl_xor(kp, o2);
-        const double K = 0.5 * b * kp;
-        for (int i2 = t; i2 < len; i2 += 64) wsh[i2] -= K * vsh[i2];
+        __syncthreads();
+        if (i < len) {
+          const double wi = wsh[i];
+          for (int l = lg; l < len; l += 8) ci[(int64_t)l * ld] -= vc[l] * wi + wsh[l] * vi;
+        }
       }
-      __syncthreads();
-      if (i < len) {
-        const double wi = wsh[i];
-        for (int l = lg; l < len; l += 8) ci[(int64_t)l * ld] -= vsh[l] * wi + wsh[l] * vi;
-      }
-    } else if (b != 0.0) {
-      // p = b * A_tr v, A_tr = A[j+1.., j+1..]; 4 row groups x 256 columns
+    } else {
+      // trailing block in global memory: apply the pending update of step j - 1 and form
+      // p = b * A_tr v in one pass (4 row groups x 256 columns)
       const int grp = t >> 8, tl = t & 255;
       const int l0 = (len * grp) / 4, l1 = (len * (grp + 1)) / 4;
       for (int i = tl; i < len; i += 256) {
-        const double* col = base + (int64_t)(j + 1 - off) * ld + (j + 1 - off) + i;
-        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        double* col = base + (int64_t)(j + 1 - off) * ld + (j + 1 - off) + i;
+        const double ui = pend ? up[1 + i] : 0.0, wi = pend ? wsh[1 + i] : 0.0;
+        double s0 = 0.0, s1 = 0.0;
         int l = l0;
-        for (; l + 3 < l1; l += 4) {
-          s0 += col[(int64_t)l * ld] * vsh[l];
-          s1 += col[(int64_t)(l + 1) * ld] * vsh[l + 1];
-          s2 += col[(int64_t)(l + 2) * ld] * vsh[l + 2];
-          s3 += col[(int64_t)(l + 3) * ld] * vsh[l + 3];
+        if (pend) {
+          for (; l + 1 < l1; l += 2) {
+            const double a0 = col[(int64_t)l * ld] - (up[1 + l] * wi + wsh[1 + l] * ui);
+            const double a1 = col[(int64_t)(l + 1) * ld] - (up[2 + l] * wi + wsh[2 + l] * ui);
+            col[(int64_t)l * ld] = a0;
+            col[(int64_t)(l + 1) * ld] = a1;
+            s0 += a0 * vc[l];
+            s1 += a1 * vc[l + 1];
+          }
+          for (; l < l1; ++l) {
+            const double a0 = col[(int64_t)l * ld] - (up[1 + l] * wi + wsh[1 + l] * ui);
+            col[(int64_t)l * ld] = a0;
+            s0 += a0 * vc[l];
+          }
+        } else {
+          for (; l + 1 < l1; l += 2) {
+            s0 += col[(int64_t)l * ld] * vc[l];
+            s1 += col[(int64_t)(l + 1) * ld] * vc[l + 1];
+          }
+          for (; l < l1; ++l) s0 += col[(int64_t)l * ld] * vc[l];
         }
-        for (; l < l1; ++l) s0 += col[(int64_t)l * ld] * vsh[l];
-        psh[grp][i] = (s0 + s1) + (s2 + s3);
+        psh[grp][i] = s0 + s1;
       }
-      __syncthreads();
-      // w = p - (b/2)(v^T p) v, by wave 0
+      __syncthreads();  // every read of the previous step's w is done
+      // w = p - (b/2)(v^T p) v, by wave 0 (zero when b = 0: the update is then empty)
       if (t < 64) {
         double kp = 0.0;
         for (int i = t; i < len; i += 64) {
           const double pi = b * (psh[0][i] + psh[1][i] + psh[2][i] + psh[3][i]);
           wsh[i] = pi;
-          kp += pi * vsh[i];
+          kp += pi * vc[i];
         }
         for (int o2 = 32; o2 > 0; o2 >>= 1) kp += __shfl_xor(kp, o2);
         const double K = 0.5 * b * kp;
-        for (int i = t; i < len; i += 64) wsh[i] -= K * vsh[i];
+        for (int i = t; i < len; i += 64) wsh[i] -= K * vc[i];
       }
-      __syncthreads();
-      for (int64_t x = t; x < (int64_t)len * len; x += EIG_THREADS) {
-        const int l = (int)(x / len), i = (int)(x % len);
-        base[(int64_t)(j + 1 + l - off) * ld + (j + 1 + i - off)] -= vsh[l] * wsh[i] + wsh[l] * vsh[i];
-      }
+      pend = true;
     }
     __syncthreads();
   }
@@ -389,13 +427,27 @@ __global__ __launch_bounds__(EIG_THREADS) void k_sym_eig(int m, int nw, const do
   }
   __syncthreads();
 
-  // ---- back-transformation V = H_0 H_1 ... H_{m-3} Y ; one wave per eigenvector column
+  // ---- back-transformation V = H_0 H_1 ... H_{m-3} Y ; one wave per eigenvector column.  The
+  // Householder vectors go back to LDS, packed after Y, when both fit (v_j of length m-1-j at
+  // offset j (m-1) - j (j-1)/2): each of the m sequential steps then reads LDS, not L2.
+  const int64_t yl = (Y == Alds) ? (int64_t)nw * m : 0;
+  const int64_t hvn = m >= 3 ? (int64_t)(m - 1) * m / 2 - 1 : 0;
+  double* hv = nullptr;
+  if (yl + hvn <= (int64_t)(sizeof(Alds) / sizeof(double))) {
+    hv = Alds + yl;
+    for (int j = tg; j + 2 < m; j += EIG_THREADS / 256) {
+      const int len = m - 1 - j;
+      double* dst = hv + (int64_t)j * (m - 1) - (int64_t)j * (j - 1) / 2;
+      for (int i = tc; i < len; i += 256) dst[i] = A[(int64_t)j * m + j + 1 + i];
+    }
+    __syncthreads();
+  }
   const int wv = t >> 6, ln = t & 63;
   for (int j = m - 3; j >= 0; --j) {
     const double b = beta[j];
     if (b != 0.0) {
       const int len = m - 1 - j;
-      const double* v = j >= o ? Alds + (int64_t)(j - o) * EIG_LDS_M + (j + 1 - o) : A + (int64_t)j * m + j + 1;
+      const double* v = hv ? hv + (int64_t)j * (m - 1) - (int64_t)j * (j - 1) / 2 : A + (int64_t)j * m + j + 1;
       for (int c = wv; c < nw; c += EIG_THREADS / 64) {
         double* y = Y + (int64_t)c * m + j + 1;
         double s = 0.0;
