@@ -155,3 +155,73 @@ def test_invalid_calls_on_a_context(P):
     ev, Z, rrn, st, status = P.sppc_solve(ctx)
     assert status == P.SPPC_OK
     P.sppc_destroy(ctx)
+
+
+def _structures():
+    """Upper CSRs whose mirror is unusual: no strict-upper entries at all, rows without any entry
+    (and without the diagonal), one row coupled to every later column, one column coupled to every
+    earlier row (a mirrored row of n - 1 entries), and n above 2^16 (three radix passes)."""
+    rng = np.random.default_rng(5)
+    out = []
+    n = 300
+    d = np.arange(n, dtype=np.int64)
+    dv = 10.0 * (d >= 20) + rng.uniform(-1, 1, n)
+    out.append(("diagonal only", _Upper(n, d, d, dv, [0, 20, n])))
+    r = rng.integers(0, n, 2000)
+    c = rng.integers(0, n, 2000)
+    r, c = np.minimum(r, c), np.maximum(r, c)
+    empty = (r % 7 == 3) | (c % 7 == 3)       # rows/columns 3, 10, 17, ... stay empty
+    keepd = (d % 7 != 3) | (d < 20)
+    rows = np.concatenate([d[keepd], r[~empty]])
+    cols = np.concatenate([d[keepd], c[~empty]])
+    pairs = np.unique(np.stack([rows, cols], 1), axis=0)
+    vals = np.where(pairs[:, 0] == pairs[:, 1], 10.0 * (pairs[:, 0] >= 20), 0.0) + rng.normal(0, 0.5, len(pairs))
+    out.append(("empty rows", _Upper(n, pairs[:, 0], pairs[:, 1], vals, [0, 20, n])))
+    n = 3000
+    d = np.arange(n, dtype=np.int64)
+    rows = np.concatenate([d, np.zeros(n - 1, np.int64), np.arange(1, n - 1)])
+    cols = np.concatenate([d, np.arange(1, n), np.full(n - 2, n - 1)])
+    pairs = np.unique(np.stack([rows, cols], 1), axis=0)
+    vals = np.where(pairs[:, 0] == pairs[:, 1], 10.0 * (pairs[:, 0] >= 30) + 1.0 + 0.01 * pairs[:, 0], 0.01)
+    out.append(("dense row and column", _Upper(n, pairs[:, 0], pairs[:, 1], vals, [0, 30, n])))
+    B = levelgen.generate((100, 1000, 70000), 8, 12)
+    out.append(("n = 71,100", B))
+    return out
+
+
+@pytest.mark.parametrize("panel", [0, 1000])
+def test_mirror_of_unusual_structures(P, panel):
+    # the device copy of both triangles, through the block product, against the oracle's product
+    # from the upper triangle (the row-wise CSR kernel, and the panel stream with 1000 columns)
+    for name, A in _structures():
+        print("case edge mirror %s panel=%d" % (name, panel), flush=True)
+        rp, col, val = P.upload(A)
+        ctx = P.sppc_setup(rp, col, val, A.level_offsets, 1, 2, P.sppc_default_opts(panel_width=panel))
+        X = np.random.default_rng(A.n).standard_normal((A.n, 3))
+        Y = torch.empty((A.n, 3), dtype=torch.float64, device="cuda")
+        P.sppc_spmm(ctx, torch.from_numpy(X).cuda(), Y)
+        torch.cuda.synchronize()
+        P.sppc_destroy(ctx)
+        ref = oracle.product_from_upper(A.row_ptr, A.col, A.val, A.n, X)
+        scale = oracle.product_from_upper(A.row_ptr, A.col, np.abs(A.val), A.n, np.abs(X))
+        assert np.max(np.abs(Y.cpu().numpy() - ref) / np.maximum(scale, 1e-300)) < 1e-14, name
+
+
+def test_cached_memory_is_reused_and_released(P):
+    # contexts of two sizes interleaved: the cache hands blocks of one size back to the next context
+    # of that size (stale contents must not matter), and releasing the cache keeps live contexts intact
+    As = [levelgen.generate((20, 90, 300), 14, 4), levelgen.generate((30, 200, 900), 16, 5)]
+    ref = [_lam(A, 2) for A in As]
+    print("case edge memory cache", flush=True)
+    for rep in range(3):
+        for i, A in enumerate(As):
+            ev, Z, rrn, st, status = _solve(P, A, 1, 2)
+            assert status == P.SPPC_OK
+            assert np.max(np.abs(np.array(ev) - ref[i]) / np.abs(ref[i])) < 1e-10
+    rp, col, val = P.upload(As[0])
+    ctx = P.sppc_setup(rp, col, val, As[0].level_offsets, 1, 2, P.sppc_default_opts())
+    assert P.sppc_release_cached_memory() > 0
+    ev, Z, rrn, st, status = P.sppc_solve(ctx)
+    P.sppc_destroy(ctx)
+    assert status == P.SPPC_OK
+    assert np.max(np.abs(np.array(ev) - ref[0]) / np.abs(ref[0])) < 1e-10
