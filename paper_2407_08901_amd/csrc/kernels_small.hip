@@ -24,14 +24,71 @@ __device__ inline double block_sum(double v, double* sh) {
   return s;
 }
 
-// Sturm count: number of eigenvalues of the tridiagonal (d, e) smaller than x.
+// Sum over the 64 lanes of a wave, returned to every lane, with DPP moves instead of the
+// LDS-routed lane shuffles (about 100 cycles of dependent latency instead of about 900):
+// prefix sums within rows of 16 lanes (shifts 1, 2, 4, 8; lanes without a source add 0), then
+// lane 15 of rows 0 and 2 into rows 1 and 3, lane 31 into rows 2 and 3, and lane 63 is read.
+template <int CTRL, int ROWS>
+__device__ inline double dpp_move(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWS, 0xF, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWS, 0xF, true);
+  return __hiloint2double(hi, lo);
+}
+__device__ inline double wave_sum(double v) {
+  v += dpp_move<0x111, 0xF>(v);  // row_shr:1
+  v += dpp_move<0x112, 0xF>(v);  // row_shr:2
+  v += dpp_move<0x114, 0xF>(v);  // row_shr:4
+  v += dpp_move<0x118, 0xF>(v);  // row_shr:8
+  v += dpp_move<0x142, 0xA>(v);  // row_bcast:15 into rows 1, 3
+  v += dpp_move<0x143, 0xC>(v);  // row_bcast:31 into rows 2, 3
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+  return __hiloint2double(hi, lo);
+}
+
+// a / b from the hardware reciprocal refined by one Newton-Raphson step, a few ulp from the
+// rounded quotient: the Sturm counts and the shifted solves of inverse iteration sit on long
+// chains of dependent divisions and do not need the correctly rounded one.  b is nonzero and
+// finite at every call (both callers clamp their pivots away from zero); below 1e-290 the
+// reciprocal could overflow, and the plain division is taken.
+__device__ inline double quick_div(double a, double b) {
+  if (fabs(b) < 1e-290) return a / b;
+  double r = __builtin_amdgcn_rcp(b);
+  r = fma(r, fma(-b, r, 1.0), r);
+  return a * r;
+}
+
+// Sturm count: number of eigenvalues of the tridiagonal (d, e) smaller than x.  The pivots are
+// kept at least 1e-290 in magnitude, so the reciprocal needs no guard.
+__device__ inline double rcp_div(double a, double b) {
+  double r = __builtin_amdgcn_rcp(b);
+  r = fma(r, fma(-b, r, 1.0), r);
+  return a * r;
+}
 __device__ int sturm_count(int m, const double* d, const double* e2, double x, double pivmin) {
+  pivmin = fmax(pivmin, 1e-290);
   int cnt = 0;
   double q = d[0] - x;
   if (fabs(q) < pivmin) q = -pivmin;
   cnt += q < 0.0;
-  for (int i = 1; i < m; ++i) {
-    q = d[i] - x - e2[i - 1] / q;
+  int i = 1;
+  // the operands of 8 steps are loaded ahead of the dependent chain
+  for (; i + 8 <= m; i += 8) {
+    double dd[8], ee[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      dd[u] = d[i + u] - x;
+      ee[u] = e2[i + u - 1];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      q = dd[u] - rcp_div(ee[u], q);
+      if (fabs(q) < pivmin) q = -pivmin;
+      cnt += q < 0.0;
+    }
+  }
+  for (; i < m; ++i) {
+    q = d[i] - x - rcp_div(e2[i - 1], q);
     if (fabs(q) < pivmin) q = -pivmin;
     cnt += q < 0.0;
   }
@@ -52,12 +109,12 @@ __device__ void tri_shifted_solve(int m, const double* d, const double* e, doubl
       const double nb = (k + 1 < m - 1) ? e[k + 1] : 0.0;
       if (fabs(ca) >= fabs(sub)) {
         if (ca == 0.0) ca = epsp;
-        const double mult = sub / ca;
+        const double mult = quick_div(sub, ca);
         u0[k] = ca; u1[k] = cb; u2[k] = 0.0; l[k] = mult; piv[k] = 0;
         ca = na - mult * cb;
         cb = nb;
       } else {
-        const double mult = ca / sub;
+        const double mult = quick_div(ca, sub);
         u0[k] = sub; u1[k] = na; u2[k] = nb; l[k] = mult; piv[k] = 1;
         ca = cb - mult * na;
         cb = -mult * nb;
@@ -76,16 +133,17 @@ __device__ void tri_shifted_solve(int m, const double* d, const double* e, doubl
     }
     y[k + 1] -= l[k] * y[k];
   }
-  y[m - 1] /= u0[m - 1];
-  if (m >= 2) y[m - 2] = (y[m - 2] - u1[m - 2] * y[m - 1]) / u0[m - 2];
-  for (int k = m - 3; k >= 0; --k) y[k] = (y[k] - u1[k] * y[k + 1] - u2[k] * y[k + 2]) / u0[k];
+  y[m - 1] = quick_div(y[m - 1], u0[m - 1]);
+  if (m >= 2) y[m - 2] = quick_div(y[m - 2] - u1[m - 2] * y[m - 1], u0[m - 2]);
+  for (int k = m - 3; k >= 0; --k) y[k] = quick_div(y[k] - u1[k] * y[k + 1] - u2[k] * y[k + 2], u0[k]);
 }
 
 __device__ void normalize(int m, double* y) {
   double s = 0.0, mx = 0.0;
   for (int i = 0; i < m; ++i) mx = fmax(mx, fabs(y[i]));
   if (mx == 0.0) return;
-  for (int i = 0; i < m; ++i) { y[i] /= mx; s += y[i] * y[i]; }
+  const double rmx = 1.0 / mx;
+  for (int i = 0; i < m; ++i) { y[i] *= rmx; s += y[i] * y[i]; }
   s = 1.0 / sqrt(s);
   for (int i = 0; i < m; ++i) y[i] *= s;
 }
@@ -102,6 +160,9 @@ __global__ __launch_bounds__(EIG_THREADS) void k_sym_eig(int m, int nw, const do
   __shared__ double red[16];
   __shared__ double sc[4];
   __shared__ double Alds[EIG_LDS_M * EIG_LDS_M];  // the working matrix when it fits
+  // d, e and beta of the steps taken in LDS (j >= o): a global store in the step would make the
+  // next barrier wait for it
+  __shared__ double dej[3][EIG_LDS_M];
   const int t = threadIdx.x;
   double* A = scr;  // the working matrix in global memory (ld m) while it does not fit in LDS
   double* d = scr + (int64_t)m * m;
@@ -132,11 +193,11 @@ __global__ __launch_bounds__(EIG_THREADS) void k_sym_eig(int m, int nw, const do
   __syncthreads();
 
   // ---- Householder tridiagonalisation (the lower part; A stays symmetric)
-  // While the trailing block is in global memory, the rank-2 update of step j - 1 is not applied
-  // in a pass of its own: step j applies it to row j as it forms its Householder vector, and to
-  // the rest of the block in the same pass that forms A v (each element read and written once
-  // per step instead of read twice and written once).  up/wp hold v and w of step j - 1 (index 0
-  // = row j), vc the vector of step j.
+  // The rank-2 update of step j - 1 is not applied in a pass of its own: step j applies it to
+  // row j as it forms its Householder vector, and to the rest of the trailing block in the same
+  // pass that forms A v (each element read and written once per step instead of read twice and
+  // written once, and one barrier less); the last 2 x 2 block takes the last step's update at
+  // the end.  up/wsh hold v and w of step j - 1 (index 0 = row j), vc the vector of step j.
   bool pend = false;
   for (int j = 0; j + 2 < m; ++j) {
     double* const vc = (j & 1) ? vsh2 : vsh;
@@ -167,7 +228,7 @@ __global__ __launch_bounds__(EIG_THREADS) void k_sym_eig(int m, int nw, const do
         const double x = xr[i] - (u0 * wsh[1 + i] + w0 * up[1 + i]);
         part += x * x;
       }
-      for (int o2 = 32; o2 > 0; o2 >>= 1) part += __shfl_xor(part, o2);
+      part = wave_sum(part);
       const double sigma = part;
       const double alpha = xr[0] - (u0 * wsh[1] + w0 * up[1]);
       double b = 0.0, v0 = 1.0, ej = alpha;
@@ -178,14 +239,22 @@ __global__ __launch_bounds__(EIG_THREADS) void k_sym_eig(int m, int nw, const do
         ej = mu;
       }
       if (t == 0) {
-        d[j] = base[(int64_t)(j - off) * ld + (j - off)] - 2.0 * u0 * w0;
-        e[j] = ej;
-        beta[j] = b;
+        const double dj = base[(int64_t)(j - off) * ld + (j - off)] - 2.0 * u0 * w0;
+        if (j >= o) {
+          dej[0][j - o] = dj;
+          dej[1][j - o] = ej;
+          dej[2][j - o] = b;
+        } else {
+          d[j] = dj;
+          e[j] = ej;
+          beta[j] = b;
+        }
         sc[0] = b;
       }
+      const double rv0 = 1.0 / v0;
       for (int i = t; i < len; i += 64) {
         const double x = i == 0 ? alpha : xr[i] - (u0 * wsh[1 + i] + w0 * up[1 + i]);
-        vc[i] = i == 0 ? 1.0 : (b == 0.0 ? 0.0 : x / v0);
+        vc[i] = i == 0 ? 1.0 : (b == 0.0 ? 0.0 : x * rv0);
       }
     }
     __syncthreads();
@@ -193,44 +262,42 @@ __global__ __launch_bounds__(EIG_THREADS) void k_sym_eig(int m, int nw, const do
     // keep v for the back-transformation in row j (no longer needed otherwise)
     for (int i = t; i < len; i += EIG_THREADS) base[(int64_t)(j - off) * ld + (j + 1 - off) + i] = vc[i];
     if (j >= o) {
-      if (b != 0.0) {
-        // trailing block in LDS (len <= 128): thread (lg, i) owns column i and the rows l = lg mod
-        // 8, with v_i and w_i in registers; p_i in 8 partial sums
-        const int i = t & 127, lg = t >> 7;
-        double* pp = &psh[0][0];  // [8][128]
-        const double vi = i < len ? vc[i] : 0.0;
-        double* ci = base + (int64_t)(j + 1 - off) * ld + (j + 1 - off) + i;
-        if (i < len) {
-          double s0 = 0.0, s1 = 0.0;
-          int l = lg;
-          for (; l + 8 < len; l += 16) {
-            s0 += ci[(int64_t)l * ld] * vc[l];
-            s1 += ci[(int64_t)(l + 8) * ld] * vc[l + 8];
+      // trailing block in LDS (len <= 128): apply the pending update of step j - 1 and form
+      // p = b * A_tr v in one pass.  Thread (lg, i) owns column i and the rows l = lg mod 8;
+      // p_i in 8 partial sums
+      const int i = t & 127, lg = t >> 7;
+      double* pp = &psh[0][0];  // [8][128]
+      double* ci = base + (int64_t)(j + 1 - off) * ld + (j + 1 - off) + i;
+      if (i < len) {
+        double s0 = 0.0;
+        if (pend) {
+          const double ui = up[1 + i], wi = wsh[1 + i];
+          for (int l = lg; l < len; l += 8) {
+            const double a0 = ci[(int64_t)l * ld] - (up[1 + l] * wi + wsh[1 + l] * ui);
+            ci[(int64_t)l * ld] = a0;
+            s0 += a0 * vc[l];
           }
-          if (l < len) s0 += ci[(int64_t)l * ld] * vc[l];
-          pp[lg * 128 + i] = s0 + s1;
+        } else {
+          for (int l = lg; l < len; l += 8) s0 += ci[(int64_t)l * ld] * vc[l];
         }
-        __syncthreads();
-        if (t < 64) {
-          double kp = 0.0;
-          for (int i2 = t; i2 < len; i2 += 64) {
-            double pi = 0.0;
-#pragma unroll
-            for (int g8 = 0; g8 < 8; ++g8) pi += pp[g8 * 128 + i2];
-            pi *= b;
-            wsh[i2] = pi;
-            kp += pi * vc[i2];
-          }
-          for (int o2 = 32; o2 > 0; o2 >>= 1) kp += __shfl_xor(kp, o2);
-          const double K = 0.5 * b * kp;
-          for (int i2 = t; i2 < len; i2 += 64) wsh[i2] -= K * vc[i2];
-        }
-        __syncthreads();
-        if (i < len) {
-          const double wi = wsh[i];
-          for (int l = lg; l < len; l += 8) ci[(int64_t)l * ld] -= vc[l] * wi + wsh[l] * vi;
-        }
+        pp[lg * 128 + i] = s0;
       }
+      __syncthreads();  // every read of the previous step's w is done
+      if (t < 64) {
+        double kp = 0.0;
+        for (int i2 = t; i2 < len; i2 += 64) {
+          double pi = 0.0;
+#pragma unroll
+          for (int g8 = 0; g8 < 8; ++g8) pi += pp[g8 * 128 + i2];
+          pi *= b;
+          wsh[i2] = pi;
+          kp += pi * vc[i2];
+        }
+        kp = wave_sum(kp);
+        const double K = 0.5 * b * kp;
+        for (int i2 = t; i2 < len; i2 += 64) wsh[i2] -= K * vc[i2];
+      }
+      pend = true;
     } else {
       // trailing block in global memory: apply the pending update of step j - 1 and form
       // p = b * A_tr v in one pass (4 row groups x 256 columns)
@@ -273,7 +340,7 @@ __global__ __launch_bounds__(EIG_THREADS) void k_sym_eig(int m, int nw, const do
           wsh[i] = pi;
           kp += pi * vc[i];
         }
-        for (int o2 = 32; o2 > 0; o2 >>= 1) kp += __shfl_xor(kp, o2);
+        kp = wave_sum(kp);
         const double K = 0.5 * b * kp;
         for (int i = t; i < len; i += 64) wsh[i] -= K * vc[i];
       }
@@ -281,13 +348,22 @@ __global__ __launch_bounds__(EIG_THREADS) void k_sym_eig(int m, int nw, const do
     }
     __syncthreads();
   }
+  for (int j = o + t; j + 2 < m; j += EIG_THREADS) {
+    d[j] = dej[0][j - o];
+    e[j] = dej[1][j - o];
+    beta[j] = dej[2][j - o];
+  }
   if (t == 0) {
-    // the last 2 x 2 block is in LDS (o <= m - 2 whenever m >= 3; o = 0 when m <= EIG_LDS_M)
+    // the last 2 x 2 block is in LDS (o <= m - 2 whenever m >= 3; o = 0 when m <= EIG_LDS_M),
+    // with the pending update of the last step (its v and w, index 0 = row m - 2)
     const double* lb = Alds + (int64_t)(m >= 2 ? m - 2 - o : 0) * EIG_LDS_M + (m >= 2 ? m - 2 - o : 0);
     if (m >= 2) {
-      d[m - 2] = lb[0];
-      d[m - 1] = lb[EIG_LDS_M + 1];
-      e[m - 2] = lb[EIG_LDS_M];
+      const double* vl = ((m - 3) & 1) ? vsh2 : vsh;
+      const double v0 = pend ? vl[0] : 0.0, v1 = pend ? vl[1] : 0.0;
+      const double w0 = pend ? wsh[0] : 0.0, w1 = pend ? wsh[1] : 0.0;
+      d[m - 2] = lb[0] - 2.0 * v0 * w0;
+      d[m - 1] = lb[EIG_LDS_M + 1] - 2.0 * v1 * w1;
+      e[m - 2] = lb[EIG_LDS_M] - (v1 * w0 + w1 * v0);
       beta[m - 2] = 0.0;
     } else {
       d[0] = lb[0];
@@ -385,7 +461,7 @@ __global__ __launch_bounds__(EIG_THREADS) void k_sym_eig(int m, int nw, const do
     double* U2 = u2 + (int64_t)t * m;
     double* Lm = lm + (int64_t)t * m;
     unsigned char* Pv = piv + (int64_t)t * m;
-    for (int it = 0; it < 3; ++it) {
+    for (int it = 0; it < 2; ++it) {  // the shift is the eigenvalue to a few ulp: two solves suffice
       tri_shifted_solve(m, dl, el, lam, epsp, U0, U1, U2, Lm, Pv, y, it == 0);
       normalize(m, y);
     }
@@ -442,23 +518,26 @@ __global__ __launch_bounds__(EIG_THREADS) void k_sym_eig(int m, int nw, const do
     }
     __syncthreads();
   }
+  // Each wave applies all reflectors to its own columns, so the steps need no barrier; lane ln
+  // always handles the entries e = ln (mod 64) of its column, so no entry passes between lanes.
+  double* bl = psh[3];  // beta, read by every wave at every step
+  for (int i = t; i < m; i += EIG_THREADS) bl[i] = beta[i];
+  __syncthreads();
   const int wv = t >> 6, ln = t & 63;
-  for (int j = m - 3; j >= 0; --j) {
-    const double b = beta[j];
-    if (b != 0.0) {
-      const int len = m - 1 - j;
+  for (int c = wv; c < nw; c += EIG_THREADS / 64) {
+    double* y = Y + (int64_t)c * m;
+    for (int j = m - 3; j >= 0; --j) {
+      const double b = bl[j];
+      if (b == 0.0) continue;
       const double* v = hv ? hv + (int64_t)j * (m - 1) - (int64_t)j * (j - 1) / 2 : A + (int64_t)j * m + j + 1;
-      for (int c = wv; c < nw; c += EIG_THREADS / 64) {
-        double* y = Y + (int64_t)c * m + j + 1;
-        double s = 0.0;
-        for (int i = ln; i < len; i += 64) s += v[i] * y[i];
-        for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
-        s *= b;
-        for (int i = ln; i < len; i += 64) y[i] -= s * v[i];
-      }
+      const int e0 = j + 1 + ((ln - (j + 1)) & 63);  // v[e - j - 1] pairs with y[e], e in [j + 1, m)
+      double s = 0.0;
+      for (int e = e0; e < m; e += 64) s += v[e - j - 1] * y[e];
+      s = wave_sum(s) * b;
+      for (int e = e0; e < m; e += 64) y[e] -= s * v[e - j - 1];
     }
-    __syncthreads();
   }
+  __syncthreads();
   // ---- sign convention (largest-magnitude entry positive) and output
   for (int c = wv; c < nw; c += EIG_THREADS / 64) {
     const double* y = Y + (int64_t)c * m;
