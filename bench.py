@@ -212,9 +212,31 @@ def main():
         # the same float64 method with inexact small-space solves (inner tolerance 1e-6)
         per_i, ev_i, d = summary("plain-inexact")
         line["plain_fp64_inner_1e-6"] = dict(d, speedup_vs_plain=round(per_p / per_i, 3))
+    # each eigenvalue's error against the float64 oracle's solution of this matrix, stored by
+    # tests/golden/make_oracle_eigs.py (solved there to rrn 1e-10), when it is present
+    ref = oracle_eigs(w, A)
+    if ref is not None:
+        line["eval_rel_err_vs_oracle"] = [float(abs(a - b) / abs(b)) for a, b in zip(ev, ref)]
+        if "plain_fp64" in line:
+            line["plain_fp64"]["max_eval_rel_err_vs_oracle"] = float(
+                np.max(np.abs(np.array(ev_p) - ref) / np.abs(ref)))
+        if "mixed_learned" in line:
+            line["mixed_learned"]["max_eval_rel_err_vs_oracle"] = float(
+                np.max(np.abs(np.array(ev_l) - ref) / np.abs(ref)))
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(A, w, st)
     print(json.dumps(line))
+
+
+def oracle_eigs(w, A):
+    path = os.path.join(ROOT, "tests", "golden", "oracle_eigs_%s.json" % w.name.replace("/", "-"))
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("workload") != w.name or rec.get("matrix_sha256") != A.sha256() or not rec.get("converged"):
+        return None
+    return np.array(rec["evals"])
 
 
 def cpu_baseline(A, w, st):
