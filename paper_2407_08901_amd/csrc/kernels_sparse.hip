@@ -698,8 +698,13 @@ void spmm_panel_b(const PanelH& P, const VT* val, const XT* X, int64_t ldx, doub
     Xc = xp;
   }
   // two-wave workgroups, two (float64 X) or four (float32 X) per CU, words and values two tiles
-  // ahead: the fastest of the measured shapes at n = 1.17M, d = 200
-  spmm_panel_rounds<B, 2, 2, VT, XT>(P, val, Xc, Y, ldy, b, sizeof(XT) == 4 ? 4 : 2, s, X64, ldx64);
+  // ahead: the fastest of the measured shapes at n = 1.17M, d = 200.  When X no longer fits the
+  // 256 MB MALL (n = 7.7M, b = 16: 494 MB in float32), its rows come from HBM at longer latency,
+  // and one-wave workgroups, four per CU, are 13-15% faster
+  if ((int64_t)P.n * B * (int64_t)sizeof(XT) > ((int64_t)256 << 20))
+    spmm_panel_rounds<B, 1, 2, VT, XT>(P, val, Xc, Y, ldy, b, 4, s, X64, ldx64);
+  else
+    spmm_panel_rounds<B, 2, 2, VT, XT>(P, val, Xc, Y, ldy, b, sizeof(XT) == 4 ? 4 : 2, s, X64, ldx64);
 }
 
 template <typename VT, typename XT>
