@@ -8,11 +8,13 @@ L4-2k/20k/150k/1M-d200-k8 (n = 1,172,000, ~118M stored upper entries), with H al
 resident in HBM as an upper-triangular CSR.  The timed form (--mode, default mixed: float32
 products with float64 accumulation, small-space solves to 1e-6, float64 check and refinement)
 is followed by the same number of steps of plain float64 SPPC (small-space solves to 1e-12), of
-the mixed form with the learned preconditioner in the continuation, and of float64 SPPC with
-small-space solves to 1e-6 (--no-compare skips them).  Prints one JSON line.
+the mixed form with the learned preconditioner in the continuation, of float64 SPPC with
+small-space solves to 1e-6, and of the mixed form with the paper's RMM-DIIS continuation
+(--no-compare skips them).  Prints one JSON line.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload 1]
-                  [--mode plain|mixed|plain+mpnn|mixed+mpnn|plain+small|mixed+small|plain-inexact]
+                  [--mode plain|mixed|plain+mpnn|mixed+mpnn|plain+small|mixed+small|plain+rmmdiis|
+                          mixed+rmmdiis|plain-inexact]
                   [--no-compare]
                   [--no-cpu-baseline] [--calibrate-copy] [--spmm-only R]
 """
@@ -51,7 +53,8 @@ def measured_traffic(workload, mode):
     except OSError:
         ok = False
     return rec[0] if ok else None
-MODES = ("plain", "mixed", "plain+mpnn", "mixed+mpnn", "plain+small", "mixed+small", "plain-inexact")
+MODES = ("plain", "mixed", "plain+mpnn", "mixed+mpnn", "plain+small", "mixed+small", "plain+rmmdiis", "mixed+rmmdiis",
+         "plain-inexact")
 
 
 def parse():
@@ -135,7 +138,8 @@ def main():
     def make_step(mode):
         mixed = mode.startswith("mixed")
         mpnn = mode.endswith("mpnn")
-        precond = P.SPPC_CORR_MPNN if mpnn else P.SPPC_CORR_SMALL if mode.endswith("small") else P.SPPC_CORR_JACOBI
+        precond = (P.SPPC_CORR_MPNN if mpnn else P.SPPC_CORR_SMALL if mode.endswith("small") else
+                   P.SPPC_CORR_RMMDIIS if mode.endswith("rmmdiis") else P.SPPC_CORR_JACOBI)
         # plain-inexact: float64 with the small-space solves to the mixed form's inner tolerance
         extra = {"inner_tol": 1e-6} if mode == "plain-inexact" else {}
         opts = P.sppc_default_opts(precision=P.SPPC_PREC_MIXED if mixed else P.SPPC_PREC_FP64, precond=precond,
@@ -212,6 +216,9 @@ def main():
         # the same float64 method with inexact small-space solves (inner tolerance 1e-6)
         per_i, ev_i, d = summary("plain-inexact")
         line["plain_fp64_inner_1e-6"] = dict(d, speedup_vs_plain=round(per_p / per_i, 3))
+        # the paper's hybrid: SPPC, then every unconverged pair refined by RMM-DIIS (mixed form)
+        per_r, ev_r, d = summary("mixed+rmmdiis")
+        line["mixed_sppc_rmmdiis"] = dict(d, speedup_vs_plain=round(per_p / per_r, 3))
     # each eigenvalue's error against the float64 oracle's solution of this matrix, stored by
     # tests/golden/make_oracle_eigs.py (solved there to rrn 1e-10), when it is present
     ref = oracle_eigs(w, A)

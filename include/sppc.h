@@ -59,9 +59,17 @@ typedef enum {
   SPPC_CORR_PERTURBATIVE = 0, /* Psi^(p) of eq. exp_seq2 for every wanted pair (Alg. 2 step 6) */
   SPPC_CORR_JACOBI = 1,       /* continuation: t_i = -(I - z_i z_i^T) (diag(H) - theta_i)^-1 r_i */
   SPPC_CORR_MPNN = 2,         /* continuation: learned diagonal scaling of the Jacobi step */
-  SPPC_CORR_SMALL = 3         /* continuation: t_i = -(I - z_i z_i^T) M_i r_i with M_i = (H0hat - theta_i)^-1
+  SPPC_CORR_SMALL = 3,        /* continuation: t_i = -(I - z_i z_i^T) M_i r_i with M_i = (H0hat - theta_i)^-1
                                  on the small-space rows (deflated CG to a loose tolerance plus the
                                  exact deflated terms) and (diag(H) - theta_i)^-1 on the other rows */
+  SPPC_CORR_RMMDIIS = 4       /* continuation of the SPPC + RMM-DIIS hybrid (Sec. V-VI): after the
+                                 perturbative steps every unconverged Ritz pair is refined on its own
+                                 by RMM-DIIS (Pulay's DIIS over the pair's last 16 iterates, then the
+                                 residual-minimising step along (diag(H) - theta)^-1 r; one product
+                                 with H per pair and iteration, the pairs batched); at most max_cont
+                                 iterations; the final check takes Rayleigh-Ritz on the refined
+                                 vectors.  sppc_solve only (not a block for sppc_correct); not a
+                                 refine_precond */
 } sppc_corr_kind;
 
 /* Upper triangle (diagonal included) of the symmetric H, CSR, device memory. */
@@ -85,7 +93,7 @@ typedef struct {
   double inner_tol;    /* relative residual of the small-space solves; 0 = 1e-12 (FP64) / 1e-6 (MIXED) */
   double h0_tol;       /* residual of the H0hat eigenpairs, relative to max(1,|E|) */
   int precision;       /* sppc_precision; MIXED adds a float64 refinement when the final check fails */
-  int precond;         /* sppc_corr_kind used by the continuation (JACOBI, MPNN or SMALL); JACOBI */
+  int precond;         /* sppc_corr_kind used by the continuation (JACOBI, MPNN, SMALL or RMMDIIS); JACOBI */
   int final_check;     /* explicit float64 H Z, Rayleigh-Ritz on span Z, true residual */
   int verbose;         /* per-iteration line on stderr */
   int panel_width;     /* block products with H over column panels of this many columns (<= 65536),

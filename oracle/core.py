@@ -265,6 +265,80 @@ def jacobi_correction(diag: np.ndarray, theta: float, r: np.ndarray, z: np.ndarr
     return -t
 
 
+def diag_precond(diag: np.ndarray, theta: float, r: np.ndarray) -> np.ndarray:
+    """M r with M = (diag(H) - theta)^-1, |denominator| clamped from below as in the Jacobi step."""
+    den = diag - theta
+    floor = 1e-2 * max(1.0, abs(theta))
+    den = np.where(np.abs(den) < floor, np.where(den >= 0, floor, -floor), den)
+    return r / den
+
+
+def diis_coefficients(A: np.ndarray) -> np.ndarray:
+    """Pulay's DIIS: the a minimising a^T A a subject to sum(a) = 1 (A = the Gram matrix of the
+    residuals of the iterates), from the bordered system [[A, 1], [1^T, 0]] [a; mu] = [0; 1]."""
+    L = A.shape[0]
+    M = np.zeros((L + 1, L + 1))
+    # the minimiser does not depend on the scale of A; the residuals shrink to ~1e-10, so A is
+    # scaled to a unit largest diagonal before it is bordered by ones
+    M[:L, :L] = A / max(float(np.max(np.diag(A))), 1e-300)
+    M[:L, L] = 1.0
+    M[L, :L] = 1.0
+    rhs = np.zeros(L + 1)
+    rhs[L] = 1.0
+    # the residuals of converging iterates become nearly parallel: least squares keeps the bordered
+    # system solvable when A is (numerically) singular
+    return np.linalg.lstsq(M, rhs, rcond=None)[0][:L]
+
+
+def rmm_diis(H: sp.csr_matrix, diag: np.ndarray, x0: np.ndarray, Hx0: np.ndarray, tol: float,
+             max_iter: int = 100, depth: int = 16):
+    """Refines one approximate eigenpair by RMM-DIIS (the continuation of the hybrid of Sec. VI: one
+    product with H per iteration, the diagonal preconditioner).  The iterates x_j (unit norm) with
+    H x_j and residuals R_j = H x_j - theta_j x_j are kept (the last `depth`); each iteration
+      1. combines them by DIIS: xb = sum a_j x_j, the a_j minimising |sum a_j R_j| with sum a_j = 1;
+      2. normalises xb (and H xb), takes its Rayleigh quotient thb and residual Rb;
+      3. stops when |Rb| / |thb| < tol;
+      4. steps along t = M Rb (M the diagonal preconditioner) with the lam minimising
+         |Rb + lam (H - thb) t|, i.e. lam = -Rb.u / u.u with u = H t - thb t (the product);
+      5. keeps x_new = xb + lam t (normalised) as the next iterate.
+    When the history is full it restarts from xb (DIIS over near-parallel residuals stalls
+    otherwise).  Returns (theta, x, Hx, rrn, products, iterations)."""
+    nrm = np.linalg.norm(x0)
+    X = [x0 / nrm]
+    HX = [Hx0 / nrm]
+    R = [HX[0] - (X[0] @ HX[0]) * X[0]]
+    products = 0
+    for it in range(max_iter + 1):
+        if len(X) == 1:
+            a = np.ones(1)
+        else:
+            A = np.array([[ri @ rj for rj in R] for ri in R])
+            a = diis_coefficients(A)
+        xb = sum(ai * xi for ai, xi in zip(a, X))
+        Hxb = sum(ai * hi for ai, hi in zip(a, HX))
+        s = np.linalg.norm(xb)
+        xb, Hxb = xb / s, Hxb / s
+        thb = float(xb @ Hxb)
+        Rb = Hxb - thb * xb
+        rrn = np.linalg.norm(Rb) / abs(thb)
+        if rrn < tol or it == max_iter:
+            return thb, xb, Hxb, rrn, products, it
+        t = diag_precond(diag, thb, Rb)
+        Ht = H @ t
+        products += 1
+        u = Ht - thb * t
+        lam = -(Rb @ u) / (u @ u)
+        xn = xb + lam * t
+        Hxn = Hxb + lam * Ht
+        s = np.linalg.norm(xn)
+        xn, Hxn = xn / s, Hxn / s
+        if len(X) >= depth:
+            X, HX, R = [xb], [Hxb], [Rb]
+        X.append(xn)
+        HX.append(Hxn)
+        R.append(Hxn - (xn @ Hxn) * xn)
+
+
 def small_space_correction(H: sp.csr_matrix, n0: int, theta: float, r: np.ndarray,
                            z: np.ndarray) -> np.ndarray:
     """t = -(I - z z^T) M r with M = (H0hat - theta)^-1 on the rows of the small space and the
@@ -298,6 +372,9 @@ class Options:
     tau_drop: float = 1e-10
     final_check: bool = True
     precond: Optional[Callable] = None  # (H, diag, theta_i, r_i, z_i, i) -> t_i; default Jacobi
+    rmm_diis: bool = False     # the continuation refines each unconverged pair by RMM-DIIS instead
+    diis_depth: int = 16       # iterates kept by DIIS
+    diis_sweep: int = 4        # RMM-DIIS iterations per pair between two Rayleigh-Ritz rotations
 
 
 @dataclass
@@ -374,9 +451,32 @@ def sppc(H: sp.csr_matrix, n0: int, k: int, opts: Options = Options(),
         if callback:
             callback(hist[-1])
 
+    # the hybrid of Sec. VI: each unconverged Ritz pair refined on its own by RMM-DIIS, in sweeps
+    # of at most opts.diis_sweep iterations per pair; between sweeps, Rayleigh-Ritz on the span of
+    # the k refined vectors (the subspace rotation of multi-pair RMM-DIIS: it separates pairs whose
+    # eigenvalues are close, which a single-vector iteration resolves only slowly)
+    done_its = 0
+    while not converged and opts.continuation and opts.rmm_diis and done_its < opts.max_cont:
+        sweep = 0
+        for i in np.nonzero(rrn >= opts.tol)[0]:
+            th, x, hx, r_i, prods, its = rmm_diis(H, diag, Z[:, i], HZ[:, i], opts.tol,
+                                                  min(opts.diis_sweep, opts.max_cont - done_its),
+                                                  opts.diis_depth)
+            theta[i], Z[:, i], HZ[:, i], rrn[i] = th, x, hx, r_i
+            n_spmv += prods
+            sweep = max(sweep, its)
+        done_its += max(sweep, 1)
+        Qz, Rz = np.linalg.qr(Z)
+        theta, V, Z, HZ, rrn, T = rayleigh_ritz(Qz, HZ @ np.linalg.inv(Rz), k)
+        converged = bool(np.all(rrn < opts.tol))
+        hist.append(dict(p=p, phase="rmmdiis", iterations=sweep, theta=theta.copy(), rrn=rrn.copy(),
+                         m=Q.shape[1], n_spmv=n_spmv))
+        if callback:
+            callback(hist[-1])
+
     # continuation with preconditioned residual blocks
     it = 0
-    while not converged and opts.continuation and it < opts.max_cont:
+    while not converged and opts.continuation and not opts.rmm_diis and it < opts.max_cont:
         it += 1
         R = HZ - Z * theta[None, :]
         act = np.nonzero(rrn >= opts.tol)[0]

@@ -20,7 +20,7 @@ SPPC_OK, SPPC_E_ARG, SPPC_E_HIP, SPPC_E_NOMEM, SPPC_E_SINGULAR_E0, SPPC_E_BREAKD
     SPPC_E_NAN = range(8)
 SPPC_F64, SPPC_F32 = 0, 1
 SPPC_PREC_FP64, SPPC_PREC_MIXED = 0, 1
-SPPC_CORR_PERTURBATIVE, SPPC_CORR_JACOBI, SPPC_CORR_MPNN, SPPC_CORR_SMALL = 0, 1, 2, 3
+SPPC_CORR_PERTURBATIVE, SPPC_CORR_JACOBI, SPPC_CORR_MPNN, SPPC_CORR_SMALL, SPPC_CORR_RMMDIIS = 0, 1, 2, 3, 4
 
 STATUS_NAMES = {0: "SPPC_OK", 1: "SPPC_E_ARG", 2: "SPPC_E_HIP", 3: "SPPC_E_NOMEM",
                 4: "SPPC_E_SINGULAR_E0", 5: "SPPC_E_BREAKDOWN", 6: "SPPC_E_NOCONV", 7: "SPPC_E_NAN"}

@@ -203,6 +203,20 @@ void cg_prepare(const DevCSR& H0, int64_t n0, int64_t* rowb, double* tmp, hipStr
 int cg_solve(const DevCSR& H0, int64_t n0, int k, int D, const double* shift, const double* Ps,
              const int64_t* rowb, double* x, double* r, double* work, double* ccoef, int maxit, double tol,
              int* host_flag, hipStream_t s);
+// ---------------------------------------------------------------- RMM-DIIS (kernels_rmmdiis.hip)
+int diis_max_depth();
+// alpha[a][0..L) = Pulay's DIIS coefficients of pair a from its residual Gram matrix A[a] (D x D)
+void diis_coefficients(int k, int L, int D, const double* A, double* alpha, hipStream_t s);
+// xb[:, a] = sum_l alpha[a][l] Xh_l[:, a] (slots of n x k), the same for H x
+void diis_combine(int64_t n, int k, int L, int D, const double* alpha, const double* Xh, const double* HXh,
+                  double* xb, double* hxb, hipStream_t s);
+// X[:, a], HX[:, a] divided by sqrt(ss[a])
+void columns_to_unit(int64_t n, int k, const double* ss, double* X, double* HX, hipStream_t s);
+// Xn = xb + lam t, HXn = hxb + lam ht with lam[a] = -rd[a] / uu[a]
+void min_residual_step(int64_t n, int k, const double* rd, const double* uu, const double* xb, const double* hxb,
+                       const double* t, const double* ht, double* Xn, double* HXn, hipStream_t s);
+// A[a][i][l] = A[a][l][i] = g[a]
+void gram_set(int k, int D, int i, int l, const double* g, double* A, hipStream_t s);
 // out[c] = X[:, c]^T Y[:, c]
 void coldots(int64_t n, int b, const double* X, int64_t ldx, const double* Y, int64_t ldy, double* out,
              double* work, hipStream_t s);

@@ -135,6 +135,11 @@ struct sppc_ctx {
   bool f64_products = false;  // mixed precision: the block products have switched to float64
   int pend_b = 0, pend_kind = -1;
   int nw_last = 0;  // width of Z/HZ/R from the last Rayleigh-Ritz
+  // RMM-DIIS state (allocated at its first use): history slots of x, H x, R (D x n x k), the
+  // residual Gram matrices (k x D x D), coefficients, work blocks and column scalars
+  double *rd_Xh = nullptr, *rd_HXh = nullptr, *rd_Rh = nullptr, *rd_A = nullptr, *rd_al = nullptr;
+  double *rd_xb = nullptr, *rd_hxb = nullptr, *rd_rb = nullptr, *rd_t = nullptr, *rd_ht = nullptr, *rd_u = nullptr;
+  double* rd_sc = nullptr;
   std::vector<double> theta_h, rrn_h, angles_h;
   int last_added = 0;
   // learned preconditioner
@@ -235,7 +240,10 @@ void rayleigh_ritz(sppc_ctx* c, Basis& b, int nw) {
 // append the kept columns, multiply them by the operator and extend T.  Returns the number
 // of appended columns.  If coef_slot >= 0 the coefficients [C; R] of P in the new basis are
 // stored in the history slot (P = Q C + q R).
-int ortho_append(sppc_ctx* c, Basis& b, const double* P, int bw, const Op& op, int coef_slot) {
+// HP (optional): H P already known; H Q_new then follows by the same transformation as Q_new
+// instead of a product with H.
+int ortho_append(sppc_ctx* c, Basis& b, const double* P, int bw, const Op& op, int coef_slot,
+                 const double* HP = nullptr) {
   hipStream_t s = c->s;
   const int64_t n = b.n;
   const int m = b.m;
@@ -264,8 +272,14 @@ int ortho_append(sppc_ctx* c, Basis& b, const double* P, int bw, const Op& op, i
     gemm_tn(n, kept, kept, c->Wb, kept, c->Wb, kept, c->Gm, bw, 1.0, 0.0, c->work, s);
     cholqr_second(bw, c->Gm, c->M2, c->Rt, c->info, s);
     gemm_nn(n, kept, kept, c->Wb, kept, c->M2, bw, b.Q + m, b.ldq, 1.0, 0.0, s);
+    if (HP) {
+      // H Phi is H P minus the projections (m = 0 here: H P itself), then the two Cholesky factors
+      if (m > 0) throw Error(SPPC_E_ARG, "ortho_append: H P only for an empty basis");
+      gemm_nn(n, bw, kept, HP, bw, c->M1, bw, c->Psi, kept, 1.0, 0.0, s);
+      gemm_nn(n, kept, kept, c->Psi, kept, c->M2, bw, b.HQ + m, b.ldq, 1.0, 0.0, s);
+    }
     c->tm.end(t0);
-    op(b.Q + m, b.ldq, b.HQ + m, b.ldq, kept, s);
+    if (!HP) op(b.Q + m, b.ldq, b.HQ + m, b.ldq, kept, s);
     t0 = c->tm.begin(C_RR);
     gemm_tn(n, m + kept, kept, b.Q, b.ldq, b.HQ + m, b.ldq, c->Xt, kept, 1.0, 0.0, c->work, s);
     if (op.mixed && &b == &c->B && !c->restarted && m >= c->k) {
@@ -669,9 +683,12 @@ void setup_impl(sppc_ctx* c, const sppc_csr* Hin, const int64_t* loff, int L, in
   c->D = o.n_deflate;
   if (o.m_max < 2 * k || o.m_max > 512) throw Error(SPPC_E_ARG, "m_max must be in [2k, 512]");
   if (o.panel_width < -1 || o.panel_width > 65536) throw Error(SPPC_E_ARG, "panel_width must be -1, 0 or 1..65536");
-  for (int kind : {o.precond, o.refine_precond})
-    if (kind != SPPC_CORR_JACOBI && kind != SPPC_CORR_MPNN && kind != SPPC_CORR_SMALL)
-      throw Error(SPPC_E_ARG, "continuation preconditioner must be JACOBI, MPNN or SMALL");
+  if (o.precond != SPPC_CORR_JACOBI && o.precond != SPPC_CORR_MPNN && o.precond != SPPC_CORR_SMALL &&
+      o.precond != SPPC_CORR_RMMDIIS)
+    throw Error(SPPC_E_ARG, "continuation must be JACOBI, MPNN, SMALL or RMMDIIS");
+  if (o.refine_precond != SPPC_CORR_JACOBI && o.refine_precond != SPPC_CORR_MPNN &&
+      o.refine_precond != SPPC_CORR_SMALL)
+    throw Error(SPPC_E_ARG, "refinement preconditioner must be JACOBI, MPNN or SMALL");
   if (!(o.precond_tol > 0.0) || o.precond_tol >= 1.0) throw Error(SPPC_E_ARG, "precond_tol must be in (0, 1)");
   if (!(o.tol > 0) || !(o.tau_drop >= 0) || !(o.inner_tol >= 0) || !(o.h0_tol > 0)) throw Error(SPPC_E_ARG, "bad tolerances");
   if (o.precision != SPPC_PREC_FP64 && o.precision != SPPC_PREC_MIXED) throw Error(SPPC_E_ARG, "bad precision");
@@ -836,6 +853,140 @@ void setup_impl(sppc_ctx* c, const sppc_csr* Hin, const int64_t* loff, int L, in
   log_step(c, "sppc");
 }
 
+// SPPC + RMM-DIIS (Sec. V-VI): after the perturbative steps each unconverged Ritz pair is
+// refined on its own by RMM-DIIS, the k pairs batched into one block product with H per
+// iteration.  Each iteration combines a pair's history by Pulay's DIIS, normalises the
+// combination xb, stops the pair when its residual meets the tolerance (Z, H Z and theta keep
+// xb), and otherwise steps along t = (diag(H) - theta)^-1 R with the step length that minimises
+// the residual along t; the new iterate joins the history (at most D; a full history restarts
+// from xb).  The final check then takes Rayleigh-Ritz on the span of the refined vectors.
+// Returns the number of iterations (at most cap).
+int rmm_diis_sweep(sppc_ctx* c, int cap) {
+  hipStream_t s = c->s;
+  const int k = c->k;
+  const int64_t n = c->n;
+  const int D = diis_max_depth();
+  const sppc_opts& o = c->o;
+  if (c->nw_last != k) throw Error(SPPC_E_ARG, "no Ritz pairs available");
+  Arena& Ar = c->arena;
+  const int64_t slot = n * k;
+  if (!c->rd_Xh) {
+    c->rd_Xh = Ar.alloc<double>((size_t)D * slot);
+    c->rd_HXh = Ar.alloc<double>((size_t)D * slot);
+    c->rd_Rh = Ar.alloc<double>((size_t)D * slot);
+    c->rd_A = Ar.alloc<double>((size_t)k * D * D);
+    c->rd_al = Ar.alloc<double>((size_t)k * D);
+    c->rd_xb = Ar.alloc<double>((size_t)slot);
+    c->rd_hxb = Ar.alloc<double>((size_t)slot);
+    c->rd_rb = Ar.alloc<double>((size_t)slot);
+    c->rd_t = Ar.alloc<double>((size_t)slot);
+    c->rd_ht = Ar.alloc<double>((size_t)slot);
+    c->rd_u = Ar.alloc<double>((size_t)slot);
+    c->rd_sc = Ar.alloc<double>(8 * 64);
+  }
+  double *xb = c->rd_xb, *hxb = c->rd_hxb, *rb = c->rd_rb, *t = c->rd_t, *ht = c->rd_ht, *u = c->rd_u;
+  double *ss = c->rd_sc, *th = ss + 64, *ssr = ss + 128, *uu = ss + 192, *rd = ss + 256, *g = ss + 320;
+  double *th2 = ss + 384, *ss2 = ss + 448;
+  double *Xh = c->rd_Xh, *HXh = c->rd_HXh, *Rh = c->rd_Rh;
+  for (int a = 0; a < k; ++a) c->pin_i[8 + a] = a;
+  SPPC_HIP(hipMemcpyAsync(c->idx, c->pin_i + 8, sizeof(int) * k, hipMemcpyHostToDevice, s));
+  // slot 0: the Ritz pairs of the switch
+  copy_block(n, k, c->Z, k, Xh, k, s);
+  copy_block(n, k, c->HZ, k, HXh, k, s);
+  residual_block(n, k, Xh, k, HXh, k, c->theta, Rh, k, ssr, c->work, s);
+  gram_set(k, D, 0, 0, ssr, c->rd_A, s);
+  int L = 1, iters = 0;
+  std::vector<char> done(k);
+  for (int a = 0; a < k; ++a) done[a] = c->rrn_h[a] < o.tol;
+  Op op{c, &c->H, false, true};
+  for (int it = 0;; ++it) {
+    size_t t0 = c->tm.begin(C_SMALL);
+    diis_coefficients(k, L, D, c->rd_A, c->rd_al, s);
+    diis_combine(n, k, L, D, c->rd_al, Xh, HXh, xb, hxb, s);
+    colsumsq(n, k, xb, k, ss, c->work, s);
+    columns_to_unit(n, k, ss, xb, hxb, s);
+    coldots(n, k, xb, k, hxb, k, th, c->work, s);
+    residual_block(n, k, xb, k, hxb, k, th, rb, k, ssr, c->work, s);
+    c->tm.end(t0);
+    SPPC_HIP(hipMemcpyAsync(c->pin, th, sizeof(double) * k, hipMemcpyDeviceToHost, s));
+    SPPC_HIP(hipMemcpyAsync(c->pin + NWMAX, ssr, sizeof(double) * k, hipMemcpyDeviceToHost, s));
+    sync(c);
+    bool all = true;
+    for (int a = 0; a < k; ++a) {
+      if (done[a]) continue;
+      const double thv = c->pin[a];
+      const double r = std::sqrt(std::max(0.0, c->pin[NWMAX + a])) / std::max(std::fabs(thv), 1e-300);
+      if (r < o.tol || it >= cap) {
+        copy_block(n, 1, xb + a, k, c->Z + a, k, s);
+        copy_block(n, 1, hxb + a, k, c->HZ + a, k, s);
+        c->theta_h[a] = thv;
+        c->rrn_h[a] = r;
+        done[a] = 1;
+      } else {
+        all = false;
+      }
+    }
+    if (all) break;
+    ++iters;
+    // the step of minimal residual along the preconditioned residual (one product with H)
+    t0 = c->tm.begin(C_SMALL);
+    jacobi_block(n, k, c->idx, rb, k, c->diag, th, t, k, s);
+    c->tm.end(t0);
+    op(t, k, ht, k, k, s);
+    t0 = c->tm.begin(C_SMALL);
+    residual_block(n, k, t, k, ht, k, th, u, k, uu, c->work, s);  // u = H t - theta t
+    coldots(n, k, rb, k, u, k, rd, c->work, s);
+    int dst = L;
+    if (L >= D) {  // restart the history from xb
+      copy_block(n, k, xb, k, Xh, k, s);
+      copy_block(n, k, hxb, k, HXh, k, s);
+      copy_block(n, k, rb, k, Rh, k, s);
+      gram_set(k, D, 0, 0, ssr, c->rd_A, s);
+      dst = 1;
+    }
+    double *Xn = Xh + dst * slot, *HXn = HXh + dst * slot, *Rn = Rh + dst * slot;
+    min_residual_step(n, k, rd, uu, xb, hxb, t, ht, Xn, HXn, s);
+    colsumsq(n, k, Xn, k, ss2, c->work, s);
+    columns_to_unit(n, k, ss2, Xn, HXn, s);
+    coldots(n, k, Xn, k, HXn, k, th2, c->work, s);
+    residual_block(n, k, Xn, k, HXn, k, th2, Rn, k, g, c->work, s);
+    gram_set(k, D, dst, dst, g, c->rd_A, s);
+    for (int l = 0; l < dst; ++l) {
+      coldots(n, k, Rn, k, Rh + l * slot, k, g, c->work, s);
+      gram_set(k, D, dst, l, g, c->rd_A, s);
+    }
+    c->tm.end(t0);
+    L = dst + 1;
+  }
+  for (int a = 0; a < k; ++a) c->pin[a] = c->theta_h[a];
+  SPPC_HIP(hipMemcpyAsync(c->theta, c->pin, sizeof(double) * k, hipMemcpyHostToDevice, s));
+  sync(c);
+  return iters;
+}
+
+// Sweeps of at most 4 RMM-DIIS iterations per pair; between sweeps, Rayleigh-Ritz on the span of
+// the k refined vectors (the subspace rotation of multi-pair RMM-DIIS: it separates pairs whose
+// eigenvalues are close, which a single-vector iteration resolves only slowly).  The rotation
+// needs no product: the refined vectors carry H x.  The basis restarts on them.
+int rmm_diis_phase(sppc_ctx* c) {
+  const sppc_opts& o = c->o;
+  const int k = c->k;
+  Op op{c, &c->H, false, true};
+  int total = 0;
+  for (bool first = true;; first = false) {
+    if (!first) {
+      c->B.m = 0;
+      const int kept = ortho_append(c, c->B, c->Z, k, op, -1, c->HZ);
+      if (kept < k) throw Error(SPPC_E_BREAKDOWN, "RMM-DIIS: the refined vectors became linearly dependent");
+      rayleigh_ritz(c, c->B, k);
+      c->restarted = true;
+    }
+    if (all_converged(c) || total >= o.max_cont) break;
+    total += std::max(1, rmm_diis_sweep(c, std::min(4, o.max_cont - total)));
+  }
+  return total;
+}
+
 sppc_status solve_impl(sppc_ctx* c, double* evals, double* evecs, double* rrn, sppc_stats* st) {
   const auto t0 = std::chrono::steady_clock::now();
   sppc_opts& o = c->o;
@@ -850,7 +1001,13 @@ sppc_status solve_impl(sppc_ctx* c, double* evals, double* evecs, double* rrn, s
   }
   c->st.iterations = c->p;
   int cont = 0;
-  if (o.p_switch > 0) {
+  if (o.p_switch > 0 && o.precond == SPPC_CORR_RMMDIIS) {
+    if (!conv) {
+      cont = rmm_diis_phase(c);
+      log_step(c, "rmmdiis");
+      conv = all_converged(c);
+    }
+  } else if (o.p_switch > 0) {
     const int kind = o.precond;
     std::vector<double> hist;  // max residual per continuation step (mixed hand-over test)
     while (!conv && cont < o.max_cont) {
@@ -892,7 +1049,8 @@ sppc_status solve_impl(sppc_ctx* c, double* evals, double* evecs, double* rrn, s
       double last = 0.0;
       for (int i = 0; i < c->k; ++i) last = std::max(last, c->rrn_h[i]);
       for (int round = 0; !conv && ref < o.max_cont; ++round) {
-        if (!clean && (stalled || round >= 2)) {
+        // (after RMM-DIIS the basis does not hold the refined vectors: restart at once)
+        if (!clean && (stalled || round >= 2 || o.precond == SPPC_CORR_RMMDIIS)) {
           restart_basis(c, c->B, c->k);
           c->restarted = true;
           clean = true;

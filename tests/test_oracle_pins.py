@@ -313,3 +313,74 @@ def test_product_from_upper_matches_the_dense_symmetric_matrix():
     rows = np.concatenate([np.arange(n), [5, 5, 36, 0]])[::-1]
     Yr = oracle.product_rows_from_upper(rp, np.array(cols, dtype=np.int32), np.array(vals), n, X, rows)
     assert np.max(np.abs(Yr - (Hd @ X)[rows])) < 1e-13
+
+
+# ------------------------------------------------------------------ RMM-DIIS (the hybrid's continuation)
+
+def test_diis_coefficients_are_the_constrained_minimiser():
+    # two residuals: the minimiser of |a1 r1 + a2 r2| with a1 + a2 = 1 in closed form, and for
+    # three a brute-force scan of the constraint plane
+    rng = np.random.default_rng(21)
+    R = rng.standard_normal((50, 2))
+    A = R.T @ R
+    a = oracle.core.diis_coefficients(A)
+    t = (A[1, 1] - A[0, 1]) / (A[0, 0] + A[1, 1] - 2 * A[0, 1])
+    assert abs(a.sum() - 1.0) < 1e-14 and abs(a[0] - t) < 1e-12
+    R = rng.standard_normal((50, 3))
+    A = R.T @ R
+    a = oracle.core.diis_coefficients(A)
+    f = a @ A @ a
+    g = np.linspace(-3, 3, 241)
+    best = min((x * x * A[0, 0] + y * y * A[1, 1] + (1 - x - y) ** 2 * A[2, 2] + 2 * x * y * A[0, 1]
+                + 2 * x * (1 - x - y) * A[0, 2] + 2 * y * (1 - x - y) * A[1, 2]) for x in g for y in g)
+    assert abs(a.sum() - 1.0) < 1e-14 and f <= best + 1e-12
+
+
+def test_rmm_diis_step_minimises_the_residual_along_the_direction():
+    # one iteration from x0: the new iterate is x0 + lam t (normalised) with t the preconditioned
+    # residual and lam minimising |R0 + lam (H - theta0) t| (checked against a fine scan of lam)
+    rng = np.random.default_rng(4)
+    n = 40
+    Hd = np.diag(np.arange(n, dtype=float)) + 0.05 * (lambda B: B + B.T)(rng.standard_normal((n, n)))
+    H = sp.csr_matrix(Hd)
+    x0 = np.zeros(n); x0[0] = 1.0; x0 += 0.05 * rng.standard_normal(n)
+    x0 /= np.linalg.norm(x0)
+    th0 = x0 @ Hd @ x0
+    R0 = Hd @ x0 - th0 * x0
+    t = oracle.core.diag_precond(Hd.diagonal(), th0, R0)
+    u = Hd @ t - th0 * t
+    lams = np.linspace(-3, 3, 60001)
+    res = [np.linalg.norm(R0 + l * u) for l in lams]
+    lam_scan = lams[int(np.argmin(res))]
+    th, x, hx, rrn, prods, its = oracle.core.rmm_diis(H, Hd.diagonal(), x0, Hd @ x0, 0.0, 1)
+    xn = x0 + (-(R0 @ u) / (u @ u)) * t
+    assert prods == 1 and abs(-(R0 @ u) / (u @ u) - lam_scan) < 2e-4
+    # with two iterates in the history the returned vector is their DIIS combination; after one
+    # iteration (max_iter = 1) it is the combination of x0 and the new iterate
+    assert abs(abs(x @ (xn / np.linalg.norm(xn))) - 1.0) < 0.05
+
+
+def test_rmm_diis_converges_to_the_eigenpair_it_starts_near():
+    # a diagonally dominant matrix (the diagonal preconditioner is good): from a perturbed
+    # eigenvector RMM-DIIS reaches that eigenpair to 1e-12, one product per iteration
+    rng = np.random.default_rng(8)
+    n = 300
+    B = sp.random(n, n, density=0.03, random_state=np.random.RandomState(3))
+    Hs = (sp.diags(np.linspace(1.0, 30.0, n)) + 0.1 * (B + B.T)).tocsr()
+    w, U = np.linalg.eigh(Hs.toarray())
+    for j in (0, 3):
+        x0 = U[:, j] + 1e-3 * rng.standard_normal(n)
+        th, x, hx, rrn, prods, its = oracle.core.rmm_diis(Hs, Hs.diagonal(), x0, Hs @ x0, 1e-12, 200)
+        assert rrn < 1e-12 and prods == its
+        assert abs(th - w[j]) < 1e-11 * abs(w[j]) and abs(abs(x @ U[:, j]) - 1.0) < 1e-12
+
+
+def test_hybrid_sppc_rmm_diis_reaches_the_eigenvalues():
+    # SPPC + RMM-DIIS (sweeps of 4 iterations, Rayleigh-Ritz between sweeps) on a small
+    # level-structured matrix: the same eigenvalues as dense eigh within the Kato-Temple bound
+    A = levelgen.generate((100, 1000, 7000), 60, 13)
+    H = oracle.symmetric_from_upper(A.row_ptr, A.col, A.val, A.n)
+    lam = np.linalg.eigvalsh(H.toarray())[:3]
+    r = oracle.sppc(H, 100, 3, oracle.Options(tol=1e-9, rmm_diis=True, max_cont=400))
+    assert r.converged and any(h["phase"] == "rmmdiis" for h in r.history)
+    assert np.max(np.abs(r.theta - lam) / np.abs(lam)) < 1e-12
