@@ -11,12 +11,13 @@ small-space solves to 1e-6, RMM-DIIS refinement of each pair after the perturbat
 check) is followed by the same number of steps of plain float64 SPPC (small-space solves to
 1e-12, Davidson continuation), of the mixed form with the Davidson continuation, of the mixed form
 with the learned preconditioner in that continuation, and of float64 SPPC with small-space solves
-to 1e-6 (--no-compare skips them).  Prints one JSON line.
+to 1e-6, and of the hybrid with the automatic switch (RMM-DIIS from the step at which SPPC
+stagnates; --auto-switch times that form instead); --no-compare skips them.  Prints one JSON line.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload 1]
                   [--mode plain|mixed|plain+mpnn|mixed+mpnn|plain+small|mixed+small|plain+rmmdiis|
                           mixed+rmmdiis|plain-inexact]
-                  [--no-compare]
+                  [--no-compare] [--auto-switch]
                   [--no-cpu-baseline] [--calibrate-copy] [--spmm-only R]
 """
 from __future__ import annotations
@@ -69,6 +70,8 @@ def parse():
     ap.add_argument("--mode", default="mixed+rmmdiis", choices=MODES)
     ap.add_argument("--no-compare", action="store_true",
                     help="do not time plain float64 SPPC and the mixed + learned-preconditioner form as well")
+    ap.add_argument("--auto-switch", action="store_true",
+                    help="switch to the continuation once SPPC stagnates instead of after step 15")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of known size (HBM counter calibration)")
@@ -138,7 +141,8 @@ def main():
     from paper_2407_08901_amd import mpnn_train
     weights = mpnn_train.load_for_levels(len(w.level_sizes))
 
-    def make_step(mode):
+    def make_step(mode, auto_switch=None):
+        auto_switch = args.auto_switch if auto_switch is None else auto_switch
         mixed = mode.startswith("mixed")
         mpnn = mode.endswith("mpnn")
         precond = (P.SPPC_CORR_MPNN if mpnn else P.SPPC_CORR_SMALL if mode.endswith("small") else
@@ -146,7 +150,8 @@ def main():
         # plain-inexact: float64 with the small-space solves to the mixed form's inner tolerance
         extra = {"inner_tol": 1e-6} if mode == "plain-inexact" else {}
         opts = P.sppc_default_opts(precision=P.SPPC_PREC_MIXED if mixed else P.SPPC_PREC_FP64, precond=precond,
-                                   verbose=1 if args.verbose else 0, panel_width=args.panel_width, **extra)
+                                   verbose=1 if args.verbose else 0, panel_width=args.panel_width,
+                                   auto_switch=1 if auto_switch else 0, **extra)
 
         def one_step():
             ctx = P.sppc_setup(rp, col, val, A.level_offsets, w.n_small_levels, w.k, opts)
@@ -157,8 +162,8 @@ def main():
             return ev, rrn, st, status
         return one_step
 
-    def timed(mode):
-        one_step = make_step(mode)
+    def timed(mode, auto_switch=None):
+        one_step = make_step(mode, auto_switch)
         for _ in range(args.warmup):
             one_step()
         torch.cuda.synchronize()
@@ -179,7 +184,7 @@ def main():
     alg_bytes = sum(r[2]["spmm_alg_bytes"] for r in results)
     achieved = alg_bytes / (spmm_ms * 1e-3) / 1e9 if spmm_ms > 0 else 0.0
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(w.name, args.mode),
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None if args.auto_switch else measured_traffic(w.name, args.mode),
             "kernel": "k_spmm (block product with H)", "launches": spmm_calls,
             "avg_launch_ms": round(spmm_ms / max(spmm_calls, 1), 4),
             "alg_bytes_per_launch_avg": int(alg_bytes / max(spmm_calls, 1))}
@@ -192,7 +197,7 @@ def main():
         "vs_baseline": None, "dtype": "f32+f64" if mixed else "f64",
         "data": "synthetic",
         "config": {"workload": w.name, "n": A.n, "n0": w.n0, "k": w.k, "nnz_upper": A.nnz,
-                   "tol": 1e-6, "mode": args.mode},
+                   "tol": 1e-6, "mode": args.mode, "auto_switch": bool(args.auto_switch)},
         "converged": bool(st["converged"]), "max_rrn": max(rrn), "evals": ev,
         "iterations": st["iterations"], "cont_steps": st["cont_steps"], "refine_steps": st["refine_steps"],
         "mpnn_steps": st["mpnn_steps"], "n_spmv": st["n_spmv"],
@@ -203,8 +208,9 @@ def main():
         "generate_s": round(t_gen, 2),
     }
     if not args.no_compare:
-        def summary(mode):
-            per_m, res_m = (per, results) if mode == args.mode else timed(mode)
+        def summary(mode, auto_switch=False):
+            same = mode == args.mode and auto_switch == args.auto_switch
+            per_m, res_m = (per, results) if same else timed(mode, auto_switch)
             ev_m, rrn_m, st_m, _ = res_m[-1]
             return per_m, ev_m, {"s": round(per_m, 4), "iterations": st_m["iterations"],
                                  "cont_steps": st_m["cont_steps"], "refine_steps": st_m["refine_steps"],
@@ -222,6 +228,9 @@ def main():
         # the mixed form with the Davidson continuation (the library's default continuation)
         per_r, ev_r, d = summary("mixed")
         line["mixed_davidson"] = dict(d, speedup_vs_plain=round(per_p / per_r, 3))
+        # the hybrid with the automatic switch: RMM-DIIS from the step at which SPPC stagnates
+        per_a, ev_a, d = summary("mixed+rmmdiis", auto_switch=True)
+        line["mixed_rmmdiis_auto_switch"] = dict(d, speedup_vs_plain=round(per_p / per_a, 3))
     # each eigenvalue's error against the float64 oracle's solution of this matrix, stored by
     # tests/golden/make_oracle_eigs.py (solved there to rrn 1e-10), when it is present
     ref = oracle_eigs(w, A)

@@ -101,6 +101,11 @@ typedef struct {
                           block of X exceeds 8 MiB), 0 = off */
   int refine_precond;  /* continuation kind of the float64 refinement after a mixed solve; SMALL */
   double precond_tol;  /* relative residual of the small-space solve inside SMALL; 1e-3 */
+  int auto_switch;     /* 1: switch to the continuation before p_switch once SPPC stagnates: after a
+                          step the smallest sine of the angle between a new correction vector and
+                          the basis is below 1e-4 (Fig. 3), or the largest rrn has not halved over
+                          the last three steps (detection left open by the paper, Sec. VII); takes
+                          effect only with p_switch > 0; 0 (default): switch at p_switch only */
 } sppc_opts;
 
 typedef struct {

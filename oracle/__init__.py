@@ -17,6 +17,7 @@ from .core import (  # noqa: F401
     zeroth_order,
     rs_corrections,
     sppc,
+    sppc_stagnated,
     final_check,
     jacobi_correction,
     small_space_correction,

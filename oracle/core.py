@@ -375,6 +375,7 @@ class Options:
     rmm_diis: bool = False     # the continuation refines each unconverged pair by RMM-DIIS instead
     diis_depth: int = 16       # iterates kept by DIIS
     diis_sweep: int = 4        # RMM-DIIS iterations per pair between two Rayleigh-Ritz rotations
+    auto_switch: bool = False  # switch before p_switch once SPPC stagnates (see sppc_stagnated)
 
 
 @dataclass
@@ -401,6 +402,19 @@ def final_check(H: sp.csr_matrix, Z: np.ndarray):
     R = HZ2 - Z2 * w[None, :]
     rrn = np.linalg.norm(R, axis=0) / np.abs(w)
     return w, Z2, rrn
+
+
+def sppc_stagnated(hist: List[dict]) -> bool:
+    """The automatic switch point (the paper leaves its detection open, Sec. VII).
+
+    SPPC has stagnated after step p when a correction vector of that step lies almost in the
+    subspace built so far (sine of the angle of Fig. 3 below 1e-4: the higher orders add nothing,
+    Sec. VI), or when the largest residual norm has not halved since step p - 3.
+    hist holds one record per SPPC step, p = 0 first.
+    """
+    if min(hist[-1]["angles"]) < 1e-4:
+        return True
+    return len(hist) >= 4 and not (max(hist[-1]["rrn"]) < 0.5 * max(hist[-4]["rrn"]))
 
 
 def sppc(H: sp.csr_matrix, n0: int, k: int, opts: Options = Options(),
@@ -450,6 +464,9 @@ def sppc(H: sp.csr_matrix, n0: int, k: int, opts: Options = Options(),
                          n_spmv=n_spmv, angles=angles.copy(), kept=kept.copy()))
         if callback:
             callback(hist[-1])
+        if opts.auto_switch and opts.continuation and opts.p_switch is not None and not converged \
+                and sppc_stagnated(hist):
+            break
 
     # the hybrid of Sec. VI: each unconverged Ritz pair refined on its own by RMM-DIIS, in sweeps
     # of at most opts.diis_sweep iterations per pair; between sweeps, Rayleigh-Ritz on the span of

@@ -658,6 +658,24 @@ void log_step(sppc_ctx* c, const char* phase) {
           c->B.m, c->last_added, mx, mn, c->theta_h.empty() ? 0.0 : c->theta_h[0]);
 }
 
+double max_rrn(const sppc_ctx* c) {
+  double mx = 0.0;
+  for (double r : c->rrn_h) mx = std::max(mx, r);
+  return mx;
+}
+
+// The automatic switch (the paper leaves its detection open, Sec. VII): SPPC has stagnated once a
+// new correction vector lies almost in the basis (sine of its angle to the basis below 1e-4, the
+// collapse of Fig. 3) or once the largest residual has not halved over the last three steps.
+// top[j] is the largest rrn after the j-th step of this call (top[0]: before the first).
+bool sppc_stagnates(const sppc_ctx* c, const std::vector<double>& top) {
+  double mn = 1.0;
+  for (double a : c->angles_h) mn = std::min(mn, a);
+  if (mn < 1e-4) return true;
+  const size_t h = top.size();
+  return h >= 4 && !(top[h - 1] < 0.5 * top[h - 4]);
+}
+
 bool all_converged(sppc_ctx* c) {
   for (int i = 0; i < c->k; ++i)
     if (!(c->rrn_h[i] < c->o.tol)) return false;
@@ -692,6 +710,7 @@ void setup_impl(sppc_ctx* c, const sppc_csr* Hin, const int64_t* loff, int L, in
   if (!(o.precond_tol > 0.0) || o.precond_tol >= 1.0) throw Error(SPPC_E_ARG, "precond_tol must be in (0, 1)");
   if (!(o.tol > 0) || !(o.tau_drop >= 0) || !(o.inner_tol >= 0) || !(o.h0_tol > 0)) throw Error(SPPC_E_ARG, "bad tolerances");
   if (o.precision != SPPC_PREC_FP64 && o.precision != SPPC_PREC_MIXED) throw Error(SPPC_E_ARG, "bad precision");
+  if (o.auto_switch != 0 && o.auto_switch != 1) throw Error(SPPC_E_ARG, "auto_switch must be 0 or 1");
   const int last_p = (o.p_switch > 0) ? std::min(o.p_switch, o.maxiter) : o.maxiter;
   if (last_p < 0) throw Error(SPPC_E_ARG, "maxiter must be >= 0");
   if ((int64_t)k * (last_p + 1) > o.m_max) throw Error(SPPC_E_ARG, "m_max < k * (perturbation order + 1)");
@@ -992,12 +1011,16 @@ sppc_status solve_impl(sppc_ctx* c, double* evals, double* evecs, double* rrn, s
   sppc_opts& o = c->o;
   const int last_p = (o.p_switch > 0) ? std::min(o.p_switch, o.maxiter) : o.maxiter;
   bool conv = all_converged(c);
+  std::vector<double> top;  // largest rrn after each SPPC step of this call (automatic switch)
+  top.push_back(max_rrn(c));
   while (!conv && c->p < last_p && !c->restarted) {
     correct_perturbative(c);
     const int added = append_and_rr(c);
     log_step(c, "sppc");
     conv = all_converged(c);
     if (added == 0 && !conv) break;  // stagnation: no new direction
+    top.push_back(max_rrn(c));
+    if (o.auto_switch && !conv && o.p_switch > 0 && sppc_stagnates(c, top)) break;
   }
   c->st.iterations = c->p;
   int cont = 0;

@@ -118,6 +118,7 @@ def test_invalid_inputs_are_refused(P):
     assert _setup_status(P, A, 1, 2, panel_width=70000) == P.SPPC_E_ARG
     assert _setup_status(P, A, 1, 2, precond=9) == P.SPPC_E_ARG
     assert _setup_status(P, A, 1, 2, precond_tol=1.5) == P.SPPC_E_ARG
+    assert _setup_status(P, A, 1, 2, auto_switch=2) == P.SPPC_E_ARG
     bad = _Upper(A.n, np.repeat(np.arange(A.n), np.diff(A.row_ptr)), A.col.astype(np.int64), A.val,
                  [0, 20, 110, 409])                                        # offsets do not end at n
     assert _setup_status(P, bad, 1, 2) == P.SPPC_E_ARG
