@@ -9,7 +9,9 @@
 //   append+RR  block Gram-Schmidt twice, Cholesky-QR twice (eqs. blkGS, QR, Qp), one block
 //              product with H, new rows/columns of T (eq. proj), lowest eigenpairs of T,
 //              residual norms (eq. rrn)
-// After p_switch SPPC steps the basis keeps growing with preconditioned residual blocks.
+// After p_switch SPPC steps (or earlier, once SPPC stagnates, with auto_switch) either the basis
+// keeps growing with preconditioned residual blocks (Davidson continuation) or each pair is
+// refined on its own by RMM-DIIS (the hybrid of Sec. V-VI).  A final float64 check follows.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
