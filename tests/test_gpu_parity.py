@@ -221,6 +221,28 @@ def test_full_solve_cfg0_matches_dense():
     assert st["n_spmv"] >= w.k * (st["iterations"] + 1)
 
 
+def test_continuation_restart_when_the_basis_is_full():
+    # m_max = 72 on cfg 0 (k = 4): 64 columns at the switch, so the third continuation step
+    # restarts the basis on the Ritz vectors (thick restart); the oracle restarts at the same
+    # size.  Same eigenvalues as dense eigh; step counts may differ by a step or two because a
+    # residual passes within 0.5% of the tolerance on the way (the active set can differ).
+    w = levelgen.WORKLOADS[0]
+    A = w.generate()
+    print("case continuation restart m_max=72", flush=True)
+    ref = _oracle_run(A, w.n0, w.k, m_max=72)
+    ms = [h["m"] for h in ref.history]
+    assert ref.converged and min(ms[16:]) < 16
+    ctx = _ctx(A, w.n_small_levels, w.k, m_max=72)
+    ev, Z, rrn, st, status = P.sppc_solve(ctx)
+    assert status == P.SPPC_OK and st["converged"] == 1 and max(rrn) < 1e-6
+    lam = np.linalg.eigvalsh(_H(A).toarray())[: w.k]
+    assert np.max(np.abs(np.array(ev) - lam) / np.abs(lam)) < 1e-10
+    assert np.max(np.abs(np.array(ev) - ref.theta) / np.abs(ref.theta)) < 1e-10
+    assert st["basis_size"] <= 72 and st["cont_steps"] > 14
+    n_cont = sum(h["phase"] == "cont" for h in ref.history)
+    assert abs(st["cont_steps"] - n_cont) <= 2, (st["cont_steps"], n_cont)
+
+
 @pytest.mark.parametrize("extra", [2, 12])
 def test_projected_eigensolver_beyond_the_lds_tile(extra):
     # m = 8 (p = 0) + 15 * 8 + extra continuation blocks > 128: the eigensolver starts in global
