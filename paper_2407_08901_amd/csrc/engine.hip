@@ -879,22 +879,28 @@ void setup_impl(sppc_ctx* c, const sppc_csr* Hin, const int64_t* loff, int L, in
 // iteration.  Each iteration combines a pair's history by Pulay's DIIS, normalises the
 // combination xb, stops the pair when its residual meets the tolerance (Z, H Z and theta keep
 // xb), and otherwise steps along t = (diag(H) - theta)^-1 R with the step length that minimises
-// the residual along t; the new iterate joins the history (at most D; a full history restarts
-// from xb).  The final check then takes Rayleigh-Ritz on the span of the refined vectors.
-// Returns the number of iterations (at most cap).
+// the residual along t; the new iterate joins the history.  A sweep of at most RMM_SWEEP
+// iterations holds at most RMM_SWEEP + 1 iterates, so only that many history slots exist (at
+// n = 7.7M and k = 16 one slot of the three histories is 3 GB); a full history would restart
+// from xb.  The final check then takes Rayleigh-Ritz on the span of the refined vectors.
+// Returns the number of iterations (at most cap <= RMM_SWEEP).
+constexpr int RMM_SWEEP = 4;
+
 int rmm_diis_sweep(sppc_ctx* c, int cap) {
   hipStream_t s = c->s;
   const int k = c->k;
   const int64_t n = c->n;
-  const int D = diis_max_depth();
+  const int D = diis_max_depth();            // leading size of the Gram matrices
+  const int NS = std::min(D, RMM_SWEEP + 1);  // history slots
   const sppc_opts& o = c->o;
   if (c->nw_last != k) throw Error(SPPC_E_ARG, "no Ritz pairs available");
+  if (cap < 0 || cap > RMM_SWEEP) throw Error(SPPC_E_ARG, "RMM-DIIS sweep longer than its history");
   Arena& Ar = c->arena;
   const int64_t slot = n * k;
   if (!c->rd_Xh) {
-    c->rd_Xh = Ar.alloc<double>((size_t)D * slot);
-    c->rd_HXh = Ar.alloc<double>((size_t)D * slot);
-    c->rd_Rh = Ar.alloc<double>((size_t)D * slot);
+    c->rd_Xh = Ar.alloc<double>((size_t)NS * slot);
+    c->rd_HXh = Ar.alloc<double>((size_t)NS * slot);
+    c->rd_Rh = Ar.alloc<double>((size_t)NS * slot);
     c->rd_A = Ar.alloc<double>((size_t)k * D * D);
     c->rd_al = Ar.alloc<double>((size_t)k * D);
     c->rd_xb = Ar.alloc<double>((size_t)slot);
@@ -958,7 +964,7 @@ int rmm_diis_sweep(sppc_ctx* c, int cap) {
     residual_block(n, k, t, k, ht, k, th, u, k, uu, c->work, s);  // u = H t - theta t
     coldots(n, k, rb, k, u, k, rd, c->work, s);
     int dst = L;
-    if (L >= D) {  // restart the history from xb
+    if (L >= NS) {  // restart the history from xb
       copy_block(n, k, xb, k, Xh, k, s);
       copy_block(n, k, hxb, k, HXh, k, s);
       copy_block(n, k, rb, k, Rh, k, s);
@@ -1003,7 +1009,7 @@ int rmm_diis_phase(sppc_ctx* c) {
       c->restarted = true;
     }
     if (all_converged(c) || total >= o.max_cont) break;
-    total += std::max(1, rmm_diis_sweep(c, std::min(4, o.max_cont - total)));
+    total += std::max(1, rmm_diis_sweep(c, std::min(RMM_SWEEP, o.max_cont - total)));
   }
   return total;
 }
