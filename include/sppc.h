@@ -192,9 +192,11 @@ sppc_status sppc_rayleigh_ritz(sppc_ctx* ctx, double* theta_host, double* rrn_ho
                                int* n_added_host);
 
 /*
- * The whole method: Alg. 2 until every rrn_i < tol or p = p_switch (or maxiter),
- * then the preconditioned continuation, then (if enabled) the final float64
- * check.  Outputs:
+ * The whole method: Alg. 2 until every rrn_i < tol or p = p_switch (or maxiter;
+ * with auto_switch also once SPPC stagnates), then the continuation chosen by
+ * opts.precond (a preconditioned basis expansion, or the per-pair RMM-DIIS
+ * refinement of the SPPC + RMM-DIIS hybrid, Sec. V-VI), then (if enabled) the
+ * final float64 check and, in mixed precision, the float64 refinement.  Outputs:
  *   evals_host  [k] ascending
  *   evecs_dev   row-major n x k float64 (may be NULL)
  *   rrn_host    [k] relative residuals (may be NULL)
