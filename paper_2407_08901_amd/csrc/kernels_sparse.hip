@@ -758,8 +758,10 @@ __global__ __launch_bounds__(256) void k_panel_bcount(int64_t n, const int64_t* 
 // in (panel, row) order gives each run's offset, (3) every entry goes to its run's offset plus
 // its index in the run (the run start comes from a ballot over the window, carried across
 // windows).  Each row keeps a cursor in LDS, so no row is searched.  The diagonal goes to dg
-// instead (when dg is given).
-constexpr int PANEL_PC = 32;
+// instead (when dg is given).  A wave takes its rows one after the other, and a row holds few
+// entries in one chunk (about 10 at n = 7.7M), so the kernel waits on one load round trip per row
+// and chunk: wide chunks (128 panels, 128 KB of LDS counters) keep the number of chunks small.
+constexpr int PANEL_PC = 128;
 constexpr int PANEL_FT = 1024;  // threads of the fill kernel
 
 template <typename VT>
