@@ -39,9 +39,8 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 # scaled by a plain-copy calibration (profiles/k_spmm_panel_L4-1.17M-k8_mixed_hbm_counters.md).
 # Keyed by (workload, mode); valid only while the kernel source has the recorded sha256.
 MEASURED_TRAFFIC = {
-    ("L4-2k/20k/150k/1M-d200-k8", "mixed+rmmdiis"): (7676863708,
-                                                     "7c05bafadbe6af2fc6478f247ad33a41756c21c3eedb02b1cd2575931e26844e"),
-    ("L4-2k/20k/150k/1M-d200-k8", "mixed"): (7685854964, "7c05bafadbe6af2fc6478f247ad33a41756c21c3eedb02b1cd2575931e26844e"),
+    ("L4-2k/20k/150k/1M-d200-k8", "mixed+rmmdiis"): (7719570560,
+                                                     "65ffad83f54e753d814751fc1c697ece9d5860f59eb780103994cb931f49b35c"),
 }
 
 
