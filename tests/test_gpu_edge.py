@@ -131,6 +131,26 @@ def test_invalid_inputs_are_refused(P):
     assert _setup_status(P, nanv, 1, 2) == P.SPPC_E_NAN
 
 
+def test_no_convergence_returns_the_best_pairs(P):
+    # pure SPPC stopped at p = 3 (cfg 0 needs far more): SPPC_E_NOCONV, and what is written is the
+    # final check's pairs, as the oracle computes them at the same point, with their true residuals
+    w = levelgen.WORKLOADS[0]
+    A = w.generate()
+    print("case edge no convergence", flush=True)
+    H = oracle.symmetric_from_upper(A.row_ptr, A.col, A.val, A.n)
+    ref = oracle.sppc(H, w.n0, w.k, oracle.Options(continuation=False, maxiter=3))
+    assert not ref.converged
+    ev, Z, rrn, st, status = _solve(P, A, w.n_small_levels, w.k, p_switch=0, maxiter=3)
+    assert status == P.SPPC_E_NOCONV and st["converged"] == 0 and st["iterations"] == 3
+    assert np.max(np.abs(np.array(ev) - ref.theta) / np.abs(ref.theta)) < 1e-10
+    Zh = Z.cpu().numpy()
+    assert np.max(np.abs(Zh.T @ Zh - np.eye(w.k))) < 1e-12
+    R = H @ Zh - Zh * np.array(ev)[None, :]
+    true = np.linalg.norm(R, axis=0) / np.abs(ev)
+    assert np.allclose(rrn, true, rtol=1e-8) and np.allclose(rrn, ref.rrn, rtol=1e-6)
+    assert min(rrn) > 1e-6
+
+
 def test_invalid_calls_on_a_context(P):
     A = levelgen.generate((20, 90, 300), 14, 4)
     print("case edge invalid calls", flush=True)
