@@ -35,7 +35,11 @@ design notes of the repository):
     Davidson continuation; M_i = diag(H) - theta_i with a clamped denominator
     is the diagonal preconditioner named in Sec. V);
   * a final explicit product H Z, Rayleigh-Ritz on span Z and the true
-    residual certify the returned pairs.
+    residual certify the returned pairs;
+  * the hybrid of Sec. V-VI refines each unconverged pair by RMM-DIIS in sweeps
+    of 4 iterations with Rayleigh-Ritz on the refined vectors between sweeps;
+  * optionally the switch comes early, once SPPC stagnates (sppc_stagnated;
+    the paper leaves the detection open, Sec. VII).
 """
 from __future__ import annotations
 
