@@ -120,6 +120,10 @@ void gemm_tn(int64_t n, int m, int b, const double* A, int64_t lda, const double
 // Y[n x b] (ldy) = beta*Y + alpha * A[n x m] C[m x b]   (C row-major, ldc)
 void gemm_nn(int64_t n, int m, int b, const double* A, int64_t lda, const double* C, int64_t ldc,
              double* Y, int64_t ldy, double alpha, double beta, hipStream_t s);
+// One pass over A for two products: Y1[n x b1] (ldy1) = beta1*Y1 + A C[:, 0:b1] and
+// Y2[n x b2] (ldy2) = beta2*Y2 + A C[:, b1:b1+b2], with b1 + b2 <= 32 (C row-major, ldc).
+void gemm_nn2(int64_t n, int m, int b1, int b2, const double* A, int64_t lda, const double* C, int64_t ldc,
+              double* Y1, int64_t ldy1, double beta1, double* Y2, int64_t ldy2, double beta2, hipStream_t s);
 // Same with float32 output (mixed-precision staging of SpMM inputs).
 void copy_to_f32(int64_t n, int b, const double* X, int64_t ldx, float* Y, int64_t ldy, hipStream_t s);
 // Y[r, c] = X[r, c] for a sub-block (row-major)

@@ -119,6 +119,11 @@ struct sppc_ctx {
   double *C1 = nullptr, *C2 = nullptr, *Gm = nullptr, *M1 = nullptr, *M2 = nullptr, *Rt = nullptr;
   double *Vrr = nullptr, *theta = nullptr, *sumsq = nullptr, *psi2 = nullptr, *angles = nullptr;
   double *Xt = nullptr, *Acoef = nullptr, *Bcoef = nullptr, *dots = nullptr, *work = nullptr;
+  // The next perturbative step's W = H Psi^(p-1) - sum E Psi (in Wb) and its coefficients (Acoef,
+  // Bcoef) formed in the Rayleigh-Ritz passes of the step before: valid for step w_next while the
+  // basis holds w_m columns.  Cq = [V | -B] and Ch = [V | A] are the right-hand sides of those passes.
+  double *Cq = nullptr, *Ch = nullptr;
+  int w_next = -1, w_m = -1;
   double* eigscr = nullptr;
   int *info = nullptr, *idx = nullptr, *mhist_dev = nullptr;
   double *cx = nullptr, *cr = nullptr,
@@ -215,12 +220,24 @@ void to_host(sppc_ctx* c, const double* dev, int count, double* host) {
 }
 
 // Rayleigh-Ritz on the basis: nw lowest pairs, Ritz vectors Z, H Z, residual R, norms.
-void rayleigh_ritz(sppc_ctx* c, Basis& b, int nw) {
+// with_next (nw = k, main basis): the passes over Q and H Q that form Z = Q V and H Z = H Q V also
+// form the next perturbative step's W = H Q A - Q B from the coefficients already in Acoef, Bcoef.
+void rayleigh_ritz(sppc_ctx* c, Basis& b, int nw, bool with_next = false) {
   hipStream_t s = c->s;
   const size_t t0 = c->tm.begin(C_RR);
   sym_eig_lowest(b.m, nw, b.T, b.ldq, c->theta, c->Vrr, nw, c->eigscr, s);
-  gemm_nn(b.n, b.m, nw, b.Q, b.ldq, c->Vrr, nw, c->Z, nw, 1.0, 0.0, s);
-  gemm_nn(b.n, b.m, nw, b.HQ, b.ldq, c->Vrr, nw, c->HZ, nw, 1.0, 0.0, s);
+  if (with_next) {
+    const int k = c->k, w2 = nw + k;
+    copy_block(b.m, nw, c->Vrr, nw, c->Cq, w2, s);
+    copy_block(b.m, nw, c->Vrr, nw, c->Ch, w2, s);
+    axpby_block(b.m, k, -1.0, c->Bcoef, k, 0.0, c->Cq + nw, w2, s);
+    copy_block(b.m, k, c->Acoef, k, c->Ch + nw, w2, s);
+    gemm_nn2(b.n, b.m, nw, k, b.Q, b.ldq, c->Cq, w2, c->Z, nw, 0.0, c->Wb, k, 0.0, s);
+    gemm_nn2(b.n, b.m, nw, k, b.HQ, b.ldq, c->Ch, w2, c->HZ, nw, 0.0, c->Wb, k, 1.0, s);
+  } else {
+    gemm_nn(b.n, b.m, nw, b.Q, b.ldq, c->Vrr, nw, c->Z, nw, 1.0, 0.0, s);
+    gemm_nn(b.n, b.m, nw, b.HQ, b.ldq, c->Vrr, nw, c->HZ, nw, 1.0, 0.0, s);
+  }
   residual_block(b.n, nw, c->Z, nw, c->HZ, nw, c->theta, c->R, nw, c->sumsq, c->work, s);
   c->tm.end(t0);
   SPPC_HIP(hipMemcpyAsync(c->pin, c->theta, sizeof(double) * nw, hipMemcpyDeviceToHost, s));
@@ -250,6 +267,7 @@ int ortho_append(sppc_ctx* c, Basis& b, const double* P, int bw, const Op& op, i
   const int64_t n = b.n;
   const int m = b.m;
   if (bw < 1 || bw > KB) throw Error(SPPC_E_ARG, "block width must be 1..32");
+  c->w_next = -1;  // Wb is scratch here
   size_t t0 = c->tm.begin(C_ORTHO);
   colsumsq(n, bw, P, bw, c->psi2, c->work, s);
   copy_block(n, bw, P, bw, c->Phi, bw, s);
@@ -424,11 +442,15 @@ void correct_perturbative(sppc_ctx* c) {
   c->p += 1;
   const int p = c->p;
   size_t t0 = c->tm.begin(C_SMALL);
-  build_correction_coefs(p, k, b.m, c->Ghist, c->gstride, k, c->mhist_dev, c->Etab, b.T, b.ldq, c->E0,
-                         c->Acoef, c->Bcoef, s);
-  // W = H Psi^(p-1) - sum_l E^(p-l) Psi^(l)  (eq. HPsip with the stored H Q)
-  gemm_nn(n, b.m, k, b.HQ, b.ldq, c->Acoef, k, c->Wb, k, 1.0, 0.0, s);
-  gemm_nn(n, b.m, k, b.Q, b.ldq, c->Bcoef, k, c->Wb, k, -1.0, 1.0, s);
+  // W = H Psi^(p-1) - sum_l E^(p-l) Psi^(l)  (eq. HPsip with the stored H Q); usually formed
+  // already by the Rayleigh-Ritz passes of step p - 1
+  if (!(c->w_next == p && c->w_m == b.m)) {
+    build_correction_coefs(p, k, b.m, c->Ghist, c->gstride, k, c->mhist_dev, c->Etab, b.T, b.ldq, c->E0,
+                           c->Acoef, c->Bcoef, s);
+    gemm_nn(n, b.m, k, b.HQ, b.ldq, c->Acoef, k, c->Wb, k, 1.0, 0.0, s);
+    gemm_nn(n, b.m, k, b.Q, b.ldq, c->Bcoef, k, c->Wb, k, -1.0, 1.0, s);
+  }
+  c->w_next = -1;
   // complement rows: x2 = -b2 / E^(0) with b2 = -W2 (H0 is zero there), eq. sm_first
   complement_rows(n0, n, k, c->Wb, k, c->E0, c->Psi, k, s);
   // small space: b1 = -W1 + H0hat Psi^(p-1)_1 (eq. exp_seq2 with eq. avoid_SpMV2)
@@ -601,8 +623,9 @@ int append_and_rr(sppc_ctx* c) {
   const bool mixed = c->o.precision == SPPC_PREC_MIXED;
   Op op{c, &c->H, mixed && !c->refining && !c->f64_products, true};
   int added = 0;
+  bool pert = false;
   if (c->pend_b > 0) {
-    const bool pert = c->pend_kind == SPPC_CORR_PERTURBATIVE;
+    pert = c->pend_kind == SPPC_CORR_PERTURBATIVE;
     added = ortho_append(c, b, c->Psi, c->pend_b, op, pert ? c->p : -1);
     if (pert) {
       c->mhist.push_back(b.m);
@@ -612,7 +635,19 @@ int append_and_rr(sppc_ctx* c) {
   }
   c->pend_b = 0;
   c->last_added = added;
-  rayleigh_ritz(c, b, c->k);
+  // when another perturbative step may follow, its coefficients depend only on T and the stored
+  // history, so its W is formed in the same passes as Z and H Z
+  const sppc_opts& o = c->o;
+  const int last_p = o.p_switch > 0 ? std::min(o.p_switch, o.maxiter) : o.maxiter;
+  const bool with_next = pert && !c->restarted && c->p < last_p && c->p + 1 < c->maxhist;
+  if (with_next)
+    build_correction_coefs(c->p + 1, c->k, b.m, c->Ghist, c->gstride, c->k, c->mhist_dev, c->Etab, b.T, b.ldq,
+                           c->E0, c->Acoef, c->Bcoef, c->s);
+  rayleigh_ritz(c, b, c->k, with_next);
+  if (with_next) {
+    c->w_next = c->p + 1;
+    c->w_m = b.m;
+  }
   if (mixed && !c->f64_products) {
     double mx = 0.0;
     for (int i = 0; i < c->k; ++i) mx = std::max(mx, c->rrn_h[i]);
@@ -625,6 +660,7 @@ void final_check(sppc_ctx* c) {
   hipStream_t s = c->s;
   const int k = c->k;
   const int64_t n = c->n;
+  c->w_next = -1;  // Wb is scratch here
   size_t t0 = c->tm.begin(C_SPMM);
   spmm_f64(c->H, c->Z, k, c->Wb, k, k, nullptr, s);
   c->tm.end(t0);
@@ -807,6 +843,8 @@ void setup_impl(sppc_ctx* c, const sppc_csr* Hin, const int64_t* loff, int L, in
   c->Xt = A.alloc<double>((size_t)mbig * KB);
   c->Acoef = A.alloc<double>((size_t)mbig * KB);
   c->Bcoef = A.alloc<double>((size_t)mbig * KB);
+  c->Cq = A.alloc<double>((size_t)mbig * KB);
+  c->Ch = A.alloc<double>((size_t)mbig * KB);
   c->Gm = A.alloc<double>(KB * KB);
   c->M1 = A.alloc<double>(KB * KB);
   c->M2 = A.alloc<double>(KB * KB);

@@ -133,11 +133,14 @@ constexpr int NN_ROWS = 128;  // rows per workgroup: 4 waves x 2 tiles of 16
 // Y = beta Y + alpha A C: the reduction dimension of the MFMA is the column index i of A.  In
 // step st of a 16-column slab, k-slot q of the MFMA is column i0 + 4 q + st when the rows of A
 // allow 32-byte loads (VEC: a lane reads its 4 columns of a row at once), else i0 + 4 st + q.
+// Columns j >= split of the product go to Y2 (column j - split, ld ldy2, beta2) instead, so that
+// two products with the same A share its pass.
 template <int NT, bool VEC>
 __global__ __launch_bounds__(256) void k_gemm_nn(int64_t n, int m, int b, const double* __restrict__ A,
                                                  int64_t lda, const double* __restrict__ C, int64_t ldc,
                                                  double* __restrict__ Y, int64_t ldy, double alpha,
-                                                 double beta) {
+                                                 double beta, int split, double* __restrict__ Y2,
+                                                 int64_t ldy2, double beta2) {
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
   const int q = lane >> 4, cl = lane & 15;
@@ -207,12 +210,16 @@ __global__ __launch_bounds__(256) void k_gemm_nn(int64_t n, int m, int b, const 
     for (int tj = 0; tj < NT; ++tj) {
       const int j = 16 * tj + cl;
       if (j >= b) continue;
+      const bool second = j >= split;
+      double* const yb = second ? Y2 + (j - split) : Y + j;
+      const int64_t ld = second ? ldy2 : ldy;
+      const double bt = second ? beta2 : beta;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int64_t r = rbase + 16 * mt + q + 4 * v;
         if (r < n) {
-          double* y = Y + r * ldy + j;
-          *y = beta == 0.0 ? alpha * acc[mt][tj][v] : beta * (*y) + alpha * acc[mt][tj][v];
+          double* y = yb + r * ld;
+          *y = bt == 0.0 ? alpha * acc[mt][tj][v] : bt * (*y) + alpha * acc[mt][tj][v];
         }
       }
     }
@@ -368,21 +375,35 @@ void gemm_tn(int64_t n, int m, int b, const double* A, int64_t lda, const double
   SPPC_LAUNCH_CHECK();
 }
 
-void gemm_nn(int64_t n, int m, int b, const double* A, int64_t lda, const double* C, int64_t ldc,
-             double* Y, int64_t ldy, double alpha, double beta, hipStream_t s) {
+namespace {
+void gemm_nn_launch(int64_t n, int m, int b, const double* A, int64_t lda, const double* C, int64_t ldc,
+                    double* Y, int64_t ldy, double alpha, double beta, int split, double* Y2, int64_t ldy2,
+                    double beta2, hipStream_t s) {
   if (n <= 0 || b <= 0) return;
   if (b > 32) throw Error(1, "gemm_nn: b must be <= 32");
   // 32-byte row loads when the rows of A are 32-byte aligned and hold m rounded up to 16 columns
   const bool vec = lda % 4 == 0 && ((uintptr_t)A & 31) == 0 && lda >= (int64_t)((m + 15) / 16) * 16;
   const unsigned g = (unsigned)cdiv(n, NN_ROWS);
   if (b <= 16) {
-    if (vec) k_gemm_nn<1, true><<<g, 256, 0, s>>>(n, m, b, A, lda, C, ldc, Y, ldy, alpha, beta);
-    else k_gemm_nn<1, false><<<g, 256, 0, s>>>(n, m, b, A, lda, C, ldc, Y, ldy, alpha, beta);
+    if (vec) k_gemm_nn<1, true><<<g, 256, 0, s>>>(n, m, b, A, lda, C, ldc, Y, ldy, alpha, beta, split, Y2, ldy2, beta2);
+    else k_gemm_nn<1, false><<<g, 256, 0, s>>>(n, m, b, A, lda, C, ldc, Y, ldy, alpha, beta, split, Y2, ldy2, beta2);
   } else {
-    if (vec) k_gemm_nn<2, true><<<g, 256, 0, s>>>(n, m, b, A, lda, C, ldc, Y, ldy, alpha, beta);
-    else k_gemm_nn<2, false><<<g, 256, 0, s>>>(n, m, b, A, lda, C, ldc, Y, ldy, alpha, beta);
+    if (vec) k_gemm_nn<2, true><<<g, 256, 0, s>>>(n, m, b, A, lda, C, ldc, Y, ldy, alpha, beta, split, Y2, ldy2, beta2);
+    else k_gemm_nn<2, false><<<g, 256, 0, s>>>(n, m, b, A, lda, C, ldc, Y, ldy, alpha, beta, split, Y2, ldy2, beta2);
   }
   SPPC_LAUNCH_CHECK();
+}
+}  // namespace
+
+void gemm_nn(int64_t n, int m, int b, const double* A, int64_t lda, const double* C, int64_t ldc,
+             double* Y, int64_t ldy, double alpha, double beta, hipStream_t s) {
+  gemm_nn_launch(n, m, b, A, lda, C, ldc, Y, ldy, alpha, beta, b, nullptr, 0, 0.0, s);
+}
+
+void gemm_nn2(int64_t n, int m, int b1, int b2, const double* A, int64_t lda, const double* C, int64_t ldc,
+              double* Y1, int64_t ldy1, double beta1, double* Y2, int64_t ldy2, double beta2, hipStream_t s) {
+  if (b1 < 1 || b2 < 1) throw Error(1, "gemm_nn2: both parts need columns");
+  gemm_nn_launch(n, m, b1 + b2, A, lda, C, ldc, Y1, ldy1, 1.0, beta1, b1, Y2, ldy2, beta2, s);
 }
 
 void copy_to_f32(int64_t n, int b, const double* X, int64_t ldx, float* Y, int64_t ldy, hipStream_t s) {
