@@ -39,7 +39,7 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 # scaled by a plain-copy calibration (profiles/k_spmm_panel_L4-1.17M-k8_mixed_hbm_counters.md).
 # Keyed by (workload, mode); valid only while the kernel source has the recorded sha256.
 MEASURED_TRAFFIC = {
-    ("L4-2k/20k/150k/1M-d200-k8", "mixed+rmmdiis"): (7719570560,
+    ("L4-2k/20k/150k/1M-d200-k8", "mixed+rmmdiis"): (7691697735,
                                                      "65ffad83f54e753d814751fc1c697ece9d5860f59eb780103994cb931f49b35c"),
 }
 
