@@ -313,6 +313,46 @@ def test_product_from_upper_matches_the_dense_symmetric_matrix():
     rows = np.concatenate([np.arange(n), [5, 5, 36, 0]])[::-1]
     Yr = oracle.product_rows_from_upper(rp, np.array(cols, dtype=np.int32), np.array(vals), n, X, rows)
     assert np.max(np.abs(Yr - (Hd @ X)[rows])) < 1e-13
+    # the full matrix the oracle solves: every entry of symmetric_from_upper equals the matrix
+    # written out entry by entry (a doubled or a missing diagonal, or a dropped mirror, fails)
+    Hs = oracle.symmetric_from_upper(rp, np.array(cols, dtype=np.int32), np.array(vals), n).toarray()
+    assert np.array_equal(Hs, Hd)
+    # the ragged case has rows with and without a stored diagonal entry
+    assert any(Hd[i, i] == 0.0 for i in range(n)) and any(Hd[i, i] != 0.0 for i in range(n))
+
+
+def test_symmetric_from_upper_hand_case():
+    # 3 x 3 upper triangle [[2, -1, 0.5], [., 0 (absent), 4], [., ., -3]] written by hand
+    rp = np.array([0, 3, 4, 5], dtype=np.int64)
+    col = np.array([0, 1, 2, 2, 2], dtype=np.int32)
+    val = np.array([2.0, -1.0, 0.5, 4.0, -3.0])
+    H = oracle.symmetric_from_upper(rp, col, val, 3).toarray()
+    want = np.array([[2.0, -1.0, 0.5], [-1.0, 0.0, 4.0], [0.5, 4.0, -3.0]])
+    assert np.array_equal(H, want)
+    X = np.array([[1.0], [2.0], [-1.0]])
+    assert np.array_equal(oracle.product_from_upper(rp, col, val, 3, X), want @ X)
+
+
+# --- the diagonal step of the continuation (Sec. V names a diagonal preconditioner): a 5 x 5 case
+# computed by hand, with one denominator clamped up to +floor, one clamped down to -floor and the
+# projection against the Ritz vector
+def test_jacobi_correction_hand_case():
+    d = np.array([1.0, 2.0, 3.004, 2.99, -1.0])
+    theta = 3.0                      # floor = 1e-2 * max(1, |theta|) = 0.03
+    r = np.array([1.0, 2.0, 3.0, 4.0, 5.0])
+    z = np.array([0.6, 0.8, 0.0, 0.0, 0.0])
+    # d - theta = [-2, -1, 0.004, -0.01, -4] -> clamped [-2, -1, 0.03, -0.03, -4]
+    # M r = [-0.5, -2, 100, -400/3, -1.25];  z . M r = -1.9
+    # (I - z z^T) M r = [0.64, -0.48, 100, -400/3, -1.25];  t = -that
+    want = np.array([-0.64, 0.48, -100.0, 400.0 / 3.0, 1.25])
+    t = oracle.jacobi_correction(d, theta, r, z)
+    assert np.allclose(t, want, rtol=1e-14, atol=1e-14)
+    # |theta| < 1: the floor is 1e-2 (not 1e-2 |theta|); d - theta = 0.005 -> +0.01
+    t = oracle.jacobi_correction(np.array([-0.495, 1.5]), -0.5, np.array([1.0, 1.0]), np.array([0.0, 1.0]))
+    assert np.allclose(t, [-100.0, 0.0], rtol=1e-14, atol=1e-14)
+    # the RMM-DIIS step uses the same clamped diagonal, without the projection
+    assert np.allclose(oracle.core.diag_precond(d, theta, r), [-0.5, -2.0, 100.0, -400.0 / 3.0, -1.25],
+                       rtol=1e-14, atol=1e-14)
 
 
 # ------------------------------------------------------------------ RMM-DIIS (the hybrid's continuation)
