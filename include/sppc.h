@@ -167,6 +167,19 @@ sppc_status sppc_setup(sppc_ctx** out, const sppc_csr* H, const int64_t* level_o
 sppc_status sppc_spmm(sppc_ctx* ctx, const void* X_dev, sppc_dtype xt, double* Y_dev, int b);
 
 /*
+ * Y = H X exactly as sppc_spmm, for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): this call allocates
+ * nothing.  When the context holds the column-panel copy of H and X is not already in the layout
+ * its kernels read (b in {4, 8, 16} columns per row, 16-byte aligned), X is copied to a row stride
+ * B = 4, 8 or 16 in the library's static device scratch array (32 MiB per device, held until the
+ * process ends) instead of the context's buffer; n * B * sizeof(X element) beyond 32 MiB is
+ * rejected with SPPC_E_ARG.  Every call on one device shares that array and it keeps the last
+ * call's contents: calls that overlap on one device (several streams or threads) race.
+ * Arguments, layout and errors as sppc_spmm.
+ */
+sppc_status sppc_spmm_noalloc(sppc_ctx* ctx, const void* X_dev, sppc_dtype xt, double* Y_dev, int b);
+
+/*
  * Computes the next block of new directions into the context (not yet in the basis):
  *   SPPC_CORR_PERTURBATIVE: E_k^(p) and Psi_k^(p) for every wanted pair from
  *     eq. exp_seq (first line) and eq. exp_seq2, with H Psi^(p-1) taken from

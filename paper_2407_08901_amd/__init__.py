@@ -25,7 +25,7 @@ SPPC_CORR_PERTURBATIVE, SPPC_CORR_JACOBI, SPPC_CORR_MPNN, SPPC_CORR_SMALL, SPPC_
 STATUS_NAMES = {0: "SPPC_OK", 1: "SPPC_E_ARG", 2: "SPPC_E_HIP", 3: "SPPC_E_NOMEM",
                 4: "SPPC_E_SINGULAR_E0", 5: "SPPC_E_BREAKDOWN", 6: "SPPC_E_NOCONV", 7: "SPPC_E_NAN"}
 
-EXPORTS = ("sppc_default_opts", "sppc_setup", "sppc_spmm", "sppc_correct", "sppc_rayleigh_ritz",
+EXPORTS = ("sppc_default_opts", "sppc_setup", "sppc_spmm", "sppc_spmm_noalloc", "sppc_correct", "sppc_rayleigh_ritz",
            "sppc_solve", "sppc_get", "sppc_last_error", "sppc_setup_error", "sppc_destroy",
            "sppc_release_cached_memory", "sppc_mpnn_set_weights", "sppc_mpnn_eval", "sppc_mpnn_train_step", "sppc_mpnn_target")
 SPPC_MPNN_NPARAM = 289
@@ -79,6 +79,7 @@ def lib():
         L.sppc_setup.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(sppc_csr), ctypes.POINTER(i64), c_int, c_int,
                                  c_int, ctypes.POINTER(sppc_opts), vp]
         L.sppc_spmm.argtypes = [vp, vp, c_int, vp, c_int]
+        L.sppc_spmm_noalloc.argtypes = [vp, vp, c_int, vp, c_int]
         L.sppc_correct.argtypes = [vp, c_int]
         L.sppc_rayleigh_ritz.argtypes = [vp, dp, dp, ctypes.POINTER(c_int)]
         L.sppc_solve.argtypes = [vp, dp, vp, dp, ctypes.POINTER(sppc_stats)]
@@ -95,7 +96,7 @@ def lib():
         L.sppc_mpnn_eval.argtypes = [vp, fp, c_int, vp, vp, dp, vp, c_int, vp, vp, dp, dp, c_int]
         L.sppc_mpnn_train_step.argtypes = [vp, vp, c_int, vp, vp, dp, vp, c_int, vp, ctypes.c_float, c_int, dp]
         L.sppc_mpnn_target.argtypes = [vp, c_int, vp, c_int, vp, vp]
-        for name in ("sppc_default_opts", "sppc_setup", "sppc_spmm", "sppc_correct", "sppc_rayleigh_ritz",
+        for name in ("sppc_default_opts", "sppc_setup", "sppc_spmm", "sppc_spmm_noalloc", "sppc_correct", "sppc_rayleigh_ritz",
                      "sppc_solve", "sppc_get", "sppc_mpnn_set_weights", "sppc_mpnn_eval", "sppc_mpnn_train_step",
                      "sppc_mpnn_target"):
             getattr(L, name).restype = c_int
@@ -172,6 +173,18 @@ def sppc_spmm(ctx: Context, X: torch.Tensor, Y: torch.Tensor) -> None:
     xt = SPPC_F32 if X.dtype == torch.float32 else SPPC_F64
     _check(lib().sppc_spmm(ctx.handle, ctypes.c_void_p(X.data_ptr()), xt, ctypes.c_void_p(Y.data_ptr()),
                            X.shape[1]), ctx.handle)
+
+
+def sppc_spmm_noalloc(ctx: Context, X: torch.Tensor, Y: torch.Tensor) -> None:
+    """Y = H X as sppc_spmm, allocating nothing (the padded copy of X goes to the library's static
+    device scratch)."""
+    if X.dim() != 2 or Y.shape != X.shape or X.shape[0] != ctx.n or Y.dtype != torch.float64:
+        raise ValueError("X, Y must be n x b, Y float64")
+    if not (X.is_contiguous() and Y.is_contiguous() and X.is_cuda and Y.is_cuda):
+        raise ValueError("X, Y must be contiguous GPU tensors")
+    xt = SPPC_F32 if X.dtype == torch.float32 else SPPC_F64
+    _check(lib().sppc_spmm_noalloc(ctx.handle, ctypes.c_void_p(X.data_ptr()), xt, ctypes.c_void_p(Y.data_ptr()),
+                                   X.shape[1]), ctx.handle)
 
 
 def sppc_correct(ctx: Context, kind: int = SPPC_CORR_PERTURBATIVE) -> None:

@@ -96,8 +96,10 @@ void extract_diag(const DevCSR& H, double* diag, hipStream_t s);
 
 // Y[n x b] = H X (- shift_c X[:,c] when shift != nullptr), row-major with leading dims.
 // X float64 with float64 or float32-exact values.
+// stage (optional, stage_bytes long): where the panel kernels put the padded copy of X when the
+// caller's X is not in their layout (default: the panel's own buffer).
 void spmm_f64(const DevCSR& H, const double* X, int64_t ldx, double* Y, int64_t ldy, int b,
-              const double* shift, hipStream_t s);
+              const double* shift, hipStream_t s, void* stage = nullptr, size_t stage_bytes = 0);
 // Chebyshev filter step: Y = ea * (H X - ec X) + eb * Zo   (Zo must be non-null)
 void spmm_cheb(const DevCSR& H, const double* X, int64_t ldx, double* Y, int64_t ldy, int b, double ea,
                double ec, double eb, const double* Zo, int64_t ldz, hipStream_t s);
@@ -108,7 +110,10 @@ void gershgorin_upper(const DevCSR& H, double* tmp, double* out, hipStream_t s);
 // diag * X64 is added in float64: the diagonal product is the largest term of a row.
 void spmm_f32(const DevCSR& H, const float* X, int64_t ldx, double* Y, int64_t ldy, int b,
               const double* shift, hipStream_t s, const double* diag = nullptr, const double* X64 = nullptr,
-              int64_t ldx64 = 0);
+              int64_t ldx64 = 0, void* stage = nullptr, size_t stage_bytes = 0);
+// Device address (on the current device) and size of the library's static scratch array used by
+// the allocation-free block product; looked up once per device.
+void* noalloc_scratch(size_t* bytes);
 
 // ---------------------------------------------------------------- dense (kernels_dense.hip)
 

@@ -754,6 +754,8 @@ void setup_impl(sppc_ctx* c, const sppc_csr* Hin, const int64_t* loff, int L, in
   if ((int64_t)k * (last_p + 1) > o.m_max) throw Error(SPPC_E_ARG, "m_max < k * (perturbation order + 1)");
   hipStream_t s = c->s;
   const bool mixed = o.precision == SPPC_PREC_MIXED;
+  // device address of the static scratch of the allocation-free block product (once per device)
+  (void)noalloc_scratch(nullptr);
 
   // device format of H
   Arena& A = c->arena;
@@ -1239,6 +1241,21 @@ sppc_status sppc_spmm(sppc_ctx* c, const void* X, sppc_dtype xt, double* Y, int 
       spmm_f32(c->H, (const float*)X, b, Y, b, b, nullptr, c->s);
     } else {
       spmm_f64(c->H, (const double*)X, b, Y, b, b, nullptr, c->s);
+    }
+    return SPPC_OK;
+  });
+}
+
+sppc_status sppc_spmm_noalloc(sppc_ctx* c, const void* X, sppc_dtype xt, double* Y, int b) {
+  if (!c || !X || !Y || b < 1 || b > 32) return SPPC_E_ARG;
+  return guarded(c, [&]() {
+    size_t cap = 0;
+    void* stage = noalloc_scratch(&cap);
+    if (xt == SPPC_F32) {
+      if (!c->H.val32) throw Error(SPPC_E_ARG, "float32 values are not stored (H is not float32-exact)");
+      spmm_f32(c->H, (const float*)X, b, Y, b, b, nullptr, c->s, nullptr, nullptr, 0, stage, cap);
+    } else {
+      spmm_f64(c->H, (const double*)X, b, Y, b, b, nullptr, c->s, stage, cap);
     }
     return SPPC_OK;
   });

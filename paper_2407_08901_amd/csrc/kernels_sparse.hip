@@ -8,6 +8,9 @@
 // atomics in the arithmetic and a deterministic entry order.
 #include "common.h"
 
+#include <mutex>
+#include <string>
+
 #include <algorithm>
 #include <vector>
 
@@ -688,12 +691,22 @@ void spmm_panel_rounds(const PanelH& P, const VT* val, const XT* Xc, double* Y, 
   SPPC_LAUNCH_CHECK();
 }
 
+// X is read from a copy with row stride B when the caller's X is not in that layout: the copy goes
+// to `stage` (stage_bytes long) when given, else to the panel's own buffer.
 template <int B, typename VT, typename XT>
 void spmm_panel_b(const PanelH& P, const VT* val, const XT* X, int64_t ldx, double* Y, int64_t ldy, int b,
-                  hipStream_t s, const double* X64, int64_t ldx64) {
+                  hipStream_t s, const double* X64, int64_t ldx64, void* stage, size_t stage_bytes) {
   const XT* Xc = X;
   if (ldx != B || ((uintptr_t)X & 15) != 0) {
     XT* xp = (XT*)P.xpad;
+    if (stage) {
+      const size_t need = (size_t)P.n * B * sizeof(XT);
+      if (need > stage_bytes)
+        throw Error(1, "the padded copy of X (" + std::to_string(need) + " bytes) exceeds the " +
+                           std::to_string(stage_bytes) + "-byte scratch; pass X with " + std::to_string(B) +
+                           " columns per row, 16-byte aligned, or use sppc_spmm");
+      xp = (XT*)stage;
+    }
     k_pad_copy<XT><<<(unsigned)cdiv(P.n * B, 256), 256, 0, s>>>(P.n, b, X, ldx, xp, B);
     Xc = xp;
   }
@@ -709,13 +722,14 @@ void spmm_panel_b(const PanelH& P, const VT* val, const XT* X, int64_t ldx, doub
 
 template <typename VT, typename XT>
 void launch_spmm_panel(const PanelH& P, const VT* val, const XT* X, int64_t ldx, double* Y, int64_t ldy, int b,
-                       hipStream_t s, const double* X64 = nullptr, int64_t ldx64 = 0) {
+                       hipStream_t s, const double* X64 = nullptr, int64_t ldx64 = 0, void* stage = nullptr,
+                       size_t stage_bytes = 0) {
   if (b <= 4)
-    spmm_panel_b<4, VT, XT>(P, val, X, ldx, Y, ldy, b, s, X64, ldx64);
+    spmm_panel_b<4, VT, XT>(P, val, X, ldx, Y, ldy, b, s, X64, ldx64, stage, stage_bytes);
   else if (b <= 8)
-    spmm_panel_b<8, VT, XT>(P, val, X, ldx, Y, ldy, b, s, X64, ldx64);
+    spmm_panel_b<8, VT, XT>(P, val, X, ldx, Y, ldy, b, s, X64, ldx64, stage, stage_bytes);
   else
-    spmm_panel_b<16, VT, XT>(P, val, X, ldx, Y, ldy, b, s, X64, ldx64);
+    spmm_panel_b<16, VT, XT>(P, val, X, ldx, Y, ldy, b, s, X64, ldx64, stage, stage_bytes);
 }
 
 // first entry of row [b, e) with column >= key (columns ascending)
@@ -1147,12 +1161,14 @@ void release_panel(PanelH& p) {
 }
 
 void spmm_f64(const DevCSR& H, const double* X, int64_t ldx, double* Y, int64_t ldy, int b,
-              const double* shift, hipStream_t s) {
+              const double* shift, hipStream_t s, void* stage, size_t stage_bytes) {
   if (H.panel && !shift && b >= 1 && b <= 16 && H.n > 0) {
     if (H.val64)
-      launch_spmm_panel<double, double>(*H.panel, H.panel->val64, X, ldx, Y, ldy, b, s);
+      launch_spmm_panel<double, double>(*H.panel, H.panel->val64, X, ldx, Y, ldy, b, s, nullptr, 0, stage,
+                                        stage_bytes);
     else
-      launch_spmm_panel<float, double>(*H.panel, H.panel->val32, X, ldx, Y, ldy, b, s);
+      launch_spmm_panel<float, double>(*H.panel, H.panel->val32, X, ldx, Y, ldy, b, s, nullptr, 0, stage,
+                                       stage_bytes);
     return;
   }
   if (H.val64)
@@ -1162,17 +1178,47 @@ void spmm_f64(const DevCSR& H, const double* X, int64_t ldx, double* Y, int64_t 
 }
 
 void spmm_f32(const DevCSR& H, const float* X, int64_t ldx, double* Y, int64_t ldy, int b,
-              const double* shift, hipStream_t s, const double* diag, const double* X64, int64_t ldx64) {
+              const double* shift, hipStream_t s, const double* diag, const double* X64, int64_t ldx64,
+              void* stage, size_t stage_bytes) {
   if (!H.val32) throw Error(1, "spmm_f32: no float32 values");
   if (diag && !X64) throw Error(1, "spmm_f32: the float64 diagonal term needs float64 X");
   if (H.panel && !shift && b >= 1 && b <= 16 && H.n > 0) {
     // the panel stream holds the diagonal apart: diag * X64 in float64 when given, else the
     // float32 product as for the other entries
     launch_spmm_panel<float, float>(*H.panel, H.panel->val32, X, ldx, Y, ldy, b, s, diag ? X64 : nullptr,
-                                    ldx64);
+                                    ldx64, stage, stage_bytes);
     return;
   }
   launch_spmm<float, float>(H, H.val32, X, ldx, Y, ldy, b, shift, s, 0.0, 0.0, 0.0, nullptr, 0, diag, X64, ldx64);
+}
+
+// ---------------------------------------------------------------- allocation-free staging
+// Device scratch of sppc_spmm_noalloc: the padded copy of X that the panel kernels read when the
+// caller's X is not already in that layout.  Each device holds its own copy of this array for the
+// life of the process; host code uses only the address found by hipGetSymbolAddress (the name
+// itself is a host-side stand-in).  Calls that overlap on one device share it and race.
+namespace {
+constexpr size_t kNoallocScratchBytes = (size_t)32 << 20;
+static __device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+// Looks up (once per device, with that device current) the device address of the scratch array.
+void* noalloc_scratch(size_t* bytes) {
+  int dev = 0;
+  SPPC_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) throw Error(1, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    SPPC_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) throw Error(2, "hipGetSymbolAddress returned no address for the scratch array");
+    g_scratch_ptr[dev] = p;
+  }
+  if (bytes) *bytes = kNoallocScratchBytes;
+  return g_scratch_ptr[dev];
 }
 
 }  // namespace sppc
