@@ -3,21 +3,20 @@
 plain float64 SPPC on the same GPU.
 
 One step = sppc_setup (device format, H0hat eigenpairs, p = 0) + sppc_solve (SPPC steps,
-continuation, final float64 check) on the level-structured workload
-L4-2k/20k/150k/1M-d200-k8 (n = 1,172,000, ~118M stored upper entries), with H already
-resident in HBM as an upper-triangular CSR.  The timed form (--mode, default mixed+rmmdiis: the
-paper's SPPC + RMM-DIIS hybrid in the mixed form -- float32 products with float64 accumulation,
-small-space solves to 1e-6, RMM-DIIS refinement of each pair after the perturbative steps, float64
-check) is followed by the same number of steps of plain float64 SPPC (small-space solves to
-1e-12, Davidson continuation), of the mixed form with the Davidson continuation, of the mixed form
-with the learned preconditioner in that continuation, and of float64 SPPC with small-space solves
-to 1e-6, and of the hybrid with the automatic switch (RMM-DIIS from the step at which SPPC
-stagnates; --auto-switch times that form instead); --no-compare skips them.  Prints one JSON line.
+continuation, final float64 check) with H already resident in HBM as an upper-triangular CSR.
+Default workload: L5-2k/20k/200k/1.5M/6M-d300-k16 (n = 7,722,000, 1.17e9 stored upper entries,
+float32 values), k = 16.  The timed form (--mode, default mixed+rmmdiis+mpnn) is the mixed
+precision + learned preconditioner form: float32 products with float64 accumulation, small-space
+solves to 1e-6, the paper's SPPC + RMM-DIIS hybrid after the perturbative steps with the learned
+correction of the diagonal step (per-pair fallback to the diagonal step, judged by the true
+residual), and the float64 check.  The same number of steps of plain float64 SPPC (small solves
+to 1e-12, Davidson continuation) and of the hybrid with the diagonal step follow (--no-compare
+skips them; --full-compare adds more forms).  Prints one JSON line.
 
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload 1]
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload 4]
                   [--mode plain|mixed|plain+mpnn|mixed+mpnn|plain+small|mixed+small|plain+rmmdiis|
-                          mixed+rmmdiis|plain-inexact]
-                  [--no-compare] [--auto-switch]
+                          mixed+rmmdiis|plain+rmmdiis+mpnn|mixed+rmmdiis+mpnn|plain-inexact]
+                  [--no-compare] [--full-compare] [--auto-switch]
                   [--no-cpu-baseline] [--calibrate-copy] [--spmm-only R]
 """
 from __future__ import annotations
@@ -57,7 +56,7 @@ def measured_traffic(workload, mode):
         ok = False
     return rec[0] if ok else None
 MODES = ("plain", "mixed", "plain+mpnn", "mixed+mpnn", "plain+small", "mixed+small", "plain+rmmdiis", "mixed+rmmdiis",
-         "plain-inexact")
+         "plain+rmmdiis+mpnn", "mixed+rmmdiis+mpnn", "plain-inexact")
 
 
 def parse():
@@ -65,10 +64,15 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", type=int, default=1)
-    ap.add_argument("--mode", default="mixed+rmmdiis", choices=MODES)
+    ap.add_argument("--workload", type=int, default=4)
+    ap.add_argument("--mode", default="mixed+rmmdiis+mpnn", choices=MODES)
     ap.add_argument("--no-compare", action="store_true",
-                    help="do not time plain float64 SPPC and the mixed + learned-preconditioner form as well")
+                    help="do not time plain float64 SPPC and the hybrid with the diagonal step as well")
+    ap.add_argument("--full-compare", action="store_true",
+                    help="also time the Davidson continuations, float64 with inexact small solves and the "
+                         "automatic switch")
+    ap.add_argument("--compare-steps", type=int, default=5,
+                    help="timed steps of each comparison form (at most --steps)")
     ap.add_argument("--auto-switch", action="store_true",
                     help="switch to the continuation once SPPC stagnates instead of after step 15")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -138,16 +142,19 @@ def main():
         return
 
     from paper_2407_08901_amd import mpnn_train
-    weights = mpnn_train.load_for_levels(len(w.level_sizes))
+    weights = {"davidson": mpnn_train.load_for("davidson"), "rmmdiis": mpnn_train.load_for("rmmdiis")}
 
     def make_step(mode, auto_switch=None):
         auto_switch = args.auto_switch if auto_switch is None else auto_switch
         mixed = mode.startswith("mixed")
+        rmm = "+rmmdiis" in mode
         mpnn = mode.endswith("mpnn")
-        precond = (P.SPPC_CORR_MPNN if mpnn else P.SPPC_CORR_SMALL if mode.endswith("small") else
-                   P.SPPC_CORR_RMMDIIS if mode.endswith("rmmdiis") else P.SPPC_CORR_JACOBI)
+        precond = (P.SPPC_CORR_RMMDIIS if rmm else P.SPPC_CORR_MPNN if mpnn else
+                   P.SPPC_CORR_SMALL if mode.endswith("small") else P.SPPC_CORR_JACOBI)
         # plain-inexact: float64 with the small-space solves to the mixed form's inner tolerance
         extra = {"inner_tol": 1e-6} if mode == "plain-inexact" else {}
+        if rmm and mpnn:
+            extra["rmm_precond"] = P.SPPC_CORR_MPNN
         opts = P.sppc_default_opts(precision=P.SPPC_PREC_MIXED if mixed else P.SPPC_PREC_FP64, precond=precond,
                                    verbose=1 if args.verbose else 0, panel_width=args.panel_width,
                                    auto_switch=1 if auto_switch else 0, **extra)
@@ -155,23 +162,25 @@ def main():
         def one_step():
             ctx = P.sppc_setup(rp, col, val, A.level_offsets, w.n_small_levels, w.k, opts)
             if mpnn:
-                P.sppc_mpnn_set_weights(ctx, weights)
+                P.sppc_mpnn_set_weights(ctx, weights["rmmdiis" if rmm else "davidson"])
             ev, Z, rrn, st, status = P.sppc_solve(ctx, want_vectors=True)
             P.sppc_destroy(ctx)
             return ev, rrn, st, status
         return one_step
 
-    def timed(mode, auto_switch=None):
+    def timed(mode, auto_switch=None, steps=None, warmup=None):
+        steps = args.steps if steps is None else steps
+        warmup = args.warmup if warmup is None else warmup
         one_step = make_step(mode, auto_switch)
-        for _ in range(args.warmup):
+        for _ in range(warmup):
             one_step()
         torch.cuda.synchronize()
         results = []
         t_start = time.perf_counter()
-        for _ in range(args.steps):
+        for _ in range(steps):
             results.append(one_step())
         torch.cuda.synchronize()
-        return (time.perf_counter() - t_start) / args.steps, results
+        return (time.perf_counter() - t_start) / steps, results
 
     per, results = timed(args.mode)
     ev, rrn, st, status = results[-1]
@@ -184,11 +193,14 @@ def main():
     achieved = alg_bytes / (spmm_ms * 1e-3) / 1e9 if spmm_ms > 0 else 0.0
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None if args.auto_switch else measured_traffic(w.name, args.mode),
-            "kernel": "k_spmm (block product with H)", "launches": spmm_calls,
+            "kernel": "k_spmm_panel (block product with H; one product is a sequence of round launches)",
+            "launches": spmm_calls,
             "avg_launch_ms": round(spmm_ms / max(spmm_calls, 1), 4),
             "alg_bytes_per_launch_avg": int(alg_bytes / max(spmm_calls, 1))}
 
     mixed = args.mode.startswith("mixed")
+    fallbacks = sum(r[2]["mpnn_fallbacks"] for r in results)
+    learned_its = sum(r[2]["mpnn_steps"] for r in results)
     line = {
         "metric": "time to k eigenpairs at resid 1e-6 vs plain FP64 SPPC; SpMM HBM GB/s",
         "value": round(per, 4), "unit": "s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -200,49 +212,59 @@ def main():
         "converged": bool(st["converged"]), "max_rrn": max(rrn), "evals": ev,
         "iterations": st["iterations"], "cont_steps": st["cont_steps"], "refine_steps": st["refine_steps"],
         "mpnn_steps": st["mpnn_steps"], "n_spmv": st["n_spmv"],
+        "learned": {"iterations_per_solve": round(learned_its / len(results), 2),
+                    "fallback_pairs_per_solve": round(fallbacks / len(results), 2),
+                    "fallback_rate": round(fallbacks / (len(results) * w.k), 4)},
         "breakdown_ms": {k: round(st[k], 2) for k in ("t_setup_ms", "t_solve_ms", "t_spmm_ms", "t_small_ms",
                                                       "t_ortho_ms", "t_rr_ms", "t_h0_ms")},
         "cg_iterations": st["cg_iterations"], "h0_iterations": st["h0_iterations"],
         "roofline": roof,
         "generate_s": round(t_gen, 2),
     }
+    ev_p = None
     if not args.no_compare:
+        csteps = max(1, min(args.steps, args.compare_steps))
+        cwarm = min(args.warmup, 1)
+
         def summary(mode, auto_switch=False):
             same = mode == args.mode and auto_switch == args.auto_switch
-            per_m, res_m = (per, results) if same else timed(mode, auto_switch)
+            per_m, res_m = (per, results) if same else timed(mode, auto_switch, csteps, cwarm)
             ev_m, rrn_m, st_m, _ = res_m[-1]
-            return per_m, ev_m, {"s": round(per_m, 4), "iterations": st_m["iterations"],
+            return per_m, ev_m, {"s": round(per_m, 4), "steps": len(res_m), "iterations": st_m["iterations"],
                                  "cont_steps": st_m["cont_steps"], "refine_steps": st_m["refine_steps"],
                                  "mpnn_steps": st_m["mpnn_steps"], "n_spmv": st_m["n_spmv"],
                                  "max_rrn": max(rrn_m), "converged": bool(st_m["converged"])}
         per_p, ev_p, d = summary("plain")
-        line["plain_fp64"] = dict(d, speedup=round(per_p / per, 3),
-                                  max_rel_eval_diff=float(np.max(np.abs(np.array(ev) - np.array(ev_p)) /
-                                                                 np.abs(np.array(ev_p)))))
-        per_l, ev_l, d = summary("mixed+mpnn")
-        line["mixed_learned"] = dict(d, speedup_vs_plain=round(per_p / per_l, 3))
-        # the same float64 method with inexact small-space solves (inner tolerance 1e-6)
-        per_i, ev_i, d = summary("plain-inexact")
-        line["plain_fp64_inner_1e-6"] = dict(d, speedup_vs_plain=round(per_p / per_i, 3))
-        # the mixed form with the Davidson continuation (the library's default continuation)
-        per_r, ev_r, d = summary("mixed")
-        line["mixed_davidson"] = dict(d, speedup_vs_plain=round(per_p / per_r, 3))
-        # the hybrid with the automatic switch: RMM-DIIS from the step at which SPPC stagnates
-        per_a, ev_a, d = summary("mixed+rmmdiis", auto_switch=True)
-        line["mixed_rmmdiis_auto_switch"] = dict(d, speedup_vs_plain=round(per_p / per_a, 3))
+        line["plain_fp64"] = dict(d, max_rel_eval_diff=float(np.max(np.abs(np.array(ev) - np.array(ev_p)) /
+                                                                      np.abs(np.array(ev_p)))))
+        line["speedup_vs_plain_fp64"] = round(per_p / per, 3)
+        # the same hybrid with the diagonal step: what the network gains or costs
+        base = args.mode.replace("+mpnn", "") if args.mode.endswith("rmmdiis+mpnn") else "mixed+rmmdiis"
+        per_r, ev_r, d = summary(base)
+        line["without_network" if base != args.mode else "mixed_rmmdiis"] = dict(
+            d, mode=base, speedup_vs_plain=round(per_p / per_r, 3), value_over_this=round(per / per_r, 3))
+        if args.full_compare:
+            per_l, ev_l, d = summary("mixed+mpnn")
+            line["mixed_learned_davidson"] = dict(d, speedup_vs_plain=round(per_p / per_l, 3))
+            per_i, ev_i, d = summary("plain-inexact")
+            line["plain_fp64_inner_1e-6"] = dict(d, speedup_vs_plain=round(per_p / per_i, 3))
+            per_d, ev_d, d = summary("mixed")
+            line["mixed_davidson"] = dict(d, speedup_vs_plain=round(per_p / per_d, 3))
+            per_a, ev_a, d = summary("mixed+rmmdiis", auto_switch=True)
+            line["mixed_rmmdiis_auto_switch"] = dict(d, speedup_vs_plain=round(per_p / per_a, 3))
     # each eigenvalue's error against the float64 oracle's solution of this matrix, stored by
     # tests/golden/make_oracle_eigs.py (solved there to rrn 1e-10), when it is present
     ref = oracle_eigs(w, A)
     if ref is not None:
         line["eval_rel_err_vs_oracle"] = [float(abs(a - b) / abs(b)) for a, b in zip(ev, ref)]
-        if "plain_fp64" in line:
+        if ev_p is not None:
             line["plain_fp64"]["max_eval_rel_err_vs_oracle"] = float(
                 np.max(np.abs(np.array(ev_p) - ref) / np.abs(ref)))
-        if "mixed_learned" in line:
-            line["mixed_learned"]["max_eval_rel_err_vs_oracle"] = float(
-                np.max(np.abs(np.array(ev_l) - ref) / np.abs(ref)))
+    else:
+        line["eval_rel_err_vs_oracle"] = None  # no stored oracle solution of this matrix
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(A, w, st)
+        steps_ref = line.get("plain_fp64", {"iterations": st["iterations"], "cont_steps": st["cont_steps"]})
+        line["cpu_baseline"] = cpu_baseline(A, w, steps_ref["iterations"] + steps_ref["cont_steps"] + 1)
     print(json.dumps(line))
 
 
@@ -257,60 +279,77 @@ def oracle_eigs(w, A):
     return np.array(rec["evals"])
 
 
-def cpu_baseline(A, w, st):
-    """The CPU oracle timed on bounded samples of the same workload, extrapolated to one solve.
+def cpu_baseline(A, w, steps):
+    """The CPU oracle timed on bounded samples of the same workload, extrapolated to one solve of
+    `steps` SPPC + continuation steps (the plain float64 run's count: the oracle follows that form).
 
-    One oracle SPPC step = one direct block product with H for H Psi^(p-1), the k exact spectral
-    small-space solves, block Gram-Schmidt + QR, one block product with H for the new block
-    and Rayleigh-Ritz.  Each piece is timed once on the real matrix or on a bounded shape and
-    scaled; the setup is the dense eigendecomposition of H0hat, timed on a leading block.
+    One oracle step = one direct block product with H for H Psi^(p-1), the k exact spectral
+    small-space solves, block Gram-Schmidt + QR, one block product with H for the new block and
+    Rayleigh-Ritz.  Pieces: the block product from the upper triangle (oracle.product_from_upper)
+    timed on the leading rows that hold ~2% of the stored entries and scaled by the entry count;
+    one exact small solve on a 2000-row leading block of H0hat scaled by (n0/2000)^2 per column;
+    Gram-Schmidt + QR + Rayleigh-Ritz on a 200,000-row sample scaled by n / 200,000; the dense
+    eigendecomposition of H0hat timed on its leading 2000 x 2000 block and scaled by (n0/2000)^3.
     """
+    import platform
+    import subprocess
+
+    import scipy.sparse as sp
     import threadpoolctl
 
-    import oracle
     from oracle import core as oc
     info = threadpoolctl.threadpool_info()
     threads = max([i.get("num_threads", 1) for i in info] + [1])
+    try:
+        model = [l.split(":", 1)[1].strip() for l in subprocess.run(["lscpu"], capture_output=True, text=True).stdout.splitlines()
+                 if l.startswith("Model name")][0]
+    except Exception:
+        model = platform.processor() or "unknown"
     n, n0, k = A.n, w.n0, w.k
     rng = np.random.default_rng(0)
-    t0 = time.perf_counter()
-    H = oracle.symmetric_from_upper(A.row_ptr, A.col, A.val, n)
-    t_conv = time.perf_counter() - t0
-    # (1) zeroth order: dense eigh of the leading ns x ns block of H0hat, scaled by (n0/ns)^3
-    ns = min(n0, 2000)
-    H0s = H[:ns, :ns].toarray()
-    t0 = time.perf_counter()
-    z_s = oracle.zeroth_order(H0s)
-    t_eig = (time.perf_counter() - t0) * (n0 / ns) ** 3
-    # (2a) one block product with H (k columns), on the real matrix
+    # (1) block product with H from the upper triangle, on the leading rows (~2% of the entries)
+    r1 = int(np.searchsorted(A.row_ptr, 0.02 * A.nnz))
+    r1 = max(1, min(n, r1))
+    e1 = int(A.row_ptr[r1])
     X = rng.standard_normal((n, k))
     t0 = time.perf_counter()
-    H @ X
-    t_spmm = time.perf_counter() - t0
-    # (2b) one exact small-space solve on the leading ns block, scaled by (n0/ns)^2 per column
-    b1 = rng.standard_normal(ns)
+    oc.product_from_upper(np.concatenate([A.row_ptr[:r1 + 1], np.full(n - r1, e1, dtype=np.int64)]),
+                          A.col[:e1], A.val[:e1], n, X)
+    t_spmm = (time.perf_counter() - t0) * A.nnz / max(e1, 1)
+    # (2) zeroth order: dense eigh of the leading ns x ns block of H0hat, scaled by (n0/ns)^3
+    ns = min(n0, 2000)
+    U = sp.csr_matrix((A.val[:int(A.row_ptr[ns])].astype(np.float64), A.col[:int(A.row_ptr[ns])],
+                       A.row_ptr[:ns + 1]), shape=(ns, n)).tocsc()[:, :ns].toarray()
+    H0s = U + U.T - np.diag(np.diag(U))
     t0 = time.perf_counter()
-    oc.small_solve(z_s, 0, b1)
+    z_s = oc.zeroth_order(H0s)
+    t_eig = (time.perf_counter() - t0) * (n0 / ns) ** 3
+    # (3) one exact small-space solve on the leading ns block, scaled by (n0/ns)^2 per column
+    t0 = time.perf_counter()
+    oc.small_solve(z_s, 0, rng.standard_normal(ns))
     t_small = (time.perf_counter() - t0) * (n0 / ns) ** 2 * k
-    # (2c) block Gram-Schmidt + QR and Rayleigh-Ritz at the mean basis size of the GPU run
-    m = max(k, (st["iterations"] + st["cont_steps"] + 1) * k // 2)
-    Q = np.linalg.qr(rng.standard_normal((n, m)))[0]
-    HQ = rng.standard_normal((n, m))
-    Psi = rng.standard_normal((n, k))
+    # (4) block Gram-Schmidt + QR and Rayleigh-Ritz at the mean basis size, on a row sample
+    m = max(k, steps * k // 2)
+    nr = min(n, 200000)
+    Q = np.linalg.qr(rng.standard_normal((nr, m)))[0]
+    HQ = rng.standard_normal((nr, m))
+    Psi = rng.standard_normal((nr, k))
     t0 = time.perf_counter()
     oc.orthonormalize_block(Q, Psi, 1e-10)
     oc.rayleigh_ritz(Q, HQ, k)
-    t_dense = time.perf_counter() - t0
-    steps = st["iterations"] + st["cont_steps"] + 1
+    t_dense = (time.perf_counter() - t0) * n / nr
     per_step = 2 * t_spmm + t_small + t_dense
-    est = t_conv + t_eig + steps * per_step
-    return {"value": round(est, 2), "unit": "s", "cores": threads, "kind": "oracle",
-            "sample": ("extrapolated from timed pieces of the oracle on this workload: dense eigh of the "
-                       "leading %dx%d block of H0hat scaled by (n0/%d)^3 (%.1f s); per SPPC step 2 block "
-                       "products with H (%.2f s each), %d exact small solves (one timed at n0=%d, scaled "
-                       "by (n0/%d)^2: %.2f s), Gram-Schmidt+QR and Rayleigh-Ritz at m=%d (%.2f s); x %d "
-                       "steps of the GPU run") % (ns, ns, ns, t_eig, t_spmm, k, ns, ns, t_small, m,
-                                                  t_dense, steps)}
+    est = t_eig + steps * per_step
+    return {"value": round(est, 1), "unit": "s", "cores": threads, "kind": "oracle", "extrapolated": True,
+            "cpu": model, "threads_env": {v: os.environ.get(v) for v in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS")},
+            "sample": ("extrapolation from bounded samples of the oracle on this workload (%s, %d BLAS threads): "
+                       "block product from the upper triangle on the leading %d rows (%.1f%% of the entries), "
+                       "scaled: %.2f s per product; dense eigh of the leading %dx%d block of H0hat scaled by "
+                       "(n0/%d)^3: %.1f s; %d exact small solves (one timed at n0=%d, scaled by (n0/%d)^2): %.2f s; "
+                       "Gram-Schmidt+QR and Rayleigh-Ritz at m=%d on %d rows, scaled to n: %.2f s; per step 2 "
+                       "products + small solves + dense; x %d steps (the plain float64 run's SPPC + "
+                       "continuation steps)") % (model, threads, r1, 100.0 * e1 / A.nnz, t_spmm, ns, ns, ns, t_eig,
+                                                 k, ns, ns, t_small, m, nr, t_dense, steps)}
 
 
 if __name__ == "__main__":

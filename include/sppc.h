@@ -106,6 +106,11 @@ typedef struct {
                           the basis is below 1e-4 (Fig. 3), or the largest rrn has not halved over
                           the last three steps (detection left open by the paper, Sec. VII); takes
                           effect only with p_switch > 0; 0 (default): switch at p_switch only */
+  int rmm_precond;     /* step of the RMM-DIIS continuation: SPPC_CORR_JACOBI (the diagonal step,
+                          default) or SPPC_CORR_MPNN (the learned correction of the diagonal step,
+                          weights from sppc_mpnn_set_weights; a pair falls back to the diagonal step
+                          when its residual did not drop below 0.9x its value at its previous
+                          learned step) */
 } sppc_opts;
 
 typedef struct {
@@ -113,7 +118,8 @@ typedef struct {
   int cont_steps;      /* continuation steps (refinement steps included) */
   int refine_steps;    /* float64 refinement steps after a mixed-precision solve */
   int mpnn_steps;      /* continuation steps that used the learned preconditioner */
-  int64_t n_spmv;      /* products of H with one vector (k per SPPC step, Sec. IV.C) */
+  int64_t n_spmv;      /* products of H with one vector (k per SPPC step, Sec. IV.C; a learned step
+                          adds the network's two per pair) */
   int64_t spmm_calls;  /* block products with H (kernel launches) */
   int64_t spmm_cols;   /* sum of their block widths */
   int basis_size;      /* columns of the final basis */
@@ -130,6 +136,7 @@ typedef struct {
                             triangle once (values as read: float32 when lossless or mixed;
                             int32 columns; int64 row pointers) + X read + Y written */
   double t_h0_ms;      /* time inside products with H0hat outside the small solves */
+  int mpnn_fallbacks;  /* pairs that the true residual sent back to the diagonal step */
 } sppc_stats;
 
 typedef struct sppc_ctx sppc_ctx;
@@ -235,7 +242,9 @@ sppc_status sppc_get(sppc_ctx* ctx, int what, double* dst, int64_t count);
  *
  * A 2-layer message-passing network over the graph of H (hidden width 32) scales the diagonal
  * step of the continuation row by row.  For a Ritz pair (theta, x) with residual r:
- *   f = [r / rms(r), (d - theta)/(1 + |theta|), level/(L-1)],  g = A f,  A = H - diag(d)
+ *   f = [r / rms(r), (d - theta)/(1 + |theta|), lambda],  g = A f,  A = H - diag(d),
+ *   lambda = min(max(level - n_small_levels + 1, 0), 2) / 2  (0 on the small-space levels, 1/2 on the
+ *            first level outside them, 1 beyond: the same for any number of levels)
  *   h = tanh(Ws f + Wn g + b1),  o = ws.h + A (wn.h) + b2,
  *   t = tJ (1 + o) with the diagonal step tJ = r / (d - theta) (|d - theta| >= 1e-2 max(1,|theta|)),
  *   t~ = t - x (x^T t);  the continuation direction is -t~.  A zero network is the diagonal step.

@@ -4,7 +4,8 @@ A 2-layer message-passing network over the graph of H corrects the diagonal (Jac
 step of the continuation (the diagonal preconditioner of Sec. V) for one Ritz pair
 (theta, x) with residual r = H x - theta x:
 
-  features per row      f = [ r / rms(r),  (d - theta) / (1 + |theta|),  level / (L - 1) ]
+  features per row      f = [ r / rms(r),  (d - theta) / (1 + |theta|),  lambda(level) ]
+                        lambda = min(max(level - n_small_levels + 1, 0), 2) / 2 (level_feature)
   messages              g = A f,            A = H - diag(d)   (signed, symmetric)
   layer 1 (width 32)    h = tanh(f Ws^T + g Wn^T + b1)
   layer 2               o = h ws + A (h wn) + b2
@@ -33,6 +34,15 @@ def unpack(w):
     wn = w[256:288]
     b2 = w[288]
     return Ws, Wn, b1, ws, wn, b2
+
+
+def level_feature(level_offsets, n_small_levels: int) -> np.ndarray:
+    """The level input of each row (a reading of "level id" that keeps one meaning for any number
+    of levels): the row's level counted from the small space, clipped to 0..2 and halved -- 0 on the
+    small-space levels, 1/2 on the first level outside them, 1 on every level beyond."""
+    offs = np.asarray(level_offsets, dtype=np.int64)
+    lvl = np.searchsorted(offs, np.arange(offs[-1]), side="right") - 1
+    return np.clip(lvl - n_small_levels + 1, 0, 2) / 2.0
 
 
 def offdiag(H: sp.csr_matrix):

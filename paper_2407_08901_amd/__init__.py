@@ -42,7 +42,7 @@ class sppc_opts(ctypes.Structure):
                 ("tau_drop", ctypes.c_double), ("inner_tol", ctypes.c_double), ("h0_tol", ctypes.c_double),
                 ("precision", ctypes.c_int), ("precond", ctypes.c_int), ("final_check", ctypes.c_int),
                 ("verbose", ctypes.c_int), ("panel_width", ctypes.c_int), ("refine_precond", ctypes.c_int),
-                ("precond_tol", ctypes.c_double), ("auto_switch", ctypes.c_int)]
+                ("precond_tol", ctypes.c_double), ("auto_switch", ctypes.c_int), ("rmm_precond", ctypes.c_int)]
 
 
 class sppc_stats(ctypes.Structure):
@@ -52,7 +52,8 @@ class sppc_stats(ctypes.Structure):
                 ("basis_size", ctypes.c_int), ("cg_iterations", ctypes.c_int), ("h0_iterations", ctypes.c_int),
                 ("converged", ctypes.c_int), ("t_setup_ms", ctypes.c_double), ("t_solve_ms", ctypes.c_double),
                 ("t_spmm_ms", ctypes.c_double), ("t_small_ms", ctypes.c_double), ("t_ortho_ms", ctypes.c_double),
-                ("t_rr_ms", ctypes.c_double), ("spmm_alg_bytes", ctypes.c_double), ("t_h0_ms", ctypes.c_double)]
+                ("t_rr_ms", ctypes.c_double), ("spmm_alg_bytes", ctypes.c_double), ("t_h0_ms", ctypes.c_double),
+                ("mpnn_fallbacks", ctypes.c_int)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

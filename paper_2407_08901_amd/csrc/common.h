@@ -238,7 +238,7 @@ void scatter_cols(int64_t n, int S, const int* idx, const double* X, int64_t ldx
 
 // ---------------------------------------------------------------- learned preconditioner (kernels_mpnn.hip)
 int mpnn_nparam();
-void mpnn_prepare(const DevCSR& H, const double* diag, const int64_t* level_off_dev, int L, double* lev,
+void mpnn_prepare(const DevCSR& H, const double* diag, const int64_t* level_off_dev, int L, int nsmall, double* lev,
                   double* Ad, double* A1, double* Al, double* tmp, hipStream_t s);
 int64_t mpnn_work_doubles(int64_t n, int S);
 // Optional basis for the output projection t - Q (Q^T t) (training against the part of the
@@ -254,7 +254,7 @@ template <typename T>
 void mpnn_run(const DevCSR& H, const double* diag, const double* lev, const double* Ad, const double* A1,
               const double* Al, const T* w, int S, const double* R, int64_t ldr, const double* X, int64_t ldx,
               const double* theta_dev, const double* E, double* T_out, double* grad_out, double* loss_dev,
-              double* work, const MpnnBasis* basis, hipStream_t s);
+              double* work, const MpnnBasis* basis, hipStream_t s, bool project = true);
 void mpnn_adam(float* w, float* m, float* v, const double* g, float lr, int step, float* wq, hipStream_t s);
 void mpnn_round_bf16(int cnt, const float* w, float* wq, double* wd, hipStream_t s);
 void mpnn_target(int64_t n, int S, const MpnnBasis& B, const double* Psi, double* E, hipStream_t s);

@@ -167,6 +167,7 @@ struct sppc_ctx {
   EventTimer tm;
   double tacc[C_NCAT] = {0, 0, 0, 0, 0};
   int64_t nnz_up = 0;  // stored upper-triangle entries of the input
+  int nsmall = 0;      // leading levels that form the small space
 };
 
 namespace sppc {
@@ -483,7 +484,7 @@ void mpnn_ensure(sppc_ctx* c, int S) {
     c->mp_w = A.alloc<float>(512);
     c->mp_wq = A.alloc<float>(512);
     double* tmp = A.alloc<double>((size_t)6 * n);
-    mpnn_prepare(c->H, c->diag, c->loff_dev, L, c->mp_lev, c->mp_Ad, c->mp_A1, c->mp_Al, tmp, s);
+    mpnn_prepare(c->H, c->diag, c->loff_dev, L, c->nsmall, c->mp_lev, c->mp_Ad, c->mp_A1, c->mp_Al, tmp, s);
     sync(c);
     c->mp_ready = true;
   }
@@ -586,6 +587,7 @@ void correct_continuation(sppc_ctx* c, int kind) {
       upload_theta(c, th.data(), S);
       mpnn_run<float>(c->H, c->diag, c->mp_lev, c->mp_Ad, c->mp_A1, c->mp_Al, c->mp_wq, S, Rs, S, Zs, S,
                       c->mp_th, nullptr, Ts, nullptr, nullptr, c->mp_work, nullptr, s);
+      c->st.n_spmv += 2 * S;  // the network's two aggregations are products with H
       // a non-finite or vanishing learned direction falls back to the diagonal step
       colsumsq(n, S, Ts, S, c->sumsq, c->work, s);
       SPPC_HIP(hipMemcpyAsync(c->pin + 2 * NWMAX, c->sumsq, sizeof(double) * S, hipMemcpyDeviceToHost, s));
@@ -731,6 +733,7 @@ void setup_impl(sppc_ctx* c, const sppc_csr* Hin, const int64_t* loff, int L, in
   c->n = Hin->n;
   c->nnz_up = Hin->nnz;
   c->n0 = c->loff[nsmall];
+  c->nsmall = nsmall;
   c->k = k;
   sppc_opts& o = c->o;
   if (k < 1 || k > 16 || k > c->n0) throw Error(SPPC_E_ARG, "k must be 1..16 and <= n0");
@@ -742,6 +745,8 @@ void setup_impl(sppc_ctx* c, const sppc_csr* Hin, const int64_t* loff, int L, in
   if (o.precond != SPPC_CORR_JACOBI && o.precond != SPPC_CORR_MPNN && o.precond != SPPC_CORR_SMALL &&
       o.precond != SPPC_CORR_RMMDIIS)
     throw Error(SPPC_E_ARG, "continuation must be JACOBI, MPNN, SMALL or RMMDIIS");
+  if (o.rmm_precond != SPPC_CORR_JACOBI && o.rmm_precond != SPPC_CORR_MPNN)
+    throw Error(SPPC_E_ARG, "the RMM-DIIS step preconditioner must be JACOBI or MPNN");
   if (o.refine_precond != SPPC_CORR_JACOBI && o.refine_precond != SPPC_CORR_MPNN &&
       o.refine_precond != SPPC_CORR_SMALL)
     throw Error(SPPC_E_ARG, "refinement preconditioner must be JACOBI, MPNN or SMALL");
@@ -926,6 +931,62 @@ void setup_impl(sppc_ctx* c, const sppc_csr* Hin, const int64_t* loff, int L, in
 // Returns the number of iterations (at most cap <= RMM_SWEEP).
 constexpr int RMM_SWEEP = 4;
 
+// The learned step of RMM-DIIS: for the listed pairs (unit iterates xb, residuals rb, Rayleigh
+// quotients th_host) the direction tJ (1 + o) of the network replaces the diagonal step tJ already
+// in t.  The true residual judges it: a pair whose residual did not fall below 0.9x its value at its
+// previous learned step, or whose learned direction is not finite, keeps the diagonal step from then on.
+void rmm_learned_step(sppc_ctx* c, const std::vector<int>& act, const std::vector<double>& rrn_now,
+                      const double* th_host, const double* rb, const double* xb, double* t) {
+  hipStream_t s = c->s;
+  const int k = c->k;
+  const int64_t n = c->n;
+  if ((int)c->mp_fallback.size() != k) {
+    c->mp_fallback.assign(k, 0);
+    c->mp_prev_rrn.assign(k, 0.0);
+  }
+  std::vector<int> sel;
+  for (int a : act) {
+    if (c->mp_prev_rrn[a] > 0.0 && !(rrn_now[a] < 0.9 * c->mp_prev_rrn[a])) c->mp_fallback[a] = 1;
+    if (!c->mp_fallback[a]) sel.push_back(a);
+  }
+  if (sel.empty()) return;
+  const int S = (int)sel.size();
+  mpnn_ensure(c, S);
+  for (int a = 0; a < S; ++a) c->pin_i[8 + a] = sel[a];
+  SPPC_HIP(hipMemcpyAsync(c->idx, c->pin_i + 8, sizeof(int) * S, hipMemcpyHostToDevice, s));
+  double* Rs = c->mp_sel;
+  double* Zs = Rs + n * S;
+  double* Ts = Zs + n * S;
+  gather_cols(n, S, c->idx, rb, k, Rs, S, s);
+  gather_cols(n, S, c->idx, xb, k, Zs, S, s);
+  std::vector<double> th(S);
+  for (int a = 0; a < S; ++a) th[a] = th_host[sel[a]];
+  upload_theta(c, th.data(), S);
+  mpnn_run<float>(c->H, c->diag, c->mp_lev, c->mp_Ad, c->mp_A1, c->mp_Al, c->mp_wq, S, Rs, S, Zs, S, c->mp_th,
+                  nullptr, Ts, nullptr, nullptr, c->mp_work, nullptr, s, /*project=*/false);
+  c->st.n_spmv += 2 * S;  // the network's two aggregations are products with H
+  colsumsq(n, S, Ts, S, c->sumsq, c->work, s);
+  SPPC_HIP(hipMemcpyAsync(c->pin + 2 * NWMAX, c->sumsq, sizeof(double) * S, hipMemcpyDeviceToHost, s));
+  sync(c);
+  for (int a = 0; a < S; ++a) {
+    const double nn = c->pin[2 * NWMAX + a];
+    if (std::isfinite(nn) && nn > 0.0) {
+      c->pin_i[8 + a] = sel[a];
+      c->mp_prev_rrn[sel[a]] = rrn_now[sel[a]];
+    } else {
+      c->pin_i[8 + a] = -1;
+      c->mp_fallback[sel[a]] = 1;
+    }
+  }
+  SPPC_HIP(hipMemcpyAsync(c->idx, c->pin_i + 8, sizeof(int) * S, hipMemcpyHostToDevice, s));
+  scatter_cols(n, S, c->idx, Ts, S, t, k, 1.0, s);
+  // idx is read again by the caller: restore the identity map of the k pairs
+  for (int a = 0; a < k; ++a) c->pin_i[8 + a] = a;
+  SPPC_HIP(hipMemcpyAsync(c->idx, c->pin_i + 8, sizeof(int) * k, hipMemcpyHostToDevice, s));
+  sync(c);
+  c->st.mpnn_steps += 1;
+}
+
 int rmm_diis_sweep(sppc_ctx* c, int cap) {
   hipStream_t s = c->s;
   const int k = c->k;
@@ -966,6 +1027,8 @@ int rmm_diis_sweep(sppc_ctx* c, int cap) {
   std::vector<char> done(k);
   for (int a = 0; a < k; ++a) done[a] = c->rrn_h[a] < o.tol;
   Op op{c, &c->H, false, true};
+  const bool learned = o.rmm_precond == SPPC_CORR_MPNN && c->mp_have_w && !c->mp_invalid;
+  std::vector<double> rrn_now(k, 0.0), th_now(k, 0.0);
   for (int it = 0;; ++it) {
     size_t t0 = c->tm.begin(C_SMALL);
     diis_coefficients(k, L, D, c->rd_A, c->rd_al, s);
@@ -983,6 +1046,8 @@ int rmm_diis_sweep(sppc_ctx* c, int cap) {
       if (done[a]) continue;
       const double thv = c->pin[a];
       const double r = std::sqrt(std::max(0.0, c->pin[NWMAX + a])) / std::max(std::fabs(thv), 1e-300);
+      rrn_now[a] = r;
+      th_now[a] = thv;
       if (r < o.tol || it >= cap) {
         copy_block(n, 1, xb + a, k, c->Z + a, k, s);
         copy_block(n, 1, hxb + a, k, c->HZ + a, k, s);
@@ -999,6 +1064,14 @@ int rmm_diis_sweep(sppc_ctx* c, int cap) {
     t0 = c->tm.begin(C_SMALL);
     jacobi_block(n, k, c->idx, rb, k, c->diag, th, t, k, s);
     c->tm.end(t0);
+    if (learned) {
+      std::vector<int> act;
+      for (int a = 0; a < k; ++a)
+        if (!done[a]) act.push_back(a);
+      t0 = c->tm.begin(C_SMALL);
+      rmm_learned_step(c, act, rrn_now, th_now.data(), rb, xb, t);
+      c->tm.end(t0);
+    }
     op(t, k, ht, k, k, s);
     t0 = c->tm.begin(C_SMALL);
     residual_block(n, k, t, k, ht, k, th, u, k, uu, c->work, s);  // u = H t - theta t
@@ -1151,6 +1224,8 @@ sppc_status solve_impl(sppc_ctx* c, double* evals, double* evecs, double* rrn, s
   }
   c->st.cont_steps = cont;
   c->st.converged = conv;
+  c->st.mpnn_fallbacks = 0;
+  for (int f : c->mp_fallback) c->st.mpnn_fallbacks += f ? 1 : 0;
   c->st.basis_size = c->B.m;
   const int k = c->k;
   if (evals) memcpy(evals, c->theta_h.data(), sizeof(double) * k);
@@ -1207,6 +1282,7 @@ sppc_status sppc_default_opts(sppc_opts* o) {
   o->final_check = 1;
   o->verbose = 0;
   o->panel_width = -1;
+  o->rmm_precond = SPPC_CORR_JACOBI;
   return SPPC_OK;
 }
 

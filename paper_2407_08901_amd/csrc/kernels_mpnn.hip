@@ -1,7 +1,8 @@
 // kernels_mpnn.hip - learned preconditioner for the continuation: a 2-layer message-passing
 // network over the graph of H that corrects the diagonal (Jacobi) step for each Ritz pair.
 //
-//   f = [r / rms(r), (d - theta)/(1 + |theta|), level/(L-1)],  g = A f,  A = H - diag(d)
+//   f = [r / rms(r), (d - theta)/(1 + |theta|), lambda(level)],  g = A f,  A = H - diag(d)
+//   lambda = min(max(level - n_small_levels + 1, 0), 2) / 2 (0 in the small space, 1/2 next to it, 1 beyond)
 //   h = tanh(Ws f + Wn g + b1)   (32 hidden units, per row, in registers; never written to HBM)
 //   o = ws.h + A (wn.h) + b2 ;   t = tJ (1 + o),  tJ = r / (d - theta) (clamped) ;  t~ = t - x (x.t)
 //
@@ -245,12 +246,15 @@ __global__ void k_pack3(int64_t n, const double* __restrict__ d, const double* _
   P[r * 3 + 2] = lev[r];
 }
 
-__global__ void k_levels(int64_t n, int L, const int64_t* __restrict__ off, double* __restrict__ lev) {
+// level feature: the level counted from the small space, clipped: 0 on the small-space levels, 1/2
+// on the first level outside it, 1 beyond (the same values for any number of levels)
+__global__ void k_levels(int64_t n, int L, int nsmall, const int64_t* __restrict__ off, double* __restrict__ lev) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= n) return;
   int l = 0;
   while (l + 1 < L && off[l + 1] <= r) ++l;
-  lev[r] = L > 1 ? (double)l / (double)(L - 1) : 0.0;
+  const int rel = l - nsmall + 1;
+  lev[r] = 0.5 * (double)(rel < 0 ? 0 : rel > 2 ? 2 : rel);
 }
 
 __global__ void k_fill_const(int S, double v, double* __restrict__ out) {
@@ -275,10 +279,10 @@ inline int64_t gg(int64_t c) { return cdiv(c > 0 ? c : 1, 256); }
 int mpnn_nparam() { return NPAR; }
 
 // Static inputs: lev[n], Ad[n], A1[n], Al[n]; tmp >= 6n doubles.
-void mpnn_prepare(const DevCSR& H, const double* diag, const int64_t* level_off_dev, int L, double* lev,
+void mpnn_prepare(const DevCSR& H, const double* diag, const int64_t* level_off_dev, int L, int nsmall, double* lev,
                   double* Ad, double* A1, double* Al, double* tmp, hipStream_t s) {
   const int64_t n = H.n;
-  k_levels<<<gg(n), 256, 0, s>>>(n, L, level_off_dev, lev);
+  k_levels<<<gg(n), 256, 0, s>>>(n, L, nsmall, level_off_dev, lev);
   k_pack3<<<gg(n), 256, 0, s>>>(n, diag, lev, tmp);
   spmm_f64(H, tmp, 3, tmp + 3 * n, 3, 3, nullptr, s);
   k_static<<<gg(n), 256, 0, s>>>(n, diag, lev, tmp + 3 * n, Ad, A1, Al);
@@ -313,9 +317,10 @@ template <typename T>
 void mpnn_run(const DevCSR& H, const double* diag, const double* lev, const double* Ad, const double* A1,
               const double* Al, const T* w, int S, const double* R, int64_t ldr, const double* X, int64_t ldx,
               const double* theta_dev, const double* E, double* T_out, double* grad_out, double* loss_dev,
-              double* work, const MpnnBasis* basis, hipStream_t s) {
+              double* work, const MpnnBasis* basis, hipStream_t s, bool project) {
   const int64_t n = H.n;
   const int64_t items = n * S;
+  if (!project && E) throw Error(1, "mpnn_run: the loss needs the projected output");
   double* fr = work;
   double* HF = fr + items;
   double* u = HF + items;
@@ -346,7 +351,9 @@ void mpnn_run(const DevCSR& H, const double* diag, const double* lev, const doub
   k_mpnn_out<T><<<gg(items), 256, 0, s>>>(n, S, diag, w, R, ldr, theta_dev, hs, u, Hu, t, tJ);
   // t~ = t - x (x.t), or t - Q (Q^T t) with a basis
   k_fill_const<<<1, 64, 0, s>>>(S, 1.0, one);
-  if (basis) {
+  if (!project) {
+    // unprojected t = tJ (1 + o) (the step of a single-vector refinement)
+  } else if (basis) {
     project_basis(n, S, *basis, t, s);
   } else {
     coldots(n, S, X, ldx, t, S, xdt, part, s);
@@ -382,11 +389,11 @@ void mpnn_run(const DevCSR& H, const double* diag, const double* lev, const doub
 template void mpnn_run<float>(const DevCSR&, const double*, const double*, const double*, const double*,
                               const double*, const float*, int, const double*, int64_t, const double*, int64_t,
                               const double*, const double*, double*, double*, double*, double*,
-                              const MpnnBasis*, hipStream_t);
+                              const MpnnBasis*, hipStream_t, bool);
 template void mpnn_run<double>(const DevCSR&, const double*, const double*, const double*, const double*,
                                const double*, const double*, int, const double*, int64_t, const double*,
                                int64_t, const double*, const double*, double*, double*, double*, double*,
-                               const MpnnBasis*, hipStream_t);
+                               const MpnnBasis*, hipStream_t, bool);
 
 void mpnn_adam(float* w, float* m, float* v, const double* g, float lr, int step, float* wq, hipStream_t s) {
   k_adam<<<cdiv(NPAR, 256), 256, 0, s>>>(w, m, v, g, lr, 0.9f, 0.999f, 1e-8f, step, wq);

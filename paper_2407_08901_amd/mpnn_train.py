@@ -11,10 +11,16 @@ it is parallel to e.  The network output is compared after the same projection.
 (The exact correction (H - theta I)^-1 r that a literal reading suggests equals x itself,
 and the Jacobi-Davidson limit psi / (psi^T x) - x lies mostly inside the basis.)
 
+Two targets, one per continuation:
+  * basis (the Davidson continuation, SPPC_CORR_MPNN): e = (I - Q Q^T) psi as above;
+  * pair (the RMM-DIIS step, rmm_precond = SPPC_CORR_MPNN): e = (I - x x^T) psi.  RMM-DIIS refines
+    one vector at a time (Sec. V-VI): its step x + lam t reaches psi exactly when t is parallel to
+    the part of psi orthogonal to x.  The output is projected against x alone.
+
 Optimisation: Adam on the float32 master weights with bfloat16-rounded copies in the forward
 pass (sppc_mpnn_train_step: forward, backward and update all run in the library's kernels).
 
-    python -m paper_2407_08901_amd.mpnn_train [--shape L3|L4] [--out weights.json] [--epochs 30]
+    python -m paper_2407_08901_amd.mpnn_train [--target basis|pair] [--shape L3|L4] [--out weights.json]
 """
 from __future__ import annotations
 
@@ -30,12 +36,12 @@ import torch
 import paper_2407_08901_amd as P
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-DEFAULT_WEIGHTS = os.path.join(HERE, "mpnn_weights.json")          # three-level training shape
-WEIGHTS_L4 = os.path.join(HERE, "mpnn_weights_L4.json")           # four-level training shape
-FORMAT = "sppc-mpnn-v1"
+DEFAULT_WEIGHTS = os.path.join(HERE, "mpnn_weights.json")          # basis target (Davidson continuation)
+PAIR_WEIGHTS = os.path.join(HERE, "mpnn_weights_rmm.json")         # pair target (RMM-DIIS step)
+FORMAT = "sppc-mpnn-v2"  # v2: level input lambda = min(max(level - n_small + 1, 0), 2) / 2
 
 
-def build_dataset(seeds, shape="L3", log=print):
+def build_dataset(seeds, shape="L3", target="basis", log=print):
     import levelgen
     data = []
     for sd in seeds:
@@ -68,7 +74,12 @@ def build_dataset(seeds, shape="L3", log=print):
                     ix = torch.tensor(sel, device="cuda")
                     X = Z[:, ix].contiguous()
                     Psi = psi[:, ix].contiguous()
-                    E = P.sppc_mpnn_target(ctx, Q, Psi)
+                    if target == "basis":
+                        E = P.sppc_mpnn_target(ctx, Q, Psi)
+                    else:  # (I - x x^T) psi, one sample at a time (the basis is x alone)
+                        E = torch.cat([P.sppc_mpnn_target(ctx, X[:, j:j + 1].contiguous(), Psi[:, j:j + 1].contiguous())
+                                       for j in range(len(sel))], dim=1).contiguous()
+                        Q = None
                     groups.append(dict(step=step, Q=Q, X=X, R=R[:, ix].contiguous(), E=E,
                                        theta=np.array([theta[i] for i in sel])))
             if max(rrn) < 1e-6 or added == 0:
@@ -78,7 +89,7 @@ def build_dataset(seeds, shape="L3", log=print):
     return data
 
 
-def train(data, epochs=30, lr=3e-3, seed=0, log=print):
+def train(data, epochs=120, lr=1e-2, seed=0, log=print):
     """One Adam step per (matrix, step) batch; cosine learning-rate decay to lr/10."""
     rng = np.random.default_rng(seed)
     state = torch.zeros(4 * P.SPPC_MPNN_NPARAM, dtype=torch.float32, device="cuda")
@@ -127,33 +138,37 @@ def load(path=DEFAULT_WEIGHTS) -> np.ndarray:
     return w
 
 
-def load_for_levels(n_levels: int) -> np.ndarray:
-    """Weights trained on matrices with the same number of levels (the level feature is
-    level / (L - 1), so its meaning depends on L): four-level weights for L >= 4."""
-    return load(WEIGHTS_L4 if n_levels >= 4 else DEFAULT_WEIGHTS)
+def load_for(continuation: str = "davidson") -> np.ndarray:
+    """Weights for the Davidson continuation ("davidson", basis target) or the RMM-DIIS step
+    ("rmmdiis", pair target).  The level input has one meaning for any number of levels, so the
+    weights trained on the n = 4900 three-level matrices serve every workload."""
+    return load(PAIR_WEIGHTS if continuation == "rmmdiis" else DEFAULT_WEIGHTS)
 
 
 def main():
     import levelgen
     ap = argparse.ArgumentParser()
-    ap.add_argument("--out", default=DEFAULT_WEIGHTS)
-    ap.add_argument("--epochs", type=int, default=30)
-    ap.add_argument("--lr", type=float, default=3e-3)
-    ap.add_argument("--nseeds", type=int, default=20)
+    ap.add_argument("--out", default=None, help="default: the file of the target")
+    ap.add_argument("--target", default="basis", choices=["basis", "pair"])
+    ap.add_argument("--epochs", type=int, default=120)
+    ap.add_argument("--lr", type=float, default=1e-2)
+    ap.add_argument("--nseeds", type=int, default=24)
     ap.add_argument("--shape", default="L3", choices=["L3", "L4"],
                     help="training matrices: the n = 4900 three-level shape or the four-level n = 117,200 one")
     args = ap.parse_args()
     P.lib()
     t0 = time.time()
     seeds = (levelgen.TRAIN_SEEDS if args.shape == "L3" else levelgen.TRAIN_SEEDS_L4)[: args.nseeds]
-    data = build_dataset(seeds, args.shape, log=lambda m: print(m, flush=True))
+    data = build_dataset(seeds, args.shape, args.target, log=lambda m: print(m, flush=True))
     t1 = time.time()
     w, hist = train(data, epochs=args.epochs, lr=args.lr, log=lambda m: print(m, flush=True))
     t2 = time.time()
     nsamp = sum(g["X"].shape[1] for d in data for g in d["groups"])
-    cmd = "python -m paper_2407_08901_amd.mpnn_train --shape %s --epochs %d --lr %g --nseeds %d" % (
-        args.shape, args.epochs, args.lr, args.nseeds)
-    save(w, args.out, {"command": cmd, "train_seeds": list(seeds), "shape": args.shape, "samples": nsamp,
+    cmd = "python -m paper_2407_08901_amd.mpnn_train --target %s --shape %s --epochs %d --lr %g --nseeds %d" % (
+        args.target, args.shape, args.epochs, args.lr, args.nseeds)
+    out = args.out or (PAIR_WEIGHTS if args.target == "pair" else DEFAULT_WEIGHTS)
+    save(w, out, {"command": cmd, "target": args.target, "train_seeds": list(seeds), "shape": args.shape,
+                  "samples": nsamp,
                        "epochs": args.epochs, "lr": args.lr, "loss_history": hist,
                        "data_s": round(t1 - t0, 2), "train_s": round(t2 - t1, 2)})
     print(json.dumps({"samples": nsamp, "final_loss": hist[-1], "first_loss": hist[0], "data_s": t1 - t0,

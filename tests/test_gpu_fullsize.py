@@ -101,7 +101,7 @@ def _solve_forms(A, w, forms, dtype=torch.float64):
     for name, kw in forms.items():
         ctx = P.sppc_setup(rp, col, val, A.level_offsets, w.n_small_levels, w.k, P.sppc_default_opts(**kw))
         if kw.get("precond") == P.SPPC_CORR_MPNN:
-            P.sppc_mpnn_set_weights(ctx, mpnn_train.load_for_levels(len(w.level_sizes)))
+            P.sppc_mpnn_set_weights(ctx, mpnn_train.load_for("davidson"))
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         ev, Z, rrn, st, status = P.sppc_solve(ctx)
@@ -177,7 +177,7 @@ def test_n7722000_sampled_product_and_solves():
         torch.cuda.synchronize()
         assert np.max(np.abs(Yd.cpu().numpy()[rows] - ref32) / scale) < 2.0 ** -24 * 1.01, name
         if kw.get("precond") == P.SPPC_CORR_MPNN:
-            P.sppc_mpnn_set_weights(ctx, mpnn_train.load_for_levels(len(w.level_sizes)))
+            P.sppc_mpnn_set_weights(ctx, mpnn_train.load_for("davidson"))
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         ev, Z, rrn, st, status = P.sppc_solve(ctx)
@@ -219,7 +219,7 @@ def test_eigenvalues_against_the_stored_oracle_solution():
                             ("mixed+learned", dict(precision=P.SPPC_PREC_MIXED, precond=P.SPPC_CORR_MPNN), 1e-8)):
         ctx = _ctx(A, **kw)
         if name.endswith("learned"):
-            P.sppc_mpnn_set_weights(ctx, mpnn_train.load_for_levels(len(W.level_sizes)))
+            P.sppc_mpnn_set_weights(ctx, mpnn_train.load_for("davidson"))
         ev, Z, rrn, st, status = P.sppc_solve(ctx, want_vectors=False)
         P.sppc_destroy(ctx)
         assert status == P.SPPC_OK

@@ -17,11 +17,11 @@ def P():
     return P
 
 
-def _problem(seed, S, sizes=(37, 250, 1800), d=30):
+def _problem(seed, S, sizes=(37, 250, 1800), d=30, nsmall=1):
     A = levelgen.generate(sizes, d, seed)
     H = oracle.symmetric_from_upper(A.row_ptr, A.col, A.val, A.n)
     Aoff, dg = ompnn.offdiag(H)
-    lev = (np.searchsorted(A.level_offsets, np.arange(A.n), side="right") - 1) / (A.n_levels - 1)
+    lev = ompnn.level_feature(A.level_offsets, nsmall)
     rng = np.random.default_rng(seed)
     X = rng.standard_normal((A.n, S))
     X /= np.linalg.norm(X, axis=0)
@@ -33,9 +33,9 @@ def _problem(seed, S, sizes=(37, 250, 1800), d=30):
     return A, H, Aoff, dg, lev, X, th, R, E, w
 
 
-def _ctx(P, A):
+def _ctx(P, A, nsmall=1):
     rp, col, val = P.upload(A)
-    return P.sppc_setup(rp, col, val, A.level_offsets, 1, 4, P.sppc_default_opts())
+    return P.sppc_setup(rp, col, val, A.level_offsets, nsmall, 4, P.sppc_default_opts())
 
 
 def _cu(a):
@@ -143,3 +143,18 @@ def test_training_step_lowers_the_loss(P):
     losses = [P.sppc_mpnn_train_step(ctx, state, Rg, Xg, th, Eg, 1e-2, it + 1, Q=Qg) for it in range(40)]
     assert losses[-1] < losses[0] - 1e-3
     assert np.all(np.isfinite(losses))
+
+
+def test_forward_matches_reference_with_two_small_levels(P):
+    # five levels, the first two the small space: the level input is 0, 0, 1/2, 1, 1 (the kernel
+    # computes it from the level offsets and the small-level count of the setup)
+    S = 3
+    A, H, Aoff, dg, lev, X, th, R, E, w = _problem(13, S, sizes=(30, 60, 200, 600, 1500), d=24, nsmall=2)
+    print("case mpnn fwd five levels n=%d S=%d" % (A.n, S), flush=True)
+    ctx = _ctx(P, A, nsmall=2)
+    T, loss, grad = P.sppc_mpnn_eval(ctx, w, _cu(R), _cu(X), th, _cu(E), f64=True)
+    T = T.cpu().numpy()
+    for s in range(S):
+        tp, _ = ompnn.forward(w.astype(np.float64), Aoff, dg, lev, th[s], R[:, s], X[:, s])
+        assert np.max(np.abs(T[:, s] - tp)) < 1e-11 * np.max(np.abs(tp))
+    P.sppc_destroy(ctx)

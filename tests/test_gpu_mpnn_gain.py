@@ -1,9 +1,13 @@
 """What the trained preconditioner gains over the diagonal step, on matrices it was not trained on.
 
-The committed weights were trained on seeds 1000..1019 of the n = 4900 three-level shape; the
+The committed weights were trained on seeds 1000..1023 of the n = 4900 three-level shape; the
 held-out matrices are seeds 3000..3007 of that shape and one four-level n = 234,400 matrix.
-Both preconditioners must reach the same eigenpairs; the learned one must need at least 10%
-fewer continuation steps in total.  The measured table is printed (pytest -s).
+Both preconditioners must reach the same eigenpairs.  In the Davidson continuation the learned
+step must need at least 15% fewer continuation steps in total (fewer basis vectors, so less
+Gram-Schmidt and Rayleigh-Ritz work) without a longer solve (wall time at most 1.1x the diagonal
+step's, best of two runs).  Products with H are reported, counting the network's own two per pair
+and application: at these sizes the learned form uses more of them than it saves.  The table is
+printed (pytest -s).
 """
 import json
 import time
@@ -27,25 +31,28 @@ def P():
     return P
 
 
-def _solve(P, A, ns, k, kind, w=None):
+def _solve(P, A, ns, k, kind, w=None, reps=2):
     rp, col, val = P.upload(A)
-    ctx = P.sppc_setup(rp, col, val, A.level_offsets, ns, k, P.sppc_default_opts(precond=kind))
-    if w is not None:
-        P.sppc_mpnn_set_weights(ctx, w)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ev, Z, rrn, st, status = P.sppc_solve(ctx)
-    torch.cuda.synchronize()
-    ms = (time.perf_counter() - t0) * 1e3
-    P.sppc_destroy(ctx)
-    return np.array(ev), np.array(rrn), st, status, ms
+    best = None
+    for _ in range(reps):
+        ctx = P.sppc_setup(rp, col, val, A.level_offsets, ns, k, P.sppc_default_opts(precond=kind))
+        if w is not None:
+            P.sppc_mpnn_set_weights(ctx, w)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ev, Z, rrn, st, status = P.sppc_solve(ctx)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
+        P.sppc_destroy(ctx)
+        best = ms if best is None else min(best, ms)
+    return np.array(ev), np.array(rrn), st, status, best
 
 
-def test_trained_network_needs_fewer_continuation_steps(P):
+def test_trained_network_on_held_out_matrices(P):
     from paper_2407_08901_amd import mpnn_train
-    w = mpnn_train.load()
+    w = mpnn_train.load_for("davidson")
     rows = []
-    tot_j = tot_m = 0
+    tot = {"cont_j": 0, "cont_m": 0, "prod_j": 0, "prod_m": 0, "ms_j": 0.0, "ms_m": 0.0}
     for name, sizes, d, sd, ns, k in HELD_OUT:
         print("case gain %s" % name, flush=True)
         A = levelgen.generate(sizes, d, sd)
@@ -54,12 +61,16 @@ def test_trained_network_needs_fewer_continuation_steps(P):
         assert s_j == P.SPPC_OK and s_m == P.SPPC_OK
         assert np.max(rrn_m) < 1e-6
         assert np.max(np.abs(ev_m - ev_j) / np.abs(ev_j)) < 1e-10
-        tot_j += st_j["cont_steps"]
-        tot_m += st_m["cont_steps"]
+        for key, a, b in (("cont", st_j["cont_steps"], st_m["cont_steps"]), ("prod", st_j["n_spmv"], st_m["n_spmv"]),
+                          ("ms", ms_j, ms_m)):
+            tot[key + "_j"] += a
+            tot[key + "_m"] += b
         rows.append(dict(matrix=name, cont_jacobi=st_j["cont_steps"], cont_mpnn=st_m["cont_steps"],
-                         learned_steps=st_m["mpnn_steps"], products_jacobi=st_j["n_spmv"],
-                         products_mpnn=st_m["n_spmv"], ms_jacobi=round(ms_j, 1), ms_mpnn=round(ms_m, 1)))
+                         learned_steps=st_m["mpnn_steps"], fallbacks=st_m["mpnn_fallbacks"],
+                         products_jacobi=st_j["n_spmv"], products_mpnn=st_m["n_spmv"],
+                         ms_jacobi=round(ms_j, 1), ms_mpnn=round(ms_m, 1)))
     for r in rows:
         print(json.dumps(r))
-    print("continuation steps: diagonal %d, learned %d" % (tot_j, tot_m))
-    assert tot_m <= 0.9 * tot_j
+    print(json.dumps(tot))
+    assert tot["cont_m"] <= 0.85 * tot["cont_j"]
+    assert tot["ms_m"] <= 1.1 * tot["ms_j"]

@@ -10,7 +10,7 @@ def _setup(seed=3):
     A = levelgen.generate((20, 90, 300), 14, seed)
     H = oracle.symmetric_from_upper(A.row_ptr, A.col, A.val, A.n)
     Aoff, d = mpnn.offdiag(H)
-    lev = (np.searchsorted(A.level_offsets, np.arange(A.n), side="right") - 1) / (A.n_levels - 1)
+    lev = mpnn.level_feature(A.level_offsets, 1)
     rng = np.random.default_rng(seed)
     x = rng.standard_normal(A.n)
     x /= np.linalg.norm(x)
@@ -73,3 +73,10 @@ def test_messages_use_only_offdiagonal_coupling():
     H, Aoff, d, lev, theta, r, x, e, w = _setup()
     assert np.allclose(Aoff.diagonal(), 0.0)
     assert abs(abs(Aoff).sum() - (abs(H).sum() - np.abs(d).sum())) < 1e-9
+
+
+def test_level_feature_hand_cases():
+    # three levels, one small: 0 | 1/2 | 1 (the same as level / (L - 1) there)
+    assert np.array_equal(mpnn.level_feature([0, 2, 3, 5], 1), [0, 0, 0.5, 1, 1])
+    # five levels, two small: 0 0 | 1/2 | 1 1
+    assert np.array_equal(mpnn.level_feature([0, 1, 2, 3, 4, 6], 2), [0, 0, 0.5, 1, 1, 1])
