@@ -153,17 +153,19 @@ def _oracle_run(A, n0, k, **kw):
     return oracle.sppc(_H(A), n0, k, oracle.Options(**kw))
 
 
-@pytest.mark.parametrize("case", ["cfg0", "ragged"])
-def test_sppc_steps_match_oracle(case):
+@pytest.mark.parametrize("case,panel", [("cfg0", -1), ("cfg0", 1024), ("ragged", -1), ("ragged", 512)])
+def test_sppc_steps_match_oracle(case, panel):
+    # panel > 0 forces the column-panel copy of H and its block-product kernel (the one the
+    # benchmark times at full size) into the per-step comparison
     if case == "cfg0":
         w = levelgen.WORKLOADS[0]
         A, ns, k = w.generate(), w.n_small_levels, w.k
     else:
         A, ns, k = levelgen.generate((37, 411, 2999), 44, 9), 1, 3
     n0 = int(A.level_offsets[ns])
-    print("case steps %s n=%d n0=%d k=%d" % (case, A.n, n0, k), flush=True)
+    print("case steps %s n=%d n0=%d k=%d panel=%d" % (case, A.n, n0, k, panel), flush=True)
     ref = _oracle_run(A, n0, k, continuation=False, maxiter=15, tol=1e-300, final_check=False)
-    ctx = _ctx(A, ns, k, p_switch=0, maxiter=15, tol=1e-300, final_check=0)
+    ctx = _ctx(A, ns, k, p_switch=0, maxiter=15, tol=1e-300, final_check=0, panel_width=panel)
     th0 = np.array(P.sppc_get(ctx, 1, k))
     assert np.max(np.abs(th0 - ref.history[0]["theta"]) / np.abs(ref.history[0]["theta"])) < 1e-12
     for p in range(1, 16):
