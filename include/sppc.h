@@ -45,6 +45,14 @@ typedef enum {
 
 typedef enum { SPPC_F64 = 0, SPPC_F32 = 1 } sppc_dtype;
 
+/* Shift of the small-space corrections in eq. sm_first and eq. sm_lin_proj. */
+typedef enum {
+  SPPC_SHIFT_E0 = 0,    /* E_k^(0), the zeroth-order energy (the paper's recursion, eq. exp_seq2) */
+  SPPC_SHIFT_RITZ = 1   /* theta_k, the Ritz value of the step before: (H0hat - theta_k) x1 = b1 and
+                           x2 = -b2 / theta_k, with the same right-hand side and E^(p) (a variant the
+                           paper does not take; it stagnates earlier on the synthetic workloads) */
+} sppc_shift;
+
 typedef enum {
   SPPC_PREC_FP64 = 0,   /* every product in float64 */
   SPPC_PREC_MIXED = 1   /* block products with H: float32 X, float32 products accumulated in
@@ -106,6 +114,7 @@ typedef struct {
                           the basis is below 1e-4 (Fig. 3), or the largest rrn has not halved over
                           the last three steps (detection left open by the paper, Sec. VII); takes
                           effect only with p_switch > 0; 0 (default): switch at p_switch only */
+  int corr_shift;      /* sppc_shift of the perturbative corrections in sppc_solve; SPPC_SHIFT_E0 */
   int rmm_precond;     /* step of the RMM-DIIS continuation: SPPC_CORR_JACOBI (the diagonal step,
                           default) or SPPC_CORR_MPNN (the learned correction of the diagonal step,
                           weights from sppc_mpnn_set_weights; a pair falls back to the diagonal step
@@ -196,9 +205,16 @@ sppc_status sppc_spmm_noalloc(sppc_ctx* ctx, const void* X_dev, sppc_dtype xt, d
  *   SPPC_CORR_JACOBI / SPPC_CORR_MPNN / SPPC_CORR_SMALL: preconditioned residuals of
  *     the current unconverged Ritz pairs (Sec. V continuation; the pending block is
  *     n x (number of unconverged pairs)).
- * Errors: SPPC_E_ARG (e.g. PERTURBATIVE after the basis was restarted), SPPC_E_HIP.
+ *   shifts_host  [k] host array or NULL.  PERTURBATIVE only: sigma_k replaces E_k^(0) in eq. sm_first
+ *     (x2 = -b2 / sigma_k) and eq. sm_lin_proj ((H0hat - sigma_k) x1 = b1 - (b1^T psi_k) psi_k,
+ *     minimum-norm, x1 orthogonal to psi_k); the right-hand side of eq. exp_seq2 and E^(p) are
+ *     unchanged.  NULL is the paper's E^(0).  Each sigma_k must be finite, nonzero and at most the
+ *     largest deflated eigenvalue E_D^(0) of H0hat (sppc_get what = 0), so that the deflated CG
+ *     operator is positive definite; the Ritz values theta_k always are.
+ * Errors: SPPC_E_ARG (e.g. PERTURBATIVE after the basis was restarted, shifts out of range or given
+ * to a continuation kind), SPPC_E_SINGULAR_E0 (a zero shift), SPPC_E_HIP.
  */
-sppc_status sppc_correct(sppc_ctx* ctx, int kind);
+sppc_status sppc_correct(sppc_ctx* ctx, int kind, const double* shifts_host);
 
 /*
  * Appends the pending block to the basis and extracts new Ritz pairs:

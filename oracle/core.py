@@ -39,7 +39,11 @@ design notes of the repository):
   * the hybrid of Sec. V-VI refines each unconverged pair by RMM-DIIS in sweeps
     of 4 iterations with Rayleigh-Ritz on the refined vectors between sweeps;
   * optionally the switch comes early, once SPPC stagnates (sppc_stagnated;
-    the paper leaves the detection open, Sec. VII).
+    the paper leaves the detection open, Sec. VII);
+  * optionally (Options.shift = "ritz") the small-space corrections use the Ritz
+    value theta_k of the step before in place of E_k^(0) in eq. sm_first and
+    eq. sm_lin_proj (the "(H11 - theta I) z = r" form), with the right-hand side
+    of eq. exp_seq2 and E^(p) unchanged.
 """
 from __future__ import annotations
 
@@ -143,13 +147,15 @@ def check_e0(z: ZerothOrder, k: int) -> None:
 # --------------------------------------------------------------------------- correction step
 
 
-def small_solve(z: ZerothOrder, kk: int, b1: np.ndarray) -> np.ndarray:
+def small_solve(z: ZerothOrder, kk: int, b1: np.ndarray, shift: Optional[float] = None) -> np.ndarray:
     """Minimum-norm x1 of (H0hat - E_k^(0)) x1 = b1 - (b1^T psi_k) psi_k (eq. sm_lin_proj).
 
     Exact spectral form: x1 = sum_{j != k} u_j (u_j^T b1) / (w_j - E_k^(0)); eigenvalues
-    equal to E_k^(0) to 1e-12 relative are treated as null directions too.
+    equal to E_k^(0) to 1e-12 relative are treated as null directions too.  With `shift` the
+    shift sigma replaces E_k^(0) in the denominators (the theta-shifted variant); psi_k is still
+    projected out.
     """
-    Ek = z.w[kk]
+    Ek = z.w[kk] if shift is None else float(shift)
     tol = 1e-12 * max(1.0, abs(Ek))
     mask = np.abs(z.w - Ek) > tol
     mask[kk] = False
@@ -168,10 +174,12 @@ def correction_rhs(VPsi_prev: np.ndarray, E_hist: List[np.ndarray], Psi_hist: Li
 
 def correction_vectors(H: sp.csr_matrix, H0hat: np.ndarray, z: ZerothOrder, k: int,
                        E_hist: List[np.ndarray], Psi_hist: List[np.ndarray],
-                       VPsi0: np.ndarray) -> tuple:
+                       VPsi0: np.ndarray, shifts: Optional[np.ndarray] = None) -> tuple:
     """E^(p) and Psi^(p) for every wanted pair from the stored lower orders.
 
     Returns (E_p [k], Psi_p [n x k]).  Uses one direct product with H (oracle only).
+    shifts (optional, [k]): sigma_k in place of E_k^(0) in eq. sm_first and eq. sm_lin_proj (the
+    right-hand side of eq. exp_seq2 and E^(p) are unchanged); None is the paper's E^(0).
     """
     p = len(Psi_hist)
     n0 = H0hat.shape[0]
@@ -180,11 +188,11 @@ def correction_vectors(H: sp.csr_matrix, H0hat: np.ndarray, z: ZerothOrder, k: i
     E_p = np.einsum("ij,ij->j", Pprev, VPsi0)              # eq. exp_seq: E^(p) = Psi^(p-1)^T V Psi^(0)
     E_all = E_hist + [E_p]
     b = correction_rhs(VPprev, E_all, Psi_hist, p)
-    E0 = z.w[:k]
+    E0 = z.w[:k] if shifts is None else np.asarray(shifts, dtype=np.float64)
     Psi_p = np.empty_like(b)
     Psi_p[n0:] = -b[n0:] / E0[None, :]                     # eq. sm_first
-    for kk in range(k):
-        Psi_p[:n0, kk] = small_solve(z, kk, b[:n0, kk])    # eq. sm_lin_proj
+    for kk in range(k):                                    # eq. sm_lin_proj
+        Psi_p[:n0, kk] = small_solve(z, kk, b[:n0, kk], None if shifts is None else E0[kk])
     return E_p, Psi_p
 
 
@@ -380,6 +388,8 @@ class Options:
     diis_depth: int = 16       # iterates kept by DIIS
     diis_sweep: int = 4        # RMM-DIIS iterations per pair between two Rayleigh-Ritz rotations
     auto_switch: bool = False  # switch before p_switch once SPPC stagnates (see sppc_stagnated)
+    shift: str = "E0"          # "E0": the paper's E^(0) in the small-space corrections; "ritz": the
+                               # Ritz values of the step before (the theta-shifted variant)
 
 
 @dataclass
@@ -453,7 +463,8 @@ def sppc(H: sp.csr_matrix, n0: int, k: int, opts: Options = Options(),
         else min(opts.maxiter, opts.p_switch)
     while not converged and p < last_p:
         p += 1
-        E_p, Psi_p = correction_vectors(H, H0hat, z, k, E_hist[:p], Psi_hist, VPsi0)
+        shifts = theta.copy() if opts.shift == "ritz" else None
+        E_p, Psi_p = correction_vectors(H, H0hat, z, k, E_hist[:p], Psi_hist, VPsi0, shifts)
         if p >= 2:
             E_hist.append(E_p)
         Psi_hist.append(Psi_p)

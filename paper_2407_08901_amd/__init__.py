@@ -21,6 +21,7 @@ SPPC_OK, SPPC_E_ARG, SPPC_E_HIP, SPPC_E_NOMEM, SPPC_E_SINGULAR_E0, SPPC_E_BREAKD
 SPPC_F64, SPPC_F32 = 0, 1
 SPPC_PREC_FP64, SPPC_PREC_MIXED = 0, 1
 SPPC_CORR_PERTURBATIVE, SPPC_CORR_JACOBI, SPPC_CORR_MPNN, SPPC_CORR_SMALL, SPPC_CORR_RMMDIIS = 0, 1, 2, 3, 4
+SPPC_SHIFT_E0, SPPC_SHIFT_RITZ = 0, 1
 
 STATUS_NAMES = {0: "SPPC_OK", 1: "SPPC_E_ARG", 2: "SPPC_E_HIP", 3: "SPPC_E_NOMEM",
                 4: "SPPC_E_SINGULAR_E0", 5: "SPPC_E_BREAKDOWN", 6: "SPPC_E_NOCONV", 7: "SPPC_E_NAN"}
@@ -42,7 +43,8 @@ class sppc_opts(ctypes.Structure):
                 ("tau_drop", ctypes.c_double), ("inner_tol", ctypes.c_double), ("h0_tol", ctypes.c_double),
                 ("precision", ctypes.c_int), ("precond", ctypes.c_int), ("final_check", ctypes.c_int),
                 ("verbose", ctypes.c_int), ("panel_width", ctypes.c_int), ("refine_precond", ctypes.c_int),
-                ("precond_tol", ctypes.c_double), ("auto_switch", ctypes.c_int), ("rmm_precond", ctypes.c_int)]
+                ("precond_tol", ctypes.c_double), ("auto_switch", ctypes.c_int), ("corr_shift", ctypes.c_int),
+                ("rmm_precond", ctypes.c_int)]
 
 
 class sppc_stats(ctypes.Structure):
@@ -81,7 +83,7 @@ def lib():
                                  c_int, ctypes.POINTER(sppc_opts), vp]
         L.sppc_spmm.argtypes = [vp, vp, c_int, vp, c_int]
         L.sppc_spmm_noalloc.argtypes = [vp, vp, c_int, vp, c_int]
-        L.sppc_correct.argtypes = [vp, c_int]
+        L.sppc_correct.argtypes = [vp, c_int, dp]
         L.sppc_rayleigh_ritz.argtypes = [vp, dp, dp, ctypes.POINTER(c_int)]
         L.sppc_solve.argtypes = [vp, dp, vp, dp, ctypes.POINTER(sppc_stats)]
         L.sppc_get.argtypes = [vp, c_int, vp, i64]
@@ -188,8 +190,14 @@ def sppc_spmm_noalloc(ctx: Context, X: torch.Tensor, Y: torch.Tensor) -> None:
                                    X.shape[1]), ctx.handle)
 
 
-def sppc_correct(ctx: Context, kind: int = SPPC_CORR_PERTURBATIVE) -> None:
-    _check(lib().sppc_correct(ctx.handle, kind), ctx.handle)
+def sppc_correct(ctx: Context, kind: int = SPPC_CORR_PERTURBATIVE, shifts=None) -> None:
+    """shifts: k per-pair shifts in place of E^(0) (perturbative corrections only), or None."""
+    sh = None
+    if shifts is not None:
+        if len(shifts) != ctx.k:
+            raise ValueError("one shift per wanted pair")
+        sh = (ctypes.c_double * ctx.k)(*[float(x) for x in shifts])
+    _check(lib().sppc_correct(ctx.handle, kind, sh), ctx.handle)
 
 
 def sppc_rayleigh_ritz(ctx: Context):

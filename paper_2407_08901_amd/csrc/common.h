@@ -191,7 +191,8 @@ void build_correction_coefs(int p, int k, int m, const double* Ghist, int64_t gs
 // theta-shifted small-space solve
 void deflate_shift(int D, int na, const double* w, const double* theta, const double* c, int64_t ldc, double* out,
                    int64_t ldo, hipStream_t s);
-void deflate_coefs(int D, int k, const double* w, const double* c, int64_t ldc, double* out,
+// shift (device, [k], optional): sigma_kk in place of E_kk^(0) = w[kk] in the denominators
+void deflate_coefs(int D, int k, const double* w, const double* shift, const double* c, int64_t ldc, double* out,
                    int64_t ldo, hipStream_t s);
 // element-wise small: C = C1 + C2 (m x b)
 void add_small(int count, const double* a, double* b, hipStream_t s);

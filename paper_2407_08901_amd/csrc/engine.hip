@@ -419,27 +419,48 @@ void zeroth_order(sppc_ctx* c) {
 // minimum-norm solution of eq. sm_lin_proj orthogonal to psi_k.  b1 in c->cr (n0 x k);
 // result into Psi rows [0, n0).  Float64 products in both precisions: float32 products in these
 // solves cost the mixed form continuation steps (measured), the product with H0hat is small.
-void small_solve(sppc_ctx* c) {
+// shift (device, [k], optional): sigma_k in place of E_k^(0) (the theta-shifted variant); the CG
+// operator H0hat - sigma_k stays positive definite on the complement of the deflated vectors when
+// sigma_k <= E_D^(0) < E_{D+1}^(0).
+void small_solve(sppc_ctx* c, const double* shift = nullptr) {
   hipStream_t s = c->s;
   const int64_t n0 = c->n0;
   const int k = c->k, D = c->D;
   const bool mixed = c->o.precision == SPPC_PREC_MIXED;
   double tol = c->o.inner_tol;
   if (tol <= 0.0) tol = mixed ? 1e-6 : 1e-12;
-  c->st.cg_iterations += cg_solve(c->H0, n0, k, D, c->E0, c->Psihat, c->cg_rowb, c->cx, c->cr, c->cgpart,
+  const double* sig = shift ? shift : c->E0;
+  c->st.cg_iterations += cg_solve(c->H0, n0, k, D, sig, c->Psihat, c->cg_rowb, c->cx, c->cr, c->cgpart,
                                   c->ccoef, 5000, tol, c->pin_i + 4, s);
-  deflate_coefs(D, k, c->E0, c->ccoef, k, c->ctmp, k, s);
+  deflate_coefs(D, k, c->E0, shift, c->ccoef, k, c->ctmp, k, s);
   gemm_nn(n0, D, k, c->Psihat, D, c->ctmp, k, c->cx, k, 1.0, 1.0, s);
   copy_block(n0, k, c->cx, k, c->Psi, k, s);
 }
 
-void correct_perturbative(sppc_ctx* c) {
+// shifts_host (optional, [k]): sigma_k in place of E_k^(0) in eq. sm_first and eq. sm_lin_proj (the
+// right-hand side of eq. exp_seq2 and E^(p) are unchanged); each must lie below E_D^(0) so that the
+// small-space operator is positive definite on the complement of the deflated eigenvectors.
+void correct_perturbative(sppc_ctx* c, const double* shifts_host = nullptr) {
   if (c->restarted) throw Error(SPPC_E_ARG, "perturbative corrections need the unrestarted basis");
   if (c->p + 1 >= c->maxhist) throw Error(SPPC_E_ARG, "perturbation order limit reached");
   hipStream_t s = c->s;
   const int k = c->k;
   const int64_t n = c->n, n0 = c->n0;
   Basis& b = c->B;
+  const double* sig = c->E0;
+  if (shifts_host) {
+    const double top = c->E0h[c->D - 1];
+    for (int i = 0; i < k; ++i) {
+      const double v = shifts_host[i];
+      if (!std::isfinite(v) || v > top)
+        throw Error(SPPC_E_ARG, "shifts must be finite and at most the largest deflated eigenvalue of H0hat");
+      if (std::fabs(v) < 1e-10 * std::max(1.0, std::fabs(top)))
+        throw Error(SPPC_E_SINGULAR_E0, "a zero shift: eq. sm_first divides by it");
+      c->pin[3 * NWMAX + i] = v;
+    }
+    SPPC_HIP(hipMemcpyAsync(c->cshift, c->pin + 3 * NWMAX, sizeof(double) * k, hipMemcpyHostToDevice, s));
+    sig = c->cshift;
+  }
   c->p += 1;
   const int p = c->p;
   size_t t0 = c->tm.begin(C_SMALL);
@@ -453,12 +474,13 @@ void correct_perturbative(sppc_ctx* c) {
   }
   c->w_next = -1;
   // complement rows: x2 = -b2 / E^(0) with b2 = -W2 (H0 is zero there), eq. sm_first
-  complement_rows(n0, n, k, c->Wb, k, c->E0, c->Psi, k, s);
+  complement_rows(n0, n, k, c->Wb, k, sig, c->Psi, k, s);
   // small space: b1 = -W1 + H0hat Psi^(p-1)_1 (eq. exp_seq2 with eq. avoid_SpMV2)
   gemm_nn(n0, b.m, k, b.Q, b.ldq, c->Acoef, k, c->cx, k, 1.0, 0.0, s);
   spmm_f64(c->H0, c->cx, k, c->cr, k, k, nullptr, s);
   axpby_block(n0, k, -1.0, c->Wb, k, 1.0, c->cr, k, s);
-  small_solve(c);
+  small_solve(c, shifts_host ? c->cshift : nullptr);
+  if (shifts_host) sync(c);  // the pinned shifts are reused by later steps
   c->tm.end(t0);
   c->pend_b = k;
   c->pend_kind = SPPC_CORR_PERTURBATIVE;
@@ -745,6 +767,8 @@ void setup_impl(sppc_ctx* c, const sppc_csr* Hin, const int64_t* loff, int L, in
   if (o.precond != SPPC_CORR_JACOBI && o.precond != SPPC_CORR_MPNN && o.precond != SPPC_CORR_SMALL &&
       o.precond != SPPC_CORR_RMMDIIS)
     throw Error(SPPC_E_ARG, "continuation must be JACOBI, MPNN, SMALL or RMMDIIS");
+  if (o.corr_shift != SPPC_SHIFT_E0 && o.corr_shift != SPPC_SHIFT_RITZ)
+    throw Error(SPPC_E_ARG, "corr_shift must be SPPC_SHIFT_E0 or SPPC_SHIFT_RITZ");
   if (o.rmm_precond != SPPC_CORR_JACOBI && o.rmm_precond != SPPC_CORR_MPNN)
     throw Error(SPPC_E_ARG, "the RMM-DIIS step preconditioner must be JACOBI or MPNN");
   if (o.refine_precond != SPPC_CORR_JACOBI && o.refine_precond != SPPC_CORR_MPNN &&
@@ -1135,7 +1159,9 @@ sppc_status solve_impl(sppc_ctx* c, double* evals, double* evecs, double* rrn, s
   std::vector<double> top;  // largest rrn after each SPPC step of this call (automatic switch)
   top.push_back(max_rrn(c));
   while (!conv && c->p < last_p && !c->restarted) {
-    correct_perturbative(c);
+    std::vector<double> sh;
+    if (o.corr_shift == SPPC_SHIFT_RITZ) sh.assign(c->theta_h.begin(), c->theta_h.begin() + c->k);
+    correct_perturbative(c, sh.empty() ? nullptr : sh.data());
     const int added = append_and_rr(c);
     log_step(c, "sppc");
     conv = all_converged(c);
@@ -1282,6 +1308,7 @@ sppc_status sppc_default_opts(sppc_opts* o) {
   o->final_check = 1;
   o->verbose = 0;
   o->panel_width = -1;
+  o->corr_shift = SPPC_SHIFT_E0;
   o->rmm_precond = SPPC_CORR_JACOBI;
   return SPPC_OK;
 }
@@ -1337,10 +1364,11 @@ sppc_status sppc_spmm_noalloc(sppc_ctx* c, const void* X, sppc_dtype xt, double*
   });
 }
 
-sppc_status sppc_correct(sppc_ctx* c, int kind) {
+sppc_status sppc_correct(sppc_ctx* c, int kind, const double* shifts_host) {
   if (!c) return SPPC_E_ARG;
   return guarded(c, [&]() {
-    if (kind == SPPC_CORR_PERTURBATIVE) correct_perturbative(c);
+    if (kind == SPPC_CORR_PERTURBATIVE) correct_perturbative(c, shifts_host);
+    else if (shifts_host) throw Error(SPPC_E_ARG, "shifts apply to the perturbative correction only");
     else if (kind == SPPC_CORR_JACOBI || kind == SPPC_CORR_MPNN || kind == SPPC_CORR_SMALL)
       correct_continuation(c, kind);
     else throw Error(SPPC_E_ARG, "unknown correction kind");

@@ -770,12 +770,14 @@ __global__ void k_corr_coefs(int p, int k, int m, const double* __restrict__ Gh,
   }
 }
 
-__global__ void k_deflate_coefs(int D, int k, const double* __restrict__ w, const double* __restrict__ c,
-                                int64_t ldc, double* __restrict__ out, int64_t ldo) {
+// out[j][kk] = c[j][kk] / (w[j] - sigma_kk) for the deflated j != kk (psi_kk is projected out),
+// sigma_kk = shift[kk] when given, else E_kk^(0) = w[kk]
+__global__ void k_deflate_coefs(int D, int k, const double* __restrict__ w, const double* __restrict__ shift,
+                                const double* __restrict__ c, int64_t ldc, double* __restrict__ out, int64_t ldo) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= D * k) return;
   const int j = e / k, kk = e % k;
-  const double Ek = w[kk];
+  const double Ek = shift ? shift[kk] : w[kk];
   const double dj = w[j] - Ek;
   double v = 0.0;
   if (j != kk && fabs(dj) > 1e-12 * fmax(1.0, fabs(Ek))) v = c[(int64_t)j * ldc + kk] / dj;
@@ -960,9 +962,9 @@ void build_correction_coefs(int p, int k, int m, const double* Ghist, int64_t gs
   SPPC_LAUNCH_CHECK();
 }
 
-void deflate_coefs(int D, int k, const double* w, const double* c, int64_t ldc, double* out, int64_t ldo,
-                   hipStream_t s) {
-  k_deflate_coefs<<<g1((int64_t)D * k), 256, 0, s>>>(D, k, w, c, ldc, out, ldo);
+void deflate_coefs(int D, int k, const double* w, const double* shift, const double* c, int64_t ldc, double* out,
+                   int64_t ldo, hipStream_t s) {
+  k_deflate_coefs<<<g1((int64_t)D * k), 256, 0, s>>>(D, k, w, shift, c, ldc, out, ldo);
   SPPC_LAUNCH_CHECK();
 }
 

@@ -246,3 +246,26 @@ def test_cached_memory_is_reused_and_released(P):
     P.sppc_destroy(ctx)
     assert status == P.SPPC_OK
     assert np.max(np.abs(np.array(ev) - ref[0]) / np.abs(ref[0])) < 1e-10
+
+
+def test_bad_shifts_are_refused(P):
+    w = levelgen.WORKLOADS[0]
+    A = w.generate()
+    print("case edge shifts", flush=True)
+    rp, col, val = P.upload(A)
+    ctx = P.sppc_setup(rp, col, val, A.level_offsets, w.n_small_levels, w.k, P.sppc_default_opts())
+    D = min(2 * w.k, 28)
+    top = P.sppc_get(ctx, 0, D)[-1]
+    for bad, code in (([top + 1.0] * w.k, P.SPPC_E_ARG), ([float("nan")] * w.k, P.SPPC_E_ARG),
+                      ([0.0] * w.k, P.SPPC_E_ARG)):  # E^(0) < 0 here: zero lies above E_D^(0)
+        with pytest.raises(P.SPPCError) as e:
+            P.sppc_correct(ctx, P.SPPC_CORR_PERTURBATIVE, shifts=bad)
+        assert e.value.status == code
+    with pytest.raises(P.SPPCError) as e:
+        P.sppc_correct(ctx, P.SPPC_CORR_JACOBI, shifts=[top] * w.k)
+    assert e.value.status == P.SPPC_E_ARG
+    # the context still works after the refusals
+    P.sppc_correct(ctx, P.SPPC_CORR_PERTURBATIVE)
+    th, rr, added = P.sppc_rayleigh_ritz(ctx)
+    assert added == w.k
+    P.sppc_destroy(ctx)

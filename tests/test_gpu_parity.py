@@ -259,3 +259,49 @@ def test_projected_eigensolver_beyond_the_lds_tile(extra):
     theta = np.array(P.sppc_get(ctx, 1, 8))
     lam = np.linalg.eigvalsh(0.5 * (T + T.T))[:8]
     assert np.max(np.abs(theta - lam) / np.abs(lam)) < 1e-13
+
+
+# ---------------------------------------------------------------- theta-shifted corrections
+@pytest.mark.parametrize("case", ["cfg0", "ragged"])
+def test_theta_shifted_steps_match_oracle(case):
+    # the variant with the Ritz values of the step before in place of E^(0) in eq. sm_first and
+    # eq. sm_lin_proj, step by step against the oracle's Options(shift="ritz")
+    if case == "cfg0":
+        w = levelgen.WORKLOADS[0]
+        A, ns, k = w.generate(), w.n_small_levels, w.k
+    else:
+        A, ns, k = levelgen.generate((37, 411, 2999), 44, 9), 1, 3
+    n0 = int(A.level_offsets[ns])
+    print("case theta-shifted steps %s n=%d k=%d" % (case, A.n, k), flush=True)
+    ref = _oracle_run(A, n0, k, continuation=False, maxiter=15, tol=1e-300, final_check=False, shift="ritz")
+    ctx = _ctx(A, ns, k, p_switch=0, maxiter=15, tol=1e-300, final_check=0)
+    th = P.sppc_get(ctx, 1, k)
+    for p in range(1, 16):
+        P.sppc_correct(ctx, P.SPPC_CORR_PERTURBATIVE, shifts=th)
+        th, rr, added = P.sppc_rayleigh_ritz(ctx)
+        h = ref.history[p]
+        rel = np.max(np.abs(np.array(th) - h["theta"]) / np.abs(h["theta"]))
+        assert rel < 1e-10, (p, rel)
+        assert added == h["m"] - ref.history[p - 1]["m"]
+    # the same through sppc_solve with corr_shift
+    ctx2 = _ctx(A, ns, k, p_switch=0, maxiter=15, tol=1e-300, final_check=0, corr_shift=P.SPPC_SHIFT_RITZ)
+    ev, Z, rrn, st, status = P.sppc_solve(ctx2, want_vectors=False)
+    assert st["iterations"] == 15
+    assert np.max(np.abs(np.array(ev) - ref.history[15]["theta"]) / np.abs(ref.history[15]["theta"])) < 1e-10
+
+
+def test_explicit_E0_shifts_equal_the_default():
+    w = levelgen.WORKLOADS[0]
+    A = w.generate()
+    print("case explicit E0 shifts", flush=True)
+    a = _ctx(A, w.n_small_levels, w.k, p_switch=0, maxiter=15, tol=1e-300, final_check=0)
+    b = _ctx(A, w.n_small_levels, w.k, p_switch=0, maxiter=15, tol=1e-300, final_check=0)
+    E0 = P.sppc_get(b, 0, min(2 * w.k, 28))[:w.k]
+    for p in range(1, 4):
+        P.sppc_correct(a, P.SPPC_CORR_PERTURBATIVE)
+        P.sppc_correct(b, P.SPPC_CORR_PERTURBATIVE, shifts=E0)
+        ga = P.sppc_get(a, 5, A.n * w.k, device=True).cpu().numpy()
+        gb = P.sppc_get(b, 5, A.n * w.k, device=True).cpu().numpy()
+        assert np.max(np.abs(ga - gb)) <= 1e-13 * np.max(np.abs(ga)), p
+        P.sppc_rayleigh_ritz(a)
+        P.sppc_rayleigh_ritz(b)

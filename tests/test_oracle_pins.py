@@ -467,3 +467,41 @@ def test_automatic_switch_stops_at_the_first_stagnated_step(cfg0, case):
         assert np.array_equal(a["theta"], b["theta"]) and a["m"] == b["m"]
     assert auto.converged and np.max(auto.rrn) < 1e-6
     assert np.max(np.abs(auto.theta - lam[:k]) / np.abs(lam[:k])) < 1e-9
+
+
+# ------------------------------------------------------------------ shifted small-space corrections
+def test_shifted_small_solve_equals_the_dense_projected_solve():
+    # the shifted form of eq. sm_lin_proj: x1 = P (H0hat - sigma)^-1 P b1 with P = I - psi_k psi_k^T
+    # (H0hat - sigma commutes with P), by a dense LU solve instead of the spectral sum; sigma = E_k^(0)
+    # is the paper's singular case, where the minimum-norm solution is the pseudo-inverse's
+    rng = np.random.default_rng(31)
+    A = levelgen.generate((40, 200), 16, 31)
+    H = oracle.symmetric_from_upper(A.row_ptr, A.col, A.val, A.n)
+    n0 = 40
+    H0 = H[:n0, :n0].toarray()
+    z = osp.zeroth_order(H0)
+    b1 = rng.standard_normal(n0)
+    for kk, sigma in ((0, z.w[0] - 0.3), (2, z.w[2] - 0.01), (1, z.w[0] + 0.2)):
+        P_ = np.eye(n0) - np.outer(z.U[:, kk], z.U[:, kk])
+        want = P_ @ np.linalg.solve(H0 - sigma * np.eye(n0), P_ @ b1)
+        got = osp.small_solve(z, kk, b1, sigma)
+        assert np.max(np.abs(got - want)) < 1e-10 * np.max(np.abs(want)), (kk, sigma)
+    kk = 1
+    P_ = np.eye(n0) - np.outer(z.U[:, kk], z.U[:, kk])
+    want = np.linalg.pinv(H0 - z.w[kk] * np.eye(n0), rcond=1e-12) @ (P_ @ b1)
+    assert np.allclose(osp.small_solve(z, kk, b1), want, rtol=0, atol=1e-10 * np.max(np.abs(want)))
+    assert np.array_equal(osp.small_solve(z, kk, b1), osp.small_solve(z, kk, b1, z.w[kk]))
+
+
+def test_theta_shifted_variant_with_E0_shifts_is_the_paper_recursion(cfg0):
+    # passing shifts equal to E^(0) reproduces the default recursion exactly
+    H, n0, k, lam, _ = cfg0
+    H0 = osp.small_space_matrix(H, n0)
+    z = osp.zeroth_order(H0)
+    Psi0 = np.zeros((H.shape[0], k))
+    Psi0[:n0] = z.U[:, :k]
+    VPsi0 = H @ Psi0 - osp.apply_H0(H0, Psi0)
+    E_hist = [z.w[:k].copy(), np.zeros(k)]
+    a = osp.correction_vectors(H, H0, z, k, E_hist[:1], [Psi0], VPsi0)
+    b = osp.correction_vectors(H, H0, z, k, E_hist[:1], [Psi0], VPsi0, shifts=z.w[:k].copy())
+    assert np.array_equal(a[1], b[1])
