@@ -115,6 +115,12 @@ typedef struct {
                           the last three steps (detection left open by the paper, Sec. VII); takes
                           effect only with p_switch > 0; 0 (default): switch at p_switch only */
   int corr_shift;      /* sppc_shift of the perturbative corrections in sppc_solve; SPPC_SHIFT_E0 */
+  int pair_index;      /* -1 (default): Alg. 2, the k lowest pairs together.  j = 0..26 with k = 1:
+                          Alg. 1 for the j-th eigenpair alone (j = 0 the lowest): the zeroth order is
+                          the j-th eigenpair of H0hat, the subspace the span of its own corrections,
+                          the approximation the lowest Ritz pair of that subspace (which may move to a
+                          lower eigenvalue, Sec. VI).  n_deflate (default max(2, j + 2), at most 28)
+                          must exceed j; sppc_get(what = 0) then lists E_j^(0) first */
   int rmm_precond;     /* step of the RMM-DIIS continuation: SPPC_CORR_JACOBI (the diagonal step,
                           default) or SPPC_CORR_MPNN (the learned correction of the diagonal step,
                           weights from sppc_mpnn_set_weights; a pair falls back to the diagonal step

@@ -26,6 +26,7 @@ from .core import (  # noqa: F401
     zeroth_order,
     rs_corrections,
     sppc,
+    sppc_pair,
     sppc_stagnated,
     final_check,
     jacobi_correction,

@@ -40,6 +40,9 @@ design notes of the repository):
     of 4 iterations with Rayleigh-Ritz on the refined vectors between sweeps;
   * optionally the switch comes early, once SPPC stagnates (sppc_stagnated;
     the paper leaves the detection open, Sec. VII);
+  * Alg. 1 (sppc_pair): the same iteration for one pair alone, its zeroth order
+    the kk-th eigenpair of H0hat and its approximation the lowest Ritz pair of
+    the span of its own corrections;
   * optionally (Options.shift = "ritz") the small-space corrections use the Ritz
     value theta_k of the step before in place of E_k^(0) in eq. sm_first and
     eq. sm_lin_proj (the "(H11 - theta I) z = r" form), with the right-hand side
@@ -429,6 +432,24 @@ def sppc_stagnated(hist: List[dict]) -> bool:
     if min(hist[-1]["angles"]) < 1e-4:
         return True
     return len(hist) >= 4 and not (max(hist[-1]["rrn"]) < 0.5 * max(hist[-4]["rrn"]))
+
+
+def sppc_pair(H: sp.csr_matrix, n0: int, kk: int, opts: Options = Options(),
+              callback: Optional[Callable] = None) -> Result:
+    """Alg. 1: SPPC for the kk-th eigenpair alone (kk = 0 is the lowest).
+
+    The zeroth order is the kk-th eigenpair of H0hat (reading of "the k-th nonzero eigenpair of
+    H0"); the subspace is spanned by that pair's own corrections Psi_kk^(0..p) (eq. Man_P) and the
+    approximation is the lowest Ritz pair of the subspace.  This is the SPPC iteration above with a
+    single wanted pair whose zeroth order is (E_kk^(0), psi_kk): the eigendecomposition of H0hat is
+    handed over reordered so that pair kk comes first (the spectral small solve sums over every
+    other eigenvector whatever their order)."""
+    H = sp.csr_matrix(H, dtype=np.float64)
+    z = zeroth_order(small_space_matrix(H, n0))
+    if not 0 <= kk < len(z.w):
+        raise ValueError("pair index out of range")
+    perm = np.concatenate([[kk], np.delete(np.arange(len(z.w)), kk)])
+    return sppc(H, n0, 1, opts, z=ZerothOrder(z.w[perm], z.U[:, perm]), callback=callback)
 
 
 def sppc(H: sp.csr_matrix, n0: int, k: int, opts: Options = Options(),

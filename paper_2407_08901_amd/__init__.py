@@ -43,7 +43,7 @@ class sppc_opts(ctypes.Structure):
                 ("tau_drop", ctypes.c_double), ("inner_tol", ctypes.c_double), ("h0_tol", ctypes.c_double),
                 ("precision", ctypes.c_int), ("precond", ctypes.c_int), ("final_check", ctypes.c_int),
                 ("verbose", ctypes.c_int), ("panel_width", ctypes.c_int), ("refine_precond", ctypes.c_int),
-                ("precond_tol", ctypes.c_double), ("auto_switch", ctypes.c_int), ("corr_shift", ctypes.c_int),
+                ("precond_tol", ctypes.c_double), ("auto_switch", ctypes.c_int), ("corr_shift", ctypes.c_int), ("pair_index", ctypes.c_int),
                 ("rmm_precond", ctypes.c_int)]
 
 

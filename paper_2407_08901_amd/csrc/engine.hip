@@ -759,8 +759,12 @@ void setup_impl(sppc_ctx* c, const sppc_csr* Hin, const int64_t* loff, int L, in
   c->k = k;
   sppc_opts& o = c->o;
   if (k < 1 || k > 16 || k > c->n0) throw Error(SPPC_E_ARG, "k must be 1..16 and <= n0");
-  if (o.n_deflate <= 0) o.n_deflate = std::min<int64_t>(std::min(2 * k, 28), c->n0);
+  const int pj = o.pair_index;
+  if (pj < -1 || pj > 26 || (pj >= 0 && (k != 1 || pj >= c->n0)))
+    throw Error(SPPC_E_ARG, "pair_index must be -1, or 0..26 (below n0) with k = 1 (Alg. 1)");
+  if (o.n_deflate <= 0) o.n_deflate = std::min<int64_t>(std::min(std::max(2 * k, pj + 2), 28), c->n0);
   if (o.n_deflate < k || o.n_deflate > 28 || o.n_deflate > c->n0) throw Error(SPPC_E_ARG, "n_deflate must be in [k, min(28, n0)]");
+  if (pj >= o.n_deflate) throw Error(SPPC_E_ARG, "n_deflate must exceed pair_index");
   c->D = o.n_deflate;
   if (o.m_max < 2 * k || o.m_max > 512) throw Error(SPPC_E_ARG, "m_max must be in [2k, 512]");
   if (o.panel_width < -1 || o.panel_width > 65536) throw Error(SPPC_E_ARG, "panel_width must be -1, 0 or 1..65536");
@@ -913,6 +917,17 @@ void setup_impl(sppc_ctx* c, const sppc_csr* Hin, const int64_t* loff, int L, in
 
   // zeroth order
   zeroth_order(c);
+  if (pj > 0) {
+    // Alg. 1 for pair pj: its zeroth order (E_pj^(0), psi_pj) goes first, so the single wanted pair
+    // starts from it and its small solves project psi_pj out; the deflation and its exact terms
+    // treat the D eigenvectors alike in any order
+    std::swap(c->E0h[0], c->E0h[pj]);
+    SPPC_HIP(hipMemcpy(c->E0, c->E0h.data(), sizeof(double) * c->D, hipMemcpyHostToDevice));
+    copy_block(c->n0, 1, c->Psihat + pj, c->D, c->cx, 1, s);
+    copy_block(c->n0, 1, c->Psihat, c->D, c->Psihat + pj, c->D, s);
+    copy_block(c->n0, 1, c->cx, 1, c->Psihat, c->D, s);
+    sync(c);
+  }
   const double scale = std::max(1.0, std::fabs(c->E0h.back()));
   for (int j = 0; j < k; ++j)
     if (std::fabs(c->E0h[j]) < 1e-10 * scale)
@@ -1309,6 +1324,7 @@ sppc_status sppc_default_opts(sppc_opts* o) {
   o->verbose = 0;
   o->panel_width = -1;
   o->corr_shift = SPPC_SHIFT_E0;
+  o->pair_index = -1;
   o->rmm_precond = SPPC_CORR_JACOBI;
   return SPPC_OK;
 }

@@ -505,3 +505,43 @@ def test_theta_shifted_variant_with_E0_shifts_is_the_paper_recursion(cfg0):
     a = osp.correction_vectors(H, H0, z, k, E_hist[:1], [Psi0], VPsi0)
     b = osp.correction_vectors(H, H0, z, k, E_hist[:1], [Psi0], VPsi0, shifts=z.w[:k].copy())
     assert np.array_equal(a[1], b[1])
+
+
+# ------------------------------------------------------------------ Alg. 1 (one pair alone)
+def test_pair_zero_is_the_single_pair_run(cfg0):
+    H, n0, k, lam, _ = cfg0
+    o = oracle.Options(continuation=False, maxiter=8, tol=1e-300, final_check=False)
+    a = oracle.sppc_pair(H, n0, 0, o)
+    b = oracle.sppc(H, n0, 1, o)
+    for ha, hb in zip(a.history, b.history):
+        assert np.array_equal(ha["theta"], hb["theta"])
+
+
+@pytest.mark.parametrize("kk", [1, 3])
+def test_pair_subspace_brute_force(cfg0, kk):
+    # Alg. 1's Ritz value after step P is the lowest eigenvalue of H on span{Psi_kk^(0..P)}, the
+    # raw Rayleigh-Schroedinger corrections of eq. exp_seq for pair kk (column kk of the k-pair
+    # recursion): one orthonormalisation and one dense eigensolve at the end, no per-step
+    # Gram-Schmidt, QR or Rayleigh-Ritz
+    H, n0, k, lam, _ = cfg0
+    P = 6
+    E, Psi = oracle.rs_corrections(H, n0, kk + 1, P)
+    run = oracle.sppc_pair(H, n0, kk, oracle.Options(continuation=False, maxiter=P, tol=1e-300,
+                                                      final_check=False))
+    for p in range(P + 1):
+        B = np.stack([Psi[l][:, kk] for l in range(p + 1)], axis=1)
+        Q, _ = np.linalg.qr(B)
+        want = np.linalg.eigvalsh(Q.T @ (H @ Q))[0]
+        got = run.history[p]["theta"][0]
+        assert abs(got - want) <= 1e-11 * abs(want), (p, got, want)
+        assert got >= lam[0] - 1e-12 * abs(lam[0])   # a Ritz value bounds lambda_1 from above
+    th = [h["theta"][0] for h in run.history]
+    assert np.all(np.diff(th) <= 1e-12 * abs(th[0]))   # nested subspaces: non-increasing
+
+
+def test_pair_is_exact_when_the_small_space_is_everything():
+    A = levelgen.generate((30, 50), 12, 12)
+    H = oracle.symmetric_from_upper(A.row_ptr, A.col, A.val, A.n)
+    lam = np.linalg.eigvalsh(H.toarray())
+    r = oracle.sppc_pair(H, A.n, 2, oracle.Options(continuation=False, maxiter=3))
+    assert r.history[0]["rrn"][0] < 1e-12 and abs(r.theta[0] - lam[2]) < 1e-12 * abs(lam[2])
