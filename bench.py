@@ -144,7 +144,7 @@ def main():
     from paper_2407_08901_amd import mpnn_train
     weights = {"davidson": mpnn_train.load_for("davidson"), "rmmdiis": mpnn_train.load_for("rmmdiis")}
 
-    def make_step(mode, auto_switch=None):
+    def mode_opts(mode, auto_switch=None):
         auto_switch = args.auto_switch if auto_switch is None else auto_switch
         mixed = mode.startswith("mixed")
         rmm = "+rmmdiis" in mode
@@ -155,12 +155,28 @@ def main():
         extra = {"inner_tol": 1e-6} if mode == "plain-inexact" else {}
         if rmm and mpnn:
             extra["rmm_precond"] = P.SPPC_CORR_MPNN
-        opts = P.sppc_default_opts(precision=P.SPPC_PREC_MIXED if mixed else P.SPPC_PREC_FP64, precond=precond,
+        return P.sppc_default_opts(precision=P.SPPC_PREC_MIXED if mixed else P.SPPC_PREC_FP64, precond=precond,
                                    verbose=1 if args.verbose else 0, panel_width=args.panel_width,
                                    auto_switch=1 if auto_switch else 0, **extra)
 
+    # one device workspace from PyTorch for every context of the run (the largest any timed form
+    # needs), allocated before the timing: no allocation or release inside the timed steps
+    forms = [(args.mode, None)]
+    if not args.no_compare:
+        forms += [("plain", False), ("mixed+rmmdiis", False)]
+        if args.full_compare:
+            forms += [("mixed+mpnn", False), ("plain-inexact", False), ("mixed", False), ("mixed+rmmdiis", True)]
+    ws_bytes = max(P.sppc_workspace_size(rp, col, val, A.level_offsets, w.n_small_levels, w.k, mode_opts(m, a))
+                   for m, a in forms)
+    workspace = P.workspace_tensor(ws_bytes)
+
+    def make_step(mode, auto_switch=None):
+        mpnn = mode.endswith("mpnn")
+        rmm = "+rmmdiis" in mode
+        opts = mode_opts(mode, auto_switch)
+
         def one_step():
-            ctx = P.sppc_setup(rp, col, val, A.level_offsets, w.n_small_levels, w.k, opts)
+            ctx = P.sppc_setup(rp, col, val, A.level_offsets, w.n_small_levels, w.k, opts, workspace=workspace)
             if mpnn:
                 P.sppc_mpnn_set_weights(ctx, weights["rmmdiis" if rmm else "davidson"])
             ev, Z, rrn, st, status = P.sppc_solve(ctx, want_vectors=True)
@@ -218,6 +234,7 @@ def main():
         "breakdown_ms": {k: round(st[k], 2) for k in ("t_setup_ms", "t_solve_ms", "t_spmm_ms", "t_small_ms",
                                                       "t_ortho_ms", "t_rr_ms", "t_h0_ms")},
         "cg_iterations": st["cg_iterations"], "h0_iterations": st["h0_iterations"],
+        "workspace": {"bytes": ws_bytes, "peak": st["workspace_peak"], "source": "torch.empty (caller-owned)"},
         "roofline": roof,
         "generate_s": round(t_gen, 2),
     }

@@ -152,12 +152,27 @@ typedef struct {
                             int32 columns; int64 row pointers) + X read + Y written */
   double t_h0_ms;      /* time inside products with H0hat outside the small solves */
   int mpnn_fallbacks;  /* pairs that the true residual sent back to the diagonal step */
+  int64_t workspace_peak; /* bytes of the caller's workspace in use at the peak so far (0 without one) */
 } sppc_stats;
 
 typedef struct sppc_ctx sppc_ctx;
 
 /* Fills *opts with the defaults listed above.  Returns SPPC_E_ARG for NULL. */
 sppc_status sppc_default_opts(sppc_opts* opts);
+
+/*
+ * Bytes of device workspace that sppc_setup followed by sppc_solve needs for this problem and these
+ * options (arguments as sppc_setup): the arrays the context keeps (the device copies of H, H0hat,
+ * the basis Q and H Q of m_max columns, the blocks, the RMM-DIIS histories or the learned
+ * preconditioner's arrays when the options use them) plus the largest set of setup temporaries
+ * alive at one time.  It runs the checks of sppc_setup and reads H's row pointer of the first row
+ * outside the small space (one 8-byte copy from the device); it allocates nothing.  The entry
+ * count of the full matrix is bounded by twice the stored entries, and for float64 values both
+ * outcomes of the float32-exactness check are covered, so the figure is an upper bound.
+ * Errors: as sppc_setup's argument checks (the message in sppc_setup_error()).
+ */
+sppc_status sppc_workspace_size(const sppc_csr* H, const int64_t* level_offsets_host, int n_levels,
+                                int n_small_levels, int k, const sppc_opts* opts, size_t* bytes);
 
 /*
  * Builds a context for the k lowest eigenpairs of H (Alg. 2 input).
@@ -167,16 +182,22 @@ sppc_status sppc_default_opts(sppc_opts* opts);
  *                     (H0hat = H[0:n0, 0:n0], eq. split2)
  *   k                 wanted pairs, 1 <= k <= 16, k <= n_deflate <= n0
  *   opts              NULL for the defaults
+ *   workspace_dev, workspace_bytes
+ *                     device memory owned by the caller (at least sppc_workspace_size bytes) from
+ *                     which every device array of the context is taken, setup temporaries
+ *                     included; it must stay valid and unused by anything else until
+ *                     sppc_destroy.  NULL: the library allocates (hipMalloc, returned by
+ *                     sppc_destroy; see sppc_set_memory_cache).
  *   stream            hipStream_t (as void*), NULL for the default stream
  * Work: device copy of H in both triangles (float32 values when every value is
  * float32-exact, else float64), H0hat, the n_deflate lowest eigenpairs of
  * H0hat (eq. EP_small), and step p = 0 of Alg. 2 (basis Psi^(0), one block
- * product with H, Rayleigh-Ritz).  The context allocates its own device memory
- * and frees it in sppc_destroy.  Errors: SPPC_E_ARG, SPPC_E_NOMEM, SPPC_E_HIP,
- * SPPC_E_SINGULAR_E0 (*out is then NULL).
+ * product with H, Rayleigh-Ritz).  Errors: SPPC_E_ARG, SPPC_E_NOMEM (also when a
+ * workspace is too small), SPPC_E_HIP, SPPC_E_SINGULAR_E0 (*out is then NULL).
  */
 sppc_status sppc_setup(sppc_ctx** out, const sppc_csr* H, const int64_t* level_offsets_host,
-                       int n_levels, int n_small_levels, int k, const sppc_opts* opts, void* stream);
+                       int n_levels, int n_small_levels, int k, const sppc_opts* opts, void* workspace_dev,
+                       size_t workspace_bytes, void* stream);
 
 /*
  * Y = H X for the matrix of the context (the paper's cost unit, Sec. IV.C).
@@ -327,16 +348,21 @@ const char* sppc_setup_error(void);
 void sppc_destroy(sppc_ctx* ctx);
 
 /*
- * Device memory of the library (context arrays and setup temporaries, including those of the
- * float64 and float32 device copies of H) comes from a process-wide cache: a block given back by
- * sppc_destroy or by setup is kept and handed to the next request of the same rounded size
- * (2 MiB granules) on the same device.  Repeated setups of one problem size then allocate
- * nothing; hipMalloc/hipFree stall the host, and VRAM that was freed recently is cleared by the
- * driver before it is handed out again (about a second per 100 GB).  The cache keeps at most 3/4
- * of a device's memory, and an allocation that fails empties the cache of its device and is
- * tried once more.  This call frees every cached block (of every device) now and returns the
- * number of bytes freed.  Thread-safe; blocks in use by live contexts are not affected.
+ * Device memory the library allocates itself (contexts set up without a workspace) is returned
+ * with hipFree when it is given back, unless this cache is enabled: with bytes_per_device > 0 a
+ * block given back by sppc_destroy or by setup is kept and handed to the next request of the same
+ * rounded size (2 MiB granules) on the same device, up to that many bytes (and at most 3/4 of the
+ * device's memory) per device.  Repeated setups of one problem size then allocate nothing
+ * (hipMalloc/hipFree stall the host, and VRAM freed recently is cleared by the driver before it is
+ * handed out again, about a second per 100 GB), but PyTorch's allocator cannot see or trim the
+ * cached blocks.  An allocation that fails empties the cache of its device and is tried once more.
+ * 0 (the default) disables the cache and frees what it holds.  Returns the previous limit.
+ * Thread-safe.
  */
+size_t sppc_set_memory_cache(size_t bytes_per_device);
+
+/* Frees every block the cache holds (of every device) now; returns the number of bytes freed.
+ * Thread-safe; blocks in use by live contexts are not affected. */
 size_t sppc_release_cached_memory(void);
 
 #ifdef __cplusplus

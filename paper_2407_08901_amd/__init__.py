@@ -7,8 +7,10 @@ no CPU fallback.  If the library is missing the import of `lib()` fails loudly.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import weakref
 from typing import Optional, Sequence
 
 import torch  # loads the HIP runtime first, so libsppc.so binds to the same one
@@ -26,9 +28,9 @@ SPPC_SHIFT_E0, SPPC_SHIFT_RITZ = 0, 1
 STATUS_NAMES = {0: "SPPC_OK", 1: "SPPC_E_ARG", 2: "SPPC_E_HIP", 3: "SPPC_E_NOMEM",
                 4: "SPPC_E_SINGULAR_E0", 5: "SPPC_E_BREAKDOWN", 6: "SPPC_E_NOCONV", 7: "SPPC_E_NAN"}
 
-EXPORTS = ("sppc_default_opts", "sppc_setup", "sppc_spmm", "sppc_spmm_noalloc", "sppc_correct", "sppc_rayleigh_ritz",
+EXPORTS = ("sppc_default_opts", "sppc_workspace_size", "sppc_setup", "sppc_spmm", "sppc_spmm_noalloc", "sppc_correct", "sppc_rayleigh_ritz",
            "sppc_solve", "sppc_get", "sppc_last_error", "sppc_setup_error", "sppc_destroy",
-           "sppc_release_cached_memory", "sppc_mpnn_set_weights", "sppc_mpnn_eval", "sppc_mpnn_train_step", "sppc_mpnn_target")
+           "sppc_release_cached_memory", "sppc_set_memory_cache", "sppc_mpnn_set_weights", "sppc_mpnn_eval", "sppc_mpnn_train_step", "sppc_mpnn_target")
 SPPC_MPNN_NPARAM = 289
 
 
@@ -55,7 +57,7 @@ class sppc_stats(ctypes.Structure):
                 ("converged", ctypes.c_int), ("t_setup_ms", ctypes.c_double), ("t_solve_ms", ctypes.c_double),
                 ("t_spmm_ms", ctypes.c_double), ("t_small_ms", ctypes.c_double), ("t_ortho_ms", ctypes.c_double),
                 ("t_rr_ms", ctypes.c_double), ("spmm_alg_bytes", ctypes.c_double), ("t_h0_ms", ctypes.c_double),
-                ("mpnn_fallbacks", ctypes.c_int)]
+                ("mpnn_fallbacks", ctypes.c_int), ("workspace_peak", ctypes.c_int64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -80,7 +82,11 @@ def lib():
         vp, i64, c_int, dp = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.POINTER(ctypes.c_double)
         L.sppc_default_opts.argtypes = [ctypes.POINTER(sppc_opts)]
         L.sppc_setup.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(sppc_csr), ctypes.POINTER(i64), c_int, c_int,
-                                 c_int, ctypes.POINTER(sppc_opts), vp]
+                                 c_int, ctypes.POINTER(sppc_opts), vp, ctypes.c_size_t, vp]
+        L.sppc_workspace_size.argtypes = [ctypes.POINTER(sppc_csr), ctypes.POINTER(i64), c_int, c_int, c_int,
+                                          ctypes.POINTER(sppc_opts), ctypes.POINTER(ctypes.c_size_t)]
+        L.sppc_set_memory_cache.argtypes = [ctypes.c_size_t]
+        L.sppc_set_memory_cache.restype = ctypes.c_size_t
         L.sppc_spmm.argtypes = [vp, vp, c_int, vp, c_int]
         L.sppc_spmm_noalloc.argtypes = [vp, vp, c_int, vp, c_int]
         L.sppc_correct.argtypes = [vp, c_int, dp]
@@ -99,7 +105,7 @@ def lib():
         L.sppc_mpnn_eval.argtypes = [vp, fp, c_int, vp, vp, dp, vp, c_int, vp, vp, dp, dp, c_int]
         L.sppc_mpnn_train_step.argtypes = [vp, vp, c_int, vp, vp, dp, vp, c_int, vp, ctypes.c_float, c_int, dp]
         L.sppc_mpnn_target.argtypes = [vp, c_int, vp, c_int, vp, vp]
-        for name in ("sppc_default_opts", "sppc_setup", "sppc_spmm", "sppc_spmm_noalloc", "sppc_correct", "sppc_rayleigh_ritz",
+        for name in ("sppc_default_opts", "sppc_workspace_size", "sppc_setup", "sppc_spmm", "sppc_spmm_noalloc", "sppc_correct", "sppc_rayleigh_ritz",
                      "sppc_solve", "sppc_get", "sppc_mpnn_set_weights", "sppc_mpnn_eval", "sppc_mpnn_train_step",
                      "sppc_mpnn_target"):
             getattr(L, name).restype = c_int
@@ -130,8 +136,26 @@ def sppc_default_opts(**kw) -> sppc_opts:
     return o
 
 
+_LIVE = weakref.WeakSet()  # contexts not destroyed yet
+_EXITING = False
+
+
+@atexit.register
+def _destroy_live_contexts():
+    # Contexts still alive at interpreter exit are destroyed here, while the HIP runtime (and a
+    # profiler's tool library) is still up: a destroy run later from garbage collection during
+    # interpreter teardown would call hipStreamSynchronize/hipFree after they were finalised.
+    global _EXITING
+    for ctx in list(_LIVE):
+        try:
+            sppc_destroy(ctx)
+        except Exception:
+            pass
+    _EXITING = True
+
+
 class Context:
-    """Owns an sppc_ctx and keeps the device arrays it borrows alive."""
+    """Owns an sppc_ctx and keeps the device arrays it borrows (and its workspace) alive."""
 
     def __init__(self, handle, n, k, keep, stream):
         self.handle = handle
@@ -139,32 +163,63 @@ class Context:
         self.k = k
         self._keep = keep
         self.stream = stream
+        _LIVE.add(self)
 
     def __del__(self):
+        if _EXITING:
+            return
         try:
             sppc_destroy(self)
         except Exception:
             pass
 
 
-def sppc_setup(row_ptr: torch.Tensor, col: torch.Tensor, val: torch.Tensor, level_offsets: Sequence[int],
-               n_small_levels: int, k: int, opts: Optional[sppc_opts] = None, stream=None) -> Context:
-    """Upper-triangular CSR of H on the GPU (int64 row_ptr, int32 col, float64/float32 val)."""
+def _csr(row_ptr, col, val):
     for t, dt in ((row_ptr, torch.int64), (col, torch.int32)):
         if not t.is_cuda or t.dtype != dt or not t.is_contiguous():
             raise TypeError("row_ptr must be int64, col int32; contiguous GPU tensors")
     if not val.is_cuda or val.dtype not in (torch.float64, torch.float32) or not val.is_contiguous():
         raise TypeError("val must be a contiguous float64/float32 GPU tensor")
     n = row_ptr.numel() - 1
-    H = sppc_csr(n, col.numel(), row_ptr.data_ptr(), col.data_ptr(), val.data_ptr(),
-                 SPPC_F32 if val.dtype == torch.float32 else SPPC_F64)
+    return n, sppc_csr(n, col.numel(), row_ptr.data_ptr(), col.data_ptr(), val.data_ptr(),
+                       SPPC_F32 if val.dtype == torch.float32 else SPPC_F64)
+
+
+def sppc_workspace_size(row_ptr: torch.Tensor, col: torch.Tensor, val: torch.Tensor, level_offsets: Sequence[int],
+                        n_small_levels: int, k: int, opts: Optional[sppc_opts] = None) -> int:
+    """Bytes of device workspace for sppc_setup + sppc_solve of this problem with these options."""
+    n, H = _csr(row_ptr, col, val)
+    lo = (ctypes.c_int64 * len(level_offsets))(*[int(x) for x in level_offsets])
+    out = ctypes.c_size_t()
+    _check(lib().sppc_workspace_size(ctypes.byref(H), lo, len(level_offsets) - 1, n_small_levels, k,
+                                     ctypes.byref(opts) if opts is not None else None, ctypes.byref(out)))
+    return int(out.value)
+
+
+def workspace_tensor(nbytes: int) -> torch.Tensor:
+    """A device workspace of nbytes from PyTorch's allocator."""
+    return torch.empty(int(nbytes), dtype=torch.uint8, device="cuda")
+
+
+def sppc_setup(row_ptr: torch.Tensor, col: torch.Tensor, val: torch.Tensor, level_offsets: Sequence[int],
+               n_small_levels: int, k: int, opts: Optional[sppc_opts] = None, stream=None,
+               workspace: Optional[torch.Tensor] = None) -> Context:
+    """Upper-triangular CSR of H on the GPU (int64 row_ptr, int32 col, float64/float32 val).
+    workspace: a uint8 GPU tensor of at least sppc_workspace_size bytes that every device array of
+    the context comes from (None: the library allocates)."""
+    n, H = _csr(row_ptr, col, val)
+    wp, wb = None, 0
+    if workspace is not None:
+        if not workspace.is_cuda or not workspace.is_contiguous():
+            raise TypeError("workspace must be a contiguous GPU tensor")
+        wp, wb = ctypes.c_void_p(workspace.data_ptr()), workspace.numel() * workspace.element_size()
     lo = (ctypes.c_int64 * len(level_offsets))(*[int(x) for x in level_offsets])
     h = ctypes.c_void_p()
     st = stream if stream is not None else torch.cuda.current_stream()
     status = lib().sppc_setup(ctypes.byref(h), ctypes.byref(H), lo, len(level_offsets) - 1, n_small_levels, k,
-                              ctypes.byref(opts) if opts is not None else None, _stream_handle(st))
+                              ctypes.byref(opts) if opts is not None else None, wp, wb, _stream_handle(st))
     _check(status)
-    return Context(h, n, k, (row_ptr, col, val), st)
+    return Context(h, n, k, (row_ptr, col, val, workspace), st)
 
 
 def sppc_spmm(ctx: Context, X: torch.Tensor, Y: torch.Tensor) -> None:
@@ -302,6 +357,12 @@ def sppc_destroy(ctx: Context) -> None:
     if ctx is not None and ctx.handle:
         lib().sppc_destroy(ctx.handle)
         ctx.handle = None
+
+
+def sppc_set_memory_cache(bytes_per_device: int) -> int:
+    """Enables (bytes > 0) or disables (0) the library's cache of freed device blocks; returns the
+    previous limit."""
+    return int(lib().sppc_set_memory_cache(int(bytes_per_device)))
 
 
 def sppc_release_cached_memory() -> int:

@@ -17,11 +17,13 @@ struct Error : std::runtime_error {
   Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
 };
 
+// A failed HIP call throws SPPC_E_HIP, or SPPC_E_NOMEM when memory (or the caller's workspace) ran out.
 #define SPPC_HIP(call)                                                                 \
   do {                                                                                 \
     hipError_t e_ = (call);                                                            \
     if (e_ != hipSuccess)                                                              \
-      throw ::sppc::Error(2, std::string(#call) + ": " + hipGetErrorString(e_));       \
+      throw ::sppc::Error(e_ == hipErrorOutOfMemory ? 3 : 2,                           \
+                          std::string(#call) + ": " + hipGetErrorString(e_));          \
   } while (0)
 
 #define SPPC_LAUNCH_CHECK() SPPC_HIP(hipGetLastError())
@@ -32,9 +34,23 @@ __host__ __device__ inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 
 
 // ---------------------------------------------------------------- memory (memory.hip)
 
-// Device and pinned host memory from the library's process-wide cache of freed blocks.  A block
-// may be given back only once the stream that last used it has been synchronised.
+// Device memory: from the active caller workspace (WsScope) when there is one, else from the
+// library (hipMalloc, or the optional cache of freed blocks).  dev_alloc_tmp marks a temporary of a
+// setup phase (taken from the workspace's top end).  A block may be given back only once the stream
+// that last used it has been synchronised.  Pinned host memory always comes from the library.
+struct Workspace;
+Workspace* ws_create(void* base, size_t bytes);
+void ws_destroy(Workspace* w);
+size_t ws_peak(const Workspace* w);
+struct WsScope {
+  Workspace* prev;
+  explicit WsScope(Workspace* w);
+  ~WsScope();
+  WsScope(const WsScope&) = delete;
+  WsScope& operator=(const WsScope&) = delete;
+};
 hipError_t dev_alloc(void** p, size_t bytes);
+hipError_t dev_alloc_tmp(void** p, size_t bytes);
 void dev_free(void* p);
 hipError_t pinned_alloc(void** p, size_t bytes);
 void pinned_free(void* p);
@@ -42,6 +58,12 @@ template <class T>
 inline hipError_t dev_malloc(T** p, size_t bytes) {
   return dev_alloc((void**)p, bytes);
 }
+template <class T>
+inline hipError_t dev_malloc_tmp(T** p, size_t bytes) {
+  return dev_alloc_tmp((void**)p, bytes);
+}
+// bytes one device array of `bytes` takes in a workspace (256-byte granules)
+inline size_t ws_bytes(size_t bytes) { return (std::max<size_t>(bytes, 1) + 255) / 256 * 256; }
 
 // ---------------------------------------------------------------- sparse (kernels_sparse.hip)
 
@@ -87,6 +109,13 @@ void build_block_view(const DevCSR& full, int64_t n0, int64_t* rend, hipStream_t
 // Device memory is allocated with hipMalloc and owned by the caller (release_panel).
 void build_panel(const DevCSR& H, int PW, PanelH& out, hipStream_t s);
 void release_panel(PanelH& p);
+// Workspace bytes of the builders: arrays kept by the context and setup temporaries.
+struct BuildBytes {
+  size_t persist = 0, temp = 0;
+};
+BuildBytes full_csr_bytes(int64_t n, int64_t nnz_up, bool want64, bool want32);
+BuildBytes panel_bytes(int64_t n, int64_t nnz_full, bool v64, bool v32);
+BuildBytes view_bytes(int64_t n0, int64_t nnz0, bool v64, bool v32);
 // out[0..n] = exclusive prefix sums of a[0..n) (out[n] = total); bsum holds cdiv(n, 1024) + 1.
 void scan_exclusive(int64_t n, const int32_t* a, int64_t* out, int64_t* bsum, hipStream_t s);
 // Contiguous copy of a block view (rows [0, n0), columns < n0); hipMalloc'd arrays.

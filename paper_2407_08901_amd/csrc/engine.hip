@@ -30,16 +30,27 @@ namespace sppc {
 constexpr int KB = 32;   // widest block handled by one product / orthonormalisation
 constexpr int NWMAX = 64;
 
+// Device arrays of a context (or, with temp, of one setup phase).  A counting arena allocates
+// nothing: it adds up the workspace bytes its requests would take (the size query runs the same
+// allocation code as the setup).
 struct Arena {
   std::vector<void*> ptrs;
+  bool temp = false;
+  bool counting = false;
+  size_t counted = 0;
   template <class T>
   T* alloc(size_t count) {
     void* p = nullptr;
     const size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
-    hipError_t e = dev_alloc(&p, bytes);
+    if (counting) {
+      counted += ws_bytes(bytes);
+      return nullptr;
+    }
+    hipError_t e = temp ? dev_alloc_tmp(&p, bytes) : dev_alloc(&p, bytes);
     if (e != hipSuccess) {
       (void)hipGetLastError();
-      throw Error(SPPC_E_NOMEM, "allocation of " + std::to_string(bytes) + " bytes of device memory failed");
+      throw Error(SPPC_E_NOMEM, "allocation of " + std::to_string(bytes) + " bytes of device memory failed" +
+                                    std::string(" (device memory, or the caller's workspace, is exhausted)"));
     }
     ptrs.push_back(p);
     return (T*)p;
@@ -168,6 +179,7 @@ struct sppc_ctx {
   double tacc[C_NCAT] = {0, 0, 0, 0, 0};
   int64_t nnz_up = 0;  // stored upper-triangle entries of the input
   int nsmall = 0;      // leading levels that form the small space
+  Workspace* ws = nullptr;  // the caller's workspace (nullptr: library-allocated memory)
 };
 
 namespace sppc {
@@ -349,6 +361,7 @@ void zeroth_order(sppc_ctx* c) {
   const int D = c->D;
   const int nb = (int)std::min<int64_t>(n0, KB);
   Arena tmp;
+  tmp.temp = true;
   Basis sb;
   sb.n = n0;
   sb.ldq = nb;
@@ -486,34 +499,50 @@ void correct_perturbative(sppc_ctx* c, const double* shifts_host = nullptr) {
   c->pend_kind = SPPC_CORR_PERTURBATIVE;
 }
 
+// Arrays of the learned preconditioner: the static inputs (A is the context's arena, or a counting
+// one) and the work of S samples.
+void alloc_mpnn_static(sppc_ctx* c, Arena& A) {
+  const int64_t n = c->n;
+  const int L = (int)c->loff.size() - 1;
+  c->loff_dev = A.alloc<int64_t>(L + 1);
+  c->mp_lev = A.alloc<double>(n);
+  c->mp_Ad = A.alloc<double>(n);
+  c->mp_A1 = A.alloc<double>(n);
+  c->mp_Al = A.alloc<double>(n);
+  c->mp_grad = A.alloc<double>(512);
+  c->mp_loss = A.alloc<double>(64);
+  c->mp_th = A.alloc<double>(64);
+  c->mp_wd = A.alloc<double>(512);
+  c->mp_w = A.alloc<float>(512);
+  c->mp_wq = A.alloc<float>(512);
+}
+void alloc_mpnn_samples(sppc_ctx* c, Arena& A, int S) {
+  c->mp_work = A.alloc<double>((size_t)mpnn_work_doubles(c->n, S));
+  c->mp_sel = A.alloc<double>((size_t)c->n * S * 3);
+}
+
 // Static inputs of the learned preconditioner and workspace for S samples (lazy).
 void mpnn_ensure(sppc_ctx* c, int S) {
   hipStream_t s = c->s;
-  Arena& A = c->arena;
   const int64_t n = c->n;
   if (!c->mp_ready) {
     const int L = (int)c->loff.size() - 1;
-    c->loff_dev = A.alloc<int64_t>(L + 1);
+    alloc_mpnn_static(c, c->arena);
     SPPC_HIP(hipMemcpy(c->loff_dev, c->loff.data(), sizeof(int64_t) * (L + 1), hipMemcpyHostToDevice));
-    c->mp_lev = A.alloc<double>(n);
-    c->mp_Ad = A.alloc<double>(n);
-    c->mp_A1 = A.alloc<double>(n);
-    c->mp_Al = A.alloc<double>(n);
-    c->mp_grad = A.alloc<double>(512);
-    c->mp_loss = A.alloc<double>(64);
-    c->mp_th = A.alloc<double>(64);
-    c->mp_wd = A.alloc<double>(512);
-    c->mp_w = A.alloc<float>(512);
-    c->mp_wq = A.alloc<float>(512);
-    double* tmp = A.alloc<double>((size_t)6 * n);
+    Arena tmpA;
+    tmpA.temp = true;
+    double* tmp = tmpA.alloc<double>((size_t)6 * n);
     mpnn_prepare(c->H, c->diag, c->loff_dev, L, c->nsmall, c->mp_lev, c->mp_Ad, c->mp_A1, c->mp_Al, tmp, s);
     sync(c);
+    tmpA.release();
     c->mp_ready = true;
   }
   if (S > c->mp_S) {
-    c->mp_work = A.alloc<double>((size_t)mpnn_work_doubles(n, S));
-    c->mp_sel = A.alloc<double>((size_t)n * S * 3);
-    c->mp_S = S;
+    // sized for all k pairs at once (the solver's calls never need more, so they allocate once;
+    // only the training entry points may ask for up to 32 samples)
+    const int Sa = std::max(S, c->k);
+    alloc_mpnn_samples(c, c->arena, Sa);
+    c->mp_S = Sa;
   }
 }
 
@@ -744,124 +773,15 @@ bool all_converged(sppc_ctx* c) {
   return true;
 }
 
-void setup_impl(sppc_ctx* c, const sppc_csr* Hin, const int64_t* loff, int L, int nsmall, int k) {
-  if (!Hin || !loff || L < 1 || nsmall < 1 || nsmall > L) throw Error(SPPC_E_ARG, "bad level partition");
-  if (Hin->n < 1 || !Hin->row_ptr_dev || !Hin->col_dev || !Hin->val_dev) throw Error(SPPC_E_ARG, "bad H");
-  if (Hin->n >= (int64_t)1 << 31) throw Error(SPPC_E_ARG, "n must be < 2^31");
-  c->loff.assign(loff, loff + L + 1);
-  if (c->loff[0] != 0 || c->loff[L] != Hin->n) throw Error(SPPC_E_ARG, "level offsets must run 0..n");
-  for (int l = 0; l < L; ++l)
-    if (c->loff[l + 1] <= c->loff[l]) throw Error(SPPC_E_ARG, "levels must be non-empty and ascending");
-  c->n = Hin->n;
-  c->nnz_up = Hin->nnz;
-  c->n0 = c->loff[nsmall];
-  c->nsmall = nsmall;
-  c->k = k;
-  sppc_opts& o = c->o;
-  if (k < 1 || k > 16 || k > c->n0) throw Error(SPPC_E_ARG, "k must be 1..16 and <= n0");
-  const int pj = o.pair_index;
-  if (pj < -1 || pj > 26 || (pj >= 0 && (k != 1 || pj >= c->n0)))
-    throw Error(SPPC_E_ARG, "pair_index must be -1, or 0..26 (below n0) with k = 1 (Alg. 1)");
-  if (o.n_deflate <= 0) o.n_deflate = std::min<int64_t>(std::min(std::max(2 * k, pj + 2), 28), c->n0);
-  if (o.n_deflate < k || o.n_deflate > 28 || o.n_deflate > c->n0) throw Error(SPPC_E_ARG, "n_deflate must be in [k, min(28, n0)]");
-  if (pj >= o.n_deflate) throw Error(SPPC_E_ARG, "n_deflate must exceed pair_index");
-  c->D = o.n_deflate;
-  if (o.m_max < 2 * k || o.m_max > 512) throw Error(SPPC_E_ARG, "m_max must be in [2k, 512]");
-  if (o.panel_width < -1 || o.panel_width > 65536) throw Error(SPPC_E_ARG, "panel_width must be -1, 0 or 1..65536");
-  if (o.precond != SPPC_CORR_JACOBI && o.precond != SPPC_CORR_MPNN && o.precond != SPPC_CORR_SMALL &&
-      o.precond != SPPC_CORR_RMMDIIS)
-    throw Error(SPPC_E_ARG, "continuation must be JACOBI, MPNN, SMALL or RMMDIIS");
-  if (o.corr_shift != SPPC_SHIFT_E0 && o.corr_shift != SPPC_SHIFT_RITZ)
-    throw Error(SPPC_E_ARG, "corr_shift must be SPPC_SHIFT_E0 or SPPC_SHIFT_RITZ");
-  if (o.rmm_precond != SPPC_CORR_JACOBI && o.rmm_precond != SPPC_CORR_MPNN)
-    throw Error(SPPC_E_ARG, "the RMM-DIIS step preconditioner must be JACOBI or MPNN");
-  if (o.refine_precond != SPPC_CORR_JACOBI && o.refine_precond != SPPC_CORR_MPNN &&
-      o.refine_precond != SPPC_CORR_SMALL)
-    throw Error(SPPC_E_ARG, "refinement preconditioner must be JACOBI, MPNN or SMALL");
-  if (!(o.precond_tol > 0.0) || o.precond_tol >= 1.0) throw Error(SPPC_E_ARG, "precond_tol must be in (0, 1)");
-  if (!(o.tol > 0) || !(o.tau_drop >= 0) || !(o.inner_tol >= 0) || !(o.h0_tol > 0)) throw Error(SPPC_E_ARG, "bad tolerances");
-  if (o.precision != SPPC_PREC_FP64 && o.precision != SPPC_PREC_MIXED) throw Error(SPPC_E_ARG, "bad precision");
-  if (o.auto_switch != 0 && o.auto_switch != 1) throw Error(SPPC_E_ARG, "auto_switch must be 0 or 1");
-  const int last_p = (o.p_switch > 0) ? std::min(o.p_switch, o.maxiter) : o.maxiter;
-  if (last_p < 0) throw Error(SPPC_E_ARG, "maxiter must be >= 0");
-  if ((int64_t)k * (last_p + 1) > o.m_max) throw Error(SPPC_E_ARG, "m_max < k * (perturbation order + 1)");
-  hipStream_t s = c->s;
-  const bool mixed = o.precision == SPPC_PREC_MIXED;
-  // device address of the static scratch of the allocation-free block product (once per device)
-  (void)noalloc_scratch(nullptr);
-
-  // device format of H
-  Arena& A = c->arena;
-  int* dflags = A.alloc<int>(4);
-  bool exact = false;
-  // first pass decides which value arrays are stored: float32 alone when lossless
-  {
-    const bool in32 = Hin->val_type == SPPC_F32;
-    // validation + exactness happen inside; request float64 storage unless exact
-    DevCSR tmp;
-    build_full_csr(c->n, Hin->nnz, Hin->row_ptr_dev, Hin->col_dev, Hin->val_dev, in32 ? 1 : 0, tmp, dflags,
-                   /*want64=*/false, /*want32=*/true, exact, s);
-    if (exact) {
-      c->H = tmp;
-    } else {
-      dev_free(tmp.val32);
-      tmp.val32 = nullptr;
-      dev_free(tmp.rp);
-      dev_free(tmp.col);
-      DevCSR t2;
-      build_full_csr(c->n, Hin->nnz, Hin->row_ptr_dev, Hin->col_dev, Hin->val_dev, 0, t2, dflags, true, mixed,
-                     exact, s);
-      c->H = t2;
-    }
-    A.ptrs.push_back(c->H.rp);
-    A.ptrs.push_back(c->H.col);
-    if (c->H.val64) A.ptrs.push_back(c->H.val64);
-    if (c->H.val32) A.ptrs.push_back(c->H.val32);
-  }
-  c->exact32 = exact;
-  c->H0 = c->H;
-  c->H0.n = c->n0;
-  c->H0.panel = nullptr;
-  {
-    // column-panel copy for the block products with H
-    int pw = o.panel_width;
-    if (pw < 0) {
-      const int64_t xbytes = c->n * (int64_t)k * 8;
-      pw = 0;
-      if (xbytes > ((int64_t)8 << 20) && c->n < ((int64_t)1 << 24)) {
-        int64_t w = ((int64_t)1 << 20) / ((int64_t)k * 8);  // 1 MiB of float64 X per panel
-        int64_t p2 = 1024;
-        while (p2 * 2 <= w && p2 * 2 <= 65536) p2 *= 2;
-        pw = (int)p2;
-      }
-    }
-    if (pw > 0) {
-      build_panel(c->H, pw, c->panel, s);
-      for (void* q : {(void*)c->panel.bstart, (void*)c->panel.bcount, (void*)c->panel.ent, (void*)c->panel.val64,
-                      (void*)c->panel.val32, (void*)c->panel.dg, c->panel.xpad})
-        if (q) A.ptrs.push_back(q);
-      c->H.panel = &c->panel;
-    }
-  }
-  c->H0.rend = A.alloc<int64_t>(c->n0);
-  build_block_view(c->H, c->n0, c->H0.rend, s);
-  {
-    // H0hat as its own contiguous CSR (no gaps where the rows continue beyond column n0)
-    DevCSR v = c->H0;
-    compact_view(v, c->H0, s);
-    A.ptrs.push_back(c->H0.rp);
-    A.ptrs.push_back(c->H0.col);
-    if (c->H0.val64) A.ptrs.push_back(c->H0.val64);
-    if (c->H0.val32) A.ptrs.push_back(c->H0.val32);
-  }
-  c->diag = A.alloc<double>(c->n);
-  extract_diag(c->H, c->diag, s);
-
-  // buffers
+// The arrays of a context that do not depend on what setup finds in H (A: the context's arena, or a
+// counting one).
+void alloc_buffers(sppc_ctx* c, Arena& A) {
+  const sppc_opts& o = c->o;
+  const int k = c->k;
   const int64_t n = c->n;
   const int mm = o.m_max;
-  c->B.n = n;
-  c->B.ldq = mm;
+  const int last_p = (o.p_switch > 0) ? std::min(o.p_switch, o.maxiter) : o.maxiter;
+  const bool mixed = o.precision == SPPC_PREC_MIXED;
   c->B.Q = A.alloc<double>((size_t)n * mm);
   c->B.HQ = A.alloc<double>((size_t)n * mm);
   c->B.T = A.alloc<double>((size_t)mm * mm);
@@ -908,9 +828,145 @@ void setup_impl(sppc_ctx* c, const sppc_csr* Hin, const int64_t* loff, int L, in
   c->cgpart = A.alloc<double>((size_t)cg_work_doubles(n0));
   c->cg_rowb = A.alloc<int64_t>(257);
   c->cshift = A.alloc<double>(KB);
-  cg_prepare(c->H0, n0, c->cg_rowb, c->cgpart, s);
   c->ccoef = A.alloc<double>((size_t)KB * KB);
   c->ctmp = A.alloc<double>((size_t)KB * KB);
+}
+
+// Columns per panel of the column-panel copy of H (0: none): opts.panel_width, or automatically
+// 1 MiB of float64 X per panel when a k-column block of X exceeds 8 MiB and n < 2^24.
+int choose_panel_width(const sppc_opts& o, int64_t n, int k) {
+  int pw = o.panel_width;
+  if (pw < 0) {
+    const int64_t xbytes = n * (int64_t)k * 8;
+    pw = 0;
+    if (xbytes > ((int64_t)8 << 20) && n < ((int64_t)1 << 24)) {
+      int64_t w = ((int64_t)1 << 20) / ((int64_t)k * 8);  // 1 MiB of float64 X per panel
+      int64_t p2 = 1024;
+      while (p2 * 2 <= w && p2 * 2 <= 65536) p2 *= 2;
+      pw = (int)p2;
+    }
+  }
+  return pw;
+}
+
+// Checks the problem and the options and fixes the sizes of the context (no device work).
+void configure(sppc_ctx* c, const sppc_csr* Hin, const int64_t* loff, int L, int nsmall, int k) {
+  if (!Hin || !loff || L < 1 || nsmall < 1 || nsmall > L) throw Error(SPPC_E_ARG, "bad level partition");
+  if (Hin->n < 1 || !Hin->row_ptr_dev || !Hin->col_dev || !Hin->val_dev) throw Error(SPPC_E_ARG, "bad H");
+  if (Hin->n >= (int64_t)1 << 31) throw Error(SPPC_E_ARG, "n must be < 2^31");
+  c->loff.assign(loff, loff + L + 1);
+  if (c->loff[0] != 0 || c->loff[L] != Hin->n) throw Error(SPPC_E_ARG, "level offsets must run 0..n");
+  for (int l = 0; l < L; ++l)
+    if (c->loff[l + 1] <= c->loff[l]) throw Error(SPPC_E_ARG, "levels must be non-empty and ascending");
+  c->n = Hin->n;
+  c->nnz_up = Hin->nnz;
+  c->n0 = c->loff[nsmall];
+  c->nsmall = nsmall;
+  c->k = k;
+  sppc_opts& o = c->o;
+  if (k < 1 || k > 16 || k > c->n0) throw Error(SPPC_E_ARG, "k must be 1..16 and <= n0");
+  const int pj = o.pair_index;
+  if (pj < -1 || pj > 26 || (pj >= 0 && (k != 1 || pj >= c->n0)))
+    throw Error(SPPC_E_ARG, "pair_index must be -1, or 0..26 (below n0) with k = 1 (Alg. 1)");
+  if (o.n_deflate <= 0) o.n_deflate = std::min<int64_t>(std::min(std::max(2 * k, pj + 2), 28), c->n0);
+  if (o.n_deflate < k || o.n_deflate > 28 || o.n_deflate > c->n0) throw Error(SPPC_E_ARG, "n_deflate must be in [k, min(28, n0)]");
+  if (pj >= o.n_deflate) throw Error(SPPC_E_ARG, "n_deflate must exceed pair_index");
+  c->D = o.n_deflate;
+  if (o.m_max < 2 * k || o.m_max > 512) throw Error(SPPC_E_ARG, "m_max must be in [2k, 512]");
+  if (o.panel_width < -1 || o.panel_width > 65536) throw Error(SPPC_E_ARG, "panel_width must be -1, 0 or 1..65536");
+  if (o.precond != SPPC_CORR_JACOBI && o.precond != SPPC_CORR_MPNN && o.precond != SPPC_CORR_SMALL &&
+      o.precond != SPPC_CORR_RMMDIIS)
+    throw Error(SPPC_E_ARG, "continuation must be JACOBI, MPNN, SMALL or RMMDIIS");
+  if (o.corr_shift != SPPC_SHIFT_E0 && o.corr_shift != SPPC_SHIFT_RITZ)
+    throw Error(SPPC_E_ARG, "corr_shift must be SPPC_SHIFT_E0 or SPPC_SHIFT_RITZ");
+  if (o.rmm_precond != SPPC_CORR_JACOBI && o.rmm_precond != SPPC_CORR_MPNN)
+    throw Error(SPPC_E_ARG, "the RMM-DIIS step preconditioner must be JACOBI or MPNN");
+  if (o.refine_precond != SPPC_CORR_JACOBI && o.refine_precond != SPPC_CORR_MPNN &&
+      o.refine_precond != SPPC_CORR_SMALL)
+    throw Error(SPPC_E_ARG, "refinement preconditioner must be JACOBI, MPNN or SMALL");
+  if (!(o.precond_tol > 0.0) || o.precond_tol >= 1.0) throw Error(SPPC_E_ARG, "precond_tol must be in (0, 1)");
+  if (!(o.tol > 0) || !(o.tau_drop >= 0) || !(o.inner_tol >= 0) || !(o.h0_tol > 0)) throw Error(SPPC_E_ARG, "bad tolerances");
+  if (o.precision != SPPC_PREC_FP64 && o.precision != SPPC_PREC_MIXED) throw Error(SPPC_E_ARG, "bad precision");
+  if (o.auto_switch != 0 && o.auto_switch != 1) throw Error(SPPC_E_ARG, "auto_switch must be 0 or 1");
+  const int last_p = (o.p_switch > 0) ? std::min(o.p_switch, o.maxiter) : o.maxiter;
+  if (last_p < 0) throw Error(SPPC_E_ARG, "maxiter must be >= 0");
+  if ((int64_t)k * (last_p + 1) > o.m_max) throw Error(SPPC_E_ARG, "m_max < k * (perturbation order + 1)");
+}
+
+void setup_impl(sppc_ctx* c, const sppc_csr* Hin, const int64_t* loff, int L, int nsmall, int k) {
+  configure(c, Hin, loff, L, nsmall, k);
+  sppc_opts& o = c->o;
+  const int pj = o.pair_index;
+  hipStream_t s = c->s;
+  const bool mixed = o.precision == SPPC_PREC_MIXED;
+  // device address of the static scratch of the allocation-free block product (once per device)
+  (void)noalloc_scratch(nullptr);
+
+  // device format of H
+  Arena& A = c->arena;
+  int* dflags = A.alloc<int>(4);
+  bool exact = false;
+  // first pass decides which value arrays are stored: float32 alone when lossless
+  {
+    const bool in32 = Hin->val_type == SPPC_F32;
+    // validation + exactness happen inside; request float64 storage unless exact
+    DevCSR tmp;
+    build_full_csr(c->n, Hin->nnz, Hin->row_ptr_dev, Hin->col_dev, Hin->val_dev, in32 ? 1 : 0, tmp, dflags,
+                   /*want64=*/false, /*want32=*/true, exact, s);
+    if (exact) {
+      c->H = tmp;
+    } else {
+      dev_free(tmp.val32);
+      tmp.val32 = nullptr;
+      dev_free(tmp.rp);
+      dev_free(tmp.col);
+      DevCSR t2;
+      build_full_csr(c->n, Hin->nnz, Hin->row_ptr_dev, Hin->col_dev, Hin->val_dev, 0, t2, dflags, true, mixed,
+                     exact, s);
+      c->H = t2;
+    }
+    A.ptrs.push_back(c->H.rp);
+    A.ptrs.push_back(c->H.col);
+    if (c->H.val64) A.ptrs.push_back(c->H.val64);
+    if (c->H.val32) A.ptrs.push_back(c->H.val32);
+  }
+  c->exact32 = exact;
+  c->H0 = c->H;
+  c->H0.n = c->n0;
+  c->H0.panel = nullptr;
+  {
+    // column-panel copy for the block products with H
+    const int pw = choose_panel_width(o, c->n, k);
+    if (pw > 0) {
+      build_panel(c->H, pw, c->panel, s);
+      for (void* q : {(void*)c->panel.bstart, (void*)c->panel.bcount, (void*)c->panel.ent, (void*)c->panel.val64,
+                      (void*)c->panel.val32, (void*)c->panel.dg, c->panel.xpad})
+        if (q) A.ptrs.push_back(q);
+      c->H.panel = &c->panel;
+    }
+  }
+  c->H0.rend = A.alloc<int64_t>(c->n0);
+  build_block_view(c->H, c->n0, c->H0.rend, s);
+  {
+    // H0hat as its own contiguous CSR (no gaps where the rows continue beyond column n0)
+    DevCSR v = c->H0;
+    compact_view(v, c->H0, s);
+    A.ptrs.push_back(c->H0.rp);
+    A.ptrs.push_back(c->H0.col);
+    if (c->H0.val64) A.ptrs.push_back(c->H0.val64);
+    if (c->H0.val32) A.ptrs.push_back(c->H0.val32);
+  }
+  c->diag = A.alloc<double>(c->n);
+  extract_diag(c->H, c->diag, s);
+
+  // buffers
+  const int64_t n = c->n;
+  const int mm = o.m_max;
+  c->B.n = n;
+  c->B.ldq = mm;
+  alloc_buffers(c, A);
+  const int64_t n0 = c->n0;
+  cg_prepare(c->H0, n0, c->cg_rowb, c->cgpart, s);
   SPPC_HIP(pinned_alloc((void**)&c->pin, sizeof(double) * 4 * NWMAX));
   SPPC_HIP(pinned_alloc((void**)&c->pin_i, sizeof(int) * 128));
   c->tm.s = s;
@@ -1026,6 +1082,27 @@ void rmm_learned_step(sppc_ctx* c, const std::vector<int>& act, const std::vecto
   c->st.mpnn_steps += 1;
 }
 
+// The RMM-DIIS arrays (A: the context's arena, or a counting one): RMM_SWEEP + 1 history slots of
+// the iterates, their products with H and their residuals, and the per-iteration blocks.
+void alloc_rmm(sppc_ctx* c, Arena& A) {
+  const int k = c->k;
+  const int D = diis_max_depth();
+  const int NS = std::min(D, RMM_SWEEP + 1);
+  const int64_t slot = c->n * k;
+  c->rd_Xh = A.alloc<double>((size_t)NS * slot);
+  c->rd_HXh = A.alloc<double>((size_t)NS * slot);
+  c->rd_Rh = A.alloc<double>((size_t)NS * slot);
+  c->rd_A = A.alloc<double>((size_t)k * D * D);
+  c->rd_al = A.alloc<double>((size_t)k * D);
+  c->rd_xb = A.alloc<double>((size_t)slot);
+  c->rd_hxb = A.alloc<double>((size_t)slot);
+  c->rd_rb = A.alloc<double>((size_t)slot);
+  c->rd_t = A.alloc<double>((size_t)slot);
+  c->rd_ht = A.alloc<double>((size_t)slot);
+  c->rd_u = A.alloc<double>((size_t)slot);
+  c->rd_sc = A.alloc<double>(8 * 64);
+}
+
 int rmm_diis_sweep(sppc_ctx* c, int cap) {
   hipStream_t s = c->s;
   const int k = c->k;
@@ -1035,22 +1112,8 @@ int rmm_diis_sweep(sppc_ctx* c, int cap) {
   const sppc_opts& o = c->o;
   if (c->nw_last != k) throw Error(SPPC_E_ARG, "no Ritz pairs available");
   if (cap < 0 || cap > RMM_SWEEP) throw Error(SPPC_E_ARG, "RMM-DIIS sweep longer than its history");
-  Arena& Ar = c->arena;
   const int64_t slot = n * k;
-  if (!c->rd_Xh) {
-    c->rd_Xh = Ar.alloc<double>((size_t)NS * slot);
-    c->rd_HXh = Ar.alloc<double>((size_t)NS * slot);
-    c->rd_Rh = Ar.alloc<double>((size_t)NS * slot);
-    c->rd_A = Ar.alloc<double>((size_t)k * D * D);
-    c->rd_al = Ar.alloc<double>((size_t)k * D);
-    c->rd_xb = Ar.alloc<double>((size_t)slot);
-    c->rd_hxb = Ar.alloc<double>((size_t)slot);
-    c->rd_rb = Ar.alloc<double>((size_t)slot);
-    c->rd_t = Ar.alloc<double>((size_t)slot);
-    c->rd_ht = Ar.alloc<double>((size_t)slot);
-    c->rd_u = Ar.alloc<double>((size_t)slot);
-    c->rd_sc = Ar.alloc<double>(8 * 64);
-  }
+  if (!c->rd_Xh) alloc_rmm(c, c->arena);
   double *xb = c->rd_xb, *hxb = c->rd_hxb, *rb = c->rd_rb, *t = c->rd_t, *ht = c->rd_ht, *u = c->rd_u;
   double *ss = c->rd_sc, *th = ss + 64, *ssr = ss + 128, *uu = ss + 192, *rd = ss + 256, *g = ss + 320;
   double *th2 = ss + 384, *ss2 = ss + 448;
@@ -1267,6 +1330,7 @@ sppc_status solve_impl(sppc_ctx* c, double* evals, double* evecs, double* rrn, s
   c->st.converged = conv;
   c->st.mpnn_fallbacks = 0;
   for (int f : c->mp_fallback) c->st.mpnn_fallbacks += f ? 1 : 0;
+  c->st.workspace_peak = (int64_t)ws_peak(c->ws);
   c->st.basis_size = c->B.m;
   const int k = c->k;
   if (evals) memcpy(evals, c->theta_h.data(), sizeof(double) * k);
@@ -1285,8 +1349,70 @@ sppc_status solve_impl(sppc_ctx* c, double* evals, double* evecs, double* rrn, s
   return conv ? SPPC_OK : SPPC_E_NOCONV;
 }
 
+// Workspace bytes of a context for sppc_setup followed by sppc_solve with its options: the arrays it
+// keeps plus the largest set of setup temporaries alive at one time, phase by phase as setup_impl
+// allocates them (the builders' sizes from the same expressions as their allocations, the other
+// arrays by a counting run of the same allocation code).  For float64 input both outcomes of the
+// float32-exactness check are covered.  The training entry points' basis projection is not.
+size_t workspace_bytes(sppc_ctx* c, const sppc_csr* Hin) {
+  const sppc_opts& o = c->o;
+  const int k = c->k;
+  const int64_t n = c->n, n0 = c->n0;
+  const bool mixed = o.precision == SPPC_PREC_MIXED;
+  const bool in32 = Hin->val_type == SPPC_F32;
+  int64_t up0 = 0;  // upper entries of the rows of the small space (bounds H0hat's entries)
+  SPPC_HIP(hipMemcpy(&up0, Hin->row_ptr_dev + n0, sizeof(int64_t), hipMemcpyDeviceToHost));
+  const int64_t nnz_full = 2 * Hin->nnz, nnz0 = 2 * up0;
+  size_t best = 0;
+  for (int exact = in32 ? 1 : 0; exact < 2; ++exact) {
+    size_t base = ws_bytes(sizeof(int) * 4), peak = 0;
+    const BuildBytes f1 = full_csr_bytes(n, Hin->nnz, false, true);
+    peak = std::max(peak, base + f1.persist + f1.temp);
+    size_t csr = f1.persist;
+    bool v64 = false, v32 = true;
+    if (!exact) {  // the float32 copy is dropped and the CSR built again with float64 values
+      const BuildBytes f2 = full_csr_bytes(n, Hin->nnz, true, mixed);
+      peak = std::max(peak, base + f2.persist + f2.temp);
+      csr = f2.persist;
+      v64 = true;
+      v32 = mixed;
+    }
+    base += csr;
+    if (choose_panel_width(o, n, k) > 0) {
+      const BuildBytes pb = panel_bytes(n, nnz_full, v64, v32);
+      peak = std::max(peak, base + pb.persist + pb.temp);
+      base += pb.persist;
+    }
+    base += ws_bytes(sizeof(int64_t) * n0);  // row ends of the H0hat view
+    const BuildBytes vb = view_bytes(n0, nnz0, v64, v32);
+    peak = std::max(peak, base + vb.persist + vb.temp);
+    base += vb.persist + ws_bytes(sizeof(double) * n);  // + diag(H)
+    Arena cnt;
+    cnt.counting = true;
+    alloc_buffers(c, cnt);
+    base += cnt.counted;
+    const int64_t nb = std::min<int64_t>(n0, KB);  // the zeroth order's temporaries
+    peak = std::max(peak, base + 2 * ws_bytes(8 * n0 * nb) + ws_bytes(8 * nb * nb) + ws_bytes(8 * n0) +
+                              ws_bytes(8 * (n0 + 1)));
+    Arena sv;  // arrays the solve adds
+    sv.counting = true;
+    size_t sv_tmp = 0;
+    if (o.precond == SPPC_CORR_RMMDIIS && o.p_switch > 0) alloc_rmm(c, sv);
+    if (o.precond == SPPC_CORR_MPNN || o.refine_precond == SPPC_CORR_MPNN ||
+        (o.precond == SPPC_CORR_RMMDIIS && o.rmm_precond == SPPC_CORR_MPNN)) {
+      alloc_mpnn_static(c, sv);
+      alloc_mpnn_samples(c, sv, k);
+      sv_tmp = ws_bytes(sizeof(double) * 6 * n);
+    }
+    peak = std::max(peak, base + sv.counted + sv_tmp);
+    best = std::max(best, peak);
+  }
+  return best + 4096;  // the start of the workspace is rounded up to 256 bytes
+}
+
 template <class F>
 sppc_status guarded(sppc_ctx* c, F&& f) {
+  WsScope scope(c ? c->ws : nullptr);
   try {
     return f();
   } catch (const Error& e) {
@@ -1329,14 +1455,35 @@ sppc_status sppc_default_opts(sppc_opts* o) {
   return SPPC_OK;
 }
 
+sppc_status sppc_workspace_size(const sppc_csr* H, const int64_t* level_offsets_host, int n_levels,
+                                int n_small_levels, int k, const sppc_opts* opts, size_t* bytes) {
+  if (!bytes) return SPPC_E_ARG;
+  *bytes = 0;
+  sppc_ctx c;
+  if (opts) c.o = *opts; else sppc_default_opts(&c.o);
+  const sppc_status st = guarded(&c, [&]() {
+    configure(&c, H, level_offsets_host, n_levels, n_small_levels, k);
+    *bytes = workspace_bytes(&c, H);
+    return SPPC_OK;
+  });
+  if (st != SPPC_OK) g_setup_err = c.err;
+  return st;
+}
+
 sppc_status sppc_setup(sppc_ctx** out, const sppc_csr* H, const int64_t* level_offsets_host, int n_levels,
-                       int n_small_levels, int k, const sppc_opts* opts, void* stream) {
+                       int n_small_levels, int k, const sppc_opts* opts, void* workspace_dev,
+                       size_t workspace_bytes, void* stream) {
   if (!out) return SPPC_E_ARG;
   *out = nullptr;
+  if (workspace_dev && workspace_bytes < 4096) {
+    g_setup_err = "workspace smaller than 4096 bytes";
+    return SPPC_E_ARG;
+  }
   sppc_ctx* c = new (std::nothrow) sppc_ctx();
   if (!c) return SPPC_E_NOMEM;
   if (opts) c->o = *opts; else sppc_default_opts(&c->o);
   c->s = (hipStream_t)stream;
+  if (workspace_dev) c->ws = ws_create(workspace_dev, workspace_bytes);
   const auto t0 = std::chrono::steady_clock::now();
   sppc_status st = guarded(c, [&]() {
     setup_impl(c, H, level_offsets_host, n_levels, n_small_levels, k);
@@ -1348,6 +1495,7 @@ sppc_status sppc_setup(sppc_ctx** out, const sppc_csr* H, const int64_t* level_o
     return st;
   }
   c->st.t_setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  c->st.workspace_peak = (int64_t)ws_peak(c->ws);
   *out = c;
   return SPPC_OK;
 }
@@ -1543,8 +1691,13 @@ void sppc_destroy(sppc_ctx* c) {
   if (c->s) (void)hipStreamSynchronize(c->s); else (void)hipDeviceSynchronize();
   pinned_free(c->pin);
   pinned_free(c->pin_i);
-  c->arena.release();
-  delete c;
+  Workspace* ws = c->ws;
+  {
+    WsScope scope(ws);  // arrays in the caller's workspace go back to it, the others to the library
+    c->arena.release();
+    delete c;
+  }
+  ws_destroy(ws);
 }
 
 }  // extern "C"

@@ -972,9 +972,9 @@ void build_full_csr(int64_t n, int64_t nnz_up, const int64_t* up_rp, const int32
     for (int i = 0; i < 2; ++i) { dev_free(key[i]); dev_free(rowi[i]); dev_free(v[i]); }
   };
   try {
-    SPPC_HIP(dev_malloc(&su_cnt, sizeof(int32_t) * (n + 1)));
-    SPPC_HIP(dev_malloc(&su_off, sizeof(int64_t) * (n + 1)));
-    SPPC_HIP(dev_malloc(&lower_rp, sizeof(int64_t) * (n + 1)));
+    SPPC_HIP(dev_malloc_tmp(&su_cnt, sizeof(int32_t) * (n + 1)));
+    SPPC_HIP(dev_malloc_tmp(&su_off, sizeof(int64_t) * (n + 1)));
+    SPPC_HIP(dev_malloc_tmp(&lower_rp, sizeof(int64_t) * (n + 1)));
     SPPC_HIP(hipMemsetAsync(d_flags, 0, sizeof(int) * 4, s));
     const int64_t grid_w = cdiv(n, 4);
     if (val_is_f32)
@@ -988,7 +988,7 @@ void build_full_csr(int64_t n, int64_t nnz_up, const int64_t* up_rp, const int32
     if (h_flags[0]) throw Error(1, "H: upper CSR expected (columns >= row, < n, strictly ascending)");
     if (h_flags[2]) throw Error(7, "H: NaN or Inf among the values");
     exact32 = val_is_f32 || !h_flags[1];
-    SPPC_HIP(dev_malloc(&bsum, sizeof(int64_t) * (cdiv(n, SCAN_BLOCK) + 1)));
+    SPPC_HIP(dev_malloc_tmp(&bsum, sizeof(int64_t) * (cdiv(n, SCAN_BLOCK) + 1)));
     scan_exclusive_impl(n, su_cnt, su_off, bsum, s);
     int64_t m = 0;  // strict-upper entries = mirrored entries
     SPPC_HIP(hipMemcpyAsync(&m, su_off + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
@@ -1004,16 +1004,16 @@ void build_full_csr(int64_t n, int64_t nnz_up, const int64_t* up_rp, const int32
     const int64_t ms = m > 0 ? m : 1;
     const size_t vb = want64 ? sizeof(double) : sizeof(float);
     for (int i = 0; i < 2; ++i) {
-      SPPC_HIP(dev_malloc(&key[i], sizeof(int32_t) * ms));
-      SPPC_HIP(dev_malloc(&rowi[i], sizeof(int32_t) * ms));
-      SPPC_HIP(dev_alloc(&v[i], vb * ms));
+      SPPC_HIP(dev_malloc_tmp(&key[i], sizeof(int32_t) * ms));
+      SPPC_HIP(dev_malloc_tmp(&rowi[i], sizeof(int32_t) * ms));
+      SPPC_HIP(dev_alloc_tmp(&v[i], vb * ms));
     }
     const int64_t ncnt = (cdiv(ms, RS_TILE) << 8) + 1;
-    SPPC_HIP(dev_malloc(&cnt, sizeof(int32_t) * ncnt));
-    SPPC_HIP(dev_malloc(&off, sizeof(int64_t) * (ncnt + 1)));
+    SPPC_HIP(dev_malloc_tmp(&cnt, sizeof(int32_t) * ncnt));
+    SPPC_HIP(dev_malloc_tmp(&off, sizeof(int64_t) * (ncnt + 1)));
     dev_free(bsum);
     bsum = nullptr;
-    SPPC_HIP(dev_malloc(&bsum, sizeof(int64_t) * (cdiv(std::max(ncnt, n + 1), SCAN_BLOCK) + 1)));
+    SPPC_HIP(dev_malloc_tmp(&bsum, sizeof(int64_t) * (cdiv(std::max(ncnt, n + 1), SCAN_BLOCK) + 1)));
     if (want64) {
       double* vv[2] = {(double*)v[0], (double*)v[1]};
       if (val_is_f32)
@@ -1055,8 +1055,8 @@ void compact_view(const DevCSR& V, DevCSR& out, hipStream_t s) {
   try {
     out = DevCSR{};
     out.n = n0;
-    SPPC_HIP(dev_malloc(&cnt, sizeof(int32_t) * (n0 + 1)));
-    SPPC_HIP(dev_malloc(&bsum, sizeof(int64_t) * (cdiv(n0 + 1, SCAN_BLOCK) + 1)));
+    SPPC_HIP(dev_malloc_tmp(&cnt, sizeof(int32_t) * (n0 + 1)));
+    SPPC_HIP(dev_malloc_tmp(&bsum, sizeof(int64_t) * (cdiv(n0 + 1, SCAN_BLOCK) + 1)));
     SPPC_HIP(dev_malloc(&out.rp, sizeof(int64_t) * (n0 + 1)));
     k_view_count<<<cdiv(n0 > 0 ? n0 : 1, 256), 256, 0, s>>>(n0, V.rp, V.rend, cnt);
     SPPC_LAUNCH_CHECK();
@@ -1102,14 +1102,14 @@ void build_panel(const DevCSR& H, int PW, PanelH& out, hipStream_t s) {
   auto cleanup = [&]() { (void)dev_free(padded); (void)dev_free(bsum); (void)dev_free(flags); };
   try {
     const int nb = out.nblocks;
-    SPPC_HIP(dev_malloc(&padded, sizeof(int32_t) * nb));
-    SPPC_HIP(dev_malloc(&bsum, sizeof(int64_t) * (cdiv(nb, SCAN_BLOCK) + 1)));
+    SPPC_HIP(dev_malloc_tmp(&padded, sizeof(int32_t) * nb));
+    SPPC_HIP(dev_malloc_tmp(&bsum, sizeof(int64_t) * (cdiv(nb, SCAN_BLOCK) + 1)));
     SPPC_HIP(dev_malloc(&out.bcount, sizeof(int32_t) * nb));
     SPPC_HIP(dev_malloc(&out.bstart, sizeof(int64_t) * (nb + 1)));
     SPPC_HIP(dev_malloc(&out.dg, sizeof(double) * n));
     SPPC_HIP(dev_malloc(&out.xpad, sizeof(double) * 16 * n));
     SPPC_HIP(hipMemsetAsync(out.dg, 0, sizeof(double) * n, s));
-    SPPC_HIP(dev_malloc(&flags, sizeof(int)));
+    SPPC_HIP(dev_malloc_tmp(&flags, sizeof(int)));
     SPPC_HIP(hipMemsetAsync(flags, 0, sizeof(int), s));
     k_panel_bcount<<<nb, 256, 0, s>>>(n, H.rp, H.col, out.bcount, padded, flags);
     scan_exclusive_impl(nb, padded, out.bstart, bsum, s);
@@ -1190,6 +1190,41 @@ void spmm_f32(const DevCSR& H, const float* X, int64_t ldx, double* Y, int64_t l
     return;
   }
   launch_spmm<float, float>(H, H.val32, X, ldx, Y, ldy, b, shift, s, 0.0, 0.0, 0.0, nullptr, 0, diag, X64, ldx64);
+}
+
+// ---------------------------------------------------------------- workspace sizes
+// Bytes the builders above take from a workspace (each array rounded up to 256 bytes), from the same
+// expressions as their allocations.  nnz_up bounds the strict-upper entries.
+BuildBytes full_csr_bytes(int64_t n, int64_t nnz_up, bool want64, bool want32) {
+  BuildBytes b;
+  const int64_t m = std::max<int64_t>(nnz_up, 1);
+  const int64_t nnz = std::max<int64_t>(nnz_up + m, 1);
+  b.persist = ws_bytes(8 * (n + 1)) + ws_bytes(4 * nnz) + (want64 ? ws_bytes(8 * nnz) : 0) +
+              (want32 ? ws_bytes(4 * nnz) : 0);
+  const int64_t vb = want64 ? 8 : 4;
+  const int64_t ncnt = (cdiv(m, RS_TILE) << 8) + 1;
+  b.temp = ws_bytes(4 * (n + 1)) + 2 * ws_bytes(8 * (n + 1)) + ws_bytes(8 * (cdiv(n, SCAN_BLOCK) + 1)) +
+           2 * (2 * ws_bytes(4 * m) + ws_bytes(vb * m)) + ws_bytes(4 * ncnt) + ws_bytes(8 * (ncnt + 1)) +
+           ws_bytes(8 * (cdiv(std::max(ncnt, n + 1), SCAN_BLOCK) + 1));
+  return b;
+}
+
+BuildBytes panel_bytes(int64_t n, int64_t nnz_full, bool v64, bool v32) {
+  BuildBytes b;
+  const int64_t nb = cdiv(n, PANEL_RB);
+  const int64_t cap = std::max<int64_t>(nnz_full + 7 * nb, 8);
+  b.persist = ws_bytes(4 * nb) + ws_bytes(8 * (nb + 1)) + ws_bytes(8 * n) + ws_bytes(8 * 16 * n) + ws_bytes(4 * cap) +
+              (v64 ? ws_bytes(8 * cap) : 0) + (v32 ? ws_bytes(4 * cap) : 0);
+  b.temp = ws_bytes(4 * nb) + ws_bytes(8 * (cdiv(nb, SCAN_BLOCK) + 1)) + ws_bytes(4);
+  return b;
+}
+
+BuildBytes view_bytes(int64_t n0, int64_t nnz0, bool v64, bool v32) {
+  BuildBytes b;
+  const int64_t z = std::max<int64_t>(nnz0, 1);
+  b.persist = ws_bytes(8 * (n0 + 1)) + ws_bytes(4 * z) + (v64 ? ws_bytes(8 * z) : 0) + (v32 ? ws_bytes(4 * z) : 0);
+  b.temp = ws_bytes(4 * (n0 + 1)) + ws_bytes(8 * (cdiv(n0 + 1, SCAN_BLOCK) + 1));
+  return b;
 }
 
 // ---------------------------------------------------------------- allocation-free staging

@@ -1,16 +1,17 @@
 // memory.hip - device and pinned host memory of the library.
 //
-// Every device buffer of the library (context arrays, setup temporaries) comes from a
-// process-wide cache.  A freed block stays mapped and goes back to the next request of the same
-// rounded size on the same device, so repeated setups of one problem size call hipMalloc and
-// hipFree only the first time.  Both calls stall the host (hipFree also waits for the whole
-// device), and a block of recently freed VRAM is cleared by the driver before hipMalloc returns
-// it, which costs about a second per 100 GB.
-//
-// Reuse is ordered by the callers: a block goes back to the cache only after the stream that
-// last used it has been synchronised.  The cache holds at most 3/4 of the device's memory; a
-// block beyond that is freed at once, and a hipMalloc that runs out of memory empties the cache
-// of its device and tries once more.  sppc_release_cached_memory() empties it on demand.
+// Device memory comes from one of two places:
+//   * a caller's workspace (sppc_setup with a workspace): every device array of the context, its
+//     setup temporaries included, is carved from that block.  Persistent arrays grow from its
+//     bottom and setup temporaries from its top; a freed block is returned when it is the last one
+//     of its end (freed blocks below it are returned with it), so the bytes sppc_workspace_size
+//     adds up (the persistent arrays plus the largest set of temporaries alive at once) suffice.
+//   * the library itself: hipMalloc on request and hipFree when the array is given back.  An
+//     optional process-wide cache (sppc_set_memory_cache) keeps freed blocks for the next request
+//     of the same rounded size on the same device instead: hipMalloc/hipFree stall the host
+//     (hipFree also waits for the whole device) and recently freed VRAM is cleared by the driver
+//     before it is handed out again.  The cache is off unless enabled; a block goes back to it
+//     only after the stream that last used it has been synchronised.
 #include "common.h"
 
 #include <map>
@@ -34,6 +35,7 @@ std::unordered_map<void*, Block> g_live;                        // handed out
 std::multimap<std::tuple<int, bool, size_t>, void*> g_cache;   // (device, host, size) -> block
 std::map<int, size_t> g_cached;  // cached bytes per device
 std::map<int, size_t> g_cap;  // per device
+size_t g_cache_limit = 0;     // bytes per device the cache may keep (0: no cache)
 
 size_t rounded(size_t bytes) {
   const size_t g = bytes >= ((size_t)1 << 20) ? ((size_t)2 << 20) : (size_t)512;
@@ -41,14 +43,15 @@ size_t rounded(size_t bytes) {
 }
 
 size_t cap_of(int dev) {  // called with g_mu held and dev current on the first call
+  if (g_cache_limit == 0) return 0;
   auto it = g_cap.find(dev);
-  if (it != g_cap.end()) return it->second;
+  if (it != g_cap.end()) return std::min(it->second, g_cache_limit);
   size_t fr = 0, tot = 0;
   if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
     (void)hipGetLastError();
     tot = 0;
   }
-  return g_cap[dev] = tot / 4 * 3;
+  return std::min(g_cap[dev] = tot / 4 * 3, g_cache_limit);
 }
 
 void release_raw(void* p, bool host) {
@@ -132,8 +135,89 @@ void give_back(void* p) {
 
 }  // namespace
 
-hipError_t dev_alloc(void** p, size_t bytes) { return take(p, bytes, false); }
-void dev_free(void* p) { give_back(p); }
+// ---------------------------------------------------------------- caller workspace
+struct Workspace {
+  struct Blk {
+    size_t off, size;
+    bool freed;
+  };
+  char* base = nullptr;
+  size_t size = 0;
+  size_t lo = 0;    // bottom end in use: [0, lo)
+  size_t hi = 0;    // top end in use: [hi, size)
+  size_t peak = 0;  // largest lo + (size - hi) seen
+  std::vector<Blk> bottom, top;
+
+  static size_t al(size_t b) { return (std::max<size_t>(b, 1) + 255) / 256 * 256; }
+  void* alloc(size_t bytes, bool temp) {
+    const size_t b = al(bytes);
+    if (b > hi - lo) return nullptr;
+    size_t off;
+    if (temp) {
+      hi -= b;
+      off = hi;
+      top.push_back({off, b, false});
+    } else {
+      off = lo;
+      lo += b;
+      bottom.push_back({off, b, false});
+    }
+    peak = std::max(peak, lo + (size - hi));
+    return base + off;
+  }
+  bool owns(const void* p) const { return p >= (const void*)base && p < (const void*)(base + size); }
+  void release(void* p) {
+    const size_t off = (size_t)((char*)p - base);
+    for (auto* v : {&bottom, &top})
+      for (auto& bk : *v)
+        if (bk.off == off && !bk.freed) {
+          bk.freed = true;
+          while (!bottom.empty() && bottom.back().freed) {
+            lo = bottom.back().off;
+            bottom.pop_back();
+          }
+          while (!top.empty() && top.back().freed) {
+            hi = top.back().off + top.back().size;
+            top.pop_back();
+          }
+          return;
+        }
+  }
+};
+
+namespace {
+thread_local Workspace* t_ws = nullptr;  // the workspace of the context an entry point works on
+}
+
+Workspace* ws_create(void* base, size_t bytes) {
+  Workspace* w = new Workspace();
+  const uintptr_t a = ((uintptr_t)base + 255) & ~(uintptr_t)255;  // 256-byte aligned start
+  w->base = (char*)a;
+  w->size = bytes > (size_t)(a - (uintptr_t)base) ? (bytes - (size_t)(a - (uintptr_t)base)) / 256 * 256 : 0;
+  w->lo = 0;
+  w->hi = w->size;
+  return w;
+}
+void ws_destroy(Workspace* w) { delete w; }
+size_t ws_peak(const Workspace* w) { return w ? w->peak : 0; }
+WsScope::WsScope(Workspace* w) : prev(t_ws) { t_ws = w; }
+WsScope::~WsScope() { t_ws = prev; }
+
+static hipError_t ws_take(void** p, size_t bytes, bool temp) {
+  *p = t_ws->alloc(bytes, temp);
+  return *p ? hipSuccess : hipErrorOutOfMemory;
+}
+
+hipError_t dev_alloc(void** p, size_t bytes) { return t_ws ? ws_take(p, bytes, false) : take(p, bytes, false); }
+hipError_t dev_alloc_tmp(void** p, size_t bytes) { return t_ws ? ws_take(p, bytes, true) : take(p, bytes, false); }
+void dev_free(void* p) {
+  if (!p) return;
+  if (t_ws && t_ws->owns(p)) {
+    t_ws->release(p);
+    return;
+  }
+  give_back(p);
+}
 hipError_t pinned_alloc(void** p, size_t bytes) { return take(p, bytes, true); }
 void pinned_free(void* p) { give_back(p); }
 size_t release_cached(void) { return trim(-1); }
@@ -141,3 +225,14 @@ size_t release_cached(void) { return trim(-1); }
 }  // namespace sppc
 
 extern "C" size_t sppc_release_cached_memory(void) { return sppc::release_cached(); }
+
+extern "C" size_t sppc_set_memory_cache(size_t bytes_per_device) {
+  size_t prev;
+  {
+    std::lock_guard<std::mutex> lk(sppc::g_mu);
+    prev = sppc::g_cache_limit;
+    sppc::g_cache_limit = bytes_per_device;
+  }
+  if (bytes_per_device == 0) sppc::release_cached();
+  return prev;
+}

@@ -229,11 +229,13 @@ def test_mirror_of_unusual_structures(P, panel):
 
 
 def test_cached_memory_is_reused_and_released(P):
-    # contexts of two sizes interleaved: the cache hands blocks of one size back to the next context
-    # of that size (stale contents must not matter), and releasing the cache keeps live contexts intact
+    # with the (opt-in) cache enabled, contexts of two sizes interleaved: the cache hands blocks of one
+    # size back to the next context of that size (stale contents must not matter), and releasing the
+    # cache keeps live contexts intact; disabling it frees what it holds
     As = [levelgen.generate((20, 90, 300), 14, 4), levelgen.generate((30, 200, 900), 16, 5)]
     ref = [_lam(A, 2) for A in As]
     print("case edge memory cache", flush=True)
+    assert P.sppc_set_memory_cache(1 << 30) == 0   # off by default
     for rep in range(3):
         for i, A in enumerate(As):
             ev, Z, rrn, st, status = _solve(P, A, 1, 2)
@@ -246,6 +248,8 @@ def test_cached_memory_is_reused_and_released(P):
     P.sppc_destroy(ctx)
     assert status == P.SPPC_OK
     assert np.max(np.abs(np.array(ev) - ref[0]) / np.abs(ref[0])) < 1e-10
+    assert P.sppc_set_memory_cache(0) == 1 << 30
+    assert P.sppc_release_cached_memory() == 0
 
 
 def test_bad_shifts_are_refused(P):
