@@ -35,11 +35,12 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 
 # HBM traffic per product with H from FETCH_SIZE / WRITE_SIZE counter runs of this same command,
-# scaled by a plain-copy calibration (profiles/k_spmm_panel_L4-1.17M-k8_mixed_hbm_counters.md).
+# scaled by a plain-copy calibration (profiles/k_spmm_panel_*_hbm_counters.md).
 # Keyed by (workload, mode); valid only while the kernel source has the recorded sha256.
 MEASURED_TRAFFIC = {
-    ("L4-2k/20k/150k/1M-d200-k8", "mixed+rmmdiis"): (7691697735,
-                                                     "65ffad83f54e753d814751fc1c697ece9d5860f59eb780103994cb931f49b35c"),
+    # profiles/k_spmm_panel_L5-7.72M-k16_hbm_counters.md: 13 products with float32 X and 11 with float64 X per solve
+    ("L5-2k/20k/200k/1.5M/6M-d300-k16", "mixed+rmmdiis+mpnn"): (182568552344,
+        "1eb2f3cab72ee86ea8b74707fcb5a95cc4d5319be721b6929e07be30f8653c55"),
 }
 
 
