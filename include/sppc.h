@@ -124,8 +124,8 @@ typedef struct {
   int rmm_precond;     /* step of the RMM-DIIS continuation: SPPC_CORR_JACOBI (the diagonal step,
                           default) or SPPC_CORR_MPNN (the learned correction of the diagonal step,
                           weights from sppc_mpnn_set_weights; a pair falls back to the diagonal step
-                          when its residual did not drop below 0.9x its value at its previous
-                          learned step) */
+                          for good as soon as the iterate a learned step produced has a relative
+                          residual not below 0.9x that of the iterate the step started from) */
 } sppc_opts;
 
 typedef struct {

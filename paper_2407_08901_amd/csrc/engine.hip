@@ -1028,10 +1028,11 @@ constexpr int RMM_SWEEP = 4;
 
 // The learned step of RMM-DIIS: for the listed pairs (unit iterates xb, residuals rb, Rayleigh
 // quotients th_host) the direction tJ (1 + o) of the network replaces the diagonal step tJ already
-// in t.  The true residual judges it: a pair whose residual did not fall below 0.9x its value at its
-// previous learned step, or whose learned direction is not finite, keeps the diagonal step from then on.
-void rmm_learned_step(sppc_ctx* c, const std::vector<int>& act, const std::vector<double>& rrn_now,
-                      const double* th_host, const double* rb, const double* xb, double* t) {
+// in t.  Returns the pairs that took it (their rrn before the step in mp_prev_rrn): the caller judges
+// each by the true residual of the iterate the step produced.  A pair whose learned direction is not
+// finite keeps the diagonal step from then on.
+std::vector<int> rmm_learned_step(sppc_ctx* c, const std::vector<int>& act, const std::vector<double>& rrn_now,
+                                  const double* th_host, const double* rb, const double* xb, double* t) {
   hipStream_t s = c->s;
   const int k = c->k;
   const int64_t n = c->n;
@@ -1039,12 +1040,10 @@ void rmm_learned_step(sppc_ctx* c, const std::vector<int>& act, const std::vecto
     c->mp_fallback.assign(k, 0);
     c->mp_prev_rrn.assign(k, 0.0);
   }
-  std::vector<int> sel;
-  for (int a : act) {
-    if (c->mp_prev_rrn[a] > 0.0 && !(rrn_now[a] < 0.9 * c->mp_prev_rrn[a])) c->mp_fallback[a] = 1;
+  std::vector<int> sel, used;
+  for (int a : act)
     if (!c->mp_fallback[a]) sel.push_back(a);
-  }
-  if (sel.empty()) return;
+  if (sel.empty()) return used;
   const int S = (int)sel.size();
   mpnn_ensure(c, S);
   for (int a = 0; a < S; ++a) c->pin_i[8 + a] = sel[a];
@@ -1068,6 +1067,7 @@ void rmm_learned_step(sppc_ctx* c, const std::vector<int>& act, const std::vecto
     if (std::isfinite(nn) && nn > 0.0) {
       c->pin_i[8 + a] = sel[a];
       c->mp_prev_rrn[sel[a]] = rrn_now[sel[a]];
+      used.push_back(sel[a]);
     } else {
       c->pin_i[8 + a] = -1;
       c->mp_fallback[sel[a]] = 1;
@@ -1080,6 +1080,7 @@ void rmm_learned_step(sppc_ctx* c, const std::vector<int>& act, const std::vecto
   SPPC_HIP(hipMemcpyAsync(c->idx, c->pin_i + 8, sizeof(int) * k, hipMemcpyHostToDevice, s));
   sync(c);
   c->st.mpnn_steps += 1;
+  return used;
 }
 
 // The RMM-DIIS arrays (A: the context's arena, or a counting one): RMM_SWEEP + 1 history slots of
@@ -1166,12 +1167,13 @@ int rmm_diis_sweep(sppc_ctx* c, int cap) {
     t0 = c->tm.begin(C_SMALL);
     jacobi_block(n, k, c->idx, rb, k, c->diag, th, t, k, s);
     c->tm.end(t0);
+    std::vector<int> took;  // pairs whose step this iteration was the learned one
     if (learned) {
       std::vector<int> act;
       for (int a = 0; a < k; ++a)
         if (!done[a]) act.push_back(a);
       t0 = c->tm.begin(C_SMALL);
-      rmm_learned_step(c, act, rrn_now, th_now.data(), rb, xb, t);
+      took = rmm_learned_step(c, act, rrn_now, th_now.data(), rb, xb, t);
       c->tm.end(t0);
     }
     op(t, k, ht, k, k, s);
@@ -1192,6 +1194,17 @@ int rmm_diis_sweep(sppc_ctx* c, int cap) {
     columns_to_unit(n, k, ss2, Xn, HXn, s);
     coldots(n, k, Xn, k, HXn, k, th2, c->work, s);
     residual_block(n, k, Xn, k, HXn, k, th2, Rn, k, g, c->work, s);
+    if (!took.empty()) {
+      // the true residual judges the learned step at once: a pair whose new iterate's residual is not
+      // below 0.9x that of the iterate it started from takes the diagonal step from now on
+      SPPC_HIP(hipMemcpyAsync(c->pin, th2, sizeof(double) * k, hipMemcpyDeviceToHost, s));
+      SPPC_HIP(hipMemcpyAsync(c->pin + NWMAX, g, sizeof(double) * k, hipMemcpyDeviceToHost, s));
+      sync(c);
+      for (int a : took) {
+        const double r = std::sqrt(std::max(0.0, c->pin[NWMAX + a])) / std::max(std::fabs(c->pin[a]), 1e-300);
+        if (!(r < 0.9 * c->mp_prev_rrn[a])) c->mp_fallback[a] = 1;
+      }
+    }
     gram_set(k, D, dst, dst, g, c->rd_A, s);
     for (int l = 0; l < dst; ++l) {
       coldots(n, k, Rn, k, Rh + l * slot, k, g, c->work, s);
