@@ -72,8 +72,9 @@ typedef enum {
                                  exact deflated terms) and (diag(H) - theta_i)^-1 on the other rows */
   SPPC_CORR_RMMDIIS = 4       /* continuation of the SPPC + RMM-DIIS hybrid (Sec. V-VI): after the
                                  perturbative steps every unconverged Ritz pair is refined on its own
-                                 by RMM-DIIS (Pulay's DIIS over the pair's last 16 iterates, then the
-                                 residual-minimising step along (diag(H) - theta)^-1 r; one product
+                                 by RMM-DIIS (Pulay's DIIS over the pair's iterates of the current sweep,
+                                 at most 5, then the residual-minimising step along
+                                 (diag(H) - theta)^-1 r or the learned step (rmm_precond); one product
                                  with H per pair and iteration, the pairs batched); at most max_cont
                                  iterations; the final check takes Rayleigh-Ritz on the refined
                                  vectors.  sppc_solve only (not a block for sppc_correct); not a
