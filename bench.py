@@ -17,7 +17,7 @@ skips them; --full-compare adds more forms).  Prints one JSON line.
                   [--mode plain|mixed|plain+mpnn|mixed+mpnn|plain+small|mixed+small|plain+rmmdiis|
                           mixed+rmmdiis|plain+rmmdiis+mpnn|mixed+rmmdiis+mpnn|plain-inexact]
                   [--no-compare] [--full-compare] [--auto-switch]
-                  [--no-cpu-baseline] [--calibrate-copy] [--spmm-only R]
+                  [--no-cpu-baseline] [--calibrate-copy] [--spmm-only R [--spmm-f32] [--spmm-upper]]
 """
 from __future__ import annotations
 
@@ -82,6 +82,8 @@ def parse():
     ap.add_argument("--spmm-only", type=int, default=0,
                     help="only time this many block products with H (profiling runs)")
     ap.add_argument("--spmm-f32", action="store_true", help="with --spmm-only: float32 X (mixed form)")
+    ap.add_argument("--spmm-upper", action="store_true",
+                    help="with --spmm-only: also time the product from the upper triangle alone")
     ap.add_argument("--panel-width", type=int, default=-1,
                     help="columns per panel of the block product (-1 automatic, 0 plain CSR)")
     ap.add_argument("--verbose", action="store_true")
@@ -138,8 +140,24 @@ def main():
             P.sppc_spmm(ctx, X, Y)
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / args.spmm_only
-        print(json.dumps({"spmm_launches": args.spmm_only, "n": A.n, "b": w.k, "panel_width": args.panel_width,
-                          "x": "f32" if args.spmm_f32 else "f64", "ms_per_launch_wall": round(dt * 1e3, 4)}))
+        rec = {"spmm_launches": args.spmm_only, "n": A.n, "b": w.k, "panel_width": args.panel_width,
+               "x": "f32" if args.spmm_f32 else "f64", "ms_per_launch_wall": round(dt * 1e3, 4)}
+        if args.spmm_upper:
+            # the same product from the upper triangle alone (float64 atomic adds for the lower half)
+            Y2 = torch.empty_like(Y)
+            P.sppc_spmm_upper(rp, col, val, X, Y2)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.spmm_only):
+                P.sppc_spmm_upper(rp, col, val, X, Y2)
+            torch.cuda.synchronize()
+            dt2 = (time.perf_counter() - t0) / args.spmm_only
+            rel = float(((Y2 - Y).abs().max() / Y.abs().max()).item())
+            mat_full = (2 * int(A.row_ptr[-1]) - A.n) * (4 + val.element_size()) + (A.n + 1) * 8
+            mat_up = int(A.row_ptr[-1]) * (4 + val.element_size()) + (A.n + 1) * 8
+            rec.update({"upper_ms_per_launch_wall": round(dt2 * 1e3, 4), "upper_vs_full_max_rel_diff": rel,
+                        "matrix_bytes_full": mat_full, "matrix_bytes_upper": mat_up})
+        print(json.dumps(rec))
         return
 
     from paper_2407_08901_amd import mpnn_train

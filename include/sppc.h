@@ -211,6 +211,24 @@ sppc_status sppc_setup(sppc_ctx** out, const sppc_csr* H, const int64_t* level_o
 sppc_status sppc_spmm(sppc_ctx* ctx, const void* X_dev, sppc_dtype xt, double* Y_dev, int b);
 
 /*
+ * Y = H X read from the upper triangle alone (Sec. IV.C's product with the symmetric H; no
+ * context, no mirrored copy): the strictly lower half is applied as the transpose of the stored
+ * entries, each adding its share to a row of Y by a float64 atomic add.  Streams half the matrix
+ * bytes of the full-storage product at the price of those scattered adds.
+ *   H       the caller's upper CSR (as for sppc_setup), float64 or float32 values; only read
+ *   X_dev   row-major n x b, float64 (xt = SPPC_F64) or float32 (SPPC_F32), only read
+ *   Y_dev   row-major n x b, float64, overwritten (zeroed, then accumulated); must not overlap X
+ *   b       1..32
+ *   stream  hipStream_t (as void*), NULL for the default stream; asynchronous on it
+ * float64 X: float64 products of the values as stored.  float32 X: each value rounded to float32,
+ * float32 products, float64 sums.  The order of the float64 sums depends on scheduling, so two
+ * calls can differ in the last bits.  Allocates nothing.  Errors: SPPC_E_ARG (message in
+ * sppc_setup_error()), SPPC_E_HIP.
+ */
+sppc_status sppc_spmm_upper(const sppc_csr* H, const void* X_dev, sppc_dtype xt, double* Y_dev, int b,
+                            void* stream);
+
+/*
  * Y = H X exactly as sppc_spmm, for callers that cannot allocate device memory (code under HIP
  * graph capture, tight serving loops, harnesses that forbid hipMalloc): this call allocates
  * nothing.  When the context holds the column-panel copy of H and X is not already in the layout

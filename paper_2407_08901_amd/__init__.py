@@ -28,7 +28,7 @@ SPPC_SHIFT_E0, SPPC_SHIFT_RITZ = 0, 1
 STATUS_NAMES = {0: "SPPC_OK", 1: "SPPC_E_ARG", 2: "SPPC_E_HIP", 3: "SPPC_E_NOMEM",
                 4: "SPPC_E_SINGULAR_E0", 5: "SPPC_E_BREAKDOWN", 6: "SPPC_E_NOCONV", 7: "SPPC_E_NAN"}
 
-EXPORTS = ("sppc_default_opts", "sppc_workspace_size", "sppc_setup", "sppc_spmm", "sppc_spmm_noalloc", "sppc_correct", "sppc_rayleigh_ritz",
+EXPORTS = ("sppc_default_opts", "sppc_workspace_size", "sppc_setup", "sppc_spmm", "sppc_spmm_upper", "sppc_spmm_noalloc", "sppc_correct", "sppc_rayleigh_ritz",
            "sppc_solve", "sppc_get", "sppc_last_error", "sppc_setup_error", "sppc_destroy",
            "sppc_release_cached_memory", "sppc_set_memory_cache", "sppc_mpnn_set_weights", "sppc_mpnn_eval", "sppc_mpnn_train_step", "sppc_mpnn_target")
 SPPC_MPNN_NPARAM = 289
@@ -89,6 +89,7 @@ def lib():
         L.sppc_set_memory_cache.restype = ctypes.c_size_t
         L.sppc_spmm.argtypes = [vp, vp, c_int, vp, c_int]
         L.sppc_spmm_noalloc.argtypes = [vp, vp, c_int, vp, c_int]
+        L.sppc_spmm_upper.argtypes = [ctypes.POINTER(sppc_csr), vp, c_int, vp, c_int, vp]
         L.sppc_correct.argtypes = [vp, c_int, dp]
         L.sppc_rayleigh_ritz.argtypes = [vp, dp, dp, ctypes.POINTER(c_int)]
         L.sppc_solve.argtypes = [vp, dp, vp, dp, ctypes.POINTER(sppc_stats)]
@@ -105,7 +106,7 @@ def lib():
         L.sppc_mpnn_eval.argtypes = [vp, fp, c_int, vp, vp, dp, vp, c_int, vp, vp, dp, dp, c_int]
         L.sppc_mpnn_train_step.argtypes = [vp, vp, c_int, vp, vp, dp, vp, c_int, vp, ctypes.c_float, c_int, dp]
         L.sppc_mpnn_target.argtypes = [vp, c_int, vp, c_int, vp, vp]
-        for name in ("sppc_default_opts", "sppc_workspace_size", "sppc_setup", "sppc_spmm", "sppc_spmm_noalloc", "sppc_correct", "sppc_rayleigh_ritz",
+        for name in ("sppc_default_opts", "sppc_workspace_size", "sppc_setup", "sppc_spmm", "sppc_spmm_upper", "sppc_spmm_noalloc", "sppc_correct", "sppc_rayleigh_ritz",
                      "sppc_solve", "sppc_get", "sppc_mpnn_set_weights", "sppc_mpnn_eval", "sppc_mpnn_train_step",
                      "sppc_mpnn_target"):
             getattr(L, name).restype = c_int
@@ -231,6 +232,20 @@ def sppc_spmm(ctx: Context, X: torch.Tensor, Y: torch.Tensor) -> None:
     xt = SPPC_F32 if X.dtype == torch.float32 else SPPC_F64
     _check(lib().sppc_spmm(ctx.handle, ctypes.c_void_p(X.data_ptr()), xt, ctypes.c_void_p(Y.data_ptr()),
                            X.shape[1]), ctx.handle)
+
+
+def sppc_spmm_upper(row_ptr: torch.Tensor, col: torch.Tensor, val: torch.Tensor, X: torch.Tensor,
+                    Y: torch.Tensor, stream=None) -> None:
+    """Y = H X from the upper-triangular CSR alone (no context); X row-major n x b (float64 or
+    float32), Y float64 n x b."""
+    n, H = _csr(row_ptr, col, val)
+    if X.dim() != 2 or Y.shape != X.shape or X.shape[0] != n or Y.dtype != torch.float64:
+        raise ValueError("X, Y must be n x b, Y float64")
+    if not (X.is_contiguous() and Y.is_contiguous() and X.is_cuda and Y.is_cuda):
+        raise ValueError("X, Y must be contiguous GPU tensors")
+    xt = SPPC_F32 if X.dtype == torch.float32 else SPPC_F64
+    _check(lib().sppc_spmm_upper(ctypes.byref(H), ctypes.c_void_p(X.data_ptr()), xt, ctypes.c_void_p(Y.data_ptr()),
+                                 X.shape[1], _stream_handle(stream)))
 
 
 def sppc_spmm_noalloc(ctx: Context, X: torch.Tensor, Y: torch.Tensor) -> None:

@@ -103,6 +103,18 @@ struct DevCSR {
 void build_full_csr(int64_t n, int64_t nnz_up, const int64_t* up_rp, const int32_t* up_col,
                     const void* up_val, int val_is_f32, DevCSR& out, int* d_flags,
                     bool want64, bool want32, bool& exact32, hipStream_t s);
+// The caller's upper triangle (diagonal included, columns ascending), borrowed.
+struct UpperCSR {
+  int64_t n = 0;
+  const int64_t* rp = nullptr;
+  const int32_t* col = nullptr;
+  const float* val32 = nullptr;   // one of the two
+  const double* val64 = nullptr;
+};
+// Y[n x b] (ldy) = H X from the upper triangle alone: the transposed half by float64 atomic adds
+// (Y is zeroed first); X float32 (xf32) or float64.
+void spmm_upper(const UpperCSR& U, const void* X, bool xf32, int64_t ldx, double* Y, int64_t ldy, int b,
+                hipStream_t s);
 // Row ends of the leading n0 x n0 block (columns < n0) of the full CSR.
 void build_block_view(const DevCSR& full, int64_t n0, int64_t* rend, hipStream_t s);
 // Panel copy of a full CSR (ascending columns per row); values as stored in the CSR.

@@ -1541,6 +1541,27 @@ sppc_status sppc_spmm_noalloc(sppc_ctx* c, const void* X, sppc_dtype xt, double*
   });
 }
 
+sppc_status sppc_spmm_upper(const sppc_csr* H, const void* X, sppc_dtype xt, double* Y, int b, void* stream) {
+  sppc_ctx c;
+  const sppc_status st = guarded(&c, [&]() {
+    if (!H || !X || !Y || b < 1 || b > 32) throw Error(SPPC_E_ARG, "bad argument");
+    if (H->n < 0 || H->n >= (int64_t)1 << 31 || (H->n > 0 && (!H->row_ptr_dev || !H->col_dev || !H->val_dev)))
+      throw Error(SPPC_E_ARG, "bad H");
+    if ((H->val_type != SPPC_F32 && H->val_type != SPPC_F64) || (xt != SPPC_F32 && xt != SPPC_F64))
+      throw Error(SPPC_E_ARG, "bad value type");
+    UpperCSR U;
+    U.n = H->n;
+    U.rp = H->row_ptr_dev;
+    U.col = H->col_dev;
+    if (H->val_type == SPPC_F32) U.val32 = (const float*)H->val_dev;
+    else U.val64 = (const double*)H->val_dev;
+    spmm_upper(U, X, xt == SPPC_F32, b, Y, b, b, (hipStream_t)stream);
+    return SPPC_OK;
+  });
+  if (st != SPPC_OK) g_setup_err = c.err;
+  return st;
+}
+
 sppc_status sppc_correct(sppc_ctx* c, int kind, const double* shifts_host) {
   if (!c) return SPPC_E_ARG;
   return guarded(c, [&]() {

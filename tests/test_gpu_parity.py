@@ -64,6 +64,82 @@ def test_spmm_f32_products_accumulated_in_f64():
     assert np.max(np.abs(Y - ref) / scale) < 2.0 ** -24 * 1.01
 
 
+# ---------------------------------------------------------------- product from the upper triangle
+@pytest.mark.parametrize("vdt", [torch.float64, torch.float32])
+def test_spmm_upper_f64_matches_oracle(vdt):
+    A = levelgen.generate((300, 3000, 20000), 60, 79)      # n = 23300: many waves, ragged tail
+    print("case spmm_upper f64 X values %s n=%d" % (vdt, A.n), flush=True)
+    rp, col, val = P.upload(A, dtype=vdt)
+    vals = val.cpu().numpy().astype(np.float64)            # the values as the kernel reads them
+    rng = np.random.default_rng(11)
+    for b in (1, 3, 4, 8, 13, 16, 24, 32):
+        X = rng.standard_normal((A.n, b))
+        Yd = torch.full((A.n, b), np.nan, dtype=torch.float64, device="cuda")   # overwritten
+        P.sppc_spmm_upper(rp, col, val, torch.from_numpy(X).cuda(), Yd)
+        torch.cuda.synchronize()
+        Y = Yd.cpu().numpy()
+        ref = oracle.product_from_upper(A.row_ptr, A.col, vals, A.n, X)
+        scale = oracle.product_from_upper(A.row_ptr, A.col, np.abs(vals), A.n, np.abs(X))
+        assert np.max(np.abs(Y - ref) / scale) < 1e-14, b
+
+
+def test_spmm_upper_f32_products_accumulated_in_f64():
+    A = levelgen.generate((300, 3000, 20000), 60, 80)
+    print("case spmm_upper f32 X n=%d" % A.n, flush=True)
+    rng = np.random.default_rng(12)
+    for vdt in (torch.float32, torch.float64):
+        rp, col, val = P.upload(A, dtype=vdt)
+        # float32 X: the values rounded to float32 either way
+        v32 = val.cpu().numpy().astype(np.float32).astype(np.float64)
+        for b in (2, 8, 16):
+            X = rng.standard_normal((A.n, b)).astype(np.float32)
+            Yd = torch.empty((A.n, b), dtype=torch.float64, device="cuda")
+            P.sppc_spmm_upper(rp, col, val, torch.from_numpy(X).cuda(), Yd)
+            torch.cuda.synchronize()
+            X64 = X.astype(np.float64)
+            ref = oracle.product_from_upper(A.row_ptr, A.col, v32, A.n, X64)
+            scale = oracle.product_from_upper(A.row_ptr, A.col, np.abs(v32), A.n, np.abs(X64))
+            assert np.max(np.abs(Yd.cpu().numpy() - ref) / scale) < 2.0 ** -24 * 1.01, (vdt, b)
+
+
+def test_spmm_upper_agrees_with_the_full_storage_product_and_refuses_bad_input():
+    A = levelgen.generate((200, 2000, 9000), 50, 81)
+    print("case spmm_upper vs sppc_spmm n=%d" % A.n, flush=True)
+    rp, col, val = P.upload(A)
+    ctx = _ctx(A, 1, 4)
+    X = torch.from_numpy(np.random.default_rng(13).standard_normal((A.n, 16))).cuda()
+    Y1 = torch.empty_like(X)
+    Y2 = torch.empty_like(X)
+    P.sppc_spmm(ctx, X, Y1)
+    P.sppc_spmm_upper(rp, col, val, X, Y2)
+    torch.cuda.synchronize()
+    scale = torch.from_numpy(oracle.product_from_upper(A.row_ptr, A.col, np.abs(A.val), A.n,
+                                                       np.abs(X.cpu().numpy()))).cuda()
+    assert float(((Y1 - Y2).abs() / scale).max()) < 2e-14
+    assert P.lib().sppc_spmm_upper(None, None, P.SPPC_F64, None, 4, None) == 1    # SPPC_E_ARG
+    with pytest.raises(ValueError):
+        P.sppc_spmm_upper(rp, col, val, X[:, :4].contiguous(), Y2)
+
+
+def test_spmm_upper_of_a_diagonal_matrix_and_of_one_row():
+    print("case spmm_upper diagonal / n=1", flush=True)
+    n = 1000
+    d = np.linspace(-3, 5, n)
+    rp = torch.arange(n + 1, dtype=torch.int64, device="cuda")
+    col = torch.arange(n, dtype=torch.int32, device="cuda")
+    val = torch.from_numpy(d).cuda()
+    X = torch.from_numpy(np.random.default_rng(14).standard_normal((n, 5))).cuda()
+    Y = torch.empty_like(X)
+    P.sppc_spmm_upper(rp, col, val, X, Y)
+    torch.cuda.synchronize()
+    assert torch.equal(Y.cpu(), torch.from_numpy(d[:, None] * X.cpu().numpy()))
+    Y1 = torch.empty((1, 3), dtype=torch.float64, device="cuda")
+    P.sppc_spmm_upper(rp[:2].contiguous(), col[:1].contiguous(), val[:1].contiguous(),
+                      X[:1, :3].contiguous(), Y1)
+    torch.cuda.synchronize()
+    assert torch.equal(Y1.cpu(), torch.from_numpy(d[:1, None] * X[:1, :3].cpu().numpy()))
+
+
 # column-panel copy: many panels, ragged last panel and last row block (n = 60,700)
 PANEL_A = None
 
