@@ -82,6 +82,8 @@ def parse():
     ap.add_argument("--spmm-only", type=int, default=0,
                     help="only time this many block products with H (profiling runs)")
     ap.add_argument("--spmm-f32", action="store_true", help="with --spmm-only: float32 X (mixed form)")
+    ap.add_argument("--rmm-weights", default=None,
+                    help="weights file of the learned RMM-DIIS step (default: the package's)")
     ap.add_argument("--spmm-upper", action="store_true",
                     help="with --spmm-only: also time the product from the upper triangle alone")
     ap.add_argument("--panel-width", type=int, default=-1,
@@ -161,7 +163,9 @@ def main():
         return
 
     from paper_2407_08901_amd import mpnn_train
-    weights = {"davidson": mpnn_train.load_for("davidson"), "rmmdiis": mpnn_train.load_for("rmmdiis")}
+    weights = {"davidson": mpnn_train.load_for("davidson"),
+               "rmmdiis": mpnn_train.load(args.rmm_weights) if args.rmm_weights
+               else mpnn_train.load_for("rmmdiis", len(w.level_sizes))}
 
     def mode_opts(mode, auto_switch=None):
         auto_switch = args.auto_switch if auto_switch is None else auto_switch

@@ -38,6 +38,7 @@ import paper_2407_08901_amd as P
 HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_WEIGHTS = os.path.join(HERE, "mpnn_weights.json")          # basis target (Davidson continuation)
 PAIR_WEIGHTS = os.path.join(HERE, "mpnn_weights_rmm.json")         # pair target (RMM-DIIS step)
+PAIR_WEIGHTS_L5 = os.path.join(HERE, "mpnn_weights_rmm_L5.json")   # pair target, five-level matrices
 FORMAT = "sppc-mpnn-v2"  # v2: level input lambda = min(max(level - n_small + 1, 0), 2) / 2
 
 
@@ -120,6 +121,21 @@ def train(data, epochs=120, lr=1e-2, seed=0, log=print):
     return w, hist
 
 
+def evaluate(data, w) -> float:
+    """Mean loss over every sample for the weights w (bfloat16-rounded as in the forward pass); the
+    zero network is the diagonal step, so evaluate(data, 0) is the loss of that step."""
+    state = torch.zeros(4 * P.SPPC_MPNN_NPARAM, dtype=torch.float32, device="cuda")
+    state[:P.SPPC_MPNN_NPARAM] = torch.as_tensor(np.asarray(w, np.float32)).cuda()
+    tot, cnt = 0.0, 0
+    for d in data:
+        for g in d["groups"]:
+            # a learning rate of 0 leaves the weights as they are
+            loss = P.sppc_mpnn_train_step(d["ctx"], state, g["R"], g["X"], g["theta"], g["E"], 0.0, 1, Q=g["Q"])
+            tot += loss * g["X"].shape[1]
+            cnt += g["X"].shape[1]
+    return tot / max(cnt, 1)
+
+
 def save(w, path, meta):
     payload = {"format": FORMAT, "nparam": int(w.size), "weights": [float(x) for x in w], **meta}
     payload["sha256"] = hashlib.sha256(np.asarray(w, np.float32).tobytes()).hexdigest()
@@ -138,11 +154,15 @@ def load(path=DEFAULT_WEIGHTS) -> np.ndarray:
     return w
 
 
-def load_for(continuation: str = "davidson") -> np.ndarray:
+def load_for(continuation: str = "davidson", n_levels: int = 3) -> np.ndarray:
     """Weights for the Davidson continuation ("davidson", basis target) or the RMM-DIIS step
-    ("rmmdiis", pair target).  The level input has one meaning for any number of levels, so the
-    weights trained on the n = 4900 three-level matrices serve every workload."""
-    return load(PAIR_WEIGHTS if continuation == "rmmdiis" else DEFAULT_WEIGHTS)
+    ("rmmdiis", pair target).  The level input has one meaning for any number of levels, but the
+    messages are sums over a row's neighbours, so their scale follows the density: on matrices of
+    five or more levels (d = 300) the RMM-DIIS step takes the weights trained on the five-level
+    shape (PAIR_WEIGHTS_L5), on which the three-level weights do worse than the diagonal step."""
+    if continuation == "rmmdiis":
+        return load(PAIR_WEIGHTS_L5 if n_levels >= 5 else PAIR_WEIGHTS)
+    return load(DEFAULT_WEIGHTS)
 
 
 def main():
@@ -153,26 +173,30 @@ def main():
     ap.add_argument("--epochs", type=int, default=120)
     ap.add_argument("--lr", type=float, default=1e-2)
     ap.add_argument("--nseeds", type=int, default=24)
-    ap.add_argument("--shape", default="L3", choices=["L3", "L4"],
-                    help="training matrices: the n = 4900 three-level shape or the four-level n = 117,200 one")
+    ap.add_argument("--shape", default="L3", choices=["L3", "L4", "L5"],
+                    help="training matrices: the n = 4900 three-level shape, the four-level n = 117,200 one or "
+                         "the five-level n = 386,100 one")
     args = ap.parse_args()
     P.lib()
     t0 = time.time()
-    seeds = (levelgen.TRAIN_SEEDS if args.shape == "L3" else levelgen.TRAIN_SEEDS_L4)[: args.nseeds]
+    seeds = {"L3": levelgen.TRAIN_SEEDS, "L4": levelgen.TRAIN_SEEDS_L4,
+             "L5": levelgen.TRAIN_SEEDS_L5}[args.shape][: args.nseeds]
     data = build_dataset(seeds, args.shape, args.target, log=lambda m: print(m, flush=True))
     t1 = time.time()
     w, hist = train(data, epochs=args.epochs, lr=args.lr, log=lambda m: print(m, flush=True))
     t2 = time.time()
     nsamp = sum(g["X"].shape[1] for d in data for g in d["groups"])
+    loss_diag = evaluate(data, np.zeros(P.SPPC_MPNN_NPARAM, np.float32))
+    loss_net = evaluate(data, w)
     cmd = "python -m paper_2407_08901_amd.mpnn_train --target %s --shape %s --epochs %d --lr %g --nseeds %d" % (
         args.target, args.shape, args.epochs, args.lr, args.nseeds)
     out = args.out or (PAIR_WEIGHTS if args.target == "pair" else DEFAULT_WEIGHTS)
     save(w, out, {"command": cmd, "target": args.target, "train_seeds": list(seeds), "shape": args.shape,
-                  "samples": nsamp,
+                  "samples": nsamp, "loss_network": loss_net, "loss_diagonal_step": loss_diag,
                        "epochs": args.epochs, "lr": args.lr, "loss_history": hist,
                        "data_s": round(t1 - t0, 2), "train_s": round(t2 - t1, 2)})
-    print(json.dumps({"samples": nsamp, "final_loss": hist[-1], "first_loss": hist[0], "data_s": t1 - t0,
-                      "train_s": t2 - t1}))
+    print(json.dumps({"samples": nsamp, "final_loss": hist[-1], "first_loss": hist[0], "loss_network": loss_net,
+                      "loss_diagonal_step": loss_diag, "data_s": t1 - t0, "train_s": t2 - t1}))
 
 
 if __name__ == "__main__":

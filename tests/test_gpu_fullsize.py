@@ -178,7 +178,7 @@ def test_n7722000_sampled_product_and_solves():
         torch.cuda.synchronize()
         assert np.max(np.abs(Yd.cpu().numpy()[rows] - ref32) / scale) < 2.0 ** -24 * 1.01, name
         if kw.get("rmm_precond") == P.SPPC_CORR_MPNN:
-            P.sppc_mpnn_set_weights(ctx, mpnn_train.load_for("rmmdiis"))
+            P.sppc_mpnn_set_weights(ctx, mpnn_train.load_for("rmmdiis", len(w.level_sizes)))
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         ev, Z, rrn, st, status = P.sppc_solve(ctx)
@@ -260,7 +260,7 @@ def test_against_the_stored_oracle_solution(wl):
                                                    rmm_precond=P.SPPC_CORR_MPNN), 1e-8)):
         ctx = ctx_of(**kw)
         if name.endswith("learned"):
-            P.sppc_mpnn_set_weights(ctx, mpnn_train.load_for("rmmdiis"))
+            P.sppc_mpnn_set_weights(ctx, mpnn_train.load_for("rmmdiis", len(wl.level_sizes)))
         ev, Z, rrn, st, status = P.sppc_solve(ctx, want_vectors=False)
         P.sppc_destroy(ctx)
         assert status == P.SPPC_OK
