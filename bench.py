@@ -82,6 +82,8 @@ def parse():
     ap.add_argument("--spmm-only", type=int, default=0,
                     help="only time this many block products with H (profiling runs)")
     ap.add_argument("--spmm-f32", action="store_true", help="with --spmm-only: float32 X (mixed form)")
+    ap.add_argument("--n-deflate", type=int, default=0,
+                    help="eigenpairs of H0hat deflated in the small-space solves (0: the library's default)")
     ap.add_argument("--rmm-weights", default=None,
                     help="weights file of the learned RMM-DIIS step (default: the package's)")
     ap.add_argument("--spmm-upper", action="store_true",
@@ -180,7 +182,7 @@ def main():
             extra["rmm_precond"] = P.SPPC_CORR_MPNN
         return P.sppc_default_opts(precision=P.SPPC_PREC_MIXED if mixed else P.SPPC_PREC_FP64, precond=precond,
                                    verbose=1 if args.verbose else 0, panel_width=args.panel_width,
-                                   auto_switch=1 if auto_switch else 0, **extra)
+                                   auto_switch=1 if auto_switch else 0, n_deflate=args.n_deflate, **extra)
 
     # one device workspace from PyTorch for every context of the run (the largest any timed form
     # needs), allocated before the timing: no allocation or release inside the timed steps
