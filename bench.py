@@ -38,9 +38,10 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 # scaled by a plain-copy calibration (profiles/k_spmm_panel_*_hbm_counters.md).
 # Keyed by (workload, mode); valid only while the kernel source has the recorded sha256.
 MEASURED_TRAFFIC = {
-    # profiles/k_spmm_panel_L5-7.72M-k16_hbm_counters.md: 13 products with float32 X and 11 with float64 X per solve
-    ("L5-2k/20k/200k/1.5M/6M-d300-k16", "mixed+rmmdiis+mpnn"): (182568552344,
-        "1eb2f3cab72ee86ea8b74707fcb5a95cc4d5319be721b6929e07be30f8653c55"),
+    # profiles/k_spmm_panel_L5-7.72M-k16_hbm_counters.md: per width-16 product of one solve (13 with float32 X,
+    # 14 with float64 X, the network's width-16 products included)
+    ("L5-2k/20k/200k/1.5M/6M-d300-k16", "mixed+rmmdiis+mpnn"): (184896172053,
+        "172bd9850376f199aa4fc43fed6e8518cedb3c6ad7ec754ddc0fb799c7bc916b"),
 }
 
 
@@ -86,6 +87,7 @@ def parse():
                     help="eigenpairs of H0hat deflated in the small-space solves (0: the library's default)")
     ap.add_argument("--rmm-weights", default=None,
                     help="weights file of the learned RMM-DIIS step (default: the package's)")
+    ap.add_argument("--spmm-width", type=int, default=0, help="with --spmm-only: block width (default k)")
     ap.add_argument("--spmm-upper", action="store_true",
                     help="with --spmm-only: also time the product from the upper triangle alone")
     ap.add_argument("--panel-width", type=int, default=-1,
@@ -133,10 +135,10 @@ def main():
         opts = P.sppc_default_opts(precision=P.SPPC_PREC_MIXED if args.spmm_f32 else P.SPPC_PREC_FP64,
                                    panel_width=args.panel_width)
         ctx = P.sppc_setup(rp, col, val, A.level_offsets, w.n_small_levels, w.k, opts)
-        X = torch.randn(A.n, w.k, dtype=torch.float64, device="cuda")
+        X = torch.randn(A.n, args.spmm_width or w.k, dtype=torch.float64, device="cuda")
         if args.spmm_f32:
             X = X.float()
-        Y = torch.empty(A.n, w.k, dtype=torch.float64, device="cuda")
+        Y = torch.empty(A.n, X.shape[1], dtype=torch.float64, device="cuda")
         P.sppc_spmm(ctx, X, Y)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -144,7 +146,7 @@ def main():
             P.sppc_spmm(ctx, X, Y)
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / args.spmm_only
-        rec = {"spmm_launches": args.spmm_only, "n": A.n, "b": w.k, "panel_width": args.panel_width,
+        rec = {"spmm_launches": args.spmm_only, "n": A.n, "b": X.shape[1], "panel_width": args.panel_width,
                "x": "f32" if args.spmm_f32 else "f64", "ms_per_launch_wall": round(dt * 1e3, 4)}
         if args.spmm_upper:
             # the same product from the upper triangle alone (float64 atomic adds for the lower half)

@@ -710,11 +710,18 @@ void spmm_panel_b(const PanelH& P, const VT* val, const XT* X, int64_t ldx, doub
     k_pad_copy<XT><<<(unsigned)cdiv(P.n * B, 256), 256, 0, s>>>(P.n, b, X, ldx, xp, B);
     Xc = xp;
   }
-  // two-wave workgroups, two (float64 X) or four (float32 X) per CU, words and values two tiles
-  // ahead: the fastest of the measured shapes at n = 1.17M, d = 200.  When X no longer fits the
-  // 256 MB MALL (n = 7.7M, b = 16: 494 MB in float32), its rows come from HBM at longer latency,
-  // and one-wave workgroups, four per CU, are 13-15% faster
-  if ((int64_t)P.n * B * (int64_t)sizeof(XT) > ((int64_t)256 << 20))
+  // Two launch shapes, words and values two tiles ahead in both: one-wave workgroups, four per
+  // CU, or two-wave workgroups, two (float64 X) or four (float32 X) per CU.  Measured per product
+  // (ms, one-wave / two-wave):
+  //   n = 7.72M, d = 300:  b = 4: 17.7 / 29.2 (float64 X), 14.0 / 21.1 (float32);
+  //                        b = 8: 20.6 / 34.4, 18.5 / 25.5;  b = 16: two-wave 13-15% slower
+  //   n = 1.17M, d = 200:  b = 4: 1.53 / 1.90 (float64);  b = 8: 1.86 / 1.88 (float64),
+  //                        1.79 / 1.72 (float32);  b = 16: 2.79 / 2.64 (float64), 2.74 / 2.10
+  // The shape follows the rows, not the width of this product: a narrow product gathers as many
+  // rows of X as a wide one.  One-wave workgroups when X at width 16 would exceed the 256 MB MALL
+  // (its rows then come from HBM at longer latency, and more rows in flight per CU pay), and for
+  // float64 X of width <= 8.
+  if ((int64_t)P.n * 16 * (int64_t)sizeof(XT) > ((int64_t)256 << 20) || (sizeof(XT) == 8 && B <= 8))
     spmm_panel_rounds<B, 1, 2, VT, XT>(P, val, Xc, Y, ldy, b, 4, s, X64, ldx64);
   else
     spmm_panel_rounds<B, 2, 2, VT, XT>(P, val, Xc, Y, ldy, b, sizeof(XT) == 4 ? 4 : 2, s, X64, ldx64);
