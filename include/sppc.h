@@ -107,7 +107,10 @@ typedef struct {
   int verbose;         /* per-iteration line on stderr */
   int panel_width;     /* block products with H over column panels of this many columns (<= 65536),
                           so that the gathered rows of X stay in L2: -1 = automatic (when a k-column
-                          block of X exceeds 8 MiB), 0 = off */
+                          block of X exceeds 8 MiB and n < 2^24), 0 = off.  The panel copy stores a
+                          column in 24 bits: an explicit width with n >= 2^24 is refused by
+                          sppc_setup (SPPC_E_ARG), and the automatic choice then keeps the row-wise
+                          products over the full CSR */
   int refine_precond;  /* continuation kind of the float64 refinement after a mixed solve; SMALL */
   double precond_tol;  /* relative residual of the small-space solve inside SMALL; 1e-3 */
   int auto_switch;     /* 1: switch to the continuation before p_switch once SPPC stagnates: after a
@@ -204,7 +207,7 @@ sppc_status sppc_setup(sppc_ctx** out, const sppc_csr* H, const int64_t* level_o
  * Y = H X for the matrix of the context (the paper's cost unit, Sec. IV.C).
  *   X_dev   row-major n x b, float64 (xt = SPPC_F64) or float32 (SPPC_F32)
  *   Y_dev   row-major n x b, float64
- *   b       1..16
+ *   b       1..32 (widths above 16 take the row-wise kernel over the full CSR)
  * float64 X uses the float64 values; float32 X uses the float32 values with
  * float32 products accumulated in float64.  Asynchronous on the context stream.
  */

@@ -874,6 +874,8 @@ void configure(sppc_ctx* c, const sppc_csr* Hin, const int64_t* loff, int L, int
   c->D = o.n_deflate;
   if (o.m_max < 2 * k || o.m_max > 512) throw Error(SPPC_E_ARG, "m_max must be in [2k, 512]");
   if (o.panel_width < -1 || o.panel_width > 65536) throw Error(SPPC_E_ARG, "panel_width must be -1, 0 or 1..65536");
+  if (o.panel_width > 0 && c->n >= ((int64_t)1 << 24))
+    throw Error(SPPC_E_ARG, "the column-panel copy stores a column in 24 bits: panel_width needs n < 2^24");
   if (o.precond != SPPC_CORR_JACOBI && o.precond != SPPC_CORR_MPNN && o.precond != SPPC_CORR_SMALL &&
       o.precond != SPPC_CORR_RMMDIIS)
     throw Error(SPPC_E_ARG, "continuation must be JACOBI, MPNN, SMALL or RMMDIIS");

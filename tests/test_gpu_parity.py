@@ -121,6 +121,27 @@ def test_spmm_upper_agrees_with_the_full_storage_product_and_refuses_bad_input()
         P.sppc_spmm_upper(rp, col, val, X[:, :4].contiguous(), Y2)
 
 
+def test_spmm_upper_ragged_rows_and_empty_rows():
+    # n = 23,305 (not a multiple of the kernel's 4 rows per workgroup); every 7th row of the
+    # upper triangle emptied (no entries at all, the diagonal included)
+    A = levelgen.generate((301, 3001, 20003), 60, 82)
+    print("case spmm_upper ragged n=%d" % A.n, flush=True)
+    keep = np.ones(A.col.size, bool)
+    rows = np.repeat(np.arange(A.n), np.diff(A.row_ptr))
+    keep[rows % 7 == 3] = False
+    rp = np.concatenate([[0], np.cumsum(np.bincount(rows[keep], minlength=A.n))]).astype(np.int64)
+    col, val = A.col[keep], A.val[keep]
+    rng = np.random.default_rng(15)
+    X = rng.standard_normal((A.n, 13))
+    Yd = torch.empty((A.n, 13), dtype=torch.float64, device="cuda")
+    P.sppc_spmm_upper(torch.from_numpy(rp).cuda(), torch.from_numpy(col.astype(np.int32)).cuda(),
+                      torch.from_numpy(val).cuda(), torch.from_numpy(X).cuda(), Yd)
+    torch.cuda.synchronize()
+    ref = oracle.product_from_upper(rp, col, val, A.n, X)
+    scale = oracle.product_from_upper(rp, col, np.abs(val), A.n, np.abs(X)) + 1e-300
+    assert np.max(np.abs(Yd.cpu().numpy() - ref) / scale) < 1e-14
+
+
 def test_spmm_upper_of_a_diagonal_matrix_and_of_one_row():
     print("case spmm_upper diagonal / n=1", flush=True)
     n = 1000
