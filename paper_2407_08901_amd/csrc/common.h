@@ -117,6 +117,8 @@ void spmm_upper(const UpperCSR& U, const void* X, bool xf32, int64_t ldx, double
                 hipStream_t s);
 // Row ends of the leading n0 x n0 block (columns < n0) of the full CSR.
 void build_block_view(const DevCSR& full, int64_t n0, int64_t* rend, hipStream_t s);
+// rend[i] = end of the entries of row i with column < c0, for rows i < nrows of the full CSR.
+void row_ends_below(const DevCSR& full, int64_t nrows, int64_t c0, int64_t* rend, hipStream_t s);
 // Panel copy of a full CSR (ascending columns per row); values as stored in the CSR.
 // Device memory is allocated with hipMalloc and owned by the caller (release_panel).
 void build_panel(const DevCSR& H, int PW, PanelH& out, hipStream_t s);

@@ -995,8 +995,23 @@ void setup_impl(sppc_ctx* c, const sppc_csr* Hin, const int64_t* loff, int L, in
   Basis& b = c->B;
   fill_block_zero(n, k, b.Q, b.ldq, s);
   copy_block(n0, k, c->Psihat, c->D, b.Q, b.ldq, s);
-  Op op{c, &c->H, false, true};  // float64 also in mixed precision: E^(p) reads H Psi^(0)
-  op(b.Q, b.ldq, b.HQ, b.ldq, k, s);
+  {
+    // H Psi^(0): Psi^(0) vanishes below row n0, so only the entries of H in columns < n0 (the
+    // leading entries of each row) take part: a row-wise product over those, float64 also in mixed
+    // precision (E^(p) reads H Psi^(0)).  With levels coupled only to adjacent levels that is a small
+    // fraction of H; the rows without such entries get zero.
+    Arena tmp;
+    tmp.temp = true;
+    int64_t* rend = tmp.alloc<int64_t>(n);
+    row_ends_below(c->H, n, n0, rend, s);
+    DevCSR Hc = c->H;
+    Hc.rend = rend;
+    Hc.panel = nullptr;
+    spmm_f64(Hc, b.Q, b.ldq, b.HQ, b.ldq, k, nullptr, s);
+    c->st.n_spmv += k;
+    sync(c);
+    tmp.release();
+  }
   gemm_tn(n, k, k, b.Q, b.ldq, b.HQ, b.ldq, c->Xt, k, 1.0, 0.0, c->work, s);
   t_from_full(k, c->Xt, k, b.T, b.ldq, s);
   b.m = k;
@@ -1409,6 +1424,7 @@ size_t workspace_bytes(sppc_ctx* c, const sppc_csr* Hin) {
     const int64_t nb = std::min<int64_t>(n0, KB);  // the zeroth order's temporaries
     peak = std::max(peak, base + 2 * ws_bytes(8 * n0 * nb) + ws_bytes(8 * nb * nb) + ws_bytes(8 * n0) +
                               ws_bytes(8 * (n0 + 1)));
+    peak = std::max(peak, base + ws_bytes(sizeof(int64_t) * n));  // row ends of the p = 0 product
     Arena sv;  // arrays the solve adds
     sv.counting = true;
     size_t sv_tmp = 0;

@@ -293,14 +293,15 @@ __global__ void k_fill(int64_t n, const int64_t* __restrict__ up_rp, const int32
   }
 }
 
-__global__ void k_block_view(int64_t n0, const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
-                             int64_t* __restrict__ rend) {
+// rend[i] = the end of the entries of row i with column < c0 (columns ascending), rows i < nrows
+__global__ void k_block_view(int64_t nrows, int64_t c0, const int64_t* __restrict__ rp,
+                             const int32_t* __restrict__ col, int64_t* __restrict__ rend) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n0) return;
-  int64_t lo = rp[i], hi = rp[i + 1];  // first position with col >= n0
+  if (i >= nrows) return;
+  int64_t lo = rp[i], hi = rp[i + 1];  // first position with col >= c0
   while (lo < hi) {
     const int64_t mid = (lo + hi) >> 1;
-    if (col[mid] < n0) lo = mid + 1; else hi = mid;
+    if (col[mid] < c0) lo = mid + 1; else hi = mid;
   }
   rend[i] = lo;
 }
@@ -1048,8 +1049,12 @@ void build_full_csr(int64_t n, int64_t nnz_up, const int64_t* up_rp, const int32
 }
 
 void build_block_view(const DevCSR& full, int64_t n0, int64_t* rend, hipStream_t s) {
-  if (n0 == 0) return;
-  k_block_view<<<cdiv(n0, 256), 256, 0, s>>>(n0, full.rp, full.col, rend);
+  row_ends_below(full, n0, n0, rend, s);
+}
+
+void row_ends_below(const DevCSR& full, int64_t nrows, int64_t c0, int64_t* rend, hipStream_t s) {
+  if (nrows <= 0) return;
+  k_block_view<<<cdiv(nrows, 256), 256, 0, s>>>(nrows, c0, full.rp, full.col, rend);
   SPPC_LAUNCH_CHECK();
 }
 
