@@ -275,17 +275,20 @@ def test_bad_shifts_are_refused(P):
     P.sppc_destroy(ctx)
 
 
-def test_values_that_float32_cannot_hold(P):
+@pytest.mark.parametrize("pw", [0, 1000])
+def test_values_that_float32_cannot_hold(P, pw):
     """float64 values that are not float32-exact: the library keeps float64 values for the float64
     products and a rounded float32 copy for the mixed form's products.  Products with float64 X use
     the exact values (1e-14), products with float32 X the rounded ones (each value and each product
     rounded once: 2 * 2^-24); plain and mixed solves reach the dense eigenvalues of the exact H
-    (1e-10, 1e-8) with the true residual (float64 H, recomputed here) below the tolerance."""
+    (1e-10, 1e-8) with the true residual (float64 H, recomputed here) below the tolerance.  With
+    pw = 1000 the products run over the column-panel copy, which then holds float64 values (and the
+    rounded float32 ones in the mixed form)."""
     A = levelgen.WORKLOADS[0].generate()
     rng = np.random.default_rng(33)
     v64 = A.val.astype(np.float64) * (1.0 + 1e-7 * rng.standard_normal(A.val.size))
     assert np.any(v64.astype(np.float32).astype(np.float64) != v64)
-    print("case edge float64 values n=%d" % A.n, flush=True)
+    print("case edge float64 values n=%d panel width %d" % (A.n, pw), flush=True)
     H = oracle.symmetric_from_upper(A.row_ptr, A.col, v64, A.n)
     lam = np.linalg.eigvalsh(H.toarray())[:4]
     rp = torch.from_numpy(np.ascontiguousarray(A.row_ptr, np.int64)).cuda()
@@ -294,7 +297,7 @@ def test_values_that_float32_cannot_hold(P):
     X = rng.standard_normal((A.n, 8))
     scale = abs(H) @ np.abs(X)
     for prec, bound in ((P.SPPC_PREC_FP64, 1e-10), (P.SPPC_PREC_MIXED, 1e-8)):
-        ctx = P.sppc_setup(rp, col, val, A.level_offsets, 1, 4, P.sppc_default_opts(precision=prec))
+        ctx = P.sppc_setup(rp, col, val, A.level_offsets, 1, 4, P.sppc_default_opts(precision=prec, panel_width=pw))
         Y = torch.empty((A.n, 8), dtype=torch.float64, device="cuda")
         P.sppc_spmm(ctx, torch.from_numpy(X).cuda(), Y)
         torch.cuda.synchronize()
