@@ -125,11 +125,14 @@ __global__ void k_full_rowptr(int64_t n, const int64_t* __restrict__ lower_rp,
 // taken in row order, by column leaves every lower row with its columns ascending.  The sort is
 // a least-significant-digit radix sort (digits of at most 8 bits): per pass, a histogram of
 // each tile of RS_TILE entries, an exclusive scan of the (digit, tile) counts in digit-major
-// order, and a scatter in which one wave ranks its tile's entries round by round (a digit's
-// peers in a round come from ballots over the digit's bits), so every entry keeps its order
-// among equal digits.  No global atomics, and the result does not depend on scheduling.
-constexpr int RS_TILE = 2048;
-constexpr int RS_ROUNDS = RS_TILE / 64;
+// order, and a scatter in which each wave of a tile ranks its part of the tile round by round (a
+// digit's peers in a round come from ballots over the digit's bits, and a wave's runs follow
+// those of the waves before it), so every entry keeps its order among equal digits.  No global
+// atomics, and the result does not depend on scheduling.
+constexpr int RS_WAVES = 4;                 // waves per tile
+constexpr int RS_WTILE = 2048;              // entries per wave
+constexpr int RS_TILE = RS_WAVES * RS_WTILE;
+constexpr int RS_ROUNDS = RS_WTILE / 64;
 
 // strict-upper entries in row order: key = column, row, value (TT: float when only float32 values
 // are kept)
@@ -166,66 +169,84 @@ __global__ __launch_bounds__(256) void k_rs_hist(int64_t m, const int32_t* __res
   if (t <= mask) cnt[(int64_t)t * ntile + blockIdx.x] = h[t];
 }
 
-// One wave per tile.  Entry i of the tile goes to off[d * ntile + tile] + (its rank among the
-// tile's entries with digit d), ranks taken in rounds of 64 entries in order.  The tile is first
-// reordered by digit in LDS (stable), then written out in that order, so consecutive lanes write
-// consecutive positions of one digit's run and the stores coalesce.
+// One workgroup of RS_WAVES waves per tile; wave w holds entries [w RS_WTILE, (w + 1) RS_WTILE)
+// of it.  Entry i of the tile goes to off[d * ntile + tile] + (its rank among the tile's entries
+// with digit d), ranks taken in tile order.  The tile is first reordered by digit in LDS
+// (stable), then written out in that order, so consecutive lanes write consecutive positions of
+// one digit's run and the stores coalesce: a tile of 8192 entries holds runs of 32 entries on
+// average for 256 digits (a one-wave tile of 2048 left runs of 8, 32-byte stores of each array).
 template <typename TT>
-__global__ __launch_bounds__(64) void k_rs_scatter(int64_t m, const int32_t* __restrict__ kin,
-                                                   const int32_t* __restrict__ rin, const TT* __restrict__ vin,
-                                                   int32_t* __restrict__ kout, int32_t* __restrict__ rout,
-                                                   TT* __restrict__ vout, int shift, int bits, int64_t ntile,
-                                                   const int32_t* __restrict__ cnt,
-                                                   const int64_t* __restrict__ off) {
-  __shared__ int64_t gbase[256];  // first global position of each digit's run of this tile
-  __shared__ int lbase[256];      // first position of each digit's run in the reordered tile
-  __shared__ int lnext[256];      // next free position of each digit's run (ranking)
+__global__ __launch_bounds__(64 * RS_WAVES) void k_rs_scatter(int64_t m, const int32_t* __restrict__ kin,
+                                                              const int32_t* __restrict__ rin,
+                                                              const TT* __restrict__ vin,
+                                                              int32_t* __restrict__ kout, int32_t* __restrict__ rout,
+                                                              TT* __restrict__ vout, int shift, int bits,
+                                                              int64_t ntile, const int32_t* __restrict__ cnt,
+                                                              const int64_t* __restrict__ off) {
+  __shared__ int64_t gbase[256];           // first global position of each digit's run of this tile
+  __shared__ int lbase[256];               // first position of each digit's run in the reordered tile
+  __shared__ int wnext[RS_WAVES][256];     // per wave: its count of each digit, then its cursor
+  __shared__ int wsum[RS_WAVES];
   __shared__ int32_t sk[RS_TILE], sr[RS_TILE];
   __shared__ TT sv[RS_TILE];
-  const int lane = threadIdx.x;
+  const int t = threadIdx.x;
+  const int lane = t & 63, w = t >> 6;
   const int mask = (1 << bits) - 1;
   const int64_t i0 = (int64_t)blockIdx.x * RS_TILE;
   const int nt = (int)min<int64_t>(RS_TILE, m - i0);
+  const int wb = w * RS_WTILE;  // this wave's first entry in the tile
   int32_t kk[RS_ROUNDS], rr[RS_ROUNDS];
   TT vv[RS_ROUNDS];
 #pragma unroll
   for (int q = 0; q < RS_ROUNDS; ++q) {
-    const int i = q * 64 + lane;
+    const int i = wb + q * 64 + lane;
     const bool ok = i < nt;
     kk[q] = ok ? kin[i0 + i] : 0;
     rr[q] = ok ? rin[i0 + i] : 0;
     vv[q] = ok ? vin[i0 + i] : TT(0);
   }
-  // exclusive prefix of this tile's digit counts: lane owns digits 4 lane .. 4 lane + 3
-  {
-    int c4[4], sum = 0;
+  for (int i = t; i < RS_WAVES * 256; i += 64 * RS_WAVES) (&wnext[0][0])[i] = 0;
+  __syncthreads();
+  // (1) each wave counts its digits
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int d = 4 * lane + u;
-      c4[u] = d <= mask ? cnt[(int64_t)d * ntile + blockIdx.x] : 0;
-      sum += c4[u];
-    }
-    int inc = sum;
+  for (int q = 0; q < RS_ROUNDS; ++q)
+    if (wb + q * 64 + lane < nt) atomicAdd(&wnext[w][((uint32_t)kk[q] >> shift) & mask], 1);
+  __syncthreads();
+  // (2) thread d (< 256): the tile's count of digit d, an exclusive scan over the digits (a wave
+  // scan, then the totals of the waves before), and each wave's cursor after the waves before it
+  {
+    int tot = 0;
+    if (t < 256)
+      for (int v = 0; v < RS_WAVES; ++v) tot += wnext[v][t];
+    int inc = tot;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
       const int y = __shfl_up(inc, o);
       if (lane >= o) inc += y;
     }
-    int run = inc - sum;
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int d = 4 * lane + u;
-      lbase[d] = run;
-      lnext[d] = run;
-      gbase[d] = d <= mask ? off[(int64_t)d * ntile + blockIdx.x] : 0;
-      run += c4[u];
+    if (lane == 63 && t < 256) wsum[w] = inc;
+    __syncthreads();
+    if (t < 256) {
+      int before = 0;
+      for (int v = 0; v < w; ++v) before += wsum[v];
+      const int run = before + inc - tot;
+      lbase[t] = run;
+      gbase[t] = t <= mask ? off[(int64_t)t * ntile + blockIdx.x] : 0;
+      int c = run;
+      for (int v = 0; v < RS_WAVES; ++v) {
+        const int cv = wnext[v][t];
+        wnext[v][t] = c;
+        c += cv;
+      }
     }
   }
   __syncthreads();
+  // (3) ranking within each wave, in rounds of 64 entries in order
   const unsigned long long below = (1ull << lane) - 1ull;
+  int* lnext = wnext[w];
 #pragma unroll
   for (int q = 0; q < RS_ROUNDS; ++q) {
-    const bool ok = q * 64 + lane < nt;
+    const bool ok = wb + q * 64 + lane < nt;
     const int d = ((uint32_t)kk[q] >> shift) & mask;
     unsigned long long peers = __ballot(ok);
 #pragma unroll
@@ -246,7 +267,7 @@ __global__ __launch_bounds__(64) void k_rs_scatter(int64_t m, const int32_t* __r
     }
   }
   __syncthreads();
-  for (int i = lane; i < nt; i += 64) {
+  for (int i = t; i < nt; i += 64 * RS_WAVES) {
     const int32_t k = sk[i];
     const int d = ((uint32_t)k >> shift) & mask;
     const int64_t pos = gbase[d] + (i - lbase[d]);
@@ -1019,7 +1040,8 @@ void mirror_and_fill(int64_t n, int64_t m, const int64_t* up_rp, const int32_t* 
       const int bits = std::min(8, (kb - shift + (passes - p) - 1) / (passes - p));
       k_rs_hist<<<ntile, 256, 0, s>>>(m, key[cur], shift, (1 << bits) - 1, ntile, cnt);
       scan_exclusive_impl(ntile << bits, cnt, off, bsum, s);
-      k_rs_scatter<TT><<<ntile, 64, 0, s>>>(m, key[cur], rowi[cur], v[cur], key[cur ^ 1], rowi[cur ^ 1], v[cur ^ 1],
+      k_rs_scatter<TT><<<ntile, 64 * RS_WAVES, 0, s>>>(m, key[cur], rowi[cur], v[cur], key[cur ^ 1], rowi[cur ^ 1],
+                                                       v[cur ^ 1],
                                             shift, bits, ntile, cnt, off);
       cur ^= 1;
       shift += bits;
