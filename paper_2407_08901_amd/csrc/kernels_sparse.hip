@@ -978,6 +978,21 @@ __global__ __launch_bounds__(PANEL_FT) void k_panel_fill(int64_t n, const int64_
   }
 }
 
+// Zero the padding slots of each block's stream, [bstart + bcount, bstart[blk + 1]), and with an
+// empty stream the whole cap.
+__global__ void k_panel_pad(int nb, const int64_t* __restrict__ bstart, const int32_t* __restrict__ bcount,
+                            int64_t cap, uint32_t* __restrict__ ent, double* __restrict__ v64,
+                            float* __restrict__ v32) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nb) return;
+  const int64_t e1 = b + 1 < nb ? bstart[b + 1] : max<int64_t>(bstart[nb], cap);
+  for (int64_t e = bstart[b] + bcount[b]; e < e1; ++e) {
+    ent[e] = 0u;
+    if (v64) v64[e] = 0.0;
+    if (v32) v32[e] = 0.0f;
+  }
+}
+
 // upper Gershgorin bound of each row: d_i + sum_{j != i} |a_ij|
 __global__ void k_gersh(int64_t n, const int64_t* __restrict__ rp, const int64_t* __restrict__ rend,
                         const int32_t* __restrict__ col, const double* __restrict__ v64,
@@ -1220,19 +1235,17 @@ void build_panel(const DevCSR& H, int PW, PanelH& out, hipStream_t s) {
     if (flag) throw Error(1, "panel: a block of rows holds 2^31 entries or more");
     const int64_t cap = std::max<int64_t>(total, 8);
     SPPC_HIP(dev_malloc(&out.ent, sizeof(uint32_t) * cap));
-    SPPC_HIP(hipMemsetAsync(out.ent, 0, sizeof(uint32_t) * cap, s));  // padding: column 0, row 0
-    if (H.val64) {
-      SPPC_HIP(dev_malloc(&out.val64, sizeof(double) * cap));
-      SPPC_HIP(hipMemsetAsync(out.val64, 0, sizeof(double) * cap, s));
+    if (H.val64) SPPC_HIP(dev_malloc(&out.val64, sizeof(double) * cap));
+    if (H.val32) SPPC_HIP(dev_malloc(&out.val32, sizeof(float) * cap));
+    // the fill writes every entry; the up to 7 padding slots of each block get column 0, row 0 and
+    // value 0 (a cap of 8 beyond an empty stream included)
+    k_panel_pad<<<cdiv(nb, 256), 256, 0, s>>>(nb, out.bstart, out.bcount, cap, out.ent, out.val64, out.val32);
+    if (H.val64)
       k_panel_fill<double><<<nb, PANEL_FT, 0, s>>>(n, H.rp, H.col, H.val64, PW, out.P, out.bstart, out.ent,
                                                     out.val64, out.dg);
-    }
-    if (H.val32) {
-      SPPC_HIP(dev_malloc(&out.val32, sizeof(float) * cap));
-      SPPC_HIP(hipMemsetAsync(out.val32, 0, sizeof(float) * cap, s));
+    if (H.val32)
       k_panel_fill<float><<<nb, PANEL_FT, 0, s>>>(n, H.rp, H.col, H.val32, PW, out.P, out.bstart, out.ent,
                                                    out.val32, H.val64 ? nullptr : out.dg);
-    }
     SPPC_LAUNCH_CHECK();
     SPPC_HIP(hipStreamSynchronize(s));
   } catch (...) {
