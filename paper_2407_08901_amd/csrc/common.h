@@ -176,6 +176,10 @@ void gemm_nn2(int64_t n, int m, int b1, int b2, const double* A, int64_t lda, co
 void copy_to_f32(int64_t n, int b, const double* X, int64_t ldx, float* Y, int64_t ldy, hipStream_t s);
 // Y[r, c] = X[r, c] for a sub-block (row-major)
 void copy_block(int64_t n, int b, const double* X, int64_t ldx, double* Y, int64_t ldy, hipStream_t s);
+// Y1[:, c] = X1[:, c], Y2[:, c] = X2[:, c] for the columns c (< b <= 32) whose bit is set in mask,
+// one pass for all of them (leading dimension ld for the four arrays).
+void copy_cols2(int64_t n, int b, uint32_t mask, const double* X1, double* Y1, const double* X2, double* Y2,
+                int64_t ld, hipStream_t s);
 void fill_zero(int64_t count, double* p, hipStream_t s);
 // R = HZ - Z diag(theta) and partial sums of squares of R's columns into out[b] (sum of squares).
 void residual_block(int64_t n, int b, const double* Z, int64_t ldz, const double* HZ, int64_t ldhz,

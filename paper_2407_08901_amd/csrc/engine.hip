@@ -1162,6 +1162,7 @@ int rmm_diis_sweep(sppc_ctx* c, int cap) {
     SPPC_HIP(hipMemcpyAsync(c->pin + NWMAX, ssr, sizeof(double) * k, hipMemcpyDeviceToHost, s));
     sync(c);
     bool all = true;
+    uint32_t fin = 0;  // pairs that stop here: their xb and H xb go to Z and H Z in one pass
     for (int a = 0; a < k; ++a) {
       if (done[a]) continue;
       const double thv = c->pin[a];
@@ -1169,8 +1170,7 @@ int rmm_diis_sweep(sppc_ctx* c, int cap) {
       rrn_now[a] = r;
       th_now[a] = thv;
       if (r < o.tol || it >= cap) {
-        copy_block(n, 1, xb + a, k, c->Z + a, k, s);
-        copy_block(n, 1, hxb + a, k, c->HZ + a, k, s);
+        fin |= 1u << a;
         c->theta_h[a] = thv;
         c->rrn_h[a] = r;
         done[a] = 1;
@@ -1178,6 +1178,7 @@ int rmm_diis_sweep(sppc_ctx* c, int cap) {
         all = false;
       }
     }
+    copy_cols2(n, k, fin, xb, c->Z, hxb, c->HZ, k, s);
     if (all) break;
     ++iters;
     // the step of minimal residual along the preconditioned residual (one product with H)

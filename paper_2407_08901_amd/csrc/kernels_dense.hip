@@ -291,6 +291,20 @@ __global__ void k_copy_block(int64_t n, int b, const double* __restrict__ X, int
   Y[r * ldy + c] = X[r * ldx + c];
 }
 
+// Y1[:, c] = X1[:, c] and Y2[:, c] = X2[:, c] for the columns c whose bit is set in mask (leading
+// dimension ld for all four): one pass over the rows, whatever the number of columns
+__global__ void k_copy_cols2(int64_t n, int b, uint32_t mask, const double* __restrict__ X1,
+                             double* __restrict__ Y1, const double* __restrict__ X2, double* __restrict__ Y2,
+                             int64_t ld) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * b) return;
+  const int c = (int)(e % b);
+  if (!((mask >> c) & 1u)) return;
+  const int64_t o = (e / b) * ld + c;
+  Y1[o] = X1[o];
+  Y2[o] = X2[o];
+}
+
 __global__ void k_copy_f32(int64_t n, int b, const double* __restrict__ X, int64_t ldx,
                            float* __restrict__ Y, int64_t ldy) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -408,6 +422,14 @@ void gemm_nn2(int64_t n, int m, int b1, int b2, const double* A, int64_t lda, co
 
 void copy_to_f32(int64_t n, int b, const double* X, int64_t ldx, float* Y, int64_t ldy, hipStream_t s) {
   k_copy_f32<<<grid1(n * b), 256, 0, s>>>(n, b, X, ldx, Y, ldy);
+  SPPC_LAUNCH_CHECK();
+}
+
+void copy_cols2(int64_t n, int b, uint32_t mask, const double* X1, double* Y1, const double* X2, double* Y2,
+                int64_t ld, hipStream_t s) {
+  if (n * b == 0 || mask == 0) return;
+  if (b > 32 || ld < b) throw Error(1, "copy_cols2: at most 32 columns within the leading dimension");
+  k_copy_cols2<<<grid1(n * b), 256, 0, s>>>(n, b, mask, X1, Y1, X2, Y2, ld);
   SPPC_LAUNCH_CHECK();
 }
 

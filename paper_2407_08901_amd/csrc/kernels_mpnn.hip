@@ -343,11 +343,25 @@ void mpnn_run(const DevCSR& H, const double* diag, const double* lev, const doub
   double* mxdt = sm + 576;
   double* part = sm + 16 * 64;
   Static st{diag, lev, Ad, A1, Al};
+  // the two aggregations: with the bfloat16 weights (T = float) their products take float32 X when
+  // float32 values are stored (float32 products, float64 sums; the network's inputs need no more),
+  // the float32 copy of X in tJ's space, which k_mpnn_out fills only after both
+  auto hprod = [&](const double* Xd, double* Yd) {
+    if constexpr (sizeof(T) == 4) {
+      if (H.val32) {
+        float* x32 = (float*)tJ;
+        copy_to_f32(n, S, Xd, S, x32, S, s);
+        spmm_f32(H, x32, S, Yd, S, S, nullptr, s);
+        return;
+      }
+    }
+    spmm_f64(H, Xd, S, Yd, S, S, nullptr, s);
+  };
   colsumsq(n, S, R, ldr, sumsq, part, s);
   k_scale_cols<<<gg(items), 256, 0, s>>>(n, S, R, ldr, sumsq, fr);
-  spmm_f64(H, fr, S, HF, S, S, nullptr, s);
+  hprod(fr, HF);
   k_mpnn_layer1<T><<<gg(items), 256, 0, s>>>(n, S, st, w, fr, HF, theta_dev, u, hs);
-  spmm_f64(H, u, S, Hu, S, S, nullptr, s);
+  hprod(u, Hu);
   k_mpnn_out<T><<<gg(items), 256, 0, s>>>(n, S, diag, w, R, ldr, theta_dev, hs, u, Hu, t, tJ);
   // t~ = t - x (x.t), or t - Q (Q^T t) with a basis
   k_fill_const<<<1, 64, 0, s>>>(S, 1.0, one);
