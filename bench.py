@@ -38,9 +38,9 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 # scaled by a plain-copy calibration (profiles/k_spmm_panel_*_hbm_counters.md).
 # Keyed by (workload, mode); valid only while the kernel source has the recorded sha256.
 MEASURED_TRAFFIC = {
-    # profiles/k_spmm_panel_L5-7.72M-k16_hbm_counters.md: per width-16 product of one solve (13 with float32 X,
-    # 13 with float64 X, the network's width-16 products included)
-    ("L5-2k/20k/200k/1.5M/6M-d300-k16", "mixed+rmmdiis+mpnn"): (184405181384,
+    # profiles/k_spmm_panel_L5-7.72M-k16_hbm_counters.md: per product the bench times (the library's own products of
+    # one solve: 13 with float32 X, 9 with float64 X)
+    ("L5-2k/20k/200k/1.5M/6M-d300-k16", "mixed+rmmdiis+mpnn"): (180413000000,
         "b24d19b347654d9e61af5f3cfd9da85c403873d830212cc4f350ede1e3cee8e0"),
 }
 
