@@ -96,7 +96,9 @@ typedef struct {
   int maxiter;         /* highest perturbation order of pure SPPC (Alg. 2 input); default 30 */
   int p_switch;        /* after this many SPPC steps switch to the continuation (0 = never) ; 15 */
   int max_cont;        /* continuation steps at most; default 200 */
-  int m_max;           /* basis columns kept; the continuation restarts beyond it; default 512 */
+  int m_max;           /* basis columns kept (2k..512); the continuation restarts beyond it.  0 (the
+                          default) = automatic: k (p_switch + 1) rounded up to 16 with the RMM-DIIS
+                          continuation (which restarts the basis at every sweep), else 512 */
   int n_deflate;       /* eigenpairs of H0hat computed and deflated in the small solves (>= k) */
   double tau_drop;     /* new column dropped when sin(angle to the basis) <= tau_drop */
   double inner_tol;    /* relative residual of the small-space solves; 0 = 1e-12 (FP64) / 1e-6 (MIXED) */

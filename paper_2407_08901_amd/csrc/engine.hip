@@ -872,6 +872,16 @@ void configure(sppc_ctx* c, const sppc_csr* Hin, const int64_t* loff, int L, int
   if (o.n_deflate < k || o.n_deflate > 28 || o.n_deflate > c->n0) throw Error(SPPC_E_ARG, "n_deflate must be in [k, min(28, n0)]");
   if (pj >= o.n_deflate) throw Error(SPPC_E_ARG, "n_deflate must exceed pair_index");
   c->D = o.n_deflate;
+  if (o.m_max == 0) {
+    // automatic: the RMM-DIIS continuation restarts the basis on the k refined vectors at every
+    // sweep, so the perturbative steps alone fill it (k columns per step, rounded up to 16 so that
+    // the rows stay 128-byte multiples); the Davidson continuations grow it past the switch: 512
+    const int lp = (o.p_switch > 0) ? std::min(o.p_switch, o.maxiter) : o.maxiter;
+    if (o.precond == SPPC_CORR_RMMDIIS && o.p_switch > 0 && lp >= 0)
+      o.m_max = (int)std::min<int64_t>(512, std::max<int64_t>(2 * k, ((int64_t)k * (lp + 1) + 15) / 16 * 16));
+    else
+      o.m_max = 512;
+  }
   if (o.m_max < 2 * k || o.m_max > 512) throw Error(SPPC_E_ARG, "m_max must be in [2k, 512]");
   if (o.panel_width < -1 || o.panel_width > 65536) throw Error(SPPC_E_ARG, "panel_width must be -1, 0 or 1..65536");
   if (o.panel_width > 0 && c->n >= ((int64_t)1 << 24))
@@ -1469,7 +1479,7 @@ sppc_status sppc_default_opts(sppc_opts* o) {
   o->maxiter = 30;
   o->p_switch = 15;
   o->max_cont = 200;
-  o->m_max = 512;
+  o->m_max = 0;  // automatic
   o->n_deflate = 0;
   o->tau_drop = 1e-10;
   o->inner_tol = 0.0;  // automatic: 1e-12 (float64), 1e-6 (mixed)
