@@ -111,8 +111,8 @@ def calibrate_copy():
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py: this build measures one GPU only (the multi-GPU path is not part of it); "
-              "run with --gpus 1", file=sys.stderr)
+        print("bench.py: the solver runs on one GPU (it has no multi-GPU path); run with --gpus 1",
+              file=sys.stderr)
         sys.exit(2)
     if args.calibrate_copy:
         calibrate_copy()

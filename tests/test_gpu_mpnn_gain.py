@@ -87,7 +87,7 @@ def test_learned_rmm_diis_step_on_held_out_five_level_matrices(P):
     eigenvalues.  Products with H, wall
     times and the pairs that the residual sent back to the diagonal step are printed: each learned
     application costs two products of its own, and where RMM-DIIS itself converges slowly (these
-    matrices take 30-120 iterations) many pairs miss the 0.9x reduction the judge asks of a
+    matrices take 30-120 iterations) many pairs miss the 0.9x reduction the residual check asks of a
     learned step."""
     from paper_2407_08901_amd import mpnn_train
     w5 = mpnn_train.load_for("rmmdiis", 5)
