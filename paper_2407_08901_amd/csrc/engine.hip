@@ -381,13 +381,22 @@ void zeroth_order(sppc_ctx* c) {
   unit_block(n0, nb, c->idx, c->Psi, nb, s);
   ortho_append(c, sb, c->Psi, nb, op, -1);
   const double tol = c->o.h0_tol;
+  // The eigenpairs kept only for the deflation of the small solves (beyond the wanted ones) need the
+  // accuracy of those solves, not more: a residual 1e-3 times their tolerance (1e-9 for the mixed
+  // form's 1e-6; the float64 form's 1e-12 keeps h0_tol)
+  const int nwant = std::max(c->k, c->o.pair_index + 1);
+  const double inner = c->o.inner_tol > 0.0 ? c->o.inner_tol
+                                            : (c->o.precision == SPPC_PREC_MIXED ? 1e-6 : 1e-12);
+  const double tol_defl = std::max(tol, 1e-3 * inner);
   int it = 0;
   for (;; ++it) {
     const int nw = sb.m;
     rayleigh_ritz(c, sb, nw);
     double worst = 0.0;
-    for (int i = 0; i < std::min(D, nw); ++i)
-      worst = std::max(worst, std::sqrt(std::max(0.0, c->pin[NWMAX + i])) / std::max(1.0, std::fabs(c->theta_h[i])));
+    for (int i = 0; i < std::min(D, nw); ++i) {
+      const double r = std::sqrt(std::max(0.0, c->pin[NWMAX + i])) / std::max(1.0, std::fabs(c->theta_h[i]));
+      worst = std::max(worst, i < nwant ? r : r * (tol / tol_defl));
+    }
     if ((worst <= tol && nw >= D) || nw == n0) break;
     if (it >= 400) throw Error(SPPC_E_BREAKDOWN, "eigensolver for H0hat did not converge");
     // filter interval [a, bup], scaled so that the lowest Ritz value maps to ~1
