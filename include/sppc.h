@@ -102,7 +102,9 @@ typedef struct {
   int n_deflate;       /* eigenpairs of H0hat computed and deflated in the small solves (>= k) */
   double tau_drop;     /* new column dropped when sin(angle to the basis) <= tau_drop */
   double inner_tol;    /* relative residual of the small-space solves; 0 = 1e-12 (FP64) / 1e-6 (MIXED) */
-  double h0_tol;       /* residual of the H0hat eigenpairs, relative to max(1,|E|) */
+  double h0_tol;       /* residual of the H0hat eigenpairs, relative to max(1,|E|); default 1e-12.
+                          The pairs beyond the wanted ones (kept only to deflate the small solves)
+                          stop at max(h0_tol, 1e-3 inner_tol): 1e-9 in the mixed form */
   int precision;       /* sppc_precision; MIXED adds a float64 refinement when the final check fails */
   int precond;         /* sppc_corr_kind used by the continuation (JACOBI, MPNN, SMALL or RMMDIIS); JACOBI */
   int final_check;     /* explicit float64 H Z, Rayleigh-Ritz on span Z, true residual */
