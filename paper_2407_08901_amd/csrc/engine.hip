@@ -877,7 +877,7 @@ void configure(sppc_ctx* c, const sppc_csr* Hin, const int64_t* loff, int L, int
   const int pj = o.pair_index;
   if (pj < -1 || pj > 26 || (pj >= 0 && (k != 1 || pj >= c->n0)))
     throw Error(SPPC_E_ARG, "pair_index must be -1, or 0..26 (below n0) with k = 1 (Alg. 1)");
-  if (o.n_deflate <= 0) o.n_deflate = std::min<int64_t>(std::min(std::max(2 * k, pj + 2), 28), c->n0);
+  if (o.n_deflate <= 0) o.n_deflate = std::min<int64_t>(std::min(std::max(3 * k, pj + 2), 28), c->n0);
   if (o.n_deflate < k || o.n_deflate > 28 || o.n_deflate > c->n0) throw Error(SPPC_E_ARG, "n_deflate must be in [k, min(28, n0)]");
   if (pj >= o.n_deflate) throw Error(SPPC_E_ARG, "n_deflate must exceed pair_index");
   c->D = o.n_deflate;

@@ -234,7 +234,7 @@ def test_zeroth_order_matches_dense():
     w = levelgen.WORKLOADS[0]
     A = w.generate()
     ctx = _ctx(A, w.n_small_levels, w.k)
-    D = 2 * w.k
+    D = min(3 * w.k, 28, w.n0)  # the default n_deflate
     E0 = np.array(P.sppc_get(ctx, 0, D))
     H0 = _H(A)[:w.n0, :w.n0].toarray()
     lam, U = np.linalg.eigh(H0)
@@ -393,7 +393,7 @@ def test_explicit_E0_shifts_equal_the_default():
     print("case explicit E0 shifts", flush=True)
     a = _ctx(A, w.n_small_levels, w.k, p_switch=0, maxiter=15, tol=1e-300, final_check=0)
     b = _ctx(A, w.n_small_levels, w.k, p_switch=0, maxiter=15, tol=1e-300, final_check=0)
-    E0 = P.sppc_get(b, 0, min(2 * w.k, 28))[:w.k]
+    E0 = P.sppc_get(b, 0, min(3 * w.k, 28, w.n0))[:w.k]
     for p in range(1, 4):
         P.sppc_correct(a, P.SPPC_CORR_PERTURBATIVE)
         P.sppc_correct(b, P.SPPC_CORR_PERTURBATIVE, shifts=E0)
