@@ -100,7 +100,9 @@ typedef struct {
                           default) = automatic: k (p_switch + 1) rounded up to 16 with the RMM-DIIS
                           continuation (which restarts the basis at every sweep), else 512 */
   int n_deflate;       /* eigenpairs of H0hat computed and deflated in the small solves (k..28);
-                          0 (the default) = min(3k, 28, n0), with pair_index j at least j + 2 */
+                          0 (the default) = min(3k, 28, n0) with small solves to 1e-9 or tighter (the
+                          float64 default), min(2k, 28, n0) with looser ones (the mixed default); with
+                          pair_index j at least j + 2 */
   double tau_drop;     /* new column dropped when sin(angle to the basis) <= tau_drop */
   double inner_tol;    /* relative residual of the small-space solves; 0 = 1e-12 (FP64) / 1e-6 (MIXED) */
   double h0_tol;       /* residual of the H0hat eigenpairs, relative to max(1,|E|); default 1e-12.
@@ -128,7 +130,7 @@ typedef struct {
                           Alg. 1 for the j-th eigenpair alone (j = 0 the lowest): the zeroth order is
                           the j-th eigenpair of H0hat, the subspace the span of its own corrections,
                           the approximation the lowest Ritz pair of that subspace (which may move to a
-                          lower eigenvalue, Sec. VI).  n_deflate (default max(3, j + 2), at most 28)
+                          lower eigenvalue, Sec. VI).  n_deflate (default at least j + 2, at most 28)
                           must exceed j; sppc_get(what = 0) then lists E_j^(0) first */
   int rmm_precond;     /* step of the RMM-DIIS continuation: SPPC_CORR_JACOBI (the diagonal step,
                           default) or SPPC_CORR_MPNN (the learned correction of the diagonal step,

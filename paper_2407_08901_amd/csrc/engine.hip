@@ -877,7 +877,14 @@ void configure(sppc_ctx* c, const sppc_csr* Hin, const int64_t* loff, int L, int
   const int pj = o.pair_index;
   if (pj < -1 || pj > 26 || (pj >= 0 && (k != 1 || pj >= c->n0)))
     throw Error(SPPC_E_ARG, "pair_index must be -1, or 0..26 (below n0) with k = 1 (Alg. 1)");
-  if (o.n_deflate <= 0) o.n_deflate = std::min<int64_t>(std::min(std::max(3 * k, pj + 2), 28), c->n0);
+  if (o.n_deflate <= 0) {
+    // tight small solves (the float64 form's 1e-12) take fewer CG iterations with more deflated
+    // directions; inexact ones (1e-6) gain nothing from them, and their deflation-only eigenpairs stop
+    // at 1e-9 (zeroth_order), which with more of them costs continuation steps (measured at k = 8)
+    const double inner = o.inner_tol > 0.0 ? o.inner_tol : (o.precision == SPPC_PREC_MIXED ? 1e-6 : 1e-12);
+    const int mult = inner <= 1e-9 ? 3 : 2;
+    o.n_deflate = std::min<int64_t>(std::min(std::max(mult * k, pj + 2), 28), c->n0);
+  }
   if (o.n_deflate < k || o.n_deflate > 28 || o.n_deflate > c->n0) throw Error(SPPC_E_ARG, "n_deflate must be in [k, min(28, n0)]");
   if (pj >= o.n_deflate) throw Error(SPPC_E_ARG, "n_deflate must exceed pair_index");
   c->D = o.n_deflate;

@@ -258,7 +258,7 @@ def test_bad_shifts_are_refused(P):
     print("case edge shifts", flush=True)
     rp, col, val = P.upload(A)
     ctx = P.sppc_setup(rp, col, val, A.level_offsets, w.n_small_levels, w.k, P.sppc_default_opts())
-    D = min(3 * w.k, 28, w.n0)  # the default n_deflate
+    D = min(3 * w.k, 28, w.n0)  # the float64 form's default n_deflate
     top = P.sppc_get(ctx, 0, D)[-1]
     for bad, code in (([top + 1.0] * w.k, P.SPPC_E_ARG), ([float("nan")] * w.k, P.SPPC_E_ARG),
                       ([0.0] * w.k, P.SPPC_E_ARG)):  # E^(0) < 0 here: zero lies above E_D^(0)

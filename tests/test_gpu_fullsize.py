@@ -235,7 +235,7 @@ def test_against_the_stored_oracle_solution(wl):
     k = wl.k
     if "sppc_steps" in ref:
         ctx = ctx_of(p_switch=0, maxiter=15, tol=1e-300, final_check=0)
-        D = int(min(3 * k, 28, wl.n0))  # the default n_deflate
+        D = int(min(3 * k, 28, wl.n0))  # the float64 form's default n_deflate
         E0 = np.array(P.sppc_get(ctx, 0, D))
         E0r = np.array(ref["E0"][:D])
         assert np.max(np.abs(E0 - E0r) / np.maximum(1.0, np.abs(E0r))) < 1e-12

@@ -234,7 +234,7 @@ def test_zeroth_order_matches_dense():
     w = levelgen.WORKLOADS[0]
     A = w.generate()
     ctx = _ctx(A, w.n_small_levels, w.k)
-    D = min(3 * w.k, 28, w.n0)  # the default n_deflate
+    D = min(3 * w.k, 28, w.n0)  # the float64 form's default n_deflate
     E0 = np.array(P.sppc_get(ctx, 0, D))
     H0 = _H(A)[:w.n0, :w.n0].toarray()
     lam, U = np.linalg.eigh(H0)
