@@ -227,7 +227,9 @@ sppc_status sppc_spmm(sppc_ctx* ctx, const void* X_dev, sppc_dtype xt, double* Y
  * bytes of the full-storage product at the price of those scattered adds.
  *   H       the caller's upper CSR (as for sppc_setup), float64 or float32 values; only read
  *   X_dev   row-major n x b, float64 (xt = SPPC_F64) or float32 (SPPC_F32), only read
- *   Y_dev   row-major n x b, float64, overwritten (zeroed, then accumulated); must not overlap X
+ *   Y_dev   row-major n x b, float64, overwritten (zeroed, then accumulated); must not overlap X, and
+ *           must be ordinary device memory (hipMalloc or a torch tensor): the float64 atomic adds run
+ *           in the device's caches and memory, not across PCIe
  *   b       1..32
  *   stream  hipStream_t (as void*), NULL for the default stream; asynchronous on it
  * float64 X: float64 products of the values as stored.  float32 X: each value rounded to float32,
