@@ -38,6 +38,8 @@ design notes of the repository):
     residual certify the returned pairs;
   * the hybrid of Sec. V-VI refines each unconverged pair by RMM-DIIS in sweeps
     of 4 iterations with Rayleigh-Ritz on the refined vectors between sweeps;
+    when the largest residual has not halved over three sweeps (rmm_stagnated)
+    the refined Ritz vectors hand over to the Davidson continuation above;
   * optionally the switch comes early, once SPPC stagnates (sppc_stagnated;
     the paper leaves the detection open, Sec. VII);
   * Alg. 1 (sppc_pair): the same iteration for one pair alone, its zeroth order
@@ -434,6 +436,19 @@ def sppc_stagnated(hist: List[dict]) -> bool:
     return len(hist) >= 4 and not (max(hist[-1]["rrn"]) < 0.5 * max(hist[-4]["rrn"]))
 
 
+def rmm_stagnated(top: List[float]) -> bool:
+    """The hand-over of the RMM-DIIS refinement to the Davidson continuation.
+
+    top[0] is the largest residual norm at the switch, top[s] the largest after sweep s (after the
+    Rayleigh-Ritz rotation).  The refinement has stagnated when the largest residual has not halved
+    since three sweeps before, the residual clause of sppc_stagnated applied to the sweeps.  A pair
+    whose minimal-residual step along the diagonally preconditioned residual becomes orthogonal to
+    the residual (an interior pair: H - theta and the preconditioner are both indefinite) makes no
+    progress however many sweeps follow.
+    """
+    return len(top) >= 4 and not (top[-1] < 0.5 * top[-4])
+
+
 def sppc_pair(H: sp.csr_matrix, n0: int, kk: int, opts: Options = Options(),
               callback: Optional[Callable] = None) -> Result:
     """Alg. 1: SPPC for the kk-th eigenpair alone (kk = 0 is the lowest).
@@ -509,6 +524,8 @@ def sppc(H: sp.csr_matrix, n0: int, k: int, opts: Options = Options(),
     # the k refined vectors (the subspace rotation of multi-pair RMM-DIIS: it separates pairs whose
     # eigenvalues are close, which a single-vector iteration resolves only slowly)
     done_its = 0
+    stagnated = False
+    top = [float(np.max(rrn))]
     while not converged and opts.continuation and opts.rmm_diis and done_its < opts.max_cont:
         sweep = 0
         for i in np.nonzero(rrn >= opts.tol)[0]:
@@ -526,10 +543,22 @@ def sppc(H: sp.csr_matrix, n0: int, k: int, opts: Options = Options(),
                          m=Q.shape[1], n_spmv=n_spmv))
         if callback:
             callback(hist[-1])
+        top.append(float(np.max(rrn)))
+        if not converged and rmm_stagnated(top):
+            # the Davidson continuation takes over from the refined Ritz vectors.  The basis
+            # restarts on them (it does not hold them), with their products taken afresh: the
+            # H x that RMM-DIIS carries through its combinations has drifted from H Z by
+            # rounding, and Rayleigh-Ritz on the drifted columns cannot see below that drift
+            stagnated = True
+            Q = Z.copy()
+            HQ = H @ Q
+            n_spmv += k
+            break
 
-    # continuation with preconditioned residual blocks
-    it = 0
-    while not converged and opts.continuation and not opts.rmm_diis and it < opts.max_cont:
+    # continuation with preconditioned residual blocks (after a stagnated RMM-DIIS refinement it
+    # shares that refinement's budget of max_cont iterations)
+    it = done_its if stagnated else 0
+    while not converged and opts.continuation and (stagnated or not opts.rmm_diis) and it < opts.max_cont:
         it += 1
         R = HZ - Z * theta[None, :]
         act = np.nonzero(rrn >= opts.tol)[0]

@@ -426,6 +426,37 @@ def test_hybrid_sppc_rmm_diis_reaches_the_eigenvalues():
     assert np.max(np.abs(r.theta - lam) / np.abs(lam)) < 1e-12
 
 
+def test_rmm_stagnation_rule():
+    # the largest residual after each sweep (top[0]: at the switch) must halve within three sweeps
+    f = oracle.core.rmm_stagnated
+    assert not f([1.0, 0.9, 0.8])                 # fewer than three sweeps
+    assert f([1.0, 0.9, 0.8, 0.5])                # exactly half is not below half
+    assert not f([1.0, 0.9, 0.8, 0.49])
+    assert f([1.0, 0.1, 0.09, 0.08, 0.06])        # against three sweeps back, not the switch
+
+
+def test_hybrid_hands_over_where_rmm_diis_stagnates():
+    # Pair 4 of this five-level matrix is interior (three eigenvalues below its Ritz value, and one
+    # diagonal entry): the minimal-residual step along its diagonally preconditioned residual turns
+    # orthogonal to that residual once a sweep restarts the DIIS history, and RMM-DIIS alone holds it
+    # near 2e-6 for all 200 iterations.  The sweeps stagnate, the Davidson continuation takes over
+    # from the refined Ritz vectors and reaches the eigenvalues of ARPACK's Lanczos (shift-free,
+    # smallest algebraic) to the Kato-Temple bound.
+    from scipy.sparse.linalg import eigsh
+    A = levelgen.generate((7, 61, 509, 3001, 7919), 30, 505)
+    H = oracle.symmetric_from_upper(A.row_ptr, A.col, A.val, A.n)
+    lam = np.sort(eigsh(H, k=4, which="SA", tol=1e-14, v0=np.ones(A.n))[0])
+    r = oracle.sppc(H, int(A.level_offsets[2]), 4, oracle.Options(tol=1e-6, rmm_diis=True, max_cont=200))
+    phases = [h["phase"] for h in r.history]
+    assert r.converged and "cont" in phases
+    i = phases.index("cont")
+    assert "rmmdiis" in phases[:i] and set(phases[i:]) == {"cont"}
+    top = [max(h["rrn"]) for h in r.history if h["phase"] in ("sppc", "rmmdiis")][-(phases.count("rmmdiis") + 1):]
+    assert oracle.core.rmm_stagnated(top) and not oracle.core.rmm_stagnated(top[:-1])
+    assert top[-1] > 1e-6  # stalled above the tolerance
+    assert np.max(np.abs(r.theta - lam) / np.abs(lam)) < 1e-12
+
+
 # --- the stagnation diagnostic of Fig. 3: the recorded angle of each correction vector is the sine
 # of its principal angle to the span of all earlier correction vectors (LAPACK-based
 # scipy.linalg.subspace_angles on the raw vectors of the Rayleigh-Schrodinger recursion)
