@@ -75,9 +75,12 @@ typedef enum {
                                  by RMM-DIIS (Pulay's DIIS over the pair's iterates of the current sweep,
                                  at most 5, then the residual-minimising step along
                                  (diag(H) - theta)^-1 r or the learned step (rmm_precond); one product
-                                 with H per pair and iteration, the pairs batched); at most max_cont
-                                 iterations; the final check takes Rayleigh-Ritz on the refined
-                                 vectors.  sppc_solve only (not a block for sppc_correct); not a
+                                 with H per pair and iteration, the pairs batched), in sweeps of 4
+                                 with Rayleigh-Ritz on the refined vectors between them; once the
+                                 largest residual has not halved over three sweeps the Davidson
+                                 continuation with the diagonal step takes over from the refined Ritz
+                                 vectors; at most max_cont iterations and steps in all; the final
+                                 check takes Rayleigh-Ritz on the refined vectors.  sppc_solve only (not a block for sppc_correct); not a
                                  refine_precond */
 } sppc_corr_kind;
 
@@ -164,6 +167,9 @@ typedef struct {
   double t_h0_ms;      /* time inside products with H0hat outside the small solves */
   int mpnn_fallbacks;  /* pairs that the true residual sent back to the diagonal step */
   int64_t workspace_peak; /* bytes of the caller's workspace in use at the peak so far (0 without one) */
+  int rmm_iterations;  /* RMM-DIIS iterations of the SPPC + RMM-DIIS hybrid (counted in cont_steps) */
+  int rmm_handover;    /* 1 if stagnated RMM-DIIS sweeps handed over to the Davidson continuation with
+                          the diagonal step (the largest residual did not halve over three sweeps) */
 } sppc_stats;
 
 typedef struct sppc_ctx sppc_ctx;

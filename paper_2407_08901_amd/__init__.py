@@ -57,7 +57,8 @@ class sppc_stats(ctypes.Structure):
                 ("converged", ctypes.c_int), ("t_setup_ms", ctypes.c_double), ("t_solve_ms", ctypes.c_double),
                 ("t_spmm_ms", ctypes.c_double), ("t_small_ms", ctypes.c_double), ("t_ortho_ms", ctypes.c_double),
                 ("t_rr_ms", ctypes.c_double), ("spmm_alg_bytes", ctypes.c_double), ("t_h0_ms", ctypes.c_double),
-                ("mpnn_fallbacks", ctypes.c_int), ("workspace_peak", ctypes.c_int64)]
+                ("mpnn_fallbacks", ctypes.c_int), ("workspace_peak", ctypes.c_int64),
+                ("rmm_iterations", ctypes.c_int), ("rmm_handover", ctypes.c_int)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

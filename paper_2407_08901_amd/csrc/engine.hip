@@ -776,6 +776,17 @@ bool sppc_stagnates(const sppc_ctx* c, const std::vector<double>& top) {
   return h >= 4 && !(top[h - 1] < 0.5 * top[h - 4]);
 }
 
+// The hand-over of the RMM-DIIS refinement to the Davidson continuation: top[0] is the largest
+// residual at the switch, top[s] the largest after sweep s.  It has stagnated when that residual
+// has not halved since three sweeps before (the residual clause of the SPPC rule above).  An
+// interior pair whose minimal-residual step along the diagonally preconditioned residual turns
+// orthogonal to the residual (H - theta and the preconditioner both indefinite) gains nothing
+// from further sweeps.
+bool rmm_stagnates(const std::vector<double>& top) {
+  const size_t h = top.size();
+  return h >= 4 && !(top[h - 1] < 0.5 * top[h - 4]);
+}
+
 bool all_converged(sppc_ctx* c) {
   for (int i = 0; i < c->k; ++i)
     if (!(c->rrn_h[i] < c->o.tol)) return false;
@@ -1266,12 +1277,18 @@ int rmm_diis_sweep(sppc_ctx* c, int cap) {
 // Sweeps of at most 4 RMM-DIIS iterations per pair; between sweeps, Rayleigh-Ritz on the span of
 // the k refined vectors (the subspace rotation of multi-pair RMM-DIIS: it separates pairs whose
 // eigenvalues are close, which a single-vector iteration resolves only slowly).  The rotation
-// needs no product: the refined vectors carry H x.  The basis restarts on them.
-int rmm_diis_phase(sppc_ctx* c) {
+// needs no product: the refined vectors carry H x.  The basis restarts on them.  Once the sweeps
+// stagnate (rmm_stagnates) *handover is set and the basis restarts on the refined Ritz vectors
+// with their products taken afresh (the H x carried through the DIIS combinations has drifted
+// from H Z by rounding, and Rayleigh-Ritz on drifted columns cannot see below that drift); the
+// Davidson continuation goes on from there.  Returns the number of iterations.
+int rmm_diis_phase(sppc_ctx* c, bool* handover) {
   const sppc_opts& o = c->o;
   const int k = c->k;
   Op op{c, &c->H, false, true};
   int total = 0;
+  std::vector<double> top{max_rrn(c)};
+  *handover = false;
   for (bool first = true;; first = false) {
     if (!first) {
       c->B.m = 0;
@@ -1279,6 +1296,18 @@ int rmm_diis_phase(sppc_ctx* c) {
       if (kept < k) throw Error(SPPC_E_BREAKDOWN, "RMM-DIIS: the refined vectors became linearly dependent");
       rayleigh_ritz(c, c->B, k);
       c->restarted = true;
+      top.push_back(max_rrn(c));
+      if (!all_converged(c) && rmm_stagnates(top)) {
+        // the products of the continuation's basis (float32 X in mixed precision until its
+        // residuals fall below kMixedF64Below)
+        Op opc{c, &c->H, o.precision == SPPC_PREC_MIXED && !c->refining && !c->f64_products, true};
+        c->B.m = 0;
+        if (ortho_append(c, c->B, c->Z, k, opc, -1, nullptr) < k)
+          throw Error(SPPC_E_BREAKDOWN, "RMM-DIIS: the refined vectors became linearly dependent");
+        rayleigh_ritz(c, c->B, k);
+        *handover = true;
+        break;
+      }
     }
     if (all_converged(c) || total >= o.max_cont) break;
     total += std::max(1, rmm_diis_sweep(c, std::min(RMM_SWEEP, o.max_cont - total)));
@@ -1306,14 +1335,25 @@ sppc_status solve_impl(sppc_ctx* c, double* evals, double* evecs, double* rrn, s
   }
   c->st.iterations = c->p;
   int cont = 0;
+  // the Davidson continuation: the default after the switch, and where RMM-DIIS stagnates
+  bool davidson = o.p_switch > 0 && o.precond != SPPC_CORR_RMMDIIS;
+  int kind = o.precond;
   if (o.p_switch > 0 && o.precond == SPPC_CORR_RMMDIIS) {
     if (!conv) {
-      cont = rmm_diis_phase(c);
+      bool handover = false;
+      cont = rmm_diis_phase(c, &handover);
+      c->st.rmm_iterations = cont;
+      c->st.rmm_handover = handover ? 1 : 0;
       log_step(c, "rmmdiis");
       conv = all_converged(c);
+      if (handover && !conv) {
+        log_step(c, "handover");
+        davidson = true;
+        kind = SPPC_CORR_JACOBI;
+      }
     }
-  } else if (o.p_switch > 0) {
-    const int kind = o.precond;
+  }
+  if (davidson) {
     std::vector<double> hist;  // max residual per continuation step (mixed hand-over test)
     while (!conv && cont < o.max_cont) {
       correct_continuation(c, kind);

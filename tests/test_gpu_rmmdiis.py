@@ -2,11 +2,14 @@
 
 On a four-level matrix with the level ratios, density and k of the bench workload at 1/10 of its
 size (n = 117,200, k = 8), where the perturbative steps leave residuals near 1e-5, both refine
-every pair by RMM-DIIS in sweeps of 4 iterations with Rayleigh-Ritz between sweeps: the
-eigenvalues agree to 1e-10 (solved to rrn 1e-9), the GPU's true residuals (the oracle's product)
-meet the tolerance, and the iteration counts agree to within one sweep (the GPU batches the
-pairs; the arithmetic order of its reductions differs).  The mixed form with the hybrid agrees
-with float64 to 1e-8.
+every pair by RMM-DIIS in sweeps of 4 iterations with Rayleigh-Ritz between sweeps.  Solved to rrn
+1e-9, the sweeps there slow to a factor of about 0.9 per sweep, and both hand over to the Davidson
+continuation after the same sweep.  The eigenvalues agree to 1e-10, the GPU's true residuals (the
+oracle's product) meet the tolerance, and the RMM-DIIS iteration counts agree to within one sweep
+(the GPU batches the pairs; the arithmetic order of its reductions differs), the Davidson steps
+after the hand-over to within three.  The mixed form with the hybrid agrees with float64 to 1e-8.
+The last test takes a five-level matrix whose interior pair stalls in RMM-DIIS alone (its step
+turns orthogonal to its residual) through the hand-over, float64 and mixed, at 1e-6 and 1e-9.
 """
 import numpy as np
 import pytest
@@ -32,7 +35,9 @@ def _ref():
     if "ref" not in _CACHE:
         A = W.generate()
         H = oracle.symmetric_from_upper(A.row_ptr, A.col, A.val, A.n)
-        r = oracle.sppc(H, W.n0, W.k, oracle.Options(tol=1e-9, rmm_diis=True, max_cont=200))
+        # the basis of the Davidson continuation restarts at 16 k columns, as the solver's
+        # automatic size for the hybrid
+        r = oracle.sppc(H, W.n0, W.k, oracle.Options(tol=1e-9, rmm_diis=True, max_cont=200, m_max=16 * W.k))
         its = sum(max(h["iterations"], 1) for h in r.history if h["phase"] == "rmmdiis")
         _CACHE["ref"] = (A, r, its)
     return _CACHE["ref"]
@@ -58,7 +63,12 @@ def test_hybrid_matches_the_oracle(P):
     Zh = Z.cpu().numpy()
     R = oracle.product_from_upper(A.row_ptr, A.col, A.val, A.n, Zh) - Zh * np.array(ev)[None, :]
     assert np.max(np.linalg.norm(R, axis=0) / np.abs(ev)) < 1e-9
-    assert abs(st["cont_steps"] - its) <= 4, (st["cont_steps"], its)
+    dav = sum(h["phase"] == "cont" for h in r.history)
+    print("oracle: %d RMM-DIIS iterations, %d Davidson steps; GPU: %d, %d" %
+          (its, dav, st["rmm_iterations"], st["cont_steps"] - st["rmm_iterations"]), flush=True)
+    assert st["rmm_handover"] == (1 if dav else 0)
+    assert abs(st["rmm_iterations"] - its) <= 4, (st["rmm_iterations"], its)
+    assert abs(st["cont_steps"] - st["rmm_iterations"] - dav) <= 3
 
 
 def test_mixed_hybrid_agrees_with_float64(P):
@@ -67,3 +77,30 @@ def test_mixed_hybrid_agrees_with_float64(P):
     ev, Z, rrn, st, status = _solve(P, A, precision=P.SPPC_PREC_MIXED)
     assert status == P.SPPC_OK and st["converged"] == 1 and max(rrn) < 1e-6
     assert np.max(np.abs(np.array(ev) - r.theta) / np.abs(r.theta)) < 1e-8
+
+
+def test_stagnated_sweeps_hand_over_to_the_davidson_continuation(P):
+    # pair 4 is interior (three eigenvalues below it): RMM-DIIS alone stalls near 2e-6 for all
+    # 200 iterations; the hand-over reaches the oracle's eigenvalues
+    A = levelgen.generate((7, 61, 509, 3001, 7919), 30, 505)
+    H = oracle.symmetric_from_upper(A.row_ptr, A.col, A.val, A.n)
+    rp, col, val = P.upload(A)
+    for tol in (1e-6, 1e-9):
+        r = oracle.sppc(H, 68, 4, oracle.Options(tol=tol, rmm_diis=True, max_cont=200, m_max=64))
+        its = sum(max(h["iterations"], 1) for h in r.history if h["phase"] == "rmmdiis")
+        assert r.converged and any(h["phase"] == "cont" for h in r.history)
+        for prec in (P.SPPC_PREC_FP64, P.SPPC_PREC_MIXED):
+            print("case rmmdiis hand-over n=%d tol=%g precision=%d oracle its %d" % (A.n, tol, prec, its), flush=True)
+            ctx = P.sppc_setup(rp, col, val, A.level_offsets, 2, 4,
+                               P.sppc_default_opts(precond=P.SPPC_CORR_RMMDIIS, tol=tol, max_cont=200, precision=prec))
+            ev, Z, rrn, st, status = P.sppc_solve(ctx)
+            P.sppc_destroy(ctx)
+            assert status == P.SPPC_OK and st["converged"] == 1
+            ev = np.array(ev)
+            Zh = Z.cpu().numpy()
+            R = oracle.product_from_upper(A.row_ptr, A.col, A.val, A.n, Zh) - Zh * ev[None, :]
+            assert np.max(np.linalg.norm(R, axis=0) / np.abs(ev)) < tol
+            bound = 1e-10 if prec == P.SPPC_PREC_FP64 else 1e-8
+            assert np.max(np.abs(ev - r.theta) / np.abs(r.theta)) < max(bound, 10 * tol * tol)
+            if prec == P.SPPC_PREC_FP64:
+                assert st["rmm_handover"] == 1 and abs(st["rmm_iterations"] - its) <= 4, (st["rmm_iterations"], its)
