@@ -80,7 +80,9 @@ typedef enum {
                                  largest residual has not halved over three sweeps the Davidson
                                  continuation with the diagonal step takes over from the refined Ritz
                                  vectors; at most max_cont iterations and steps in all; the final
-                                 check takes Rayleigh-Ritz on the refined vectors.  sppc_solve only (not a block for sppc_correct); not a
+                                 check takes Rayleigh-Ritz on the refined vectors, and if its true
+                                 residuals miss the tolerance the float64 refinement follows
+                                 (refine_precond), as after a mixed solve.  sppc_solve only (not a block for sppc_correct); not a
                                  refine_precond */
 } sppc_corr_kind;
 
@@ -121,7 +123,8 @@ typedef struct {
                           column in 24 bits: an explicit width with n >= 2^24 is refused by
                           sppc_setup (SPPC_E_ARG), and the automatic choice then keeps the row-wise
                           products over the full CSR */
-  int refine_precond;  /* continuation kind of the float64 refinement after a mixed solve; SMALL */
+  int refine_precond;  /* continuation kind of the float64 refinement after a failed check of a mixed
+                          solve or of the SPPC + RMM-DIIS hybrid; SMALL */
   double precond_tol;  /* relative residual of the small-space solve inside SMALL; 1e-3 */
   int auto_switch;     /* 1: switch to the continuation before p_switch once SPPC stagnates: after a
                           step the smallest sine of the angle between a new correction vector and
@@ -145,7 +148,8 @@ typedef struct {
 typedef struct {
   int iterations;      /* SPPC steps p reached */
   int cont_steps;      /* continuation steps (refinement steps included) */
-  int refine_steps;    /* float64 refinement steps after a mixed-precision solve */
+  int refine_steps;    /* float64 refinement steps after a failed check of a mixed-precision solve or
+                          of the float64 SPPC + RMM-DIIS hybrid */
   int mpnn_steps;      /* continuation steps that used the learned preconditioner */
   int64_t n_spmv;      /* products of H with one vector (k per SPPC step, Sec. IV.C; a learned step
                           adds the network's two per pair) */

@@ -297,7 +297,8 @@ int ortho_append(sppc_ctx* c, Basis& b, const double* P, int bw, const Op& op, i
   SPPC_HIP(hipMemcpyAsync(c->pin_i, c->info, sizeof(int) * 2, hipMemcpyDeviceToHost, s));
   SPPC_HIP(hipMemcpyAsync(c->pin, c->angles, sizeof(double) * bw, hipMemcpyDeviceToHost, s));
   sync(c);
-  const int kept = std::min(c->pin_i[0], std::max(0, b.ldq - m));
+  // never more basis columns than rows
+  const int kept = std::min(c->pin_i[0], std::max(0, (int)std::min<int64_t>(b.ldq, n) - m));
   c->angles_h.assign(c->pin, c->pin + bw);
   if (kept > 0) {
     t0 = c->tm.begin(C_ORTHO);
@@ -1380,8 +1381,11 @@ sppc_status solve_impl(sppc_ctx* c, double* evals, double* evecs, double* rrn, s
     conv = all_converged(c);
     // mixed precision: the float32 products limit what the loop's residuals can see; restart on
     // the checked Ritz vectors (float64 H Z) and continue with float64 products until the true
-    // residual meets the tolerance
-    if (!conv && o.precision == SPPC_PREC_MIXED && o.p_switch > 0) {
+    // residual meets the tolerance.  The float64 SPPC + RMM-DIIS hybrid takes the same path: its
+    // residuals come from the H x carried through the DIIS combinations, which can sit just below
+    // the tolerance while the checked ones sit just above it
+    const bool rmm64 = o.precond == SPPC_CORR_RMMDIIS && o.precision != SPPC_PREC_MIXED;
+    if (!conv && (o.precision == SPPC_PREC_MIXED || rmm64) && o.p_switch > 0) {
       // New basis columns get float64 products.  The basis is kept at first (its float32-product
       // columns still span the directions found so far); the loop's residuals carry the float32
       // noise, so each round ends with the float64 check, which decides convergence.  The

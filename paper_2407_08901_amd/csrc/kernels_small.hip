@@ -561,6 +561,13 @@ __global__ __launch_bounds__(EIG_THREADS) void k_sym_eig(int m, int nw, const do
 // ---------------------------------------------------------------- Cholesky-QR factors
 constexpr int KB = 32;
 
+// A column whose Schur complement (what remains of it after the pivots taken) has fallen to this
+// fraction of its own Gram diagonal is dependent on those pivots: the complement of a Gram matrix
+// carries rounding of about b eps times that diagonal (b <= 32), so below ~1e-14 it is noise, and
+// keeping it would normalise rounding into a basis vector.  1e-12 (a remaining part of 1e-6 of the
+// column's norm) leaves the second Cholesky-QR pass a condition number of at most ~1e6.
+constexpr double kRelPivot = 1e-12;
+
 // Pivoted Cholesky of G restricted to the columns whose angle exceeds tau (one wave, LDS).
 __global__ __launch_bounds__(64) void k_cholqr_first(int b, const double* __restrict__ G,
                                                      const double* __restrict__ psi2, double tau,
@@ -571,6 +578,7 @@ __global__ __launch_bounds__(64) void k_cholqr_first(int b, const double* __rest
   __shared__ double Ri[KB][KB + 1];
   __shared__ int perm[KB];
   __shared__ int cand[KB];
+  __shared__ double gd[KB];
   __shared__ int best_sh, stop_sh;
   __shared__ double r_sh;
   const int t = threadIdx.x;
@@ -583,6 +591,7 @@ __global__ __launch_bounds__(64) void k_cholqr_first(int b, const double* __rest
     const double a = sqrt(fmax(G[t * b + t], 0.0) / pn);
     angles[t] = a;
     cand[t] = a > tau;
+    gd[t] = G[t * b + t];
   }
   __syncthreads();
   int s = 0;
@@ -590,8 +599,10 @@ __global__ __launch_bounds__(64) void k_cholqr_first(int b, const double* __rest
     if (t == 0) {
       int best = -1;
       double bv = 0.0;
-      for (int i = 0; i < b; ++i)
+      for (int i = 0; i < b; ++i) {
+        if (cand[i] && !(W[i][i] > kRelPivot * gd[i])) cand[i] = 0;  // dependent on the pivots
         if (cand[i] && W[i][i] > bv) { bv = W[i][i]; best = i; }
+      }
       int stop = best < 0;
       if (!stop) {
         const double pn = psi2[best] > 0.0 ? psi2[best] : 1.0;

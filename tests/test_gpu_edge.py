@@ -63,6 +63,30 @@ def test_tiny_ragged_levels(P):
     assert np.max(np.abs(np.array(ev) - lam) / np.abs(lam)) < 1e-10
 
 
+def test_basis_that_fills_the_whole_space(P):
+    # n = 285, k = 14, solved to 1e-9: the 15 perturbative steps alone fill 224 columns, and the
+    # continuation brings the basis to all n directions.  The last blocks are then dependent on the
+    # basis and on each other; the Cholesky-QR must drop what only rounding keeps apart (the oracle's
+    # pivoted Householder QR does), or the basis loses orthogonality and the solve breaks down.
+    A = levelgen.generate((33, 252), 79, 275309)
+    print("case edge full basis n=%d" % A.n, flush=True)
+    H = oracle.symmetric_from_upper(A.row_ptr, A.col, A.val, A.n)
+    lam = np.linalg.eigvalsh(H.toarray())[:14]
+    r = oracle.sppc(H, 33, 14, oracle.Options(tol=1e-9))
+    assert r.converged and r.Q.shape[1] == A.n
+    for prec in (P.SPPC_PREC_FP64, P.SPPC_PREC_MIXED):
+        rp, col, val = P.upload(A)
+        ctx = P.sppc_setup(rp, col, val, A.level_offsets, 1, 14, P.sppc_default_opts(tol=1e-9, precision=prec))
+        ev, Z, rrn, st, status = P.sppc_solve(ctx)
+        P.sppc_destroy(ctx)
+        assert status == P.SPPC_OK and st["basis_size"] <= A.n, (status, st["basis_size"])
+        ev = np.array(ev)
+        Zh = Z.cpu().numpy()
+        assert np.max(np.abs(Zh.T @ Zh - np.eye(14))) < 1e-12
+        assert np.max(np.linalg.norm(H @ Zh - Zh * ev[None, :], axis=0) / np.abs(ev)) < 1e-9
+        assert np.max(np.abs(ev - lam) / np.abs(lam)) < 1e-12
+
+
 def test_small_space_is_everything(P):
     # n0 = n: H0 = H and V = 0, so the zeroth order is exact (converged at p = 0)
     A = levelgen.generate((40, 300), 20, 8)

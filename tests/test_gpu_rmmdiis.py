@@ -104,3 +104,27 @@ def test_stagnated_sweeps_hand_over_to_the_davidson_continuation(P):
             assert np.max(np.abs(ev - r.theta) / np.abs(r.theta)) < max(bound, 10 * tol * tol)
             if prec == P.SPPC_PREC_FP64:
                 assert st["rmm_handover"] == 1 and abs(st["rmm_iterations"] - its) <= 4, (st["rmm_iterations"], its)
+
+
+def test_float64_hybrid_that_ends_at_the_tolerance_is_refined(P):
+    # SPPC + RMM-DIIS at 1e-9 on a three-level matrix (n = 4,276, k = 16) whose last sweep leaves the
+    # largest residual at 9.44e-10 (oracle): the residuals RMM-DIIS sees come from the H x it carries
+    # through the DIIS combinations, so with the GPU's rounding the float64 check can put that pair just
+    # above the tolerance; the float64 refinement from the checked Ritz vectors then finishes the solve
+    A = levelgen.generate((54, 451, 3771), 46, 789128)
+    H = oracle.symmetric_from_upper(A.row_ptr, A.col, A.val, A.n)
+    lam = np.linalg.eigvalsh(H.toarray())[:16]
+    rp, col, val = P.upload(A)
+    print("case rmmdiis float64 at the tolerance n=%d" % A.n, flush=True)
+    for rep in range(3):
+        ctx = P.sppc_setup(rp, col, val, A.level_offsets, 2, 16,
+                           P.sppc_default_opts(precond=P.SPPC_CORR_RMMDIIS, tol=1e-9, max_cont=200))
+        ev, Z, rrn, st, status = P.sppc_solve(ctx)
+        P.sppc_destroy(ctx)
+        print("run %d: %d RMM-DIIS iterations, %d refinement steps" % (rep, st["rmm_iterations"], st["refine_steps"]), flush=True)
+        assert status == P.SPPC_OK and st["converged"] == 1
+        ev = np.array(ev)
+        Zh = Z.cpu().numpy()
+        R = H @ Zh - Zh * ev[None, :]
+        assert np.max(np.linalg.norm(R, axis=0) / np.abs(ev)) < 1e-9
+        assert np.max(np.abs(ev - lam) / np.abs(lam)) < 1e-11
