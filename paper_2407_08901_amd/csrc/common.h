@@ -216,7 +216,7 @@ void sym_eig_lowest(int m, int nwant, const double* S, int64_t lds, double* w, d
 // columns with sin(angle) <= tau, pivoted Cholesky of the rest.  Outputs:
 //   M[b x b] (row-major, columns >= kept are zero) with Phi1 = Phi M, R1[b x b] (Phi[:,kept] =
 //   Phi1 R1 restricted), perm/kept count in info[0..], angles[b].
-void cholqr_first(int b, const double* G, const double* psi_sumsq, double tau, double* M,
+void cholqr_first(int b, const double* G, const double* psi_sumsq, double tau, double rel, double* M,
                   double* Rfac, double* angles, int* info, hipStream_t s);
 // Step 2: G2 = Phi1^T Phi1 (kept x kept) -> M2 = R2^-1 and Rtot = R2 * R1 (kept x b in the
 // original column order); info[1] := 1 if the Cholesky failed.

@@ -292,7 +292,12 @@ int ortho_append(sppc_ctx* c, Basis& b, const double* P, int bw, const Op& op, i
     add_small(m * bw, c->C2, c->C1, s);
   }
   gemm_tn(n, bw, bw, c->Phi, bw, c->Phi, bw, c->Gm, bw, 1.0, 0.0, c->work, s);
-  cholqr_first(bw, c->Gm, c->psi2, c->o.tau_drop, c->M1, c->Rt, c->angles, c->info, s);
+  // appended to a basis, a column that depends on the block's own pivots (its Schur complement at
+  // the rounding of the Gram matrix, below 1e-12 of its Gram diagonal: a remaining part of 1e-6 of
+  // its norm) is dropped, or it would be normalised from rounding into a direction that is not
+  // orthogonal to Q.  An empty basis keeps such columns (they are then random directions of the
+  // block, as in the filtered subspace iteration of the zeroth order)
+  cholqr_first(bw, c->Gm, c->psi2, c->o.tau_drop, m > 0 ? 1e-12 : 0.0, c->M1, c->Rt, c->angles, c->info, s);
   c->tm.end(t0);
   SPPC_HIP(hipMemcpyAsync(c->pin_i, c->info, sizeof(int) * 2, hipMemcpyDeviceToHost, s));
   SPPC_HIP(hipMemcpyAsync(c->pin, c->angles, sizeof(double) * bw, hipMemcpyDeviceToHost, s));

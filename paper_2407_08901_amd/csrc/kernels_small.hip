@@ -561,16 +561,14 @@ __global__ __launch_bounds__(EIG_THREADS) void k_sym_eig(int m, int nw, const do
 // ---------------------------------------------------------------- Cholesky-QR factors
 constexpr int KB = 32;
 
-// A column whose Schur complement (what remains of it after the pivots taken) has fallen to this
-// fraction of its own Gram diagonal is dependent on those pivots: the complement of a Gram matrix
-// carries rounding of about b eps times that diagonal (b <= 32), so below ~1e-14 it is noise, and
-// keeping it would normalise rounding into a basis vector.  1e-12 (a remaining part of 1e-6 of the
-// column's norm) leaves the second Cholesky-QR pass a condition number of at most ~1e6.
-constexpr double kRelPivot = 1e-12;
-
 // Pivoted Cholesky of G restricted to the columns whose angle exceeds tau (one wave, LDS).
+// rel > 0: a column whose Schur complement (what remains of it after the pivots taken) has fallen
+// to rel times its own Gram diagonal is dropped as dependent on those pivots.  The complement of a
+// Gram matrix carries rounding of about b eps times that diagonal (b <= 32), so below ~1e-14 it is
+// noise; normalised, it becomes a direction that is not orthogonal to the basis the block was
+// projected against (the second pass orthonormalises the block only within itself).
 __global__ __launch_bounds__(64) void k_cholqr_first(int b, const double* __restrict__ G,
-                                                     const double* __restrict__ psi2, double tau,
+                                                     const double* __restrict__ psi2, double tau, double rel,
                                                      double* __restrict__ M, double* __restrict__ Rfac,
                                                      double* __restrict__ angles, int* __restrict__ info) {
   __shared__ double W[KB][KB + 1];
@@ -600,7 +598,7 @@ __global__ __launch_bounds__(64) void k_cholqr_first(int b, const double* __rest
       int best = -1;
       double bv = 0.0;
       for (int i = 0; i < b; ++i) {
-        if (cand[i] && !(W[i][i] > kRelPivot * gd[i])) cand[i] = 0;  // dependent on the pivots
+        if (cand[i] && !(W[i][i] > rel * gd[i])) cand[i] = 0;  // dependent on the pivots
         if (cand[i] && W[i][i] > bv) { bv = W[i][i]; best = i; }
       }
       int stop = best < 0;
@@ -933,10 +931,10 @@ void sym_eig_lowest(int m, int nwant, const double* S, int64_t lds, double* w, d
   SPPC_LAUNCH_CHECK();
 }
 
-void cholqr_first(int b, const double* G, const double* psi_sumsq, double tau, double* M, double* Rfac,
-                  double* angles, int* info, hipStream_t s) {
+void cholqr_first(int b, const double* G, const double* psi_sumsq, double tau, double rel, double* M,
+                  double* Rfac, double* angles, int* info, hipStream_t s) {
   if (b < 1 || b > KB) throw Error(1, "cholqr: block width must be 1..32");
-  k_cholqr_first<<<1, 64, 0, s>>>(b, G, psi_sumsq, tau, M, Rfac, angles, info);
+  k_cholqr_first<<<1, 64, 0, s>>>(b, G, psi_sumsq, tau, rel, M, Rfac, angles, info);
   SPPC_LAUNCH_CHECK();
 }
 

@@ -87,6 +87,26 @@ def test_basis_that_fills_the_whole_space(P):
         assert np.max(np.abs(ev - lam) / np.abs(lam)) < 1e-12
 
 
+@pytest.mark.parametrize("shape", [((9, 26, 80, 239, 715), 20, 485638, 11), ((8, 28, 104, 376), 21, 873697, 12)],
+                         ids=["n0=35-k11", "n0=36-k12"])
+def test_zeroth_order_filter_block_near_the_small_space(P, shape):
+    # two small levels of 35 and 36 rows with k = 11 and 12: the float64 form deflates 28 eigenpairs of
+    # H0hat, so the filtered block (32 columns) nearly fills the small space.  The filter amplifies
+    # its lowest directions by up to ~7e10, so some columns come out almost parallel; the block is
+    # orthonormalised on its own there (no basis to stay orthogonal to) and keeps them
+    sizes, d, seed, k = shape
+    A = levelgen.generate(sizes, d, seed)
+    print("case edge zeroth-order block n0=%d k=%d" % (sizes[0] + sizes[1], k), flush=True)
+    H = oracle.symmetric_from_upper(A.row_ptr, A.col, A.val, A.n)
+    lam = np.linalg.eigvalsh(H.toarray())[:k]
+    rp, col, val = P.upload(A)
+    ctx = P.sppc_setup(rp, col, val, A.level_offsets, 2, k, P.sppc_default_opts())
+    ev, Z, rrn, st, status = P.sppc_solve(ctx)
+    P.sppc_destroy(ctx)
+    assert status == P.SPPC_OK
+    assert np.max(np.abs(np.array(ev) - lam) / np.abs(lam)) < 1e-10
+
+
 def test_small_space_is_everything(P):
     # n0 = n: H0 = H and V = 0, so the zeroth order is exact (converged at p = 0)
     A = levelgen.generate((40, 300), 20, 8)
