@@ -87,3 +87,27 @@ def test_too_small_a_workspace_is_refused(P):
     ev, _, rrn, st, status = P.sppc_solve(ctx, want_vectors=False)
     assert status == P.SPPC_OK
     P.sppc_destroy(ctx)
+
+
+@pytest.mark.parametrize("name,sizes,d,seed,ns,k,tol", [
+    ("rmmdiis hand-over", (7, 61, 509, 3001, 7919), 30, 505, 2, 4, 1e-6),
+    ("rmmdiis refined after its check", (54, 451, 3771), 46, 789128, 2, 16, 1e-9)])
+def test_hybrid_continuations_on_a_torch_workspace(P, name, sizes, d, seed, ns, k, tol):
+    # the Davidson steps after a stagnated RMM-DIIS and the float64 refinement after a failed
+    # check run inside the workspace that sppc_workspace_size sized for the hybrid
+    A = levelgen.generate(sizes, d, seed)
+    print("case workspace %s n=%d" % (name, A.n), flush=True)
+    rp, col, val = P.upload(A)
+    opts = P.sppc_default_opts(precond=P.SPPC_CORR_RMMDIIS, tol=tol, max_cont=200)
+    need = P.sppc_workspace_size(rp, col, val, A.level_offsets, ns, k, opts)
+    ctx = P.sppc_setup(rp, col, val, A.level_offsets, ns, k, opts)
+    ev0, _, _, st0, s0 = P.sppc_solve(ctx, want_vectors=False)
+    P.sppc_destroy(ctx)
+    ws = P.workspace_tensor(need)
+    ctx = P.sppc_setup(rp, col, val, A.level_offsets, ns, k, opts, workspace=ws)
+    ev, _, rrn, st, status = P.sppc_solve(ctx, want_vectors=False)
+    P.sppc_destroy(ctx)
+    assert status == s0 == P.SPPC_OK and max(rrn) < tol
+    assert st["rmm_handover"] + st["refine_steps"] > 0
+    assert 0 < st["workspace_peak"] <= need
+    assert np.max(np.abs(np.array(ev) - np.array(ev0)) / np.abs(np.array(ev0))) < 1e-10
