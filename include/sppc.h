@@ -100,7 +100,9 @@ typedef struct {
   double tol;          /* convergence: every rrn_i < tol (eq. rrn); default 1e-6 */
   int maxiter;         /* highest perturbation order of pure SPPC (Alg. 2 input); default 30 */
   int p_switch;        /* after this many SPPC steps switch to the continuation (0 = never) ; 15 */
-  int max_cont;        /* continuation steps at most; default 200 */
+  int max_cont;        /* continuation steps at most (RMM-DIIS iterations and the Davidson steps after
+                          its hand-over together); the float64 refinement after a failed check has
+                          a budget of its own of the same size; default 200 */
   int m_max;           /* basis columns kept (2k..512); the continuation restarts beyond it.  0 (the
                           default) = automatic: k (p_switch + 1) rounded up to 16 with the RMM-DIIS
                           continuation (which restarts the basis at every sweep), else 512 */
