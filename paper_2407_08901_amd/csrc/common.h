@@ -213,7 +213,9 @@ void sym_eig_lowest(int m, int nwant, const double* S, int64_t lds, double* w, d
 
 // Orthonormalisation helpers (block of width b <= 32):
 // Step 1: from G = Phi^T Phi (b x b) and the squared norms of the original columns, drop
-// columns with sin(angle) <= tau, pivoted Cholesky of the rest.  Outputs:
+// columns with sin(angle) <= tau, pivoted Cholesky of the rest; with rel > 0 a column whose
+// Schur complement falls to rel times its own diagonal of G is dropped as dependent on the
+// pivots taken (0 keeps it while it exceeds tau^2 times its original squared norm).  Outputs:
 //   M[b x b] (row-major, columns >= kept are zero) with Phi1 = Phi M, R1[b x b] (Phi[:,kept] =
 //   Phi1 R1 restricted), perm/kept count in info[0..], angles[b].
 void cholqr_first(int b, const double* G, const double* psi_sumsq, double tau, double rel, double* M,
