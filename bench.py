@@ -255,6 +255,7 @@ def main():
         "converged": bool(st["converged"]), "max_rrn": max(rrn), "evals": ev,
         "iterations": st["iterations"], "cont_steps": st["cont_steps"], "refine_steps": st["refine_steps"],
         "mpnn_steps": st["mpnn_steps"], "n_spmv": st["n_spmv"],
+        "rmm_iterations": st["rmm_iterations"], "rmm_handover": bool(st["rmm_handover"]),
         "learned": {"iterations_per_solve": round(learned_its / len(results), 2),
                     "fallback_pairs_per_solve": round(fallbacks / len(results), 2),
                     "fallback_rate": round(fallbacks / (len(results) * w.k), 4)},
@@ -277,6 +278,7 @@ def main():
             return per_m, ev_m, {"s": round(per_m, 4), "steps": len(res_m), "iterations": st_m["iterations"],
                                  "cont_steps": st_m["cont_steps"], "refine_steps": st_m["refine_steps"],
                                  "mpnn_steps": st_m["mpnn_steps"], "n_spmv": st_m["n_spmv"],
+                                 "rmm_iterations": st_m["rmm_iterations"], "rmm_handover": bool(st_m["rmm_handover"]),
                                  "max_rrn": max(rrn_m), "converged": bool(st_m["converged"])}
         per_p, ev_p, d = summary("plain")
         line["plain_fp64"] = dict(d, max_rel_eval_diff=float(np.max(np.abs(np.array(ev) - np.array(ev_p)) /
