@@ -107,6 +107,28 @@ def test_zeroth_order_filter_block_near_the_small_space(P, shape):
     assert np.max(np.abs(np.array(ev) - lam) / np.abs(lam)) < 1e-10
 
 
+@pytest.mark.parametrize("sizes,d,seed", [((8, 100, 900), 20, 71), ((16, 150, 1500), 30, 72)], ids=["n0=8", "n0=16"])
+def test_k_equals_the_small_space(P, sizes, d, seed):
+    # k = n0: every eigenpair of H0hat is a wanted zeroth order, and the small solves deflate all of
+    # them (n_deflate = n0), so the CG works on an empty complement
+    A = levelgen.generate(sizes, d, seed)
+    k = sizes[0]
+    print("case edge k=n0=%d" % k, flush=True)
+    H = oracle.symmetric_from_upper(A.row_ptr, A.col, A.val, A.n)
+    lam = np.linalg.eigvalsh(H.toarray())[:k]
+    ref = oracle.sppc(H, k, k, oracle.Options())
+    assert ref.converged and np.max(np.abs(ref.theta - lam) / np.abs(lam)) < 1e-10
+    rp, col, val = P.upload(A)
+    for kw, bound in ((dict(), 1e-10), (dict(precision=P.SPPC_PREC_MIXED), 1e-8),
+                      (dict(precond=P.SPPC_CORR_RMMDIIS), 1e-10),
+                      (dict(precision=P.SPPC_PREC_MIXED, precond=P.SPPC_CORR_RMMDIIS), 1e-8)):
+        ctx = P.sppc_setup(rp, col, val, A.level_offsets, 1, k, P.sppc_default_opts(**kw))
+        ev, Z, rrn, st, status = P.sppc_solve(ctx)
+        P.sppc_destroy(ctx)
+        assert status == P.SPPC_OK and max(rrn) < 1e-6, kw
+        assert np.max(np.abs(np.array(ev) - lam) / np.abs(lam)) < bound, kw
+
+
 def test_small_space_is_everything(P):
     # n0 = n: H0 = H and V = 0, so the zeroth order is exact (converged at p = 0)
     A = levelgen.generate((40, 300), 20, 8)
