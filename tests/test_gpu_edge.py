@@ -129,6 +129,21 @@ def test_k_equals_the_small_space(P, sizes, d, seed):
         assert np.max(np.abs(np.array(ev) - lam) / np.abs(lam)) < bound, kw
 
 
+def test_one_row_small_space(P):
+    # n0 = 1, k = 1: H0hat is the scalar H[0][0], the zeroth order the first unit vector
+    A = levelgen.generate((1, 50, 400), 12, 73)
+    print("case edge n0=1", flush=True)
+    H = oracle.symmetric_from_upper(A.row_ptr, A.col, A.val, A.n)
+    lam = np.linalg.eigvalsh(H.toarray())[:1]
+    rp, col, val = P.upload(A)
+    for kw in (dict(), dict(precision=P.SPPC_PREC_MIXED), dict(precond=P.SPPC_CORR_RMMDIIS)):
+        ctx = P.sppc_setup(rp, col, val, A.level_offsets, 1, 1, P.sppc_default_opts(**kw))
+        ev, Z, rrn, st, status = P.sppc_solve(ctx)
+        P.sppc_destroy(ctx)
+        assert status == P.SPPC_OK and max(rrn) < 1e-6, kw
+        assert abs(ev[0] - lam[0]) / abs(lam[0]) < 1e-8, kw
+
+
 def test_small_space_is_everything(P):
     # n0 = n: H0 = H and V = 0, so the zeroth order is exact (converged at p = 0)
     A = levelgen.generate((40, 300), 20, 8)
